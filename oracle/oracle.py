@@ -1,0 +1,173 @@
+"""Python front end of the FP64 CPU oracle (level 1: the paper's Parseval method).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the HIP product path.
+
+Steps follow the paper (Gatti et al., Section "General structure of the
+program"):
+  Step 1 -- means, dU/dy, one-point moments and pseudo-dissipation
+            (``liboracle.or_means`` / ``or_onepoint``);
+  Step 2 -- two-point correlations through the Parseval identity for each
+            requested ordered pair (Y1, Y2) and assembly of the terms that
+            need no wall-normal derivative (``or_pairs``);
+  Step 3 -- the viscous Phi_ry and phi parts from the five-point derivative of
+            <du^2> along Y1 and Y2 (Section "Step 3": d/dry = (d/dY2 - d/dY1)/2,
+            d/dY = d/dY1 + d/dY2), done here.
+
+Term slots T1..T14 (index 0..13):
+  T1 <du^2>                         T8  -2 nu d<du^2>/drz
+  T2 <du^2 du>                      T9  <v* du^2>
+  T3 <du^2 dU>                      T10 (2/rho)<dp dv>
+  T4 -2 nu d<du^2>/drx              T11 -(nu/2) d<du^2>/dY
+  T5 <du^2 dv>                      T12 -2<du dv>(dU/dy)*
+  T6 -2 nu d<du^2>/dry              T13 -2<du v*> d(dU/dy)
+  T7 <du^2 dw>                      T14 -4<eps*>
+Maps are indexed [rz index q][rx index p] over the full periodic grid.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "gke_oracle.c")
+
+NT = 14
+PROFILE_ROWS = ["U", "V", "W", "P", "S", "q", "uv", "pv", "Tx", "Ty", "Tz", "eps"]
+NPROF = len(PROFILE_ROWS)
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (building the checker, not running it)."""
+    if force or not os.path.exists(_LIB_PATH) or (
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build())
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.or_fft1.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int]
+        L.or_fd5.argtypes = [ctypes.c_int, dp, dp]
+        L.or_means.argtypes = [ctypes.c_int] * 4 + [dp, dp]
+        L.or_onepoint.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp, ctypes.c_double,
+                                                       ctypes.c_double, ctypes.c_double, dp]
+        L.or_pairs.argtypes = ([ctypes.c_int] * 4 + [dp, dp] + [ctypes.c_double] * 3
+                               + [ctypes.c_int, ip, ip, dp, ctypes.c_int])
+        for f in (L.or_fft1, L.or_fd5, L.or_means, L.or_onepoint, L.or_pairs):
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def fft1(x: np.ndarray, sign: int = -1) -> np.ndarray:
+    """The oracle's own unnormalised 1-D DFT with exp(sign*2*pi*i*n*k/N)."""
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    out = np.empty_like(x)
+    rc = lib().or_fft1(x.size, _dp(x.view(np.float64)), _dp(out.view(np.float64)), int(sign))
+    assert rc == 0
+    return out
+
+
+def fd5_matrix(y: np.ndarray) -> np.ndarray:
+    """Dense five-point first-derivative operator on the grid y."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    D = np.zeros((y.size, y.size))
+    rc = lib().or_fd5(y.size, _dp(y), _dp(D))
+    if rc:
+        raise ValueError("five-point stencil needs at least 5 nodes")
+    return D
+
+
+def _as_snap(snap: np.ndarray) -> np.ndarray:
+    if snap.ndim != 5 or snap.shape[1] != 4:
+        raise ValueError("snapshots must be [S][4][ny][nz][nx]")
+    return np.ascontiguousarray(snap, dtype=np.float64)
+
+
+def step1(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float) -> np.ndarray:
+    """Profiles [NPROF][ny]: U V W P S=dU/dy <q> <uv> <pv> Tx Ty Tz eps."""
+    snap = _as_snap(snap)
+    ns, _, ny, nz, nx = snap.shape
+    means = np.zeros((4, ny))
+    lib().or_means(nx, ny, nz, ns, _dp(snap), _dp(means))
+    D = fd5_matrix(y)
+    prof = np.zeros((NPROF, ny))
+    rc = lib().or_onepoint(nx, ny, nz, ns, _dp(snap), _dp(means), _dp(D),
+                           float(lx), float(lz), float(nu), _dp(prof))
+    assert rc == 0
+    return prof
+
+
+def _raw_pairs(snap, prof, lx, lz, nu, pairs, nthreads):
+    ns, _, ny, nz, nx = snap.shape
+    pairs = np.asarray(pairs, dtype=np.int32).reshape(-1, 2)
+    y1 = np.ascontiguousarray(pairs[:, 0])
+    y2 = np.ascontiguousarray(pairs[:, 1])
+    out = np.zeros((len(pairs), NT, nz, nx))
+    prof = np.ascontiguousarray(prof, dtype=np.float64)
+    rc = lib().or_pairs(nx, ny, nz, ns, _dp(snap), _dp(prof), float(lx), float(lz), float(nu),
+                        len(pairs), _ip(y1), _ip(y2), _dp(out), int(nthreads or 0))
+    if rc:
+        raise RuntimeError(f"or_pairs failed ({rc})")
+    return out
+
+
+def pair_terms(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float,
+               pairs, prof: np.ndarray | None = None, nthreads: int | None = None):
+    """All 14 term maps for each ordered pair (Y1, Y2): array [npairs][14][nz][nx].
+
+    T6 and T11 (Step 3) use T1 on the five-point stencil neighbours along Y1
+    and Y2, which are computed as extra pairs.
+    """
+    snap = _as_snap(snap)
+    ny = snap.shape[2]
+    if prof is None:
+        prof = step1(snap, y, lx, lz, nu)
+    D = fd5_matrix(y)
+    pairs = [tuple(int(v) for v in p) for p in np.asarray(pairs).reshape(-1, 2)]
+    need = list(dict.fromkeys(pairs))
+    for (j1, j2) in pairs:
+        for m in np.nonzero(D[j1])[0]:
+            need.append((int(m), j2))
+        for m in np.nonzero(D[j2])[0]:
+            need.append((j1, int(m)))
+    need = list(dict.fromkeys(need))
+    index = {p: i for i, p in enumerate(need)}
+    raw = _raw_pairs(snap, prof, lx, lz, nu, need, nthreads)
+    out = np.empty((len(pairs),) + raw.shape[1:])
+    for k, (j1, j2) in enumerate(pairs):
+        o = raw[index[(j1, j2)]].copy()
+        d1 = sum(D[j1, m] * raw[index[(int(m), j2)], 0] for m in np.nonzero(D[j1])[0])
+        d2 = sum(D[j2, m] * raw[index[(j1, int(m))], 0] for m in np.nonzero(D[j2])[0])
+        o[5] = -nu * (d2 - d1)          # -2 nu * (d/dY2 - d/dY1)/2 <du^2>
+        o[10] = -0.5 * nu * (d1 + d2)   # -(nu/2) (d/dY1 + d/dY2) <du^2>
+        out[k] = o
+    del ny
+    return out
+
+
+def all_pairs(ny: int):
+    return [(a, b) for a in range(ny) for b in range(ny)]
