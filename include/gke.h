@@ -1,0 +1,182 @@
+/*
+ * gke.h -- C ABI of the MI355X (gfx950) GKE two-point-statistics library.
+ *
+ * The library computes the terms of the Generalised Kolmogorov Equation for
+ * plane channel flow (Gatti, Remigi, Chiarini, Cimarelli, Quadrio, "An
+ * efficient numerical method for the Generalised Kolmogorov Equation"):
+ * the scale energy <du^2> (eq. du2) and every flux and source component of
+ * eqs. scale-flux, physical-flux and source, on the four-dimensional domain
+ * (rx, rz, Y1, Y2) (Section "Structure of the GKE computer code": Y1 = Y - ry/2,
+ * Y2 = Y + ry/2).  Correlations in the homogeneous directions x, z are
+ * computed through the Parseval identity (Section "Products instead of
+ * correlations"); derivatives along Y1, Y2 use an explicit five-point stencil
+ * on the nonuniform y grid (Section "Step 3").
+ *
+ * Problem statement (Section "General structure of the program"): a database
+ * of snapshots of (u~, v~, w~, p~) on a Cartesian grid, periodic in x and z,
+ * nonuniform in y.  Step 1 scans it for the means, Step 2 scans it again and
+ * averages the two-point statistics, Step 3 takes the wall-normal derivatives.
+ * This ABI maps the two scans onto two sequences of gke_accumulate calls
+ * separated by gke_begin_stats, and Step 3 onto gke_finalize.
+ *
+ * Conventions
+ *   grid      x_m = m Lx/Nx, z_n = n Lz/Nz, nodes y[0..Ny) strictly increasing;
+ *   fields    device arrays [Ny][Nz][Nx] row-major (x fastest), F64 or F32;
+ *   average   <.> = mean over the Nx*Nz points of a plane (periodic
+ *             wrap-around of separations) and over the snapshots;
+ *   rho = 1   (the pressure flux is 2<dp dv>);
+ *   separations are grid multiples rx = p Lx/Nx, rz = q Lz/Nz; an index
+ *             q >= Nz/2 stands for the negative separation (q - Nz) Lz/Nz;
+ *   x- and z-derivatives are spectral with a zero multiplier at the Nyquist
+ *             wavenumber; y-derivatives use the five-point stencil (centred in
+ *             the interior, shifted to the five nodes nearest a wall).
+ *
+ * Errors: every call returns a gke_status; no exception crosses the ABI.
+ * gke_last_error(plan) describes the last failure on that plan.  A plan is
+ * not thread-safe; separate plans are independent.  Work is enqueued on the
+ * plan's HIP stream; only gke_begin_stats, gke_finalize, gke_get_profiles and
+ * gke_destroy synchronise it.
+ */
+#ifndef GKE_H
+#define GKE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gke_plan_s *gke_plan_t;
+
+typedef enum {
+    GKE_OK = 0,
+    GKE_ERR_ARG = 1,          /* invalid argument (shape, pointer, value) */
+    GKE_ERR_STATE = 2,        /* call not allowed in the plan's current state */
+    GKE_ERR_OOM = 3,          /* workspace missing or too small */
+    GKE_ERR_HIP = 4,          /* a HIP runtime call or kernel launch failed */
+    GKE_ERR_UNSUPPORTED = 5   /* valid request this build does not implement */
+} gke_status;
+
+/* option keys for gke_set_option (allowed before gke_set_workspace) */
+enum {
+    GKE_OPT_DTYPE = 1,        /* input storage: GKE_DTYPE_F64 (default) or GKE_DTYPE_F32 */
+    GKE_OPT_PRECISION = 2,    /* rank-k arithmetic: GKE_PREC_FP64 (default) or GKE_PREC_BF16X3 */
+    GKE_OPT_CHUNK = 3,        /* snapshots per cross-spectral batch, even, 2..4096 (default 64) */
+    GKE_OPT_PAIR_BATCH = 4    /* finalize pair-tile batch, 0 = all at once (default) */
+};
+enum { GKE_DTYPE_F64 = 0, GKE_DTYPE_F32 = 1 };
+enum { GKE_PREC_FP64 = 0, GKE_PREC_BF16X3 = 1 };
+
+/* term slots: the fourteen components of the budget, T1..T14 -> 0..13
+ *   GKE_T_DU2      <du_i du_i>                    (eq. du2)
+ *   GKE_T_PHIX_T   <du^2 du>                      (eq. scale-flux, turbulent, x)
+ *   GKE_T_PHIX_M   <du^2 dU>                      (eq. scale-flux, mean flow)
+ *   GKE_T_PHIX_V   -2 nu d<du^2>/drx              (eq. scale-flux, viscous, x)
+ *   GKE_T_PHIY_T   <du^2 dv>                      (eq. scale-flux, turbulent, y)
+ *   GKE_T_PHIY_V   -2 nu d<du^2>/dry              (eq. scale-flux, viscous, y)
+ *   GKE_T_PHIZ_T   <du^2 dw>                      (eq. scale-flux, turbulent, z)
+ *   GKE_T_PHIZ_V   -2 nu d<du^2>/drz              (eq. scale-flux, viscous, z)
+ *   GKE_T_PHI_T    <v* du^2>                      (eq. physical-flux, turbulent)
+ *   GKE_T_PHI_P    2 <dp dv>                      (eq. physical-flux, pressure)
+ *   GKE_T_PHI_V    -(nu/2) d<du^2>/dY             (eq. physical-flux, viscous)
+ *   GKE_T_XI_P1    -2 <du dv> (dU/dy)*            (eq. source, production 1)
+ *   GKE_T_XI_P2    -2 <du v*> d(dU/dy)            (eq. source, production 2)
+ *   GKE_T_XI_D     -4 <eps*>                      (eq. source, dissipation)
+ * Totals: Phi_rx = T2+T3+T4, Phi_ry = T5+T6, Phi_rz = T7+T8,
+ *         phi = T9+T10+T11, xi = T12+T13+T14. */
+enum {
+    GKE_T_DU2 = 0, GKE_T_PHIX_T, GKE_T_PHIX_M, GKE_T_PHIX_V, GKE_T_PHIY_T, GKE_T_PHIY_V,
+    GKE_T_PHIZ_T, GKE_T_PHIZ_V, GKE_T_PHI_T, GKE_T_PHI_P, GKE_T_PHI_V, GKE_T_XI_P1,
+    GKE_T_XI_P2, GKE_T_XI_D, GKE_NTERMS
+};
+
+/* Output of gke_finalize.  Each non-NULL t[i] is a caller-owned FP64 device
+ * array.  Maps T1..T13 are laid out [Y1 0..Ny)[Y2 0..Ny)[q 0..Nz)[p 0..Nx/2]
+ * (all ordered pairs, the half plane rx >= 0; the half rx <= 0 of pair
+ * (Y1,Y2) is the half rx >= 0 of pair (Y2,Y1) by the r-inversion symmetry of
+ * Section "Exploiting symmetries").  T14 does not depend on r and is laid out
+ * [Y1][Y2].  on_device must be 1. */
+typedef struct {
+    void *t[GKE_NTERMS];
+    int on_device;
+    int reserved;
+} gke_terms;
+
+/* profile rows returned by gke_get_profiles, each of length Ny (FP64):
+ * U V W P = means (Section "Step 1"), S = dU/dy (five-point stencil),
+ * q = <u'_i u'_i>, uv = <u'v'>, pv = <p'v'>, Tx Ty Tz = <q u'_j>,
+ * eps = nu <du'_i/dx_j du'_i/dx_j> (pseudo-dissipation, below eq. GKE). */
+enum { GKE_P_U = 0, GKE_P_V, GKE_P_W, GKE_P_P, GKE_P_S, GKE_P_Q, GKE_P_UV, GKE_P_PV,
+       GKE_P_TX, GKE_P_TY, GKE_P_TZ, GKE_P_EPS, GKE_NPROF };
+
+/* Create a plan for an Nx x Ny x Nz grid.
+ *   y   host array of Ny strictly increasing wall-normal nodes (copied);
+ *   Nx, Nz even, >= 4, with no prime factor other than 2, 3, 5; Ny >= 5;
+ *   Lx, Lz > 0 box lengths; nu > 0 kinematic viscosity.
+ * On success *out receives the plan (release with gke_destroy).
+ * Errors: GKE_ERR_ARG on any violation (then *out is NULL). */
+gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double Lz,
+                    double nu, gke_plan_t *out);
+
+/* Set an option (keys above) before gke_set_workspace.
+ * Errors: GKE_ERR_ARG (unknown key, bad value), GKE_ERR_STATE (too late),
+ * GKE_ERR_UNSUPPORTED (value not built). */
+gke_status gke_set_option(gke_plan_t plan, int key, int64_t value);
+
+/* Device workspace bytes the plan needs with its current options. */
+gke_status gke_workspace_size(gke_plan_t plan, size_t *bytes);
+
+/* Hand the plan a caller-owned device buffer of at least gke_workspace_size
+ * bytes (256-byte aligned).  The caller keeps ownership and must keep it
+ * alive until gke_destroy.  Fixes the options.  Errors: GKE_ERR_OOM if too
+ * small, GKE_ERR_ARG for NULL/misaligned, GKE_ERR_STATE if already set. */
+gke_status gke_set_workspace(gke_plan_t plan, void *device_ptr, size_t bytes);
+
+/* HIP stream (hipStream_t) on which all work is enqueued; NULL = default. */
+gke_status gke_set_stream(gke_plan_t plan, void *hip_stream);
+
+/* Add one snapshot: device pointers to u~, v~, w~, p~ ([Ny][Nz][Nx], the
+ * plan's dtype).  Before gke_begin_stats the call belongs to the first scan
+ * (sums for the means); afterwards to the second scan (two-point statistics).
+ * Asynchronous; the library does not keep the pointers once the enqueued work
+ * has run, so the caller may reuse the buffers after a stream synchronisation.
+ * Errors: GKE_ERR_ARG (NULL), GKE_ERR_STATE (no workspace), GKE_ERR_HIP. */
+gke_status gke_accumulate(gke_plan_t plan, const void *u, const void *v, const void *w,
+                          const void *p);
+
+/* Close the first scan: means U V W P from the snapshots accumulated so far
+ * and S = dU/dy.  Errors: GKE_ERR_STATE if no snapshot was accumulated or
+ * the second scan already started. */
+gke_status gke_begin_stats(gke_plan_t plan);
+
+/* Alternative to the first scan: host FP64 means U, V, W, P of length Ny.
+ * Errors: GKE_ERR_ARG (NULL), GKE_ERR_STATE (second scan already started). */
+gke_status gke_set_means(gke_plan_t plan, const double *U, const double *V, const double *W,
+                         const double *P);
+
+/* Average, inverse transforms, assembly and the five-point derivatives; write
+ * the requested maps (see gke_terms).  Blocking.  Does not consume the plan:
+ * more snapshots may be accumulated and finalize called again.  Errors:
+ * GKE_ERR_STATE (no second-scan snapshot, or the two scans have different
+ * snapshot counts), GKE_ERR_ARG, GKE_ERR_UNSUPPORTED (host outputs), GKE_ERR_HIP. */
+gke_status gke_finalize(gke_plan_t plan, const gke_terms *out);
+
+/* Copy the GKE_NPROF x Ny profile block (row-major, FP64) to host memory
+ * `out`.  Valid after gke_finalize (rows U..S after gke_begin_stats). */
+gke_status gke_get_profiles(gke_plan_t plan, double *out);
+
+/* Release the plan (synchronises its stream; never frees the workspace). */
+void gke_destroy(gke_plan_t plan);
+
+/* Text of the last error on `plan` (or of the last failed gke_plan when
+ * plan is NULL).  The string lives until the next call on the plan. */
+const char *gke_last_error(gke_plan_t plan);
+
+/* Library version string. */
+const char *gke_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GKE_H */

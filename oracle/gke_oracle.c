@@ -57,7 +57,7 @@ static cplx unit_root(long num, long den, int sign)
     return cos(a) + (double)sign * sin(a) * I;
 }
 
-/* work must hold n elements */
+/* work must hold 2n elements: n for the combination, n for the roots */
 static void dft_rec(int n, const cplx *in, long stride, cplx *out, int sign, cplx *work)
 {
     if (n == 1) { out[0] = in[0]; return; }
@@ -66,18 +66,21 @@ static void dft_rec(int n, const cplx *in, long stride, cplx *out, int sign, cpl
     /* sub-transforms of the p decimated sequences */
     for (int q = 0; q < p; ++q)
         dft_rec(m, in + q * stride, stride * p, out + q * m, sign, work);
+    /* roots of unity exp(sign 2 pi i t/n), t < n */
+    cplx *root = work + n;
+    for (int t = 0; t < n; ++t) root[t] = unit_root(t, n, sign);
     /* combine: X[k] = sum_q w^{q k} Y_q[k mod m] */
     for (int k = 0; k < n; ++k) {
         cplx acc = 0.0;
         for (int q = 0; q < p; ++q)
-            acc += unit_root((long)q * k, n, sign) * out[q * m + (k % m)];
+            acc += root[((long)q * k) % n] * out[q * m + (k % m)];
         work[k] = acc;
     }
     memcpy(out, work, sizeof(cplx) * (size_t)n);
 }
 
 /* 1-D transform of a strided complex sequence, result written back in place */
-static void fft1(int n, cplx *data, long stride, int sign, cplx *buf /* 3n */)
+static void fft1(int n, cplx *data, long stride, int sign, cplx *buf /* 4n */)
 {
     cplx *in = buf, *out = buf + n, *work = buf + 2 * n;
     for (int i = 0; i < n; ++i) in[i] = data[i * stride];
@@ -97,7 +100,7 @@ int or_fft1(int n, const double *in_ri, double *out_ri, int sign)
 {
     if (n < 1) return 1;
     cplx *d = malloc(sizeof(cplx) * (size_t)n);
-    cplx *buf = malloc(sizeof(cplx) * 3 * (size_t)n);
+    cplx *buf = malloc(sizeof(cplx) * 4 * (size_t)n);
     for (int i = 0; i < n; ++i) d[i] = in_ri[2 * i] + in_ri[2 * i + 1] * I;
     fft1(n, d, 1, sign, buf);
     for (int i = 0; i < n; ++i) { out_ri[2 * i] = creal(d[i]); out_ri[2 * i + 1] = cimag(d[i]); }
@@ -174,7 +177,8 @@ static double kx_mult(int k, int n, double len)
 }
 
 int or_onepoint(int nx, int ny, int nz, int ns, const double *snap, const double *means,
-                const double *D, double lx, double lz, double nu, double *prof /* [NPROF][ny] */)
+                const double *D, double lx, double lz, double nu, const int *mask,
+                double *prof /* [NPROF][ny] */)
 {
     long npl = (long)nx * nz;
     memset(prof, 0, sizeof(double) * NPROF * (size_t)ny);
@@ -186,11 +190,17 @@ int or_onepoint(int nx, int ny, int nz, int ns, const double *snap, const double
         prof[P_S * ny + j] = s;
     }
     int nmax = nx > nz ? nx : nz;
-    cplx *buf = malloc(sizeof(cplx) * 3 * (size_t)nmax);
-    cplx *pl = malloc(sizeof(cplx) * (size_t)npl);
-    double *dfl = malloc(sizeof(double) * (size_t)npl);
     double norm = 1.0 / ((double)ns * (double)npl);
+    /* planes are independent; mask (optional) selects the planes to compute */
+    #pragma omp parallel
+    {
+    cplx *buf = malloc(sizeof(cplx) * 4 * (size_t)nmax);
+    cplx *pl = malloc(sizeof(cplx) * (size_t)npl);
+    cplx *dp = malloc(sizeof(cplx) * (size_t)npl);
+    double *dfl = malloc(sizeof(double) * (size_t)npl);
+    #pragma omp for schedule(dynamic)
     for (int j = 0; j < ny; ++j) {
+        if (mask && !mask[j]) continue;
         double aq = 0, auv = 0, apv = 0, atx = 0, aty = 0, atz = 0, aeps = 0;
         for (int s = 0; s < ns; ++s) {
             const double *uu = FLD(snap, s, 0, j), *vv = FLD(snap, s, 1, j);
@@ -208,10 +218,7 @@ int or_onepoint(int nx, int ny, int nz, int ns, const double *snap, const double
                 double mu = means[c * ny + j];
                 for (long i = 0; i < npl; ++i) pl[i] = src[i] - mu;
                 fft2(nx, nz, pl, -1, buf);
-                for (int z = 0; z < nz; ++z)
-                    for (int x = 0; x < nx; ++x) pl[(long)z * nx + x] /= (double)npl;
-                /* d/dx */
-                cplx *dp = malloc(sizeof(cplx) * (size_t)npl);
+                for (long i = 0; i < npl; ++i) pl[i] /= (double)npl;
                 for (int dir = 0; dir < 2; ++dir) {
                     for (int z = 0; z < nz; ++z)
                         for (int x = 0; x < nx; ++x) {
@@ -221,7 +228,6 @@ int or_onepoint(int nx, int ny, int nz, int ns, const double *snap, const double
                     fft2(nx, nz, dp, +1, buf);
                     for (long i = 0; i < npl; ++i) aeps += creal(dp[i]) * creal(dp[i]);
                 }
-                free(dp);
                 /* d/dy with the five-point weights */
                 for (long i = 0; i < npl; ++i) dfl[i] = 0.0;
                 for (int m = 0; m < ny; ++m) {
@@ -242,7 +248,8 @@ int or_onepoint(int nx, int ny, int nz, int ns, const double *snap, const double
         prof[P_TZ * ny + j] = atz * norm;
         prof[P_EPS * ny + j] = nu * aeps * norm;
     }
-    free(buf); free(pl); free(dfl);
+    free(buf); free(pl); free(dp); free(dfl);
+    }
     return 0;
 }
 
@@ -333,7 +340,7 @@ int or_pairs(int nx, int ny, int nz, int ns, const double *snap, const double *p
         /* fluctuations, in-plane products in physical space, forward transforms */
         #pragma omp parallel
         {
-            cplx *buf = malloc(sizeof(cplx) * 3 * (size_t)nmax);
+            cplx *buf = malloc(sizeof(cplx) * 4 * (size_t)nmax);
             #pragma omp for schedule(dynamic)
             for (int t = 0; t < nplanes * NF; ++t) {
                 int pi = t / NF, f = t % NF, j = plane_of[pi];
@@ -380,7 +387,7 @@ int or_pairs(int nx, int ny, int nz, int ns, const double *snap, const double *p
     /* average, inverse transform, assembly */
     #pragma omp parallel
     {
-        cplx *buf = malloc(sizeof(cplx) * 3 * (size_t)nmax);
+        cplx *buf = malloc(sizeof(cplx) * 4 * (size_t)nmax);
         double *C = malloc(sizeof(double) * NCORR * (size_t)npl);
         cplx *tmp = malloc(sizeof(cplx) * (size_t)npl);
         #pragma omp for schedule(dynamic)

@@ -65,7 +65,7 @@ def lib():
         L.or_fd5.argtypes = [ctypes.c_int, dp, dp]
         L.or_means.argtypes = [ctypes.c_int] * 4 + [dp, dp]
         L.or_onepoint.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp, ctypes.c_double,
-                                                       ctypes.c_double, ctypes.c_double, dp]
+                                                       ctypes.c_double, ctypes.c_double, ip, dp]
         L.or_pairs.argtypes = ([ctypes.c_int] * 4 + [dp, dp] + [ctypes.c_double] * 3
                                + [ctypes.c_int, ip, ip, dp, ctypes.c_int])
         for f in (L.or_fft1, L.or_fd5, L.or_means, L.or_onepoint, L.or_pairs):
@@ -107,16 +107,30 @@ def _as_snap(snap: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(snap, dtype=np.float64)
 
 
-def step1(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float) -> np.ndarray:
-    """Profiles [NPROF][ny]: U V W P S=dU/dy <q> <uv> <pv> Tx Ty Tz eps."""
+def step1(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float,
+          planes=None, means=None) -> np.ndarray:
+    """Profiles [NPROF][ny]: U V W P S=dU/dy <q> <uv> <pv> Tx Ty Tz eps.
+
+    planes: optional iterable of plane indices; the one-point moments are then
+    computed on those planes only (the other rows of q..eps are left 0).
+    means: optional [4][ny] means to use instead of the ensemble means.
+    """
     snap = _as_snap(snap)
     ns, _, ny, nz, nx = snap.shape
-    means = np.zeros((4, ny))
-    lib().or_means(nx, ny, nz, ns, _dp(snap), _dp(means))
+    if means is None:
+        means = np.zeros((4, ny))
+        lib().or_means(nx, ny, nz, ns, _dp(snap), _dp(means))
+    else:
+        means = np.ascontiguousarray(np.asarray(means, dtype=np.float64)[:4])
     D = fd5_matrix(y)
     prof = np.zeros((NPROF, ny))
+    mask = None
+    if planes is not None:
+        mask = np.zeros(ny, dtype=np.int32)
+        mask[np.asarray(list(planes), dtype=np.int64)] = 1
     rc = lib().or_onepoint(nx, ny, nz, ns, _dp(snap), _dp(means), _dp(D),
-                           float(lx), float(lz), float(nu), _dp(prof))
+                           float(lx), float(lz), float(nu),
+                           _ip(mask) if mask is not None else None, _dp(prof))
     assert rc == 0
     return prof
 
@@ -144,8 +158,6 @@ def pair_terms(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float,
     """
     snap = _as_snap(snap)
     ny = snap.shape[2]
-    if prof is None:
-        prof = step1(snap, y, lx, lz, nu)
     D = fd5_matrix(y)
     pairs = [tuple(int(v) for v in p) for p in np.asarray(pairs).reshape(-1, 2)]
     need = list(dict.fromkeys(pairs))
@@ -155,6 +167,9 @@ def pair_terms(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float,
         for m in np.nonzero(D[j2])[0]:
             need.append((j1, int(m)))
     need = list(dict.fromkeys(need))
+    if prof is None:
+        planes = sorted({j for pr in need for j in pr})
+        prof = step1(snap, y, lx, lz, nu, planes=planes)
     index = {p: i for i, p in enumerate(need)}
     raw = _raw_pairs(snap, prof, lx, lz, nu, need, nthreads)
     out = np.empty((len(pairs),) + raw.shape[1:])

@@ -1,0 +1,202 @@
+// fft_lds.h -- batched mixed-radix (2, 3, 4, 5, 8) Stockham FFT in LDS.
+//
+// Used for the in-plane transforms of the method (Section "Products instead of
+// correlations": correlations in x and z through the Parseval identity).
+// A batch of `batch` transforms of length n lives in LDS with element
+// (b, i) at buf[b * bs + i]; every pass reads one buffer and writes the
+// other (ping-pong), so the result ends in natural order in the buffer
+// returned by lds_fft.  Twiddles come from a table tw[m] = exp(-2 pi i m/n),
+// m < n, built on the host in FP64; the inverse direction conjugates them.
+//   sign = -1: X[k] = sum_j x[j] exp(-2 pi i jk/n)      (forward)
+//   sign = +1: x[j] = sum_k X[k] exp(+2 pi i jk/n)      (inverse, unscaled)
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace gke {
+
+template <typename T>
+struct cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmk(T a, T b) { return cx<T>{a, b}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return cx<T>{a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return cx<T>{a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
+{
+    return cx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return cx<T>{a.x * s, a.y * s}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) { return cx<T>{a.x, -a.y}; }
+// multiply by (sign * i)
+template <typename T>
+__device__ __forceinline__ cx<T> cmul_si(cx<T> a, int sign)
+{
+    return sign > 0 ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x};
+}
+
+struct FftPlanDev {
+    int n;
+    int npass;
+    int radix[16];
+};
+
+template <int R, typename T>
+struct Dft;
+
+template <typename T>
+struct Dft<2, T> {
+    __device__ __forceinline__ static void run(cx<T> *v, int)
+    {
+        cx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <typename T>
+struct Dft<3, T> {
+    __device__ __forceinline__ static void run(cx<T> *v, int sign)
+    {
+        // w = exp(sign 2 pi i/3) = -1/2 + sign i sqrt(3)/2
+        const T h = T(0.86602540378443864676372317075294);  // sqrt(3)/2
+        cx<T> a = v[0], b = v[1], c = v[2];
+        cx<T> t1 = cadd(b, c);
+        cx<T> t2 = cscale(cmul_si(csub(b, c), sign), h);
+        cx<T> m = csub(a, cscale(t1, T(0.5)));
+        v[0] = cadd(a, t1);
+        v[1] = cadd(m, t2);
+        v[2] = csub(m, t2);
+    }
+};
+
+template <typename T>
+struct Dft<4, T> {
+    __device__ __forceinline__ static void run(cx<T> *v, int sign)
+    {
+        cx<T> a = v[0], b = v[1], c = v[2], d = v[3];
+        cx<T> s0 = cadd(a, c), d0 = csub(a, c);
+        cx<T> s1 = cadd(b, d), d1 = cmul_si(csub(b, d), sign);
+        v[0] = cadd(s0, s1);
+        v[1] = cadd(d0, d1);
+        v[2] = csub(s0, s1);
+        v[3] = csub(d0, d1);
+    }
+};
+
+template <typename T>
+struct Dft<5, T> {
+    __device__ __forceinline__ static void run(cx<T> *v, int sign)
+    {
+        const T c1 = T(0.30901699437494742410229341718282);   // cos(2pi/5)
+        const T c2 = T(-0.80901699437494742410229341718282);  // cos(4pi/5)
+        const T s1 = T(0.95105651629515357211643933337938);   // sin(2pi/5)
+        const T s2 = T(0.58778525229247312916870595463907);   // sin(4pi/5)
+        cx<T> a = v[0];
+        cx<T> be = cadd(v[1], v[4]), bm = csub(v[1], v[4]);
+        cx<T> cd = cadd(v[2], v[3]), cm = csub(v[2], v[3]);
+        cx<T> r1 = cadd(a, cadd(cscale(be, c1), cscale(cd, c2)));
+        cx<T> r2 = cadd(a, cadd(cscale(be, c2), cscale(cd, c1)));
+        cx<T> i1 = cmul_si(cadd(cscale(bm, s1), cscale(cm, s2)), sign);
+        cx<T> i2 = cmul_si(csub(cscale(bm, s2), cscale(cm, s1)), sign);
+        v[0] = cadd(a, cadd(be, cd));
+        v[1] = cadd(r1, i1);
+        v[4] = csub(r1, i1);
+        v[2] = cadd(r2, i2);
+        v[3] = csub(r2, i2);
+    }
+};
+
+template <typename T>
+struct Dft<8, T> {
+    __device__ __forceinline__ static void run(cx<T> *v, int sign)
+    {
+        // two radix-4 transforms on the even and odd samples, then radix-2
+        cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+        cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4, T>::run(e, sign);
+        Dft<4, T>::run(o, sign);
+        const T r = T(0.70710678118654752440084436210485);
+        // w8^k, k = 0..3, with w8 = exp(sign 2 pi i/8)
+        cx<T> w1 = cx<T>{r, T(sign) * r};
+        cx<T> w3 = cx<T>{-r, T(sign) * r};
+        cx<T> t0 = o[0];
+        cx<T> t1 = cmul(o[1], w1);
+        cx<T> t2 = cmul_si(o[2], sign);
+        cx<T> t3 = cmul(o[3], w3);
+        v[0] = cadd(e[0], t0);
+        v[4] = csub(e[0], t0);
+        v[1] = cadd(e[1], t1);
+        v[5] = csub(e[1], t1);
+        v[2] = cadd(e[2], t2);
+        v[6] = csub(e[2], t2);
+        v[3] = cadd(e[3], t3);
+        v[7] = csub(e[3], t3);
+    }
+};
+
+// One Stockham pass of radix R.  p = product of the radices already applied.
+template <int R, typename T>
+__device__ __forceinline__ void stockham_pass(const cx<T> *src, cx<T> *dst, int n, int p,
+                                              int batch, int bs, const cx<T> *tw, int sign)
+{
+    const int m = n / R;
+    const int total = batch * m;
+    const int twstep = n / (p * R);
+    for (int it = threadIdx.x; it < total; it += blockDim.x) {
+        const int b = it / m;
+        const int i = it - b * m;
+        const int k = i % p;
+        const cx<T> *s = src + b * bs;
+        cx<T> v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = s[i + j * m];
+        if (p > 1) {
+#pragma unroll
+            for (int j = 1; j < R; ++j) {
+                cx<T> w = tw[j * k * twstep];
+                if (sign > 0) w.y = -w.y;
+                v[j] = cmul(v[j], w);
+            }
+        }
+        Dft<R, T>::run(v, sign);
+        const int base = (i - k) * R + k;
+        cx<T> *d = dst + b * bs;
+#pragma unroll
+        for (int j = 0; j < R; ++j) d[base + j * p] = v[j];
+    }
+}
+
+// Run every pass; data starts in `a`, `b` is scratch of the same shape.
+// Returns the buffer that holds the result.  Ends with a barrier.
+template <typename T>
+__device__ cx<T> *lds_fft(cx<T> *a, cx<T> *b, int batch, int bs, const FftPlanDev &pl,
+                          const cx<T> *tw, int sign)
+{
+    cx<T> *src = a, *dst = b;
+    int p = 1;
+    for (int ps = 0; ps < pl.npass; ++ps) {
+        const int R = pl.radix[ps];
+        switch (R) {
+        case 2: stockham_pass<2, T>(src, dst, pl.n, p, batch, bs, tw, sign); break;
+        case 3: stockham_pass<3, T>(src, dst, pl.n, p, batch, bs, tw, sign); break;
+        case 4: stockham_pass<4, T>(src, dst, pl.n, p, batch, bs, tw, sign); break;
+        case 5: stockham_pass<5, T>(src, dst, pl.n, p, batch, bs, tw, sign); break;
+        default: stockham_pass<8, T>(src, dst, pl.n, p, batch, bs, tw, sign); break;
+        }
+        __syncthreads();
+        cx<T> *t = src;
+        src = dst;
+        dst = t;
+        p *= R;
+    }
+    return src;
+}
+
+}  // namespace gke

@@ -1,0 +1,92 @@
+// gke_internal.h -- shapes and kernel launchers shared by the library's own
+// sources (never by the CPU oracle).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "fft_lds.h"
+
+namespace gke {
+
+// fields carried in the spectra, in this order: fluctuations and the six
+// in-plane products formed in physical space (Section "Products instead of
+// correlations")
+enum { F_U = 0, F_V, F_W, F_P, F_UU, F_VV, F_WW, F_UV, F_UW, F_VW, NFIELD };
+
+// term spectra accumulated per unordered pair tile (see k_rankk.hip)
+enum { S_R = 0, S_FX, S_FY, S_FZ, S_PHI, S_PP, S_UVS, S_UVA, NSPEC };
+
+// r-space maps produced by the inverse transforms in finalize
+enum { M_R = 0, M_DRX, M_DRZ, M_FX, M_FY, M_FZ, M_PHI, M_PP, M_UVS, M_UVA, NMAP };
+
+// profile rows (same order as the public GKE_P_* rows)
+enum { P_U = 0, P_V, P_W, P_P, P_S, P_Q, P_UV, P_PV, P_TX, P_TY, P_TZ, P_EPS, NPROF };
+
+// physical-space moment partials per (plane, z block): q uv pv qu qv qw gy
+enum { MP_Q = 0, MP_UV, MP_PV, MP_QU, MP_QV, MP_QW, MP_GY, NMOMP };
+
+struct Dims {
+    int nx, ny, nz;
+    int nkx;        // nx/2 + 1
+    int nk;         // nkx * nz
+    int nyp;        // ny rounded up to 16
+    int ntile;      // nyp / 16
+    int ntp;        // ntile (ntile + 1) / 2 unordered tile pairs
+    int zb, nzb;    // z rows per block in the x pass, number of blocks
+    int jb;         // planes per block in the z pass
+    int chunk;      // snapshot slots in the spectra buffer
+    double lx, lz, nu;
+};
+
+struct Tables {
+    const cx<double> *twx;   // exp(-2 pi i m/nx)
+    const cx<double> *twz;   // exp(-2 pi i m/nz)
+    const double *w5;        // [ny][5] five-point weights
+    const int *j0;           // [ny] first stencil node
+    const int *tile_a;       // [ntp] tile-pair rows
+    const int *tile_b;       // [ntp] tile-pair columns (a <= b)
+    FftPlanDev px, pz;
+};
+
+// pass 1: plane sums of u~ v~ w~ p~ added into sums[4][ny]
+hipError_t launch_plane_sums(hipStream_t st, const Dims &d, int f32, const void *u,
+                             const void *v, const void *w, const void *p, double *sums);
+// means = sums / count, S = D U (profile rows U V W P S)
+hipError_t launch_means(hipStream_t st, const Dims &d, const Tables &t, const double *sums,
+                        double count, double *prof);
+// S = D U only (means already in prof)
+hipError_t launch_shear(hipStream_t st, const Dims &d, const Tables &t, double *prof);
+// reduce moment partials into the remaining profile rows
+hipError_t launch_profiles(hipStream_t st, const Dims &d, const double *momp,
+                           const double *momg, double count, double *prof);
+
+// pass 2, per snapshot: fluctuations, products, x transforms, moments
+hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int f32,
+                             const void *u, const void *v, const void *w, const void *p,
+                             const double *prof, cx<double> *inter, double *momp);
+// z transforms, packing into the spectra slot, gradient energy
+hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t,
+                            const cx<double> *inter, int slot, cx<double> *spec,
+                            double *momg);
+// cross-spectral rank-k update over the snapshots of one chunk
+hipError_t launch_rankk_f64(hipStream_t st, const Dims &d, const Tables &t,
+                            const cx<double> *spec, int nsnap, int accumulate,
+                            cx<double> *acc);
+// finalize: inverse transform along kz of the term spectra of tile pairs
+// [tp0, tp1), scaled by 1/count
+hipError_t launch_fin_kz(hipStream_t st, const Dims &d, const Tables &t,
+                         const cx<double> *acc, int tp0, int tp1, double inv_count,
+                         cx<double> *mid);
+// finalize: inverse real transform along kx, FP64 assembly, both orientations
+hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
+                         const cx<double> *mid, int tp0, int tp1, const double *prof,
+                         double *const *out);
+// Step 3: T6 and T11 from T1 along Y1 and Y2
+hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const double *t1,
+                           double *t6, double *t11);
+// T14 = -2 (eps(Y1) + eps(Y2))
+hipError_t launch_t14(hipStream_t st, const Dims &d, const double *prof, double *t14);
+
+}  // namespace gke

@@ -1,0 +1,423 @@
+// gke_plan.cpp -- the C ABI declared in include/gke.h: plan state machine,
+// workspace carving, host-built tables and the launch sequence of the two
+// scans (Sections "Step 1", "Step 2", "Step 3").
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gke.h"
+#include "gke_internal.h"
+
+using gke::cx;
+
+struct gke_plan_s {
+    gke::Dims d{};
+    std::vector<double> y;
+    int dtype = GKE_DTYPE_F64;
+    int prec = GKE_PREC_FP64;
+    int chunk = 64;
+    int pair_batch = 0;  // tile pairs per finalize batch (0 = all)
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+
+    // host copies of the tables (kept alive for the async uploads)
+    std::vector<cx<double>> h_twx, h_twz;
+    std::vector<double> h_w5;
+    std::vector<int> h_j0, h_ta, h_tb;
+
+    // carved device pointers
+    cx<double> *twx = nullptr, *twz = nullptr;
+    double *w5 = nullptr;
+    int *j0 = nullptr, *ta = nullptr, *tb = nullptr;
+    double *sums1 = nullptr, *prof = nullptr, *momp = nullptr, *momg = nullptr;
+    cx<double> *inter = nullptr, *spec = nullptr, *acc = nullptr, *mid = nullptr;
+    gke::Tables tab{};
+
+    long long n1 = 0;          // first-scan snapshots
+    long long n2 = 0;          // second-scan snapshots
+    int pending = 0;           // snapshots in the current chunk
+    long long chunks_done = 0;
+    bool second_scan = false;
+    bool means_from_host = false;
+    std::string err;
+};
+
+static std::string g_plan_error;
+
+namespace {
+
+gke_status fail(gke_plan_t p, gke_status s, const std::string &msg)
+{
+    if (p) p->err = msg;
+    else g_plan_error = msg;
+    return s;
+}
+
+#define GKE_HIP(plan, call)                                                         \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return fail(plan, GKE_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool factors_235(int n)
+{
+    for (int f : {2, 3, 5})
+        while (n % f == 0) n /= f;
+    return n == 1;
+}
+
+gke::FftPlanDev radix_plan(int n)
+{
+    gke::FftPlanDev pl{};
+    pl.n = n;
+    int m = n, k = 0;
+    while (m % 5 == 0) { pl.radix[k++] = 5; m /= 5; }
+    while (m % 3 == 0) { pl.radix[k++] = 3; m /= 3; }
+    int e2 = 0;
+    while (m % 2 == 0) { ++e2; m /= 2; }
+    while (e2 >= 3 && e2 != 4) { pl.radix[k++] = 8; e2 -= 3; }
+    while (e2 >= 2) { pl.radix[k++] = 4; e2 -= 2; }
+    if (e2 == 1) pl.radix[k++] = 2;
+    pl.npass = k;
+    return pl;
+}
+
+std::vector<cx<double>> twiddles(int n)
+{
+    std::vector<cx<double>> t(n);
+    for (int m = 0; m < n; ++m) {
+        const double a = 2.0 * M_PI * (double)m / (double)n;
+        t[m] = cx<double>{std::cos(a), -std::sin(a)};
+    }
+    return t;
+}
+
+// First-derivative weights at x0 on the nodes x[0..n) by Fornberg's recurrence
+// (B. Fornberg, Math. Comp. 51 (1988) 699-706), derivative orders 0 and 1.
+void fornberg_d1(double x0, const double *x, int n, double *w)
+{
+    std::vector<double> c0(n, 0.0), c1(n, 0.0);
+    double a = 1.0, xd = x[0] - x0;
+    c0[0] = 1.0;
+    for (int i = 1; i < n; ++i) {
+        double b = 1.0;
+        const double xd_prev = xd;
+        xd = x[i] - x0;
+        for (int j = 0; j < i; ++j) {
+            const double dx = x[i] - x[j];
+            b *= dx;
+            if (j == i - 1) {
+                c1[i] = a * (c0[i - 1] - xd_prev * c1[i - 1]) / b;
+                c0[i] = -a * xd_prev * c0[i - 1] / b;
+            }
+            c1[j] = (xd * c1[j] - c0[j]) / dx;
+            c0[j] = xd * c0[j] / dx;
+        }
+        a = b;
+    }
+    for (int i = 0; i < n; ++i) w[i] = c1[i];
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace layout; with base != nullptr also assigns the pointers.
+size_t layout(gke_plan_t p, char *base)
+{
+    const gke::Dims &d = p->d;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return base ? base + o : nullptr;
+    };
+    const int pbt = (p->pair_batch > 0 && p->pair_batch < d.ntp) ? p->pair_batch : d.ntp;
+    p->twx = (cx<double> *)take(sizeof(cx<double>) * d.nx);
+    p->twz = (cx<double> *)take(sizeof(cx<double>) * d.nz);
+    p->w5 = (double *)take(sizeof(double) * 5 * d.ny);
+    p->j0 = (int *)take(sizeof(int) * d.ny);
+    p->ta = (int *)take(sizeof(int) * d.ntp);
+    p->tb = (int *)take(sizeof(int) * d.ntp);
+    p->sums1 = (double *)take(sizeof(double) * 4 * d.ny);
+    p->prof = (double *)take(sizeof(double) * gke::NPROF * d.ny);
+    p->momp = (double *)take(sizeof(double) * d.ny * gke::NMOMP * d.nzb);
+    p->momg = (double *)take(sizeof(double) * d.ny * 3 * d.nkx);
+    p->inter = (cx<double> *)take(sizeof(cx<double>) * (size_t)d.ny * gke::NFIELD * d.nkx * d.nz);
+    p->spec = (cx<double> *)take(sizeof(cx<double>) * (size_t)d.nk * gke::NFIELD * d.chunk * d.nyp);
+    p->acc = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NSPEC * d.nk * d.ntp * 256);
+    p->mid = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NMAP * d.nkx * d.nz * pbt * 256);
+    return off;
+}
+
+gke_status launch_flush(gke_plan_t p)
+{
+    if (p->pending == 0) return GKE_OK;
+    GKE_HIP(p, gke::launch_rankk_f64(p->stream, p->d, p->tab, p->spec, p->pending,
+                                     p->chunks_done > 0 ? 1 : 0, p->acc));
+    ++p->chunks_done;
+    p->pending = 0;
+    return GKE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double Lz, double nu,
+                    gke_plan_t *out)
+{
+    if (!out) return fail(nullptr, GKE_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!y) return fail(nullptr, GKE_ERR_ARG, "y is NULL");
+    if (Nx < 4 || Nz < 4 || Nx % 2 || Nz % 2)
+        return fail(nullptr, GKE_ERR_ARG, "Nx and Nz must be even and >= 4");
+    if (!factors_235(Nx) || !factors_235(Nz))
+        return fail(nullptr, GKE_ERR_ARG, "Nx and Nz must factor into 2, 3 and 5");
+    if (Nx > 4096 || Nz > 4096) return fail(nullptr, GKE_ERR_UNSUPPORTED, "Nx, Nz > 4096");
+    if (Ny < 5 || Ny > 4096) return fail(nullptr, GKE_ERR_ARG, "Ny must be in [5, 4096]");
+    if (!(Lx > 0) || !(Lz > 0) || !(nu > 0))
+        return fail(nullptr, GKE_ERR_ARG, "Lx, Lz and nu must be positive");
+    for (int j = 1; j < Ny; ++j)
+        if (!(y[j] > y[j - 1])) return fail(nullptr, GKE_ERR_ARG, "y must be strictly increasing");
+    gke_plan_t p = new (std::nothrow) gke_plan_s();
+    if (!p) return fail(nullptr, GKE_ERR_OOM, "host allocation failed");
+    p->y.assign(y, y + Ny);
+    gke::Dims &d = p->d;
+    d.nx = Nx;
+    d.ny = Ny;
+    d.nz = Nz;
+    d.nkx = Nx / 2 + 1;
+    d.nk = d.nkx * Nz;
+    d.nyp = (Ny + 15) / 16 * 16;
+    d.ntile = d.nyp / 16;
+    d.ntp = d.ntile * (d.ntile + 1) / 2;
+    d.lx = Lx;
+    d.lz = Lz;
+    d.nu = nu;
+    // x pass: zb rows per block, LDS = 2 zb (nx + 1) complex doubles <= 64 KiB
+    d.zb = 8;
+    while (d.zb > 1 && (Nz % d.zb || 2 * (size_t)d.zb * (Nx + 1) * 16 > 65536)) d.zb >>= 1;
+    d.nzb = Nz / d.zb;
+    d.jb = 8;
+    while (d.jb > 1 && 2 * (size_t)d.jb * (Nz + 1) * 16 > 65536) d.jb >>= 1;
+    if (2 * (size_t)(Nx + 1) * 16 > 65536 || 2 * (size_t)(Nz + 1) * 16 > 65536) {
+        delete p;
+        return fail(nullptr, GKE_ERR_UNSUPPORTED, "transform length too large for one block");
+    }
+    d.chunk = p->chunk;
+
+    p->h_twx = twiddles(Nx);
+    p->h_twz = twiddles(Nz);
+    p->h_w5.assign(5 * (size_t)Ny, 0.0);
+    p->h_j0.assign(Ny, 0);
+    for (int j = 0; j < Ny; ++j) {
+        const int s = std::min(std::max(j - 2, 0), Ny - 5);
+        p->h_j0[j] = s;
+        fornberg_d1(y[j], y + s, 5, &p->h_w5[5 * (size_t)j]);
+    }
+    for (int a = 0; a < d.ntile; ++a)
+        for (int b = a; b < d.ntile; ++b) {
+            p->h_ta.push_back(a);
+            p->h_tb.push_back(b);
+        }
+    p->tab.px = radix_plan(Nx);
+    p->tab.pz = radix_plan(Nz);
+    *out = p;
+    return GKE_OK;
+}
+
+gke_status gke_set_option(gke_plan_t p, int key, int64_t value)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (p->ws) return fail(p, GKE_ERR_STATE, "options are fixed once the workspace is set");
+    switch (key) {
+    case GKE_OPT_DTYPE:
+        if (value != GKE_DTYPE_F64 && value != GKE_DTYPE_F32)
+            return fail(p, GKE_ERR_ARG, "dtype must be GKE_DTYPE_F64 or GKE_DTYPE_F32");
+        p->dtype = (int)value;
+        return GKE_OK;
+    case GKE_OPT_PRECISION:
+        if (value == GKE_PREC_FP64) {
+            p->prec = (int)value;
+            return GKE_OK;
+        }
+        if (value == GKE_PREC_BF16X3) return fail(p, GKE_ERR_UNSUPPORTED, "split-BF16 not built");
+        return fail(p, GKE_ERR_ARG, "unknown precision");
+    case GKE_OPT_CHUNK:
+        if (value < 2 || value > 4096 || value % 2)
+            return fail(p, GKE_ERR_ARG, "chunk must be even and in [2, 4096]");
+        p->chunk = (int)value;
+        p->d.chunk = (int)value;
+        return GKE_OK;
+    case GKE_OPT_PAIR_BATCH:
+        if (value < 0 || value > 1000000) return fail(p, GKE_ERR_ARG, "bad pair batch");
+        p->pair_batch = (int)value;
+        return GKE_OK;
+    default:
+        return fail(p, GKE_ERR_ARG, "unknown option key");
+    }
+}
+
+gke_status gke_workspace_size(gke_plan_t p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(p, GKE_ERR_ARG, "NULL argument");
+    *bytes = layout(p, nullptr);
+    return GKE_OK;
+}
+
+gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (p->ws) return fail(p, GKE_ERR_STATE, "workspace already set");
+    if (!dev || ((uintptr_t)dev & 255)) return fail(p, GKE_ERR_ARG, "workspace NULL or not 256-byte aligned");
+    const size_t need = layout(p, nullptr);
+    if (bytes < need)
+        return fail(p, GKE_ERR_OOM, "workspace too small: need " + std::to_string(need) + " bytes");
+    p->ws = (char *)dev;
+    p->ws_bytes = bytes;
+    layout(p, p->ws);
+    const gke::Dims &d = p->d;
+    hipStream_t st = p->stream;
+    GKE_HIP(p, hipMemcpyAsync(p->twx, p->h_twx.data(), sizeof(cx<double>) * d.nx, hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->twz, p->h_twz.data(), sizeof(cx<double>) * d.nz, hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->w5, p->h_w5.data(), sizeof(double) * 5 * d.ny, hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->j0, p->h_j0.data(), sizeof(int) * d.ny, hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->ta, p->h_ta.data(), sizeof(int) * d.ntp, hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->tb, p->h_tb.data(), sizeof(int) * d.ntp, hipMemcpyHostToDevice, st));
+    // accumulators and the spectra (whose padding planes must stay zero)
+    GKE_HIP(p, hipMemsetAsync(p->sums1, 0, (char *)p->inter - (char *)p->sums1, st));
+    GKE_HIP(p, hipMemsetAsync(p->spec, 0, sizeof(cx<double>) * (size_t)d.nk * gke::NFIELD * d.chunk * d.nyp, st));
+    GKE_HIP(p, hipStreamSynchronize(st));
+    p->tab.twx = p->twx;
+    p->tab.twz = p->twz;
+    p->tab.w5 = p->w5;
+    p->tab.j0 = p->j0;
+    p->tab.tile_a = p->ta;
+    p->tab.tile_b = p->tb;
+    return GKE_OK;
+}
+
+gke_status gke_set_stream(gke_plan_t p, void *stream)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    p->stream = (hipStream_t)stream;
+    return GKE_OK;
+}
+
+gke_status gke_accumulate(gke_plan_t p, const void *u, const void *v, const void *w,
+                          const void *pr)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (!u || !v || !w || !pr) return fail(p, GKE_ERR_ARG, "field pointer is NULL");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    const int f32 = p->dtype == GKE_DTYPE_F32;
+    if (!p->second_scan) {
+        GKE_HIP(p, gke::launch_plane_sums(p->stream, p->d, f32, u, v, w, pr, p->sums1));
+        ++p->n1;
+        return GKE_OK;
+    }
+    GKE_HIP(p, gke::launch_fluct_xfft(p->stream, p->d, p->tab, f32, u, v, w, pr, p->prof,
+                                      p->inter, p->momp));
+    GKE_HIP(p, gke::launch_zfft_pack(p->stream, p->d, p->tab, p->inter, p->pending, p->spec,
+                                     p->momg));
+    ++p->pending;
+    ++p->n2;
+    if (p->pending == p->d.chunk) return launch_flush(p);
+    return GKE_OK;
+}
+
+gke_status gke_begin_stats(gke_plan_t p)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    if (p->second_scan) return fail(p, GKE_ERR_STATE, "second scan already started");
+    if (p->n1 == 0) return fail(p, GKE_ERR_STATE, "no first-scan snapshot");
+    GKE_HIP(p, gke::launch_means(p->stream, p->d, p->tab, p->sums1, (double)p->n1, p->prof));
+    GKE_HIP(p, hipStreamSynchronize(p->stream));
+    p->second_scan = true;
+    return GKE_OK;
+}
+
+gke_status gke_set_means(gke_plan_t p, const double *U, const double *V, const double *W,
+                         const double *P)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (!U || !V || !W || !P) return fail(p, GKE_ERR_ARG, "mean pointer is NULL");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    if (p->second_scan) return fail(p, GKE_ERR_STATE, "second scan already started");
+    const int ny = p->d.ny;
+    const double *src[4] = {U, V, W, P};
+    for (int f = 0; f < 4; ++f)
+        GKE_HIP(p, hipMemcpyAsync(p->prof + f * ny, src[f], sizeof(double) * ny,
+                                  hipMemcpyHostToDevice, p->stream));
+    GKE_HIP(p, gke::launch_shear(p->stream, p->d, p->tab, p->prof));
+    GKE_HIP(p, hipStreamSynchronize(p->stream));
+    p->second_scan = true;
+    p->means_from_host = true;
+    return GKE_OK;
+}
+
+gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (!out) return fail(p, GKE_ERR_ARG, "out is NULL");
+    if (!out->on_device) return fail(p, GKE_ERR_UNSUPPORTED, "host outputs are not supported");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    if (!p->second_scan || p->n2 == 0) return fail(p, GKE_ERR_STATE, "no second-scan snapshot");
+    if (!p->means_from_host && p->n1 != p->n2)
+        return fail(p, GKE_ERR_STATE, "the two scans saw different snapshot counts");
+    if ((out->t[GKE_T_PHIY_V] || out->t[GKE_T_PHI_V]) && !out->t[GKE_T_DU2])
+        return fail(p, GKE_ERR_ARG, "the Y-derivative terms need the <du^2> output buffer");
+    gke_status s = launch_flush(p);
+    if (s != GKE_OK) return s;
+    const gke::Dims &d = p->d;
+    hipStream_t st = p->stream;
+    GKE_HIP(p, gke::launch_profiles(st, d, p->momp, p->momg, (double)p->n2, p->prof));
+    double *outp[14];
+    for (int i = 0; i < 14; ++i) outp[i] = (double *)out->t[i];
+    const int pbt = (p->pair_batch > 0 && p->pair_batch < d.ntp) ? p->pair_batch : d.ntp;
+    const double inv = 1.0 / (double)p->n2;
+    for (int tp0 = 0; tp0 < d.ntp; tp0 += pbt) {
+        const int tp1 = std::min(d.ntp, tp0 + pbt);
+        GKE_HIP(p, gke::launch_fin_kz(st, d, p->tab, p->acc, tp0, tp1, inv, p->mid));
+        GKE_HIP(p, gke::launch_fin_kx(st, d, p->tab, p->mid, tp0, tp1, p->prof, outp));
+    }
+    if (outp[GKE_T_PHIY_V] || outp[GKE_T_PHI_V])
+        GKE_HIP(p, gke::launch_fd_terms(st, d, p->tab, outp[GKE_T_DU2], outp[GKE_T_PHIY_V],
+                                        outp[GKE_T_PHI_V]));
+    if (outp[GKE_T_XI_D]) GKE_HIP(p, gke::launch_t14(st, d, p->prof, outp[GKE_T_XI_D]));
+    GKE_HIP(p, hipStreamSynchronize(st));
+    return GKE_OK;
+}
+
+gke_status gke_get_profiles(gke_plan_t p, double *out)
+{
+    if (!p || !out) return fail(p, GKE_ERR_ARG, "NULL argument");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    GKE_HIP(p, hipStreamSynchronize(p->stream));
+    GKE_HIP(p, hipMemcpy(out, p->prof, sizeof(double) * gke::NPROF * p->d.ny, hipMemcpyDeviceToHost));
+    return GKE_OK;
+}
+
+void gke_destroy(gke_plan_t p)
+{
+    if (!p) return;
+    if (p->ws) (void)hipStreamSynchronize(p->stream);
+    delete p;
+}
+
+const char *gke_last_error(gke_plan_t p)
+{
+    return p ? p->err.c_str() : g_plan_error.c_str();
+}
+
+const char *gke_version(void) { return "gke-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+"""Thin ctypes binding of the C ABI in include/gke.h (same names, marshalling only).
+
+Every computation happens in the HIP library ``libgke.so``; this module only
+converts arguments.  Loading fails loudly when the library is missing: there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgke.so")
+
+GKE_OK, GKE_ERR_ARG, GKE_ERR_STATE, GKE_ERR_OOM, GKE_ERR_HIP, GKE_ERR_UNSUPPORTED = range(6)
+GKE_OPT_DTYPE, GKE_OPT_PRECISION, GKE_OPT_CHUNK, GKE_OPT_PAIR_BATCH = 1, 2, 3, 4
+GKE_DTYPE_F64, GKE_DTYPE_F32 = 0, 1
+GKE_PREC_FP64, GKE_PREC_BF16X3 = 0, 1
+GKE_NTERMS = 14
+GKE_NPROF = 12
+TERM_NAMES = ["du2", "phix_t", "phix_m", "phix_v", "phiy_t", "phiy_v", "phiz_t", "phiz_v",
+              "phi_t", "phi_p", "phi_v", "xi_p1", "xi_p2", "xi_d"]
+PROFILE_NAMES = ["U", "V", "W", "P", "S", "q", "uv", "pv", "Tx", "Ty", "Tz", "eps"]
+
+
+class GkeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gke status {status}: {msg}")
+        self.status = status
+
+
+class gke_terms(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_void_p * GKE_NTERMS), ("on_device", ctypes.c_int),
+                ("reserved", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgke.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python paper_1910_06409_amd/csrc/build.py`")
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime first)
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH, mode=ctypes.RTLD_GLOBAL)
+    vp, i32, i64, dp, sz = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                            ctypes.POINTER(ctypes.c_double), ctypes.c_size_t)
+    sig = {
+        "gke_plan": ([i32, i32, i32, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                      ctypes.POINTER(vp)], i32),
+        "gke_set_option": ([vp, i32, i64], i32),
+        "gke_workspace_size": ([vp, ctypes.POINTER(sz)], i32),
+        "gke_set_workspace": ([vp, vp, sz], i32),
+        "gke_set_stream": ([vp, vp], i32),
+        "gke_accumulate": ([vp, vp, vp, vp, vp], i32),
+        "gke_begin_stats": ([vp], i32),
+        "gke_set_means": ([vp, dp, dp, dp, dp], i32),
+        "gke_finalize": ([vp, ctypes.POINTER(gke_terms)], i32),
+        "gke_get_profiles": ([vp, dp], i32),
+        "gke_destroy": ([vp], None),
+        "gke_last_error": ([vp], ctypes.c_char_p),
+        "gke_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(status: int, plan) -> None:
+    if status != GKE_OK:
+        raise GkeError(status, gke_last_error(plan))
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def gke_last_error(plan) -> str:
+    s = lib().gke_last_error(plan)
+    return s.decode() if s else ""
+
+
+def gke_version() -> str:
+    return lib().gke_version().decode()
+
+
+def gke_plan(Nx: int, Ny: int, Nz: int, y, Lx: float, Lz: float, nu: float):
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    if y.size != Ny:
+        raise ValueError("y must have Ny entries")
+    out = ctypes.c_void_p()
+    _check(lib().gke_plan(Nx, Ny, Nz, _dp(y), Lx, Lz, nu, ctypes.byref(out)), None)
+    return out
+
+
+def gke_set_option(plan, key: int, value: int) -> None:
+    _check(lib().gke_set_option(plan, key, value), plan)
+
+
+def gke_workspace_size(plan) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().gke_workspace_size(plan, ctypes.byref(n)), plan)
+    return n.value
+
+
+def gke_set_workspace(plan, device_ptr: int, nbytes: int) -> None:
+    _check(lib().gke_set_workspace(plan, device_ptr, nbytes), plan)
+
+
+def gke_set_stream(plan, stream_ptr: int) -> None:
+    _check(lib().gke_set_stream(plan, stream_ptr), plan)
+
+
+def gke_accumulate(plan, u: int, v: int, w: int, p: int) -> None:
+    _check(lib().gke_accumulate(plan, u, v, w, p), plan)
+
+
+def gke_begin_stats(plan) -> None:
+    _check(lib().gke_begin_stats(plan), plan)
+
+
+def gke_set_means(plan, U, V, W, P) -> None:
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (U, V, W, P)]
+    _check(lib().gke_set_means(plan, *[_dp(a) for a in arrs]), plan)
+
+
+def gke_finalize(plan, ptrs) -> None:
+    """ptrs: sequence of 14 device pointers (int) or None for terms to skip."""
+    t = gke_terms()
+    for i in range(GKE_NTERMS):
+        t.t[i] = ptrs[i] if ptrs[i] else None
+    t.on_device = 1
+    _check(lib().gke_finalize(plan, ctypes.byref(t)), plan)
+
+
+def gke_get_profiles(plan, ny: int) -> np.ndarray:
+    out = np.zeros((GKE_NPROF, ny))
+    _check(lib().gke_get_profiles(plan, _dp(out)), plan)
+    return out
+
+
+def gke_destroy(plan) -> None:
+    lib().gke_destroy(plan)

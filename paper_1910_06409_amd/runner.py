@@ -1,0 +1,101 @@
+"""Device-memory plumbing around the C ABI: torch allocates the workspace and
+the output maps and supplies the stream; the HIP library does the work.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import gke
+
+
+class GkeRun:
+    """One plan with its torch-owned workspace.
+
+    Usage: r = GkeRun(nx, ny, nz, y, lx, lz, nu, dtype=..., chunk=...);
+    r.scan1(snapshots); r.scan2(snapshots); maps = r.finalize().
+    """
+
+    def __init__(self, nx, ny, nz, y, lx, lz, nu, *, dtype="f64", precision="fp64",
+                 chunk=64, pair_batch=0, device="cuda", stream=None):
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.plan = gke.gke_plan(nx, ny, nz, y, lx, lz, nu)
+        gke.gke_set_option(self.plan, gke.GKE_OPT_DTYPE,
+                           gke.GKE_DTYPE_F32 if dtype == "f32" else gke.GKE_DTYPE_F64)
+        gke.gke_set_option(self.plan, gke.GKE_OPT_PRECISION,
+                           gke.GKE_PREC_BF16X3 if precision == "bf16x3" else gke.GKE_PREC_FP64)
+        gke.gke_set_option(self.plan, gke.GKE_OPT_CHUNK, int(chunk))
+        gke.gke_set_option(self.plan, gke.GKE_OPT_PAIR_BATCH, int(pair_batch))
+        gke.gke_set_stream(self.plan, self.stream.cuda_stream)
+        nbytes = gke.gke_workspace_size(self.plan)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        gke.gke_set_workspace(self.plan, aligned, nbytes)
+        self.tdtype = torch.float32 if dtype == "f32" else torch.float64
+
+    def accumulate(self, u, v, w, p):
+        for t in (u, v, w, p):
+            if t.dtype != self.tdtype or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("fields must be contiguous device tensors of the plan dtype")
+            if tuple(t.shape) != (self.ny, self.nz, self.nx):
+                raise ValueError("fields must be [ny][nz][nx]")
+        gke.gke_accumulate(self.plan, u.data_ptr(), v.data_ptr(), w.data_ptr(), p.data_ptr())
+
+    def accumulate_snapshot(self, snap):
+        """snap: device tensor [4][ny][nz][nx]."""
+        self.accumulate(snap[0], snap[1], snap[2], snap[3])
+
+    def begin_stats(self):
+        gke.gke_begin_stats(self.plan)
+
+    def set_means(self, U, V, W, P):
+        gke.gke_set_means(self.plan, U, V, W, P)
+
+    def alloc_terms(self, which=None):
+        which = range(gke.GKE_NTERMS) if which is None else which
+        shape = (self.ny, self.ny, self.nz, self.nx // 2 + 1)
+        out = [None] * gke.GKE_NTERMS
+        for i in which:
+            shp = (self.ny, self.ny) if i == 13 else shape
+            out[i] = torch.empty(shp, dtype=torch.float64, device=self.device)
+        return out
+
+    def finalize(self, out=None):
+        if out is None:
+            out = self.alloc_terms()
+        gke.gke_finalize(self.plan, [t.data_ptr() if t is not None else 0 for t in out])
+        return out
+
+    def profiles(self) -> np.ndarray:
+        return gke.gke_get_profiles(self.plan, self.ny)
+
+    def close(self):
+        if self.plan is not None:
+            gke.gke_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_snapshots(snaps_dev, y, lx, lz, nu, *, dtype="f64", precision="fp64", chunk=64,
+                  pair_batch=0, which=None):
+    """Both scans over a device tensor [S][4][ny][nz][nx]; returns (maps, profiles)."""
+    S, _, ny, nz, nx = snaps_dev.shape
+    r = GkeRun(nx, ny, nz, y, lx, lz, nu, dtype=dtype, precision=precision, chunk=chunk,
+               pair_batch=pair_batch, device=snaps_dev.device)
+    for s in range(S):
+        r.accumulate_snapshot(snaps_dev[s])
+    r.begin_stats()
+    for s in range(S):
+        r.accumulate_snapshot(snaps_dev[s])
+    out = r.finalize(r.alloc_terms(which))
+    prof = r.profiles()
+    r.close()
+    return out, prof

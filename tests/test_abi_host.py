@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/gke.h declares, and validates arguments before any
+device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1910_06409_amd import gke
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gke.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gke_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = gke.lib()
+    names = declared_functions()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(L, n), n
+    assert "gfx950" in gke.gke_version()
+
+
+def test_plan_argument_validation():
+    y = np.linspace(-1, 1, 17)
+    bad = [
+        dict(Nx=15, Ny=17, Nz=16),   # odd
+        dict(Nx=14, Ny=17, Nz=16),   # factor 7
+        dict(Nx=16, Ny=4, Nz=16),    # too few planes
+        dict(Nx=16, Ny=17, Nz=2),    # too short
+    ]
+    for b in bad:
+        yy = np.linspace(-1, 1, b["Ny"])
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_plan(b["Nx"], b["Ny"], b["Nz"], yy, 1.0, 1.0, 0.01)
+        assert e.value.status == gke.GKE_ERR_ARG
+    with pytest.raises(gke.GkeError):
+        gke.gke_plan(16, 17, 16, y[::-1].copy(), 1.0, 1.0, 0.01)   # not increasing
+    with pytest.raises(gke.GkeError):
+        gke.gke_plan(16, 17, 16, y, -1.0, 1.0, 0.01)
+    with pytest.raises(gke.GkeError):
+        gke.gke_plan(16, 17, 16, y, 1.0, 1.0, 0.0)
+
+
+def test_options_and_state_errors():
+    y = np.linspace(-1, 1, 17)
+    p = gke.gke_plan(16, 17, 16, y, 2 * np.pi, np.pi, 0.005)
+    try:
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_set_option(p, gke.GKE_OPT_CHUNK, 3)
+        assert e.value.status == gke.GKE_ERR_ARG
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_set_option(p, 99, 1)
+        assert e.value.status == gke.GKE_ERR_ARG
+        n64 = gke.gke_workspace_size(p)
+        gke.gke_set_option(p, gke.GKE_OPT_CHUNK, 8)
+        n8 = gke.gke_workspace_size(p)
+        assert n64 > n8 > 0
+        # no workspace yet: every device step is refused with a state error
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_accumulate(p, 1, 1, 1, 1)
+        assert e.value.status == gke.GKE_ERR_STATE
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_begin_stats(p)
+        assert e.value.status == gke.GKE_ERR_STATE
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_finalize(p, [0] * 14)
+        assert e.value.status == gke.GKE_ERR_STATE
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_set_workspace(p, 0, 1 << 20)
+        assert e.value.status == gke.GKE_ERR_ARG
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_set_workspace(p, 256, 16)
+        assert e.value.status == gke.GKE_ERR_OOM
+        assert "workspace" in gke.gke_last_error(p)
+    finally:
+        gke.gke_destroy(p)
+
+
+def test_workspace_scales_with_grid():
+    from paper_1910_06409_amd import synth
+    w = synth.workload("re200")
+    p = gke.gke_plan(w.nx, w.ny, w.nz, synth.y_grid(w), w.lx, w.lz, w.nu)
+    try:
+        gke.gke_set_option(p, gke.GKE_OPT_CHUNK, 100)
+        n = gke.gke_workspace_size(p)
+        # spectra: nk * 10 fields * chunk * 144 padded planes * 16 B
+        spec = w.nk * 10 * 100 * 144 * 16
+        acc = 8 * w.nk * 45 * 256 * 16
+        assert spec + acc < n < 2 * (spec + acc)
+        assert n < 200 * 2 ** 30
+    finally:
+        gke.gke_destroy(p)

@@ -1,0 +1,198 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bar: norm-wise error max|gpu - oracle| / max|oracle| <= 1e-10 per term for
+the FP64 path (inputs in FP64, or FP32 inputs read exactly by both sides).
+The GPU writes the half plane rx >= 0 of every ordered pair; the oracle
+computes the full periodic plane, whose columns p = 0..Nx/2 are compared.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import direct, oracle
+from paper_1910_06409_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-10
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(snap, w, y, **kw):
+    torch = _torch()
+    from paper_1910_06409_amd import runner
+    dt = torch.float32 if snap.dtype == np.float32 else torch.float64
+    dev = torch.from_numpy(np.ascontiguousarray(snap)).to(device="cuda", dtype=dt)
+    out, prof = runner.run_snapshots(dev, y, w.lx, w.lz, w.nu,
+                                     dtype="f32" if snap.dtype == np.float32 else "f64", **kw)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() if o is not None else None for o in out], prof
+
+
+def compare(gpu_maps, ref, pairs, nx, label, tol=TOL_FP64):
+    """ref: [npairs][14][nz][nx] full plane; gpu_maps[t]: [ny][ny][nz][nx/2+1]."""
+    nkx = nx // 2 + 1
+    worst = 0.0
+    for t in range(14):
+        if t == 13:
+            g = np.array([[gpu_maps[13][a, b]] for (a, b) in pairs])
+            r = ref[:, 13, 0, 0][:, None]
+        else:
+            g = np.array([gpu_maps[t][a, b] for (a, b) in pairs])
+            r = ref[:, t, :, :nkx]
+        m = np.abs(r).max()
+        e = np.abs(g - r).max() / (m if m > 0 else 1.0)
+        worst = max(worst, e)
+        assert e <= tol, f"{label}: T{t + 1} norm-wise error {e:.3e} > {tol:.0e}"
+    say(f"{label}: worst norm-wise error {worst:.3e}")
+    return worst
+
+
+def test_tiny_all_pairs_fp64(tiny):
+    w, y, snap = tiny
+    say("case tiny all pairs", snap.shape)
+    g, prof = run_gpu(snap, w, y)
+    pairs = oracle.all_pairs(w.ny)
+    ref = oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs)
+    compare(g, ref, pairs, w.nx, "tiny")
+    p_ref = oracle.step1(snap, y, w.lx, w.lz, w.nu)
+    assert np.abs(prof - p_ref).max() <= 1e-12 * np.abs(p_ref).max()
+
+
+def test_tiny_direct_sums_sampled(tiny):
+    """GPU against the level-0 definitions at a few points."""
+    w, y, snap = tiny
+    g, _ = run_gpu(snap, w, y)
+    mean, fl, S, eps, _ = direct.profiles(snap, y, w.lx, w.lz, w.nu)
+    for (j1, j2, p, q) in [(0, 16, 3, 5), (7, 2, 8, 0), (11, 11, 1, 15), (4, 9, 0, 7)]:
+        st = direct.point_stats(fl, mean, S, eps, j1, j2, p, q)
+        for t, val in st.items():
+            gv = g[t - 1][j1, j2] if t == 14 else g[t - 1][j1, j2, q, p]
+            scale = np.abs(g[t - 1]).max()
+            assert abs(gv - val) <= TOL_FP64 * scale, (j1, j2, p, q, t)
+
+
+def test_odd_snapshots_multi_chunk():
+    w = synth.workload("tiny", S=5)
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 21)
+    say("case multi-chunk S=5 chunk=2")
+    g, _ = run_gpu(snap, w, y, chunk=2)
+    pairs = oracle.all_pairs(w.ny)
+    ref = oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs)
+    compare(g, ref, pairs, w.nx, "chunk=2")
+
+
+def test_radix_3_5_ragged_planes():
+    # Nx = 24 (2^3 3), Nz = 20 (2^2 5), Ny = 21 (two plane tiles, ragged tail)
+    w = synth.workload("tiny", nx=24, nz=20, ny=21, S=3, M=6)
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 4)
+    say("case 24x21x20")
+    g, _ = run_gpu(snap, w, y, chunk=4, pair_batch=1)
+    pairs = oracle.all_pairs(w.ny)
+    ref = oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs)
+    compare(g, ref, pairs, w.nx, "24x21x20")
+
+
+def test_fp32_inputs():
+    w = synth.workload("tiny", dtype="f32")
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 9)
+    assert snap.dtype == np.float32
+    say("case f32 inputs")
+    g, _ = run_gpu(snap, w, y)
+    pairs = oracle.all_pairs(w.ny)
+    ref = oracle.pair_terms(snap.astype(np.float64), y, w.lx, w.lz, w.nu, pairs)
+    compare(g, ref, pairs, w.nx, "f32-in")
+
+
+def test_set_means_and_refinalize():
+    torch = _torch()
+    from paper_1910_06409_amd import runner
+    w = synth.workload("tiny", S=6)
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 13)
+    prof_all = oracle.step1(snap, y, w.lx, w.lz, w.nu)
+    dev = torch.from_numpy(snap).cuda()
+    r = runner.GkeRun(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu, chunk=4)
+    r.set_means(*prof_all[:4])
+    for s in range(3):
+        r.accumulate_snapshot(dev[s])
+    first = [t.cpu().numpy() if t is not None else None for t in r.finalize()]
+    for s in range(3, 6):
+        r.accumulate_snapshot(dev[s])
+    second = [t.cpu().numpy() if t is not None else None for t in r.finalize()]
+    r.close()
+    pairs = oracle.all_pairs(w.ny)
+    # profiles of the first three snapshots about the given (six-snapshot) means
+    ref3 = oracle.pair_terms(snap[:3], y, w.lx, w.lz, w.nu, pairs,
+                             prof=_onepoint(snap[:3], y, w, prof_all))
+    compare(first, ref3, pairs, w.nx, "set_means 3 snapshots")
+    ref6 = oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs, prof=prof_all)
+    compare(second, ref6, pairs, w.nx, "re-finalize 6 snapshots")
+
+
+def _onepoint(snap, y, w, prof_means):
+    """Oracle one-point profiles of `snap` about externally given means."""
+    return oracle.step1(snap, y, w.lx, w.lz, w.nu, means=prof_means[:4])
+
+
+def test_scan_count_mismatch_is_refused():
+    torch = _torch()
+    from paper_1910_06409_amd import gke, runner
+    w = synth.workload("tiny")
+    y = synth.y_grid(w)
+    snap = torch.from_numpy(synth.snapshots(w, 1)).cuda()
+    r = runner.GkeRun(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu)
+    for s in range(4):
+        r.accumulate_snapshot(snap[s])
+    r.begin_stats()
+    for s in range(3):
+        r.accumulate_snapshot(snap[s])
+    with pytest.raises(gke.GkeError) as e:
+        r.finalize()
+    assert e.value.status == gke.GKE_ERR_STATE
+    r.close()
+
+
+@pytest.mark.timeout(900)
+def test_re200_full_size_sampled_pairs():
+    """The benchmark's workload (192 x 129 x 160, 100 FP64 snapshots, chunk 100)
+    checked on sampled pairs against the oracle, and at sampled points against
+    the direct sums of the definitions."""
+    w = synth.workload("re200")
+    y = synth.y_grid(w)
+    say("case re200 full size: generating", w.S, "snapshots")
+    snap = synth.snapshots(w, 2024)
+    say("case re200 full size: GPU run")
+    g, prof = run_gpu(snap, w, y, chunk=100)
+    pairs = [(0, 0), (3, 120), (64, 64), (20, 90), (128, 5), (100, 101)]
+    say("case re200 full size: oracle on", len(pairs), "pairs")
+    ref = oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs)
+    compare(g, ref, pairs, w.nx, "re200 sampled pairs")
+    # level-0 definitions at sampled points (T1..T13 except the derivative terms)
+    mean = snap.mean(axis=(0, 3, 4))
+    S = direct.fd5_weights(y) @ mean[0]
+    for (j1, j2, p, q) in [(2, 126, 17, 100), (60, 61, 96, 0), (33, 33, 0, 80)]:
+        sel = [j1, j2]
+        fl = snap[:, :, sel] - mean[None, :, sel, None, None]
+        st = direct.point_stats(fl, mean[:, sel], S[sel], np.zeros(2), 0, 1, p, q)
+        for t, val in st.items():
+            if t == 14:
+                continue
+            scale = np.abs(g[t - 1][j1, j2]).max()
+            assert abs(g[t - 1][j1, j2, q, p] - val) <= TOL_FP64 * scale, (j1, j2, p, q, t)
+    say("re200 direct-sum points ok")
