@@ -31,7 +31,8 @@
 //   B (lane l): for the real output (Rr, Ri), for the imaginary output
 //               (Ri, -Rr) of R[Y2 = 16b + l%16][s0 + (l/16)/2];
 //   so sum_k A B = Re/Im of conj(L) R.
-//   D (lane l, register v): element (Y1 = 16a + 4(l/16) + v, Y2 = 16b + l%16).
+//   D (lane l, register v): element (Y1 = 16a + l/16 + 4v, Y2 = 16b + l%16)
+//   (checked on the device: the f64 form strides the rows by 4 across registers).
 #include "gke_internal.h"
 
 namespace gke {
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(64) void k_rankk_f64(const cx<double> *__restrict__
     const size_t ptot = (size_t)d.ntp * 256;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const size_t el = (size_t)tp * 256 + (4 * kq + v) * 16 + row;
+        const size_t el = (size_t)tp * 256 + (kq + 4 * v) * 16 + row;
         double sr[NSPEC], si[NSPEC];
         sr[S_R] = ar[0][v];
         si[S_R] = ai[0][v];

@@ -19,7 +19,10 @@ class GkeRun:
     def __init__(self, nx, ny, nz, y, lx, lz, nu, *, dtype="f64", precision="fp64",
                  chunk=64, pair_batch=0, device="cuda", stream=None):
         self.nx, self.ny, self.nz = nx, ny, nz
-        self.device = torch.device(device)
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.plan = gke.gke_plan(nx, ny, nz, y, lx, lz, nu)
         gke.gke_set_option(self.plan, gke.GKE_OPT_DTYPE,
