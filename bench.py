@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Throughput of the GKE two-point-statistics hot path on one MI355X.
+
+A step is one pass of the whole path over one ensemble of synthetic
+snapshots already resident in HBM: the first scan (plane sums -> means),
+the second scan (fluctuations, products, forward transforms, cross-spectral
+rank-k accumulation) and finalize (inverse transforms, FP64 assembly of the
+14 term maps, five-point Y derivatives).
+
+value = P_out * S / T_step   [(Y1, Y2, rx, rz) points x snapshots per second]
+with P_out = Ny^2 (Nx/2 + 1) Nz points per term (all ordered pairs, rx >= 0).
+
+Also reported: per-kernel device time from HIP events on the plan's stream,
+the roofline of the dominant kernel, and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GKE (y1,y2,rx,rz) term-map points/s; split-BF16 vs FP64 at stated rel. err"
+UNIT = "point-snapshots/s"
+PEAK = {"fp64_mfma": 78.6, "bf16_mfma": 2500.0, "hbm": 8000.0}   # TFLOP/s, TFLOP/s, GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_work(w, chunk):
+    """Algorithmic work per launch of each kernel family (flops or bytes)."""
+    ny, nx, nz, nkx, nk = w.ny, w.nx, w.nz, w.nx // 2 + 1, w.nk
+    b_in = 8 if w.dtype == "f64" else 4
+    n_pts = nx * ny * nz
+    c16 = 16  # complex FP64
+    npair_u = ny * (ny + 1) // 2
+    return {
+        # 27 complex MACs (216 flops) per (snapshot, wavenumber, unordered pair Y1 <= Y2)
+        "rankk": ("flop", 216.0 * chunk * nk * npair_u),
+        # read the 4 input fields once, write the 10 x-transformed fields
+        "fluct_xfft": ("byte", 4.0 * n_pts * b_in + 10.0 * ny * nkx * nz * c16),
+        # read the x-transformed fields, write the 10 spectra
+        "zfft_pack": ("byte", 2 * 10.0 * ny * nkx * nz * c16),
+        "plane_sums": ("byte", 4.0 * n_pts * b_in),
+        # read 8 term spectra of every unordered pair, write 10 kz-transformed maps
+        "fin_kz": ("byte", (8 + 10) * float(nk) * npair_u * c16),
+        # read 10 maps, write 12 FP64 term maps for both orientations
+        "fin_kx": ("byte", 10.0 * nk * npair_u * c16 + 12.0 * ny * ny * nkx * nz * 8),
+        # read <du^2>, write two maps
+        "fd_terms": ("byte", 3.0 * ny * ny * nkx * nz * 8),
+    }
+
+
+def cpu_baseline(w, y, seed, threads, s_sample, j1, nb=8):
+    """The oracle on a bounded sample: S_sample snapshots, the nb x nb block of
+    ordered pairs with Y1, Y2 in [j1, j1 + nb)."""
+    import numpy as np
+
+    from oracle import oracle
+    from paper_1910_06409_amd import synth
+
+    used = oracle.set_threads(threads)
+    snap = np.stack([synth.snapshot(w, seed, s) for s in range(s_sample)])
+    pairs = [(a, b) for a in range(j1, j1 + nb) for b in range(j1, j1 + nb)]
+    t0 = time.perf_counter()
+    oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs, nthreads=threads)
+    dt = time.perf_counter() - t0
+    pts = len(pairs) * (w.nx // 2 + 1) * w.nz
+    return {"value": pts * s_sample / dt, "unit": UNIT, "cores": used, "kind": "oracle",
+            "seconds": dt,
+            "sample": f"{w.name}: first {s_sample} snapshots, the {nb}x{nb} block of ordered "
+                      f"pairs Y1, Y2 in [{j1}, {j1 + nb}) (plus the five-point neighbour pairs "
+                      f"the oracle needs), whole oracle path incl. Step 1 on the touched "
+                      f"planes; value = pairs*(Nx/2+1)*Nz*S_sample/seconds"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="re200")
+    ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--chunk", type=int, default=0, help="0: one chunk for the ensemble")
+    ap.add_argument("--snapshots", type=int, default=0, help="override S (0: workload's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=16)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}); "
+              "the multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1910_06409_amd import gke, runner, synth
+
+    w = synth.workload(args.workload)
+    if args.snapshots:
+        w = synth.workload(args.workload, S=args.snapshots)
+    S = w.S
+    chunk = args.chunk or (S + (S & 1))
+    y = synth.y_grid(w)
+    dev = torch.device("cuda", 0)
+    tdt = torch.float64 if w.dtype == "f64" else torch.float32
+
+    log(f"[bench] generating {S} snapshots of {w.name} ({w.nx}x{w.ny}x{w.nz}, {w.dtype})")
+    t0 = time.perf_counter()
+    snaps = torch.empty((S, 4, w.ny, w.nz, w.nx), dtype=tdt, device=dev)
+    for s in range(S):
+        snaps[s].copy_(torch.from_numpy(synth.snapshot(w, args.seed, s)))
+        if (s + 1) % 20 == 0:
+            log(f"[bench]   {s + 1}/{S} snapshots resident ({time.perf_counter() - t0:.0f} s)")
+    torch.cuda.synchronize()
+
+    r = runner.GkeRun(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu, dtype=w.dtype,
+                      precision=w.precision, chunk=chunk, device=dev)
+    outs = r.alloc_terms()
+    log(f"[bench] workspace {r.workspace.numel() / 2**30:.1f} GiB, outputs "
+        f"{sum(o.numel() for o in outs) * 8 / 2**30:.1f} GiB")
+
+    def step():
+        r.reset()
+        for s in range(S):
+            r.accumulate_snapshot(snaps[s])
+        r.begin_stats()
+        for s in range(S):
+            r.accumulate_snapshot(snaps[s])
+        r.finalize(outs)
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench] warmup step {i + 1}/{args.warmup} done")
+    r.set_timing(True)
+    r.timings(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        log(f"[bench] timed step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = r.timings(reset=True)
+    r.set_timing(False)
+
+    ms_step = 1e3 * elapsed / args.steps
+    p_out = w.points_out
+    value = p_out * S / (elapsed / args.steps)
+
+    work = kernel_work(w, chunk)
+    kernels = {}
+    for name, (ms, n) in tm.items():
+        if n == 0:
+            continue
+        avg = ms / n
+        k = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
+             "avg_launch_ms": avg}
+        if name in work:
+            kind, amount = work[name]
+            if name == "rankk":
+                # the last launch of a step may hold fewer snapshots: use the mean
+                launches = n / args.steps
+                amount = amount * (S / chunk) / launches
+            if kind == "flop":
+                k["achieved_tflops"] = amount / (avg * 1e-3) / 1e12
+            else:
+                k["achieved_gbs"] = amount / (avg * 1e-3) / 1e9
+        kernels[name] = k
+    dom = max(kernels, key=lambda n: kernels[n]["ms_per_step"])
+    dk = kernels[dom]
+    if "achieved_tflops" in dk:
+        ach, peak, unit, bound = dk["achieved_tflops"], PEAK["fp64_mfma"], "TFLOP/s", "mfma"
+    else:
+        ach, peak, unit, bound = dk.get("achieved_gbs", 0.0), PEAK["hbm"], "GB/s", "hbm"
+    roof = {"kernel": dom, "bound": bound, "achieved": ach, "peak": peak, "unit": unit,
+            "frac": ach / peak, "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(w, y, args.seed, args.cpu_threads, s_sample=min(30, S), j1=w.ny // 2 - 4)
+        log(f"[bench] oracle sample took {cpu['seconds']:.1f} s")
+
+    res = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if w.precision == "fp64" else "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} channel grid, {S} "
+                               f"{w.dtype} snapshots, all (Y1,Y2) pairs, rx>=0 half plane, "
+                               f"14 term maps", "grid": [w.nx, w.ny, w.nz], "snapshots": S,
+                   "precision": w.precision, "chunk": chunk, "points_out": p_out},
+        "points_per_s": p_out / (elapsed / args.steps),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    print(json.dumps(res), flush=True)
+    r.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -63,7 +63,8 @@ enum {
     GKE_OPT_DTYPE = 1,        /* input storage: GKE_DTYPE_F64 (default) or GKE_DTYPE_F32 */
     GKE_OPT_PRECISION = 2,    /* rank-k arithmetic: GKE_PREC_FP64 (default) or GKE_PREC_BF16X3 */
     GKE_OPT_CHUNK = 3,        /* snapshots per cross-spectral batch, even, 2..4096 (default 64) */
-    GKE_OPT_PAIR_BATCH = 4    /* finalize pair-tile batch, 0 = all at once (default) */
+    GKE_OPT_PAIR_BATCH = 4,   /* finalize pair-tile batch, 0 = all at once (default) */
+    GKE_OPT_TIMING = 5        /* 1: record HIP events around every kernel launch (any time) */
 };
 enum { GKE_DTYPE_F64 = 0, GKE_DTYPE_F32 = 1 };
 enum { GKE_PREC_FP64 = 0, GKE_PREC_BF16X3 = 1 };
@@ -165,6 +166,22 @@ gke_status gke_finalize(gke_plan_t plan, const gke_terms *out);
 /* Copy the GKE_NPROF x Ny profile block (row-major, FP64) to host memory
  * `out`.  Valid after gke_finalize (rows U..S after gke_begin_stats). */
 gke_status gke_get_profiles(gke_plan_t plan, double *out);
+
+/* Forget every accumulated snapshot (both scans) so that the same plan and
+ * workspace start a new ensemble; enqueued on the plan's stream.
+ * Errors: GKE_ERR_STATE (no workspace), GKE_ERR_HIP. */
+gke_status gke_reset(gke_plan_t plan);
+
+/* kernel families reported by gke_timings */
+enum { GKE_K_PLANE_SUMS = 0, GKE_K_FLUCT_XFFT, GKE_K_ZFFT_PACK, GKE_K_RANKK, GKE_K_FIN_KZ,
+       GKE_K_FIN_KX, GKE_K_FD, GKE_K_SMALL, GKE_NKERNELS };
+
+/* With GKE_OPT_TIMING set, HIP events bracket every kernel launch on the
+ * plan's stream.  Synchronises the stream, then writes per kernel family the
+ * summed device time in milliseconds (total_ms[GKE_NKERNELS]) and the number
+ * of launches (launches[GKE_NKERNELS]) since the last reset of the counters;
+ * reset != 0 clears them.  Either output may be NULL. */
+gke_status gke_timings(gke_plan_t plan, double *total_ms, int64_t *launches, int reset);
 
 /* Release the plan (synchronises its stream; never frees the workspace). */
 void gke_destroy(gke_plan_t plan);

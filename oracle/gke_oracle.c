@@ -57,23 +57,21 @@ static cplx unit_root(long num, long den, int sign)
     return cos(a) + (double)sign * sin(a) * I;
 }
 
-/* work must hold 2n elements: n for the combination, n for the roots */
-static void dft_rec(int n, const cplx *in, long stride, cplx *out, int sign, cplx *work)
+/* root[t * rs] = exp(sign 2 pi i t/n) for t < n; work must hold n elements */
+static void dft_rec(int n, const cplx *in, long stride, cplx *out, const cplx *root, long rs,
+                    cplx *work)
 {
     if (n == 1) { out[0] = in[0]; return; }
     int p = smallest_factor(n);
     int m = n / p;
-    /* sub-transforms of the p decimated sequences */
+    /* sub-transforms of the p decimated sequences (their roots: every p-th) */
     for (int q = 0; q < p; ++q)
-        dft_rec(m, in + q * stride, stride * p, out + q * m, sign, work);
-    /* roots of unity exp(sign 2 pi i t/n), t < n */
-    cplx *root = work + n;
-    for (int t = 0; t < n; ++t) root[t] = unit_root(t, n, sign);
-    /* combine: X[k] = sum_q w^{q k} Y_q[k mod m] */
+        dft_rec(m, in + q * stride, stride * p, out + q * m, root, rs * p, work);
+    /* combine: X[k] = sum_q w^{q k} Y_q[k mod m], w = exp(sign 2 pi i/n) */
     for (int k = 0; k < n; ++k) {
         cplx acc = 0.0;
         for (int q = 0; q < p; ++q)
-            acc += root[((long)q * k) % n] * out[q * m + (k % m)];
+            acc += root[(((long)q * k) % n) * rs] * out[q * m + (k % m)];
         work[k] = acc;
     }
     memcpy(out, work, sizeof(cplx) * (size_t)n);
@@ -82,9 +80,10 @@ static void dft_rec(int n, const cplx *in, long stride, cplx *out, int sign, cpl
 /* 1-D transform of a strided complex sequence, result written back in place */
 static void fft1(int n, cplx *data, long stride, int sign, cplx *buf /* 4n */)
 {
-    cplx *in = buf, *out = buf + n, *work = buf + 2 * n;
+    cplx *in = buf, *out = buf + n, *work = buf + 2 * n, *root = buf + 3 * n;
+    for (int t = 0; t < n; ++t) root[t] = unit_root(t, n, sign);
     for (int i = 0; i < n; ++i) in[i] = data[i * stride];
-    dft_rec(n, in, 1, out, sign, work);
+    dft_rec(n, in, 1, out, root, 1, work);
     for (int i = 0; i < n; ++i) data[i * stride] = out[i];
 }
 
@@ -93,6 +92,18 @@ static void fft2(int nx, int nz, cplx *plane, int sign, cplx *buf)
 {
     for (int z = 0; z < nz; ++z) fft1(nx, plane + (long)z * nx, 1, sign, buf);
     for (int x = 0; x < nx; ++x) fft1(nz, plane + x, nx, sign, buf);
+}
+
+/* thread count of the OpenMP regions (the CPU-baseline timing states it) */
+int or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* exported for the tests: plain 1-D transform of n complex values */

@@ -46,7 +46,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB_PATH) or (
             os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-fcx-limited-range",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -62,6 +62,8 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         L.or_fft1.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int]
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_set_threads.restype = ctypes.c_int
         L.or_fd5.argtypes = [ctypes.c_int, dp, dp]
         L.or_means.argtypes = [ctypes.c_int] * 4 + [dp, dp]
         L.or_onepoint.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp, ctypes.c_double,
@@ -72,6 +74,11 @@ def lib():
             f.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Set the OpenMP thread count of the oracle; returns the count in effect."""
+    return lib().or_set_threads(int(n))
 
 
 def _dp(a):

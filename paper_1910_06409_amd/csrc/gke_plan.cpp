@@ -47,6 +47,13 @@ struct gke_plan_s {
     bool second_scan = false;
     bool means_from_host = false;
     std::string err;
+
+    // optional HIP-event timing of every launch
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;   // created once, reused
+    std::vector<std::pair<int, int>> ev_used;  // (kernel family, pool index of start)
+    double t_ms[GKE_NKERNELS] = {};
+    int64_t t_n[GKE_NKERNELS] = {};
 };
 
 static std::string g_plan_error;
@@ -128,6 +135,43 @@ void fornberg_d1(double x0, const double *x, int n, double *w)
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Bracket one launch with HIP events when timing is on.
+template <typename F>
+hipError_t timed(gke_plan_t p, int kind, F &&launch)
+{
+    if (!p->timing) return launch();
+    const size_t need = 2 * (p->ev_used.size() + 1);
+    while (p->ev_pool.size() < need) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        p->ev_pool.push_back(e);
+    }
+    const int i0 = (int)(2 * p->ev_used.size());
+    hipError_t r = hipEventRecord(p->ev_pool[i0], p->stream);
+    if (r != hipSuccess) return r;
+    r = launch();
+    if (r != hipSuccess) return r;
+    r = hipEventRecord(p->ev_pool[i0 + 1], p->stream);
+    if (r != hipSuccess) return r;
+    p->ev_used.emplace_back(kind, i0);
+    return hipSuccess;
+}
+
+// Fold the recorded event pairs into the per-family totals (stream synced).
+hipError_t collect_timings(gke_plan_t p)
+{
+    for (const auto &u : p->ev_used) {
+        float ms = 0.f;
+        hipError_t r = hipEventElapsedTime(&ms, p->ev_pool[u.second], p->ev_pool[u.second + 1]);
+        if (r != hipSuccess) return r;
+        p->t_ms[u.first] += ms;
+        p->t_n[u.first] += 1;
+    }
+    p->ev_used.clear();
+    return hipSuccess;
+}
+
 // Workspace layout; with base != nullptr also assigns the pointers.
 size_t layout(gke_plan_t p, char *base)
 {
@@ -159,8 +203,10 @@ size_t layout(gke_plan_t p, char *base)
 gke_status launch_flush(gke_plan_t p)
 {
     if (p->pending == 0) return GKE_OK;
-    GKE_HIP(p, gke::launch_rankk_f64(p->stream, p->d, p->tab, p->spec, p->pending,
-                                     p->chunks_done > 0 ? 1 : 0, p->acc));
+    GKE_HIP(p, timed(p, GKE_K_RANKK, [&] {
+        return gke::launch_rankk_f64(p->stream, p->d, p->tab, p->spec, p->pending,
+                                     p->chunks_done > 0 ? 1 : 0, p->acc);
+    }));
     ++p->chunks_done;
     p->pending = 0;
     return GKE_OK;
@@ -236,6 +282,11 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
 gke_status gke_set_option(gke_plan_t p, int key, int64_t value)
 {
     if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (key == GKE_OPT_TIMING) {
+        if (value != 0 && value != 1) return fail(p, GKE_ERR_ARG, "timing must be 0 or 1");
+        p->timing = value != 0;
+        return GKE_OK;
+    }
     if (p->ws) return fail(p, GKE_ERR_STATE, "options are fixed once the workspace is set");
     switch (key) {
     case GKE_OPT_DTYPE:
@@ -319,14 +370,20 @@ gke_status gke_accumulate(gke_plan_t p, const void *u, const void *v, const void
     if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
     const int f32 = p->dtype == GKE_DTYPE_F32;
     if (!p->second_scan) {
-        GKE_HIP(p, gke::launch_plane_sums(p->stream, p->d, f32, u, v, w, pr, p->sums1));
+        GKE_HIP(p, timed(p, GKE_K_PLANE_SUMS, [&] {
+            return gke::launch_plane_sums(p->stream, p->d, f32, u, v, w, pr, p->sums1);
+        }));
         ++p->n1;
         return GKE_OK;
     }
-    GKE_HIP(p, gke::launch_fluct_xfft(p->stream, p->d, p->tab, f32, u, v, w, pr, p->prof,
-                                      p->inter, p->momp));
-    GKE_HIP(p, gke::launch_zfft_pack(p->stream, p->d, p->tab, p->inter, p->pending, p->spec,
-                                     p->momg));
+    GKE_HIP(p, timed(p, GKE_K_FLUCT_XFFT, [&] {
+        return gke::launch_fluct_xfft(p->stream, p->d, p->tab, f32, u, v, w, pr, p->prof,
+                                      p->inter, p->momp);
+    }));
+    GKE_HIP(p, timed(p, GKE_K_ZFFT_PACK, [&] {
+        return gke::launch_zfft_pack(p->stream, p->d, p->tab, p->inter, p->pending, p->spec,
+                                     p->momg);
+    }));
     ++p->pending;
     ++p->n2;
     if (p->pending == p->d.chunk) return launch_flush(p);
@@ -339,7 +396,9 @@ gke_status gke_begin_stats(gke_plan_t p)
     if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
     if (p->second_scan) return fail(p, GKE_ERR_STATE, "second scan already started");
     if (p->n1 == 0) return fail(p, GKE_ERR_STATE, "no first-scan snapshot");
-    GKE_HIP(p, gke::launch_means(p->stream, p->d, p->tab, p->sums1, (double)p->n1, p->prof));
+    GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {
+        return gke::launch_means(p->stream, p->d, p->tab, p->sums1, (double)p->n1, p->prof);
+    }));
     GKE_HIP(p, hipStreamSynchronize(p->stream));
     p->second_scan = true;
     return GKE_OK;
@@ -379,20 +438,31 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
     if (s != GKE_OK) return s;
     const gke::Dims &d = p->d;
     hipStream_t st = p->stream;
-    GKE_HIP(p, gke::launch_profiles(st, d, p->momp, p->momg, (double)p->n2, p->prof));
+    GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {
+        return gke::launch_profiles(st, d, p->momp, p->momg, (double)p->n2, p->prof);
+    }));
     double *outp[14];
     for (int i = 0; i < 14; ++i) outp[i] = (double *)out->t[i];
     const int pbt = (p->pair_batch > 0 && p->pair_batch < d.ntp) ? p->pair_batch : d.ntp;
     const double inv = 1.0 / (double)p->n2;
     for (int tp0 = 0; tp0 < d.ntp; tp0 += pbt) {
         const int tp1 = std::min(d.ntp, tp0 + pbt);
-        GKE_HIP(p, gke::launch_fin_kz(st, d, p->tab, p->acc, tp0, tp1, inv, p->mid));
-        GKE_HIP(p, gke::launch_fin_kx(st, d, p->tab, p->mid, tp0, tp1, p->prof, outp));
+        GKE_HIP(p, timed(p, GKE_K_FIN_KZ, [&] {
+            return gke::launch_fin_kz(st, d, p->tab, p->acc, tp0, tp1, inv, p->mid);
+        }));
+        GKE_HIP(p, timed(p, GKE_K_FIN_KX, [&] {
+            return gke::launch_fin_kx(st, d, p->tab, p->mid, tp0, tp1, p->prof, outp);
+        }));
     }
     if (outp[GKE_T_PHIY_V] || outp[GKE_T_PHI_V])
-        GKE_HIP(p, gke::launch_fd_terms(st, d, p->tab, outp[GKE_T_DU2], outp[GKE_T_PHIY_V],
-                                        outp[GKE_T_PHI_V]));
-    if (outp[GKE_T_XI_D]) GKE_HIP(p, gke::launch_t14(st, d, p->prof, outp[GKE_T_XI_D]));
+        GKE_HIP(p, timed(p, GKE_K_FD, [&] {
+            return gke::launch_fd_terms(st, d, p->tab, outp[GKE_T_DU2], outp[GKE_T_PHIY_V],
+                                        outp[GKE_T_PHI_V]);
+        }));
+    if (outp[GKE_T_XI_D])
+        GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {
+            return gke::launch_t14(st, d, p->prof, outp[GKE_T_XI_D]);
+        }));
     GKE_HIP(p, hipStreamSynchronize(st));
     return GKE_OK;
 }
@@ -406,10 +476,42 @@ gke_status gke_get_profiles(gke_plan_t p, double *out)
     return GKE_OK;
 }
 
+gke_status gke_reset(gke_plan_t p)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    // sums, profiles and moment partials are contiguous in the workspace;
+    // the cross-spectral accumulators are overwritten by the first chunk
+    GKE_HIP(p, hipMemsetAsync(p->sums1, 0, (char *)p->inter - (char *)p->sums1, p->stream));
+    p->n1 = p->n2 = 0;
+    p->pending = 0;
+    p->chunks_done = 0;
+    p->second_scan = false;
+    p->means_from_host = false;
+    return GKE_OK;
+}
+
+gke_status gke_timings(gke_plan_t p, double *total_ms, int64_t *launches, int reset)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    GKE_HIP(p, hipStreamSynchronize(p->stream));
+    GKE_HIP(p, collect_timings(p));
+    for (int k = 0; k < GKE_NKERNELS; ++k) {
+        if (total_ms) total_ms[k] = p->t_ms[k];
+        if (launches) launches[k] = p->t_n[k];
+        if (reset) {
+            p->t_ms[k] = 0.0;
+            p->t_n[k] = 0;
+        }
+    }
+    return GKE_OK;
+}
+
 void gke_destroy(gke_plan_t p)
 {
     if (!p) return;
     if (p->ws) (void)hipStreamSynchronize(p->stream);
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     delete p;
 }
 

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgke.so")
 
 GKE_OK, GKE_ERR_ARG, GKE_ERR_STATE, GKE_ERR_OOM, GKE_ERR_HIP, GKE_ERR_UNSUPPORTED = range(6)
-GKE_OPT_DTYPE, GKE_OPT_PRECISION, GKE_OPT_CHUNK, GKE_OPT_PAIR_BATCH = 1, 2, 3, 4
+GKE_OPT_DTYPE, GKE_OPT_PRECISION, GKE_OPT_CHUNK, GKE_OPT_PAIR_BATCH, GKE_OPT_TIMING = 1, 2, 3, 4, 5
 GKE_DTYPE_F64, GKE_DTYPE_F32 = 0, 1
 GKE_PREC_FP64, GKE_PREC_BF16X3 = 0, 1
 GKE_NTERMS = 14
@@ -23,6 +23,9 @@ GKE_NPROF = 12
 TERM_NAMES = ["du2", "phix_t", "phix_m", "phix_v", "phiy_t", "phiy_v", "phiz_t", "phiz_v",
               "phi_t", "phi_p", "phi_v", "xi_p1", "xi_p2", "xi_d"]
 PROFILE_NAMES = ["U", "V", "W", "P", "S", "q", "uv", "pv", "Tx", "Ty", "Tz", "eps"]
+KERNEL_NAMES = ["plane_sums", "fluct_xfft", "zfft_pack", "rankk", "fin_kz", "fin_kx", "fd_terms",
+                "small"]
+GKE_NKERNELS = len(KERNEL_NAMES)
 
 
 class GkeError(RuntimeError):
@@ -66,6 +69,9 @@ def lib() -> ctypes.CDLL:
         "gke_set_means": ([vp, dp, dp, dp, dp], i32),
         "gke_finalize": ([vp, ctypes.POINTER(gke_terms)], i32),
         "gke_get_profiles": ([vp, dp], i32),
+        "gke_reset": ([vp], i32),
+        "gke_timings": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                         i32], i32),
         "gke_destroy": ([vp], None),
         "gke_last_error": ([vp], ctypes.c_char_p),
         "gke_version": ([], ctypes.c_char_p),
@@ -149,6 +155,18 @@ def gke_get_profiles(plan, ny: int) -> np.ndarray:
     out = np.zeros((GKE_NPROF, ny))
     _check(lib().gke_get_profiles(plan, _dp(out)), plan)
     return out
+
+
+def gke_reset(plan) -> None:
+    _check(lib().gke_reset(plan), plan)
+
+
+def gke_timings(plan, reset: bool = False):
+    """{kernel family: (total ms, launches)} since the last counter reset."""
+    ms = (ctypes.c_double * GKE_NKERNELS)()
+    n = (ctypes.c_int64 * GKE_NKERNELS)()
+    _check(lib().gke_timings(plan, ms, n, 1 if reset else 0), plan)
+    return {KERNEL_NAMES[i]: (ms[i], n[i]) for i in range(GKE_NKERNELS)}
 
 
 def gke_destroy(plan) -> None:

@@ -72,6 +72,15 @@ class GkeRun:
         gke.gke_finalize(self.plan, [t.data_ptr() if t is not None else 0 for t in out])
         return out
 
+    def reset(self):
+        gke.gke_reset(self.plan)
+
+    def set_timing(self, on: bool):
+        gke.gke_set_option(self.plan, gke.GKE_OPT_TIMING, 1 if on else 0)
+
+    def timings(self, reset=False):
+        return gke.gke_timings(self.plan, reset)
+
     def profiles(self) -> np.ndarray:
         return gke.gke_get_profiles(self.plan, self.ny)
 
