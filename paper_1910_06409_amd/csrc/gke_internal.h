@@ -27,18 +27,27 @@ enum { P_U = 0, P_V, P_W, P_P, P_S, P_Q, P_UV, P_PV, P_TX, P_TY, P_TZ, P_EPS, NP
 // physical-space moment partials per (plane, z block): q uv pv qu qv qw gy
 enum { MP_Q = 0, MP_UV, MP_PV, MP_QU, MP_QV, MP_QW, MP_GY, NMOMP };
 
+// pass-1 plane sums are split over this many blocks per plane
+constexpr int NSPLIT = 8;
+
 struct Dims {
     int nx, ny, nz;
-    int nkx;        // nx/2 + 1
-    int nk;         // nkx * nz
-    int nyp;        // ny rounded up to 16
-    int ntile;      // nyp / 16
-    int ntp;        // ntile (ntile + 1) / 2 unordered tile pairs
-    int zb, nzb;    // z rows per block in the x pass, number of blocks
-    int jb;         // planes per block in the z pass
-    int chunk;      // snapshot slots in the spectra buffer
+    int nkx;          // nx/2 + 1
+    int nk;           // nkx * nz
+    int ntile;        // full 16-plane tiles: ny / 16
+    int ntp;          // ntile (ntile + 1) / 2 unordered tile pairs
+    int npair_tiles;  // 256 ntp pairs handled on the matrix cores
+    int npair;        // all unordered pairs (tile pairs + remainder pairs)
+    int zb, nzb;      // z rows per block in the x pass, number of blocks
+    int jb;           // planes per block in the z pass
+    int chunk;        // snapshot slots in the spectra buffer
     double lx, lz, nu;
 };
+
+// pair table entry: j1 | j2 << 12 | mirror << 24 (mirror: also write (j2, j1))
+__host__ __device__ inline int pair_j1(int code) { return code & 4095; }
+__host__ __device__ inline int pair_j2(int code) { return (code >> 12) & 4095; }
+__host__ __device__ inline int pair_mirror(int code) { return (code >> 24) & 1; }
 
 struct Tables {
     const cx<double> *twx;   // exp(-2 pi i m/nx)
@@ -47,10 +56,11 @@ struct Tables {
     const int *j0;           // [ny] first stencil node
     const int *tile_a;       // [ntp] tile-pair rows
     const int *tile_b;       // [ntp] tile-pair columns (a <= b)
+    const int *pairs;        // [npair] pair table
     FftPlanDev px, pz;
 };
 
-// pass 1: plane sums of u~ v~ w~ p~ added into sums[4][ny]
+// pass 1: plane sums of u~ v~ w~ p~ added into sums[4][ny][NSPLIT]
 hipError_t launch_plane_sums(hipStream_t st, const Dims &d, int f32, const void *u,
                              const void *v, const void *w, const void *p, double *sums);
 // means = sums / count, S = D U (profile rows U V W P S)
@@ -74,14 +84,14 @@ hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t,
 hipError_t launch_rankk_f64(hipStream_t st, const Dims &d, const Tables &t,
                             const cx<double> *spec, int nsnap, int accumulate,
                             cx<double> *acc);
-// finalize: inverse transform along kz of the term spectra of tile pairs
-// [tp0, tp1), scaled by 1/count
+// finalize: inverse transform along kz of the term spectra of the pairs
+// [p0, p1) of the compact pair index, scaled by 1/count
 hipError_t launch_fin_kz(hipStream_t st, const Dims &d, const Tables &t,
-                         const cx<double> *acc, int tp0, int tp1, double inv_count,
+                         const cx<double> *acc, int p0, int p1, double inv_count,
                          cx<double> *mid);
 // finalize: inverse real transform along kx, FP64 assembly, both orientations
 hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
-                         const cx<double> *mid, int tp0, int tp1, const double *prof,
+                         const cx<double> *mid, int p0, int p1, const double *prof,
                          double *const *out);
 // Step 3: T6 and T11 from T1 along Y1 and Y2
 hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const double *t1,

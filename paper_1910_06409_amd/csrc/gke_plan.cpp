@@ -22,7 +22,7 @@ struct gke_plan_s {
     int dtype = GKE_DTYPE_F64;
     int prec = GKE_PREC_FP64;
     int chunk = 64;
-    int pair_batch = 0;  // tile pairs per finalize batch (0 = all)
+    int pair_batch = 0;  // pairs per finalize batch (0 = all)
     hipStream_t stream = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -30,12 +30,12 @@ struct gke_plan_s {
     // host copies of the tables (kept alive for the async uploads)
     std::vector<cx<double>> h_twx, h_twz;
     std::vector<double> h_w5;
-    std::vector<int> h_j0, h_ta, h_tb;
+    std::vector<int> h_j0, h_ta, h_tb, h_pairs;
 
     // carved device pointers
     cx<double> *twx = nullptr, *twz = nullptr;
     double *w5 = nullptr;
-    int *j0 = nullptr, *ta = nullptr, *tb = nullptr;
+    int *j0 = nullptr, *ta = nullptr, *tb = nullptr, *pairs = nullptr;
     double *sums1 = nullptr, *prof = nullptr, *momp = nullptr, *momg = nullptr;
     cx<double> *inter = nullptr, *spec = nullptr, *acc = nullptr, *mid = nullptr;
     gke::Tables tab{};
@@ -182,21 +182,22 @@ size_t layout(gke_plan_t p, char *base)
         off = align256(off + bytes);
         return base ? base + o : nullptr;
     };
-    const int pbt = (p->pair_batch > 0 && p->pair_batch < d.ntp) ? p->pair_batch : d.ntp;
+    const int pbt = (p->pair_batch > 0 && p->pair_batch < d.npair) ? p->pair_batch : d.npair;
     p->twx = (cx<double> *)take(sizeof(cx<double>) * d.nx);
     p->twz = (cx<double> *)take(sizeof(cx<double>) * d.nz);
     p->w5 = (double *)take(sizeof(double) * 5 * d.ny);
     p->j0 = (int *)take(sizeof(int) * d.ny);
-    p->ta = (int *)take(sizeof(int) * d.ntp);
-    p->tb = (int *)take(sizeof(int) * d.ntp);
-    p->sums1 = (double *)take(sizeof(double) * 4 * d.ny);
+    p->ta = (int *)take(sizeof(int) * std::max(d.ntp, 1));
+    p->tb = (int *)take(sizeof(int) * std::max(d.ntp, 1));
+    p->pairs = (int *)take(sizeof(int) * d.npair);
+    p->sums1 = (double *)take(sizeof(double) * 4 * d.ny * gke::NSPLIT);
     p->prof = (double *)take(sizeof(double) * gke::NPROF * d.ny);
     p->momp = (double *)take(sizeof(double) * d.ny * gke::NMOMP * d.nzb);
     p->momg = (double *)take(sizeof(double) * d.ny * 3 * d.nkx);
     p->inter = (cx<double> *)take(sizeof(cx<double>) * (size_t)d.ny * gke::NFIELD * d.nkx * d.nz);
-    p->spec = (cx<double> *)take(sizeof(cx<double>) * (size_t)d.nk * gke::NFIELD * d.chunk * d.nyp);
-    p->acc = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NSPEC * d.nk * d.ntp * 256);
-    p->mid = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NMAP * d.nkx * d.nz * pbt * 256);
+    p->spec = (cx<double> *)take(sizeof(cx<double>) * (size_t)d.nk * gke::NFIELD * d.chunk * d.ny);
+    p->acc = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NSPEC * d.nk * d.npair);
+    p->mid = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NMAP * d.nkx * d.nz * pbt);
     return off;
 }
 
@@ -241,9 +242,11 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
     d.nz = Nz;
     d.nkx = Nx / 2 + 1;
     d.nk = d.nkx * Nz;
-    d.nyp = (Ny + 15) / 16 * 16;
-    d.ntile = d.nyp / 16;
+    d.ntile = Ny / 16;
     d.ntp = d.ntile * (d.ntile + 1) / 2;
+    d.npair_tiles = 256 * d.ntp;
+    // tile entries (diagonal tiles hold both orientations) + remainder pairs
+    d.npair = d.npair_tiles + Ny * (Ny + 1) / 2 - (16 * d.ntile) * (16 * d.ntile + 1) / 2;
     d.lx = Lx;
     d.lz = Lz;
     d.nu = nu;
@@ -268,11 +271,27 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
         p->h_j0[j] = s;
         fornberg_d1(y[j], y + s, 5, &p->h_w5[5 * (size_t)j]);
     }
+    // pair table: tile pairs (a <= b) element by element, then the pairs of
+    // the remainder planes j2 >= 16 ntile with j1 <= j2
     for (int a = 0; a < d.ntile; ++a)
         for (int b = a; b < d.ntile; ++b) {
             p->h_ta.push_back(a);
             p->h_tb.push_back(b);
+            for (int i = 0; i < 16; ++i)
+                for (int k = 0; k < 16; ++k)
+                    p->h_pairs.push_back((16 * a + i) | (16 * b + k) << 12 | (a < b ? 1 : 0) << 24);
         }
+    if (p->h_ta.empty()) {
+        p->h_ta.push_back(0);
+        p->h_tb.push_back(0);
+    }
+    for (int j2 = 16 * d.ntile; j2 < Ny; ++j2)
+        for (int j1 = 0; j1 <= j2; ++j1)
+            p->h_pairs.push_back(j1 | j2 << 12 | (j1 < j2 ? 1 : 0) << 24);
+    if ((int)p->h_pairs.size() != d.npair) {
+        delete p;
+        return fail(nullptr, GKE_ERR_UNSUPPORTED, "internal pair count mismatch");
+    }
     p->tab.px = radix_plan(Nx);
     p->tab.pz = radix_plan(Nz);
     *out = p;
@@ -340,11 +359,11 @@ gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
     GKE_HIP(p, hipMemcpyAsync(p->twz, p->h_twz.data(), sizeof(cx<double>) * d.nz, hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->w5, p->h_w5.data(), sizeof(double) * 5 * d.ny, hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->j0, p->h_j0.data(), sizeof(int) * d.ny, hipMemcpyHostToDevice, st));
-    GKE_HIP(p, hipMemcpyAsync(p->ta, p->h_ta.data(), sizeof(int) * d.ntp, hipMemcpyHostToDevice, st));
-    GKE_HIP(p, hipMemcpyAsync(p->tb, p->h_tb.data(), sizeof(int) * d.ntp, hipMemcpyHostToDevice, st));
-    // accumulators and the spectra (whose padding planes must stay zero)
+    GKE_HIP(p, hipMemcpyAsync(p->ta, p->h_ta.data(), sizeof(int) * p->h_ta.size(), hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->tb, p->h_tb.data(), sizeof(int) * p->h_tb.size(), hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->pairs, p->h_pairs.data(), sizeof(int) * d.npair, hipMemcpyHostToDevice, st));
+    // sums, profiles and moment partials start at zero
     GKE_HIP(p, hipMemsetAsync(p->sums1, 0, (char *)p->inter - (char *)p->sums1, st));
-    GKE_HIP(p, hipMemsetAsync(p->spec, 0, sizeof(cx<double>) * (size_t)d.nk * gke::NFIELD * d.chunk * d.nyp, st));
     GKE_HIP(p, hipStreamSynchronize(st));
     p->tab.twx = p->twx;
     p->tab.twz = p->twz;
@@ -352,6 +371,7 @@ gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
     p->tab.j0 = p->j0;
     p->tab.tile_a = p->ta;
     p->tab.tile_b = p->tb;
+    p->tab.pairs = p->pairs;
     return GKE_OK;
 }
 
@@ -443,15 +463,15 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
     }));
     double *outp[14];
     for (int i = 0; i < 14; ++i) outp[i] = (double *)out->t[i];
-    const int pbt = (p->pair_batch > 0 && p->pair_batch < d.ntp) ? p->pair_batch : d.ntp;
+    const int pbt = (p->pair_batch > 0 && p->pair_batch < d.npair) ? p->pair_batch : d.npair;
     const double inv = 1.0 / (double)p->n2;
-    for (int tp0 = 0; tp0 < d.ntp; tp0 += pbt) {
-        const int tp1 = std::min(d.ntp, tp0 + pbt);
+    for (int q0 = 0; q0 < d.npair; q0 += pbt) {
+        const int q1 = std::min(d.npair, q0 + pbt);
         GKE_HIP(p, timed(p, GKE_K_FIN_KZ, [&] {
-            return gke::launch_fin_kz(st, d, p->tab, p->acc, tp0, tp1, inv, p->mid);
+            return gke::launch_fin_kz(st, d, p->tab, p->acc, q0, q1, inv, p->mid);
         }));
         GKE_HIP(p, timed(p, GKE_K_FIN_KX, [&] {
-            return gke::launch_fin_kx(st, d, p->tab, p->mid, tp0, tp1, p->prof, outp);
+            return gke::launch_fin_kx(st, d, p->tab, p->mid, q0, q1, p->prof, outp);
         }));
     }
     if (outp[GKE_T_PHIY_V] || outp[GKE_T_PHI_V])

@@ -18,7 +18,7 @@ namespace gke {
 // Inverse transform along kz for PB pairs of one term spectrum at one kx.
 // mid layout: [NMAP][nkx][nz (rz)][ptot (pairs of this batch)].
 __global__ __launch_bounds__(256) void k_fin_kz(const cx<double> *__restrict__ acc, Dims d,
-                                                Tables t, int tp0, int ptot, int pb,
+                                                Tables t, int p0, int ptot, int pb,
                                                 double inv_count, cx<double> *__restrict__ mid)
 {
     extern __shared__ cx<double> lds[];
@@ -26,8 +26,8 @@ __global__ __launch_bounds__(256) void k_fin_kz(const cx<double> *__restrict__ a
     const int pblk = blockIdx.x, kx = blockIdx.y, sp = blockIdx.z;
     const int pl0 = pblk * pb;                       // first pair within the batch
     const int np = min(pb, ptot - pl0);
-    const size_t pall = (size_t)d.ntp * 256;
-    const size_t pg0 = (size_t)tp0 * 256 + pl0;      // first pair within acc
+    const size_t pall = (size_t)d.npair;
+    const size_t pg0 = (size_t)p0 + pl0;             // first pair within acc
     const int bs = nz + 1;
     cx<double> *A = lds;
     cx<double> *B = lds + pb * bs;
@@ -68,15 +68,15 @@ __global__ __launch_bounds__(256) void k_fin_kz(const cx<double> *__restrict__ a
 }
 
 hipError_t launch_fin_kz(hipStream_t st, const Dims &d, const Tables &t,
-                         const cx<double> *acc, int tp0, int tp1, double inv_count,
+                         const cx<double> *acc, int p0, int p1, double inv_count,
                          cx<double> *mid)
 {
-    const int ptot = (tp1 - tp0) * 256;
+    const int ptot = p1 - p0;
     int pb = 8;
     while (pb > 1 && sizeof(cx<double>) * 2 * (size_t)pb * (d.nz + 1) > 65536) pb >>= 1;
     const size_t lds = sizeof(cx<double>) * 2 * (size_t)pb * (d.nz + 1);
     dim3 grid((ptot + pb - 1) / pb, d.nkx, NSPEC);
-    hipLaunchKernelGGL(k_fin_kz, grid, dim3(256), lds, st, acc, d, t, tp0, ptot, pb, inv_count,
+    hipLaunchKernelGGL(k_fin_kz, grid, dim3(256), lds, st, acc, d, t, p0, ptot, pb, inv_count,
                        mid);
     return hipGetLastError();
 }
@@ -140,10 +140,10 @@ __device__ __forceinline__ void assemble_store(int m, double val, int j1, int j2
 }
 
 // Inverse real transform along kx of 2*nt pairs (two real maps per complex
-// transform), then assembly for pair (Y1, Y2) and, below the tile diagonal,
-// the mirrored pair (Y2, Y1) from r -> -r.
+// transform), then assembly for pair (Y1, Y2) and, when the pair table asks
+// for it, the mirrored pair (Y2, Y1) from r -> -r.
 __global__ __launch_bounds__(256) void k_fin_kx(const cx<double> *__restrict__ mid, Dims d,
-                                                Tables t, int tp0, int ptot, int nt,
+                                                Tables t, int p0, int ptot, int nt,
                                                 const double *__restrict__ prof, OutPtrs out)
 {
     extern __shared__ cx<double> lds[];
@@ -181,17 +181,14 @@ __global__ __launch_bounds__(256) void k_fin_kx(const cx<double> *__restrict__ m
     const size_t plane = (size_t)nz * nkx;
     for (int e = threadIdx.x; e < np * nkx; e += blockDim.x) {
         const int b = e / nkx, rx = e - b * nkx;
-        const size_t pg = (size_t)tp0 * 256 + pl0 + b;
-        const int tp = (int)(pg >> 8), el = (int)(pg & 255);
-        const int ta = t.tile_a[tp], tb = t.tile_b[tp];
-        const int j1 = ta * 16 + (el >> 4), j2 = tb * 16 + (el & 15);
-        if (j1 >= ny || j2 >= ny) continue;
+        const int code = t.pairs[p0 + pl0 + b];
+        const int j1 = pair_j1(code), j2 = pair_j2(code);
         const int c = b >> 1;
         const cx<double> zv = R[c * bs + rx];
         const double val = (b & 1) ? zv.y : zv.x;
         assemble_store(m, val, j1, j2, prof, ny, d.nu, out,
                        ((size_t)j1 * ny + j2) * plane + (size_t)rz * nkx + rx);
-        if (ta < tb) {
+        if (pair_mirror(code)) {
             const int rxm = (rx == 0) ? 0 : nx - rx;
             const cx<double> zm = R[c * bs + rxm];
             const double vm = sig * ((b & 1) ? zm.y : zm.x);
@@ -203,10 +200,10 @@ __global__ __launch_bounds__(256) void k_fin_kx(const cx<double> *__restrict__ m
 }
 
 hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
-                         const cx<double> *mid, int tp0, int tp1, const double *prof,
+                         const cx<double> *mid, int p0, int p1, const double *prof,
                          double *const *out)
 {
-    const int ptot = (tp1 - tp0) * 256;
+    const int ptot = p1 - p0;
     int nt = 8;
     auto need = [&](int n) {
         return sizeof(cx<double>) * ((size_t)n * (d.nx + 1) +
@@ -216,7 +213,7 @@ hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
     OutPtrs op;
     for (int i = 0; i < 14; ++i) op.t[i] = out[i];
     dim3 grid((ptot + 2 * nt - 1) / (2 * nt), d.nz, NMAP);
-    hipLaunchKernelGGL(k_fin_kx, grid, dim3(256), need(nt), st, mid, d, t, tp0, ptot, nt, prof, op);
+    hipLaunchKernelGGL(k_fin_kx, grid, dim3(256), need(nt), st, mid, d, t, p0, ptot, nt, prof, op);
     return hipGetLastError();
 }
 

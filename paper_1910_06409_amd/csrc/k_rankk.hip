@@ -1,4 +1,4 @@
-// k_rankk.hip -- cross-spectral accumulation over snapshots, FP64 MFMA.
+// k_rankk.hip -- cross-spectral accumulation over snapshots, FP64.
 //
 // Every GKE term is a linear combination of two-point correlations
 // (Section "Products instead of correlations", eq. expansion and its analogues
@@ -21,9 +21,14 @@
 //   c7 = (u, v),             c8 = (v, u)
 //   <du^2 dv>: c3 - c4;  <v* du^2>: 2 c5 - c3 - c4;  <dp dv>: c6;
 //   <du dv>: c7 + c8;    <du v*>: c8 - c7     (r-dependent parts)
-// Only tile pairs (a <= b) of 16x16 planes are computed; the pairs below the
-// diagonal follow from the r-inversion symmetry (Section "Exploiting
-// symmetries") at finalize.
+// Only unordered pairs are computed; the reverse orientation follows from the
+// r-inversion symmetry (Section "Exploiting symmetries") at finalize.
+//
+// The planes split into full 16-plane tiles, handled on the matrix cores by
+// tile pairs (a <= b), and the remaining Ny mod 16 planes, whose pairs go to a
+// small FP64 vector kernel.  Accumulators are indexed by a compact pair index
+// P: tile pair tp covers P = 256 tp + 16 (Y1 offset) + (Y2 offset), the
+// remainder pairs follow in the order of the host-built pair table.
 //
 // MFMA mapping (v_mfma_f64_16x16x4f64, one wave per 16x16 output tile):
 //   K index = (snapshot pair s0, s0+1) x (real, imaginary part);
@@ -39,14 +44,69 @@ namespace gke {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-#define GKE_MFMA2(acc_r, acc_i, a, br, bi)                                       \
+#define GKE_MFMA2(c, a, br, bi)                                                   \
     do {                                                                         \
-        acc_r = __builtin_amdgcn_mfma_f64_16x16x4f64((a), (br), acc_r, 0, 0, 0); \
-        acc_i = __builtin_amdgcn_mfma_f64_16x16x4f64((a), (bi), acc_i, 0, 0, 0); \
+        ar[c] = __builtin_amdgcn_mfma_f64_16x16x4f64((a), (br), ar[c], 0, 0, 0); \
+        ai[c] = __builtin_amdgcn_mfma_f64_16x16x4f64((a), (bi), ai[c], 0, 0, 0); \
     } while (0)
 
-// acc layout: [NSPEC][nk][ntp * 256] complex, element index within a tile
-// pair = (Y1 offset) * 16 + (Y2 offset).
+// Store the eight term spectra of one element from the nine accumulators.
+__device__ __forceinline__ void store_spectra(cx<double> *acc, size_t sp_stride, size_t o,
+                                              const double *cr, const double *ci,
+                                              int accumulate)
+{
+    double sr[NSPEC], si[NSPEC];
+    sr[S_R] = cr[0];
+    si[S_R] = ci[0];
+    sr[S_FX] = cr[1];
+    si[S_FX] = ci[1];
+    sr[S_FY] = cr[3] - cr[4];
+    si[S_FY] = ci[3] - ci[4];
+    sr[S_FZ] = cr[2];
+    si[S_FZ] = ci[2];
+    sr[S_PHI] = 2.0 * cr[5] - cr[3] - cr[4];
+    si[S_PHI] = 2.0 * ci[5] - ci[3] - ci[4];
+    sr[S_PP] = cr[6];
+    si[S_PP] = ci[6];
+    sr[S_UVS] = cr[7] + cr[8];
+    si[S_UVS] = ci[7] + ci[8];
+    sr[S_UVA] = cr[8] - cr[7];
+    si[S_UVA] = ci[8] - ci[7];
+#pragma unroll
+    for (int sp = 0; sp < NSPEC; ++sp) {
+        cx<double> *dst = acc + sp * sp_stride + o;
+        cx<double> val = cx<double>{sr[sp], si[sp]};
+        if (accumulate) {
+            const cx<double> old = *dst;
+            val.x += old.x;
+            val.y += old.y;
+        }
+        *dst = val;
+    }
+}
+
+struct Operands {
+    double L[NFIELD];
+    cx<double> R[NFIELD];
+};
+
+// Branch-free: a slot past the end reloads the last valid slot; the caller
+// zeroes the left operand of such a slot when it uses it (a zero left value
+// cancels every product of that snapshot), so the loads stay in flight.
+__device__ __forceinline__ void load_operands(Operands &op, const double *lbase,
+                                              const cx<double> *rbase, size_t fstride,
+                                              int ny, int s, int nsnap)
+{
+    const int sc = s < nsnap ? s : nsnap - 1;
+#pragma unroll
+    for (int f = 0; f < NFIELD; ++f) {
+        const size_t o = f * fstride + (size_t)sc * ny;
+        op.L[f] = lbase[2 * o];
+        op.R[f] = rbase[o];
+    }
+}
+
+// acc layout: [NSPEC][nk][P] complex.
 __global__ __launch_bounds__(64) void k_rankk_f64(const cx<double> *__restrict__ spec, Dims d,
                                                   const int *__restrict__ tile_a,
                                                   const int *__restrict__ tile_b, int nsnap,
@@ -66,7 +126,7 @@ __global__ __launch_bounds__(64) void k_rankk_f64(const cx<double> *__restrict__
 
     const int lane = threadIdx.x;
     const int row = lane & 15, kq = lane >> 4, soff = kq >> 1, ri = kq & 1;
-    const size_t fstride = (size_t)d.chunk * d.nyp;  // complex elements per field
+    const size_t fstride = (size_t)d.chunk * d.ny;  // complex elements per field
     const cx<double> *kb = spec + (size_t)k * NFIELD * fstride;
     const double *lbase = reinterpret_cast<const double *>(kb + ta * 16 + row) + ri;
     const cx<double> *rbase = kb + tb * 16 + row;
@@ -78,29 +138,35 @@ __global__ __launch_bounds__(64) void k_rankk_f64(const cx<double> *__restrict__
         ai[c] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
+    Operands cur;
+    load_operands(cur, lbase, rbase, fstride, d.ny, soff, nsnap);
     for (int s0 = 0; s0 < nsnap; s0 += 2) {
-        const int s = s0 + soff;
-        const bool ok = s < nsnap;
-        double Lf[NFIELD];
-        cx<double> Rf[NFIELD];
+        // prefetch the next snapshot pair while this one is multiplied
+        Operands nxt;
+        const int sn = s0 + 2 + soff;
+        load_operands(nxt, lbase, rbase, fstride, d.ny, sn, nsnap);
+        // keep the scheduler from pulling the consumers of these loads into
+        // this iteration: they are waited for only at the next one
+        __builtin_amdgcn_sched_barrier(0);
+
+        // left operand (planes Y1): fluctuations and Q_ij; zero past the end
+        const bool ok = s0 + soff < nsnap;
+        double Lc[NFIELD];
 #pragma unroll
-        for (int f = 0; f < NFIELD; ++f) {
-            const size_t o = f * fstride + (size_t)s * d.nyp;
-            Lf[f] = ok ? lbase[2 * o] : 0.0;
-            Rf[f] = ok ? rbase[o] : cx<double>{0.0, 0.0};
-        }
-        // left operand (planes Y1): fluctuations and Q_ij
-        const double lu = Lf[F_U], lv = Lf[F_V], lw = Lf[F_W], lp = Lf[F_P];
-        const double lq = Lf[F_UU] + Lf[F_VV] + Lf[F_WW];
-        const double lQxx = 2.0 * Lf[F_UU] + lq, lQyy = 2.0 * Lf[F_VV] + lq;
-        const double lQzz = 2.0 * Lf[F_WW] + lq;
-        const double lQxy = 2.0 * Lf[F_UV], lQxz = 2.0 * Lf[F_UW], lQyz = 2.0 * Lf[F_VW];
+        for (int f = 0; f < NFIELD; ++f) Lc[f] = ok ? cur.L[f] : 0.0;
+        const double lu = Lc[F_U], lv = Lc[F_V], lw = Lc[F_W], lp = Lc[F_P];
+        const double lq = Lc[F_UU] + Lc[F_VV] + Lc[F_WW];
+        const double lQxx = 2.0 * Lc[F_UU] + lq, lQyy = 2.0 * Lc[F_VV] + lq;
+        const double lQzz = 2.0 * Lc[F_WW] + lq;
+        const double lQxy = 2.0 * Lc[F_UV], lQxz = 2.0 * Lc[F_UW];
+        const double lQyz = 2.0 * Lc[F_VW];
+        const double nu_ = -lu, nv = -lv, nw = -lw;
         // right operand (planes Y2): real-output and imaginary-output forms
         double br[NFIELD], bi[NFIELD];
 #pragma unroll
         for (int f = 0; f < NFIELD; ++f) {
-            br[f] = ri ? Rf[f].y : Rf[f].x;
-            bi[f] = ri ? -Rf[f].x : Rf[f].y;
+            br[f] = ri ? cur.R[f].y : cur.R[f].x;
+            bi[f] = ri ? -cur.R[f].x : cur.R[f].y;
         }
         const double rqr = br[F_UU] + br[F_VV] + br[F_WW];
         const double rqi = bi[F_UU] + bi[F_VV] + bi[F_WW];
@@ -113,87 +179,129 @@ __global__ __launch_bounds__(64) void k_rankk_f64(const cx<double> *__restrict__
         const double ur = br[F_U], ui = bi[F_U], vr = br[F_V], vi = bi[F_V];
         const double wr = br[F_W], wi = bi[F_W], pr = br[F_P], pi = bi[F_P];
 
-        // c0: scale energy
-        GKE_MFMA2(ar[0], ai[0], lu, ur, ui);
-        GKE_MFMA2(ar[0], ai[0], lv, vr, vi);
-        GKE_MFMA2(ar[0], ai[0], lw, wr, wi);
-        // c1: flux x
-        GKE_MFMA2(ar[1], ai[1], lQxx, ur, ui);
-        GKE_MFMA2(ar[1], ai[1], lQxy, vr, vi);
-        GKE_MFMA2(ar[1], ai[1], lQxz, wr, wi);
-        GKE_MFMA2(ar[1], ai[1], -lu, rQxxr, rQxxi);
-        GKE_MFMA2(ar[1], ai[1], -lv, rQxyr, rQxyi);
-        GKE_MFMA2(ar[1], ai[1], -lw, rQxzr, rQxzi);
-        // c2: flux z
-        GKE_MFMA2(ar[2], ai[2], lQxz, ur, ui);
-        GKE_MFMA2(ar[2], ai[2], lQyz, vr, vi);
-        GKE_MFMA2(ar[2], ai[2], lQzz, wr, wi);
-        GKE_MFMA2(ar[2], ai[2], -lu, rQxzr, rQxzi);
-        GKE_MFMA2(ar[2], ai[2], -lv, rQyzr, rQyzi);
-        GKE_MFMA2(ar[2], ai[2], -lw, rQzzr, rQzzi);
-        // c3, c4: y-flux halves
-        GKE_MFMA2(ar[3], ai[3], lQxy, ur, ui);
-        GKE_MFMA2(ar[3], ai[3], lQyy, vr, vi);
-        GKE_MFMA2(ar[3], ai[3], lQyz, wr, wi);
-        GKE_MFMA2(ar[4], ai[4], lu, rQxyr, rQxyi);
-        GKE_MFMA2(ar[4], ai[4], lv, rQyyr, rQyyi);
-        GKE_MFMA2(ar[4], ai[4], lw, rQyzr, rQyzi);
-        // c5: (v, q) + (q, v)
-        GKE_MFMA2(ar[5], ai[5], lv, rqr, rqi);
-        GKE_MFMA2(ar[5], ai[5], lq, vr, vi);
-        // c6: (p, v) + (v, p)
-        GKE_MFMA2(ar[6], ai[6], lp, vr, vi);
-        GKE_MFMA2(ar[6], ai[6], lv, pr, pi);
-        // c7, c8
-        GKE_MFMA2(ar[7], ai[7], lu, vr, vi);
-        GKE_MFMA2(ar[8], ai[8], lv, ur, ui);
+        // 27 products, ordered so that successive ones feed different accumulators
+        GKE_MFMA2(0, lu, ur, ui);
+        GKE_MFMA2(1, lQxx, ur, ui);
+        GKE_MFMA2(2, lQxz, ur, ui);
+        GKE_MFMA2(3, lQxy, ur, ui);
+        GKE_MFMA2(8, lv, ur, ui);
+        GKE_MFMA2(4, lu, rQxyr, rQxyi);
+        GKE_MFMA2(1, nu_, rQxxr, rQxxi);
+        GKE_MFMA2(2, nu_, rQxzr, rQxzi);
+        GKE_MFMA2(5, lv, rqr, rqi);
+        GKE_MFMA2(0, lv, vr, vi);
+        GKE_MFMA2(1, lQxy, vr, vi);
+        GKE_MFMA2(2, lQyz, vr, vi);
+        GKE_MFMA2(3, lQyy, vr, vi);
+        GKE_MFMA2(6, lp, vr, vi);
+        GKE_MFMA2(7, lu, vr, vi);
+        GKE_MFMA2(4, lv, rQyyr, rQyyi);
+        GKE_MFMA2(5, lq, vr, vi);
+        GKE_MFMA2(1, nv, rQxyr, rQxyi);
+        GKE_MFMA2(2, nv, rQyzr, rQyzi);
+        GKE_MFMA2(6, lv, pr, pi);
+        GKE_MFMA2(0, lw, wr, wi);
+        GKE_MFMA2(1, lQxz, wr, wi);
+        GKE_MFMA2(2, lQzz, wr, wi);
+        GKE_MFMA2(3, lQyz, wr, wi);
+        GKE_MFMA2(4, lw, rQyzr, rQyzi);
+        GKE_MFMA2(1, nw, rQxzr, rQxzi);
+        GKE_MFMA2(2, nw, rQzzr, rQzzi);
+        __builtin_amdgcn_sched_barrier(0);
+        cur = nxt;
     }
 
-    // term spectra: R FX FY FZ PHI PP UVS UVA
-    const size_t ptot = (size_t)d.ntp * 256;
+    const size_t sp_stride = (size_t)d.nk * d.npair;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const size_t el = (size_t)tp * 256 + (kq + 4 * v) * 16 + row;
-        double sr[NSPEC], si[NSPEC];
-        sr[S_R] = ar[0][v];
-        si[S_R] = ai[0][v];
-        sr[S_FX] = ar[1][v];
-        si[S_FX] = ai[1][v];
-        sr[S_FY] = ar[3][v] - ar[4][v];
-        si[S_FY] = ai[3][v] - ai[4][v];
-        sr[S_FZ] = ar[2][v];
-        si[S_FZ] = ai[2][v];
-        sr[S_PHI] = 2.0 * ar[5][v] - ar[3][v] - ar[4][v];
-        si[S_PHI] = 2.0 * ai[5][v] - ai[3][v] - ai[4][v];
-        sr[S_PP] = ar[6][v];
-        si[S_PP] = ai[6][v];
-        sr[S_UVS] = ar[7][v] + ar[8][v];
-        si[S_UVS] = ai[7][v] + ai[8][v];
-        sr[S_UVA] = ar[8][v] - ar[7][v];
-        si[S_UVA] = ai[8][v] - ai[7][v];
+        const size_t o = (size_t)k * d.npair + (size_t)tp * 256 + (kq + 4 * v) * 16 + row;
+        double cr[9], ci[9];
 #pragma unroll
-        for (int sp = 0; sp < NSPEC; ++sp) {
-            cx<double> *dst = acc + ((size_t)sp * d.nk + k) * ptot + el;
-            cx<double> val = cx<double>{sr[sp], si[sp]};
-            if (accumulate) {
-                const cx<double> old = *dst;
-                val.x += old.x;
-                val.y += old.y;
-            }
-            *dst = val;
+        for (int c = 0; c < 9; ++c) {
+            cr[c] = ar[c][v];
+            ci[c] = ai[c][v];
         }
+        store_spectra(acc, sp_stride, o, cr, ci, accumulate);
     }
+}
+
+// Pairs that involve the last Ny mod 16 planes: one thread per (k, pair), FP64
+// vector arithmetic.  pairs[i] = j1 | j2 << 12 for compact index P = P0 + i.
+__global__ __launch_bounds__(64) void k_rankk_rem_f64(const cx<double> *__restrict__ spec, Dims d,
+                                                      const int *__restrict__ pairs, int nrem,
+                                                      int nsnap, int accumulate,
+                                                      cx<double> *__restrict__ acc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (i >= nrem) return;
+    const int code = pairs[d.npair_tiles + i];
+    const int j1 = code & 4095, j2 = (code >> 12) & 4095;
+    const size_t fstride = (size_t)d.chunk * d.ny;
+    const cx<double> *kb = spec + (size_t)k * NFIELD * fstride;
+    double cr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ci[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < nsnap; ++s) {
+        cx<double> A[NFIELD], B[NFIELD];
+#pragma unroll
+        for (int f = 0; f < NFIELD; ++f) {
+            A[f] = kb[f * fstride + (size_t)s * d.ny + j1];
+            B[f] = kb[f * fstride + (size_t)s * d.ny + j2];
+        }
+        auto derive = [](const cx<double> *F, cx<double> *q, cx<double> *Q) {
+            q->x = F[F_UU].x + F[F_VV].x + F[F_WW].x;
+            q->y = F[F_UU].y + F[F_VV].y + F[F_WW].y;
+            // Q: xx yy zz xy xz yz
+            Q[0] = cx<double>{2.0 * F[F_UU].x + q->x, 2.0 * F[F_UU].y + q->y};
+            Q[1] = cx<double>{2.0 * F[F_VV].x + q->x, 2.0 * F[F_VV].y + q->y};
+            Q[2] = cx<double>{2.0 * F[F_WW].x + q->x, 2.0 * F[F_WW].y + q->y};
+            Q[3] = cx<double>{2.0 * F[F_UV].x, 2.0 * F[F_UV].y};
+            Q[4] = cx<double>{2.0 * F[F_UW].x, 2.0 * F[F_UW].y};
+            Q[5] = cx<double>{2.0 * F[F_VW].x, 2.0 * F[F_VW].y};
+        };
+        cx<double> qa, qb, Qa[6], Qb[6];
+        derive(A, &qa, Qa);
+        derive(B, &qb, Qb);
+        // conj(a) b accumulated into channel c with sign sg
+        auto mac = [&](int c, cx<double> a, cx<double> b, double sg) {
+            cr[c] += sg * (a.x * b.x + a.y * b.y);
+            ci[c] += sg * (a.x * b.y - a.y * b.x);
+        };
+        const cx<double> ua = A[F_U], va = A[F_V], wa = A[F_W], pa = A[F_P];
+        const cx<double> ub = B[F_U], vb = B[F_V], wb = B[F_W], pb = B[F_P];
+        mac(0, ua, ub, 1.0); mac(0, va, vb, 1.0); mac(0, wa, wb, 1.0);
+        mac(1, Qa[0], ub, 1.0); mac(1, Qa[3], vb, 1.0); mac(1, Qa[4], wb, 1.0);
+        mac(1, ua, Qb[0], -1.0); mac(1, va, Qb[3], -1.0); mac(1, wa, Qb[4], -1.0);
+        mac(2, Qa[4], ub, 1.0); mac(2, Qa[5], vb, 1.0); mac(2, Qa[2], wb, 1.0);
+        mac(2, ua, Qb[4], -1.0); mac(2, va, Qb[5], -1.0); mac(2, wa, Qb[2], -1.0);
+        mac(3, Qa[3], ub, 1.0); mac(3, Qa[1], vb, 1.0); mac(3, Qa[5], wb, 1.0);
+        mac(4, ua, Qb[3], 1.0); mac(4, va, Qb[1], 1.0); mac(4, wa, Qb[5], 1.0);
+        mac(5, va, qb, 1.0); mac(5, qa, vb, 1.0);
+        mac(6, pa, vb, 1.0); mac(6, va, pb, 1.0);
+        mac(7, ua, vb, 1.0);
+        mac(8, va, ub, 1.0);
+    }
+    store_spectra(acc, (size_t)d.nk * d.npair, (size_t)k * d.npair + d.npair_tiles + i, cr, ci,
+                  accumulate);
 }
 
 hipError_t launch_rankk_f64(hipStream_t st, const Dims &d, const Tables &t,
                             const cx<double> *spec, int nsnap, int accumulate,
                             cx<double> *acc)
 {
-    const long long total = (long long)d.nk * d.ntp;
-    if (total >= (1LL << 31) - 8) return hipErrorInvalidValue;
-    const int G = (int)((total + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_rankk_f64, dim3(G), dim3(64), 0, st, spec, d, t.tile_a, t.tile_b, nsnap,
-                       accumulate, (int)total, acc);
+    if (d.ntp > 0) {
+        const long long total = (long long)d.nk * d.ntp;
+        if (total >= (1LL << 31) - 8) return hipErrorInvalidValue;
+        const int G = (int)((total + 7) / 8 * 8);
+        hipLaunchKernelGGL(k_rankk_f64, dim3(G), dim3(64), 0, st, spec, d, t.tile_a, t.tile_b,
+                           nsnap, accumulate, (int)total, acc);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int nrem = d.npair - d.npair_tiles;
+    if (nrem > 0) {
+        hipLaunchKernelGGL(k_rankk_rem_f64, dim3((nrem + 63) / 64, d.nk), dim3(64), 0, st, spec,
+                           d, t.pairs, nrem, nsnap, accumulate, acc);
+    }
     return hipGetLastError();
 }
 

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_zfft_pack(const cx<double> *__restrict_
         const int kz = e / jb, b = e - kz * jb;
         if (b < nb) {
             const cx<double> X = cscale(R[b * bs + kz], scale);
-            spec[((((size_t)kx * nz + kz) * NFIELD + f) * d.chunk + slot) * d.nyp + j0 + b] = X;
+            spec[((((size_t)kx * nz + kz) * NFIELD + f) * d.chunk + slot) * ny + j0 + b] = X;
             if (f < 3) {
                 const int kzs = (kz <= nz / 2) ? kz : kz - nz;
                 const double beta = (2 * kz == nz) ? 0.0 : two_pi * kzs / d.lz;

@@ -20,6 +20,8 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return r;
 }
 
+// Block (j, part) sums 1/NSPLIT of plane j for the four fields and adds the
+// four results to sums[f][j][part] (one owner per slot: fixed order).
 template <typename TI>
 __global__ __launch_bounds__(256) void k_plane_sums(const TI *__restrict__ u,
                                                     const TI *__restrict__ v,
@@ -28,14 +30,20 @@ __global__ __launch_bounds__(256) void k_plane_sums(const TI *__restrict__ u,
                                                     double *__restrict__ sums)
 {
     __shared__ double sh[8];
-    const int j = blockIdx.x;
+    const int j = blockIdx.x, part = blockIdx.y;
+    const int len = (npl + NSPLIT - 1) / NSPLIT;
+    const int i0 = part * len, i1 = min(npl, i0 + len);
     const size_t off = (size_t)j * npl;
-    const TI *src[4] = {u + off, v + off, w + off, p + off};
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        a[0] += (double)u[off + i];
+        a[1] += (double)v[off + i];
+        a[2] += (double)w[off + i];
+        a[3] += (double)p[off + i];
+    }
     for (int f = 0; f < 4; ++f) {
-        double a = 0.0;
-        for (int i = threadIdx.x; i < npl; i += blockDim.x) a += (double)src[f][i];
-        const double r = block_sum(a, sh);
-        if (threadIdx.x == 0) sums[f * ny + j] += r;
+        const double r = block_sum(a[f], sh);
+        if (threadIdx.x == 0) sums[((size_t)f * ny + j) * NSPLIT + part] += r;
     }
 }
 
@@ -43,12 +51,13 @@ hipError_t launch_plane_sums(hipStream_t st, const Dims &d, int f32, const void 
                              const void *v, const void *w, const void *p, double *sums)
 {
     const int npl = d.nx * d.nz;
+    dim3 grid(d.ny, NSPLIT);
     if (f32)
-        hipLaunchKernelGGL(k_plane_sums<float>, dim3(d.ny), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_plane_sums<float>, grid, dim3(256), 0, st,
                            (const float *)u, (const float *)v, (const float *)w,
                            (const float *)p, npl, d.ny, sums);
     else
-        hipLaunchKernelGGL(k_plane_sums<double>, dim3(d.ny), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_plane_sums<double>, grid, dim3(256), 0, st,
                            (const double *)u, (const double *)v, (const double *)w,
                            (const double *)p, npl, d.ny, sums);
     return hipGetLastError();
@@ -68,7 +77,11 @@ __global__ void k_means(int ny, const double *__restrict__ sums, double inv_coun
                         const double *__restrict__ w5, const int *__restrict__ j0,
                         double *__restrict__ prof)
 {
-    for (int i = threadIdx.x; i < 4 * ny; i += blockDim.x) prof[i] = sums[i] * inv_count;
+    for (int i = threadIdx.x; i < 4 * ny; i += blockDim.x) {
+        double a = 0.0;
+        for (int part = 0; part < NSPLIT; ++part) a += sums[(size_t)i * NSPLIT + part];
+        prof[i] = a * inv_count;
+    }
     __syncthreads();
     shear_rows(ny, w5, j0, prof);
 }

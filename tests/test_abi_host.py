@@ -91,9 +91,10 @@ def test_workspace_scales_with_grid():
     try:
         gke.gke_set_option(p, gke.GKE_OPT_CHUNK, 100)
         n = gke.gke_workspace_size(p)
-        # spectra: nk * 10 fields * chunk * 144 padded planes * 16 B
-        spec = w.nk * 10 * 100 * 144 * 16
-        acc = 8 * w.nk * 45 * 256 * 16
+        # spectra: nk * 10 fields * chunk * planes * 16 B; accumulators: 8 spectra
+        # per compact pair (36 tile pairs of 256 + 129 pairs of the last plane)
+        spec = w.nk * 10 * 100 * 129 * 16
+        acc = 8 * w.nk * (36 * 256 + 129) * 16
         assert spec + acc < n < 2 * (spec + acc)
         assert n < 200 * 2 ** 30
     finally:

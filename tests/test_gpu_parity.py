@@ -101,7 +101,7 @@ def test_radix_3_5_ragged_planes():
     y = synth.y_grid(w)
     snap = synth.snapshots(w, 4)
     say("case 24x21x20")
-    g, _ = run_gpu(snap, w, y, chunk=4, pair_batch=1)
+    g, _ = run_gpu(snap, w, y, chunk=4, pair_batch=97)
     pairs = oracle.all_pairs(w.ny)
     ref = oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs)
     compare(g, ref, pairs, w.nx, "24x21x20")
