@@ -40,14 +40,17 @@ def kernel_work(w, chunk):
     b_in = 8 if w.dtype == "f64" else 4
     n_pts = nx * ny * nz
     c16 = 16  # complex FP64
+    c8 = 8 if w.precision == "bf16x3" else 16  # x-transformed values and spectra
     npair_u = ny * (ny + 1) // 2
+    # 27 complex MACs (216 flops) per (snapshot, wavenumber, unordered pair
+    # Y1 <= Y2); the split-BF16 form takes three real products for each one
+    fl = 216.0 * (3 if w.precision == "bf16x3" else 1)
     return {
-        # 27 complex MACs (216 flops) per (snapshot, wavenumber, unordered pair Y1 <= Y2)
-        "rankk": ("flop", 216.0 * chunk * nk * npair_u),
+        "rankk": ("flop", fl * chunk * nk * npair_u),
         # read the 4 input fields once, write the 10 x-transformed fields
-        "fluct_xfft": ("byte", 4.0 * n_pts * b_in + 10.0 * ny * nkx * nz * c16),
+        "fluct_xfft": ("byte", 4.0 * n_pts * b_in + 10.0 * ny * nkx * nz * c8),
         # read the x-transformed fields, write the 10 spectra
-        "zfft_pack": ("byte", 2 * 10.0 * ny * nkx * nz * c16),
+        "zfft_pack": ("byte", 2 * 10.0 * ny * nkx * nz * c8),
         "plane_sums": ("byte", 4.0 * n_pts * b_in),
         # read 8 term spectra of every unordered pair, write 10 kz-transformed maps
         "fin_kz": ("byte", (8 + 10) * float(nk) * npair_u * c16),
@@ -90,6 +93,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--chunk", type=int, default=0, help="0: one chunk for the ensemble")
     ap.add_argument("--snapshots", type=int, default=0, help="override S (0: workload's)")
+    ap.add_argument("--precision", default="", choices=["", "fp64", "bf16x3"],
+                    help="override the rank-k arithmetic of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
     args = ap.parse_args()
@@ -108,6 +113,8 @@ def main():
     w = synth.workload(args.workload)
     if args.snapshots:
         w = synth.workload(args.workload, S=args.snapshots)
+    if args.precision:
+        w = synth.workload(args.workload, S=w.S, precision=args.precision)
     S = w.S
     chunk = args.chunk or (S + (S & 1))
     y = synth.y_grid(w)
@@ -179,7 +186,8 @@ def main():
     dom = max(kernels, key=lambda n: kernels[n]["ms_per_step"])
     dk = kernels[dom]
     if "achieved_tflops" in dk:
-        ach, peak, unit, bound = dk["achieved_tflops"], PEAK["fp64_mfma"], "TFLOP/s", "mfma"
+        peak = PEAK["bf16_mfma" if w.precision == "bf16x3" else "fp64_mfma"]
+        ach, unit, bound = dk["achieved_tflops"], "TFLOP/s", "mfma"
     else:
         ach, peak, unit, bound = dk.get("achieved_gbs", 0.0), PEAK["hbm"], "GB/s", "hbm"
     roof = {"kernel": dom, "bound": bound, "achieved": ach, "peak": peak, "unit": unit,

@@ -47,6 +47,26 @@ struct FftPlanDev {
     int radix[16];
 };
 
+// LDS layout of a batch of transforms of length n: element i of transform b
+// sits at b * fft_stride(n) + pad(i).  One padding slot per 32 elements and an
+// odd stride keep the strided accesses of the passes on distinct banks.
+__host__ __device__ __forceinline__ int fft_pad(int i) { return i + (i >> 5); }
+__host__ __device__ __forceinline__ int fft_stride(int n)
+{
+    const int s = n + (n >> 5) + 1;
+    return s | 1;
+}
+
+// a / d and a % d for 0 <= a < 2^24 through a float reciprocal, corrected
+__device__ __forceinline__ int div_small(int a, int d, float inv_d)
+{
+    int q = (int)((float)a * inv_d);
+    const int r = a - q * d;
+    q += (r >= d) ? 1 : 0;
+    q -= (r < 0) ? 1 : 0;
+    return q;
+}
+
 template <int R, typename T>
 struct Dft;
 
@@ -197,6 +217,108 @@ __device__ cx<T> *lds_fft(cx<T> *a, cx<T> *b, int batch, int bs, const FftPlanDe
         p *= R;
     }
     return src;
+}
+
+// In-place variant for large batches (one LDS buffer): every pass first reads
+// the inputs of all its butterflies into registers, then, after a barrier,
+// writes the outputs.  CAP bounds batch * n and BLOCK the block size, so a
+// thread holds at most ceil(CAP / (R * BLOCK)) butterflies of radix R.
+// Element i of transform b lives at b * bs + fft_pad(i).
+template <int R, typename T, int CAP, int BLOCK>
+__device__ __forceinline__ void stockham_pass_ip(cx<T> *buf, int n, int p, int batch, int bs,
+                                                 const cx<T> *tw, int sign)
+{
+    constexpr int MAXIT = (CAP / R + BLOCK - 1) / BLOCK;
+    const int m = n / R;
+    const int total = batch * m;
+    const int twstep = n / (p * R);
+    const float inv_m = 1.0f / (float)m, inv_p = 1.0f / (float)p;
+    cx<T> v[MAXIT][R];
+    int out0[MAXIT];
+#pragma unroll
+    for (int q = 0; q < MAXIT; ++q) {
+        const int it = threadIdx.x + q * BLOCK;
+        out0[q] = -1;
+        if (it < total) {
+            const int b = div_small(it, m, inv_m);
+            const int i = it - b * m;
+            const int k = i - p * div_small(i, p, inv_p);
+            const cx<T> *s = buf + b * bs;
+#pragma unroll
+            for (int j = 0; j < R; ++j) v[q][j] = s[fft_pad(i + j * m)];
+            if (p > 1) {
+#pragma unroll
+                for (int j = 1; j < R; ++j) {
+                    cx<T> w = tw[j * k * twstep];
+                    if (sign > 0) w.y = -w.y;
+                    v[q][j] = cmul(v[q][j], w);
+                }
+            }
+            Dft<R, T>::run(v[q], sign);
+            out0[q] = (b << 16) | ((i - k) * R + k);   // transform, first output
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXIT; ++q) {
+        if (out0[q] >= 0) {
+            const int o = out0[q] & 0xffff;
+            cx<T> *d = buf + (out0[q] >> 16) * bs;
+#pragma unroll
+            for (int j = 0; j < R; ++j) d[fft_pad(o + j * p)] = v[q][j];
+        }
+    }
+    __syncthreads();
+}
+
+// Copy a twiddle table of n entries into LDS (call before the first pass; the
+// passes' first barrier orders it).
+template <typename T>
+__device__ __forceinline__ void load_twiddles(cx<T> *dst, const cx<T> *src, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// Gather `count` elements, MAXE per thread at a time: the loads of a group are
+// all issued before any is consumed, so a thread keeps MAXE loads in flight.
+// get(e) loads element e, put(e, v) stores it.
+template <int MAXE, int BLOCK, typename V, typename G, typename P>
+__device__ __forceinline__ void gather_batched(int count, G &&get, P &&put)
+{
+    for (int base = 0; base < count; base += MAXE * BLOCK) {
+        V v[MAXE];
+#pragma unroll
+        for (int q = 0; q < MAXE; ++q) {
+            const int e = base + threadIdx.x + q * BLOCK;
+            if (e < count) v[q] = get(e);
+        }
+#pragma unroll
+        for (int q = 0; q < MAXE; ++q) {
+            const int e = base + threadIdx.x + q * BLOCK;
+            if (e < count) put(e, v[q]);
+        }
+    }
+}
+
+// Batched in-place transform: batch transforms of length pl.n, element i of
+// transform b at buf[b * bs + fft_pad(i)] (bs >= fft_stride(n),
+// batch * pl.n <= CAP, blockDim.x == BLOCK).  Ends with a barrier.
+template <typename T, int CAP, int BLOCK>
+__device__ void lds_fft_ip(cx<T> *buf, int batch, int bs, const FftPlanDev &pl,
+                           const cx<T> *tw, int sign)
+{
+    int p = 1;
+    for (int ps = 0; ps < pl.npass; ++ps) {
+        const int R = pl.radix[ps];
+        switch (R) {
+        case 2: stockham_pass_ip<2, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, tw, sign); break;
+        case 3: stockham_pass_ip<3, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, tw, sign); break;
+        case 4: stockham_pass_ip<4, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, tw, sign); break;
+        case 5: stockham_pass_ip<5, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, tw, sign); break;
+        default: stockham_pass_ip<8, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, tw, sign); break;
+        }
+        p *= R;
+    }
 }
 
 }  // namespace gke

@@ -10,10 +10,21 @@
 
 namespace gke {
 
-// fields carried in the spectra, in this order: fluctuations and the six
-// in-plane products formed in physical space (Section "Products instead of
-// correlations")
-enum { F_U = 0, F_V, F_W, F_P, F_UU, F_VV, F_WW, F_UV, F_UW, F_VW, NFIELD };
+// fields carried in the spectra, in this order: the fluctuations and six
+// combinations of the in-plane products formed in physical space (Section
+// "Products instead of correlations"): Q_ij = 2 u'_i u'_j + delta_ij q with
+// q = u'_i u'_i.  q itself is (Q_xx + Q_yy + Q_zz) / 5.
+enum { F_U = 0, F_V, F_W, F_P, F_QXX, F_QYY, F_QZZ, F_QXY, F_QXZ, F_QYZ, NFIELD };
+
+// precision of the cross-spectral update (GKE_PREC_*)
+enum { PREC_FP64 = 0, PREC_BF16X3 = 1 };
+
+// one complex spectral value split for the three-term BF16 products:
+// (re_hi, re_lo, im_hi, im_lo) as BF16 bit patterns, lo = RN(x - hi)
+struct bf16x4 {
+    unsigned int re;  // re_hi | re_lo << 16
+    unsigned int im;  // im_hi | im_lo << 16
+};
 
 // term spectra accumulated per unordered pair tile (see k_rankk.hip)
 enum { S_R = 0, S_FX, S_FY, S_FZ, S_PHI, S_PP, S_UVS, S_UVA, NSPEC };
@@ -30,6 +41,12 @@ enum { MP_Q = 0, MP_UV, MP_PV, MP_QU, MP_QV, MP_QW, MP_GY, NMOMP };
 // pass-1 plane sums are split over this many blocks per plane
 constexpr int NSPLIT = 8;
 
+// LDS transforms: at most FFT_CAP complex FP64 elements per block (128 KiB of
+// the 160 KiB LDS of a gfx950 workgroup), FFT_BLOCK threads per block
+constexpr int FFT_CAP = 8192;
+constexpr int FFT_BLOCK = 1024;
+constexpr size_t LDS_BUDGET = 156 * 1024;
+
 struct Dims {
     int nx, ny, nz;
     int nkx;          // nx/2 + 1
@@ -39,8 +56,11 @@ struct Dims {
     int npair_tiles;  // 256 ntp pairs handled on the matrix cores
     int npair;        // all unordered pairs (tile pairs + remainder pairs)
     int zb, nzb;      // z rows per block in the x pass, number of blocks
-    int jb;           // planes per block in the z pass
+    int jb, njb;      // planes per block in the z pass, number of blocks
+    int pbz;          // pairs per block in the finalize kz pass
+    int ntx;          // complex transforms (two pairs each) per block in the kx pass
     int chunk;        // snapshot slots in the spectra buffer
+    int prec;         // PREC_FP64 or PREC_BF16X3
     double lx, lz, nu;
 };
 
@@ -52,6 +72,8 @@ __host__ __device__ inline int pair_mirror(int code) { return (code >> 24) & 1; 
 struct Tables {
     const cx<double> *twx;   // exp(-2 pi i m/nx)
     const cx<double> *twz;   // exp(-2 pi i m/nz)
+    const cx<float> *twx32;  // the same rounded to FP32
+    const cx<float> *twz32;
     const double *w5;        // [ny][5] five-point weights
     const int *j0;           // [ny] first stencil node
     const int *tile_a;       // [ntp] tile-pair rows
@@ -59,6 +81,20 @@ struct Tables {
     const int *pairs;        // [npair] pair table
     FftPlanDev px, pz;
 };
+
+// twiddle table of the x (which = 0) or z (which = 1) transforms in type T
+template <typename T>
+__device__ __forceinline__ const cx<T> *tw_of(const Tables &t, int which);
+template <>
+__device__ __forceinline__ const cx<double> *tw_of<double>(const Tables &t, int which)
+{
+    return which ? t.twz : t.twx;
+}
+template <>
+__device__ __forceinline__ const cx<float> *tw_of<float>(const Tables &t, int which)
+{
+    return which ? t.twz32 : t.twx32;
+}
 
 // pass 1: plane sums of u~ v~ w~ p~ added into sums[4][ny][NSPLIT]
 hipError_t launch_plane_sums(hipStream_t st, const Dims &d, int f32, const void *u,
@@ -72,18 +108,23 @@ hipError_t launch_shear(hipStream_t st, const Dims &d, const Tables &t, double *
 hipError_t launch_profiles(hipStream_t st, const Dims &d, const double *momp,
                            const double *momg, double count, double *prof);
 
-// pass 2, per snapshot: fluctuations, products, x transforms, moments
+// pass 2, per snapshot: fluctuations, products, x transforms, moments.
+// inter holds cx<double> (FP64 path) or cx<float> (split-BF16 path).
 hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int f32,
                              const void *u, const void *v, const void *w, const void *p,
-                             const double *prof, cx<double> *inter, double *momp);
-// z transforms, packing into the spectra slot, gradient energy
-hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t,
-                            const cx<double> *inter, int slot, cx<double> *spec,
-                            double *momg);
-// cross-spectral rank-k update over the snapshots of one chunk
+                             const double *prof, void *inter, double *momp);
+// z transforms, packing into the spectra slot, gradient energy.  spec holds
+// cx<double> (FP64 path) or bf16x4 (split-BF16 path).
+hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t, const void *inter,
+                            int slot, void *spec, double *momg);
+// cross-spectral rank-k update over the snapshots of one chunk (FP64 MFMA)
 hipError_t launch_rankk_f64(hipStream_t st, const Dims &d, const Tables &t,
                             const cx<double> *spec, int nsnap, int accumulate,
                             cx<double> *acc);
+// the same with split-BF16 three-term MFMA products and FP32 accumulation
+hipError_t launch_rankk_bf16x3(hipStream_t st, const Dims &d, const Tables &t,
+                               const bf16x4 *spec, int nsnap, int accumulate,
+                               cx<double> *acc);
 // finalize: inverse transform along kz of the term spectra of the pairs
 // [p0, p1) of the compact pair index, scaled by 1/count
 hipError_t launch_fin_kz(hipStream_t st, const Dims &d, const Tables &t,

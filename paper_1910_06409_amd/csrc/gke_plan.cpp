@@ -29,15 +29,19 @@ struct gke_plan_s {
 
     // host copies of the tables (kept alive for the async uploads)
     std::vector<cx<double>> h_twx, h_twz;
+    std::vector<cx<float>> h_twx32, h_twz32;
     std::vector<double> h_w5;
     std::vector<int> h_j0, h_ta, h_tb, h_pairs;
 
     // carved device pointers
     cx<double> *twx = nullptr, *twz = nullptr;
+    cx<float> *twx32 = nullptr, *twz32 = nullptr;
     double *w5 = nullptr;
     int *j0 = nullptr, *ta = nullptr, *tb = nullptr, *pairs = nullptr;
     double *sums1 = nullptr, *prof = nullptr, *momp = nullptr, *momg = nullptr;
-    cx<double> *inter = nullptr, *spec = nullptr, *acc = nullptr, *mid = nullptr;
+    void *inter = nullptr;  // cx<double> (FP64) or cx<float> (split-BF16)
+    void *spec = nullptr;   // cx<double> (FP64) or gke::bf16x4 (split-BF16)
+    cx<double> *acc = nullptr, *mid = nullptr;
     gke::Tables tab{};
 
     long long n1 = 0;          // first-scan snapshots
@@ -185,6 +189,8 @@ size_t layout(gke_plan_t p, char *base)
     const int pbt = (p->pair_batch > 0 && p->pair_batch < d.npair) ? p->pair_batch : d.npair;
     p->twx = (cx<double> *)take(sizeof(cx<double>) * d.nx);
     p->twz = (cx<double> *)take(sizeof(cx<double>) * d.nz);
+    p->twx32 = (cx<float> *)take(sizeof(cx<float>) * d.nx);
+    p->twz32 = (cx<float> *)take(sizeof(cx<float>) * d.nz);
     p->w5 = (double *)take(sizeof(double) * 5 * d.ny);
     p->j0 = (int *)take(sizeof(int) * d.ny);
     p->ta = (int *)take(sizeof(int) * std::max(d.ntp, 1));
@@ -194,8 +200,10 @@ size_t layout(gke_plan_t p, char *base)
     p->prof = (double *)take(sizeof(double) * gke::NPROF * d.ny);
     p->momp = (double *)take(sizeof(double) * d.ny * gke::NMOMP * d.nzb);
     p->momg = (double *)take(sizeof(double) * d.ny * 3 * d.nkx);
-    p->inter = (cx<double> *)take(sizeof(cx<double>) * (size_t)d.ny * gke::NFIELD * d.nkx * d.nz);
-    p->spec = (cx<double> *)take(sizeof(cx<double>) * (size_t)d.nk * gke::NFIELD * d.chunk * d.ny);
+    // both split-BF16 buffers hold 8-byte elements (cx<float>, bf16x4)
+    const size_t esz = d.prec == gke::PREC_BF16X3 ? 8 : sizeof(cx<double>);
+    p->inter = take(esz * (size_t)d.ny * d.nzb * gke::NFIELD * d.nkx * d.zb);
+    p->spec = take(esz * (size_t)d.nk * gke::NFIELD * d.chunk * d.ny);
     p->acc = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NSPEC * d.nk * d.npair);
     p->mid = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NMAP * d.nkx * d.nz * pbt);
     return off;
@@ -205,8 +213,12 @@ gke_status launch_flush(gke_plan_t p)
 {
     if (p->pending == 0) return GKE_OK;
     GKE_HIP(p, timed(p, GKE_K_RANKK, [&] {
-        return gke::launch_rankk_f64(p->stream, p->d, p->tab, p->spec, p->pending,
-                                     p->chunks_done > 0 ? 1 : 0, p->acc);
+        const int accumulate = p->chunks_done > 0 ? 1 : 0;
+        if (p->d.prec == gke::PREC_BF16X3)
+            return gke::launch_rankk_bf16x3(p->stream, p->d, p->tab, (const gke::bf16x4 *)p->spec,
+                                            p->pending, accumulate, p->acc);
+        return gke::launch_rankk_f64(p->stream, p->d, p->tab, (const cx<double> *)p->spec,
+                                     p->pending, accumulate, p->acc);
     }));
     ++p->chunks_done;
     p->pending = 0;
@@ -250,20 +262,38 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
     d.lx = Lx;
     d.lz = Lz;
     d.nu = nu;
-    // x pass: zb rows per block, LDS = 2 zb (nx + 1) complex doubles <= 64 KiB
-    d.zb = 8;
-    while (d.zb > 1 && (Nz % d.zb || 2 * (size_t)d.zb * (Nx + 1) * 16 > 65536)) d.zb >>= 1;
-    d.nzb = Nz / d.zb;
-    d.jb = 8;
-    while (d.jb > 1 && 2 * (size_t)d.jb * (Nz + 1) * 16 > 65536) d.jb >>= 1;
-    if (2 * (size_t)(Nx + 1) * 16 > 65536 || 2 * (size_t)(Nz + 1) * 16 > 65536) {
+    // block shapes of the LDS transforms (complex FP64 elements, one buffer)
+    // batch * stride <= cap bounds both the LDS bytes (plus the twiddle table)
+    // and the per-thread work of the register-staged passes
+    const size_t cap = std::min<size_t>(gke::LDS_BUDGET / 16 - std::max(Nx, Nz), gke::FFT_CAP);
+    const size_t sx = gke::fft_stride(Nx), sz = gke::fft_stride(Nz);
+    if (sx * 5 > cap || sz > cap) {
         delete p;
         return fail(nullptr, GKE_ERR_UNSUPPORTED, "transform length too large for one block");
+    }
+    // x pass: 5 complex rows per z row (ten real fields), zb | Nz
+    d.zb = 16;
+    while (d.zb > 1 && (Nz % d.zb || (size_t)5 * d.zb * sx > cap)) d.zb >>= 1;
+    d.nzb = Nz / d.zb;
+    // z pass: planes per block, spread evenly over the blocks
+    {
+        const int jmax = (int)std::min<size_t>(64, cap / sz);
+        d.njb = (Ny + jmax - 1) / jmax;
+        d.jb = (Ny + d.njb - 1) / d.njb;
+    }
+    // finalize: pairs per kz block, complex transforms (2 pairs) per kx block
+    d.pbz = (int)std::min<size_t>(48, cap / sz);
+    d.ntx = (int)std::min<size_t>(16, cap / (sx + 2 * (size_t)d.nkx));
+    if (d.zb < 1 || d.jb < 1 || d.pbz < 1 || d.ntx < 1) {
+        delete p;
+        return fail(nullptr, GKE_ERR_UNSUPPORTED, "grid too large for the LDS transforms");
     }
     d.chunk = p->chunk;
 
     p->h_twx = twiddles(Nx);
     p->h_twz = twiddles(Nz);
+    for (const auto &c : p->h_twx) p->h_twx32.push_back(cx<float>{(float)c.x, (float)c.y});
+    for (const auto &c : p->h_twz) p->h_twz32.push_back(cx<float>{(float)c.x, (float)c.y});
     p->h_w5.assign(5 * (size_t)Ny, 0.0);
     p->h_j0.assign(Ny, 0);
     for (int j = 0; j < Ny; ++j) {
@@ -314,12 +344,11 @@ gke_status gke_set_option(gke_plan_t p, int key, int64_t value)
         p->dtype = (int)value;
         return GKE_OK;
     case GKE_OPT_PRECISION:
-        if (value == GKE_PREC_FP64) {
-            p->prec = (int)value;
-            return GKE_OK;
-        }
-        if (value == GKE_PREC_BF16X3) return fail(p, GKE_ERR_UNSUPPORTED, "split-BF16 not built");
-        return fail(p, GKE_ERR_ARG, "unknown precision");
+        if (value != GKE_PREC_FP64 && value != GKE_PREC_BF16X3)
+            return fail(p, GKE_ERR_ARG, "unknown precision");
+        p->prec = (int)value;
+        p->d.prec = value == GKE_PREC_BF16X3 ? gke::PREC_BF16X3 : gke::PREC_FP64;
+        return GKE_OK;
     case GKE_OPT_CHUNK:
         if (value < 2 || value > 4096 || value % 2)
             return fail(p, GKE_ERR_ARG, "chunk must be even and in [2, 4096]");
@@ -357,6 +386,8 @@ gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
     hipStream_t st = p->stream;
     GKE_HIP(p, hipMemcpyAsync(p->twx, p->h_twx.data(), sizeof(cx<double>) * d.nx, hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->twz, p->h_twz.data(), sizeof(cx<double>) * d.nz, hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->twx32, p->h_twx32.data(), sizeof(cx<float>) * d.nx, hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->twz32, p->h_twz32.data(), sizeof(cx<float>) * d.nz, hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->w5, p->h_w5.data(), sizeof(double) * 5 * d.ny, hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->j0, p->h_j0.data(), sizeof(int) * d.ny, hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->ta, p->h_ta.data(), sizeof(int) * p->h_ta.size(), hipMemcpyHostToDevice, st));
@@ -367,6 +398,8 @@ gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
     GKE_HIP(p, hipStreamSynchronize(st));
     p->tab.twx = p->twx;
     p->tab.twz = p->twz;
+    p->tab.twx32 = p->twx32;
+    p->tab.twz32 = p->twz32;
     p->tab.w5 = p->w5;
     p->tab.j0 = p->j0;
     p->tab.tile_a = p->ta;

@@ -15,53 +15,62 @@
 
 namespace gke {
 
-// Inverse transform along kz for PB pairs of one term spectrum at one kx.
+template <typename F>
+static void set_lds_limit(F *kernel)
+{
+    (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)LDS_BUDGET);
+}
+
+// Inverse transform along kz for pb pairs of one term spectrum at one kx.
 // mid layout: [NMAP][nkx][nz (rz)][ptot (pairs of this batch)].
-__global__ __launch_bounds__(256) void k_fin_kz(const cx<double> *__restrict__ acc, Dims d,
-                                                Tables t, int p0, int ptot, int pb,
-                                                double inv_count, cx<double> *__restrict__ mid)
+__global__ __launch_bounds__(FFT_BLOCK) void k_fin_kz(const cx<double> *__restrict__ acc, Dims d,
+                                                      Tables t, int p0, int ptot,
+                                                      double inv_count,
+                                                      cx<double> *__restrict__ mid)
 {
     extern __shared__ cx<double> lds[];
-    const int nz = d.nz, nkx = d.nkx;
+    const int nz = d.nz, nkx = d.nkx, pb = d.pbz;
     const int pblk = blockIdx.x, kx = blockIdx.y, sp = blockIdx.z;
     const int pl0 = pblk * pb;                       // first pair within the batch
     const int np = min(pb, ptot - pl0);
     const size_t pall = (size_t)d.npair;
     const size_t pg0 = (size_t)p0 + pl0;             // first pair within acc
-    const int bs = nz + 1;
-    cx<double> *A = lds;
-    cx<double> *B = lds + pb * bs;
+    const int bs = fft_stride(nz);
     const double two_pi = 6.283185307179586476925286766559;
     const double alpha = (2 * kx == d.nx) ? 0.0 : two_pi * kx / d.lx;
     const int nout_tr = (sp == S_R) ? 2 : 1;
+    cx<double> *tw = lds + pb * bs;
+    load_twiddles(tw, t.twz, nz);
     for (int tr = 0; tr < nout_tr; ++tr) {
-        for (int e = threadIdx.x; e < nz * pb; e += blockDim.x) {
-            const int kz = e / pb, b = e - kz * pb;
-            if (b < np) {
-                cx<double> X = cscale(acc[((size_t)sp * d.nk + (size_t)kx * nz + kz) * pall + pg0 + b],
-                                      inv_count);
+        gather_batched<4, FFT_BLOCK, cx<double>>(
+            nz * np,
+            [&](int e) {
+                const int kz = e / np, b = e - kz * np;
+                return acc[((size_t)sp * d.nk + (size_t)kx * nz + kz) * pall + pg0 + b];
+            },
+            [&](int e, cx<double> X) {
+                const int kz = e / np, b = e - kz * np;
+                X = cscale(X, inv_count);
                 if (tr == 1) {  // i beta R^
                     const int kzs = (kz <= nz / 2) ? kz : kz - nz;
                     const double beta = (2 * kz == nz) ? 0.0 : two_pi * kzs / d.lz;
                     X = cx<double>{-beta * X.y, beta * X.x};
                 }
-                A[b * bs + kz] = X;
-            }
-        }
+                lds[b * bs + fft_pad(kz)] = X;
+            });
         __syncthreads();
-        const cx<double> *R = lds_fft<double>(A, B, np, bs, t.pz, t.twz, +1);
+        lds_fft_ip<double, FFT_CAP, FFT_BLOCK>(lds, np, bs, t.pz, tw, +1);
         int m0;
         if (sp == S_R) m0 = (tr == 0) ? M_R : M_DRZ;
         else m0 = M_FX + (sp - S_FX);  // FX FY FZ PHI PP UVS UVA map one to one
-        for (int e = threadIdx.x; e < nz * pb; e += blockDim.x) {
-            const int rz = e / pb, b = e - rz * pb;
-            if (b < np) {
-                const cx<double> Y = R[b * bs + rz];
-                const size_t o = ((size_t)kx * nz + rz) * ptot + pl0 + b;
-                mid[(size_t)m0 * nkx * nz * ptot + o] = Y;
-                if (sp == S_R && tr == 0)  // i alpha R^: alpha is constant along kz
-                    mid[(size_t)M_DRX * nkx * nz * ptot + o] = cx<double>{-alpha * Y.y, alpha * Y.x};
-            }
+        for (int e = threadIdx.x; e < nz * np; e += blockDim.x) {
+            const int rz = e / np, b = e - rz * np;
+            const cx<double> Y = lds[b * bs + fft_pad(rz)];
+            const size_t o = ((size_t)kx * nz + rz) * ptot + pl0 + b;
+            mid[(size_t)m0 * nkx * nz * ptot + o] = Y;
+            if (sp == S_R && tr == 0)  // i alpha R^: alpha is constant along kz
+                mid[(size_t)M_DRX * nkx * nz * ptot + o] = cx<double>{-alpha * Y.y, alpha * Y.x};
         }
         __syncthreads();
     }
@@ -72,11 +81,10 @@ hipError_t launch_fin_kz(hipStream_t st, const Dims &d, const Tables &t,
                          cx<double> *mid)
 {
     const int ptot = p1 - p0;
-    int pb = 8;
-    while (pb > 1 && sizeof(cx<double>) * 2 * (size_t)pb * (d.nz + 1) > 65536) pb >>= 1;
-    const size_t lds = sizeof(cx<double>) * 2 * (size_t)pb * (d.nz + 1);
-    dim3 grid((ptot + pb - 1) / pb, d.nkx, NSPEC);
-    hipLaunchKernelGGL(k_fin_kz, grid, dim3(256), lds, st, acc, d, t, p0, ptot, pb, inv_count,
+    const size_t lds = sizeof(cx<double>) * ((size_t)d.pbz * fft_stride(d.nz) + d.nz);
+    dim3 grid((ptot + d.pbz - 1) / d.pbz, d.nkx, NSPEC);
+    set_lds_limit(k_fin_kz);
+    hipLaunchKernelGGL(k_fin_kz, grid, dim3(FFT_BLOCK), lds, st, acc, d, t, p0, ptot, inv_count,
                        mid);
     return hipGetLastError();
 }
@@ -142,28 +150,34 @@ __device__ __forceinline__ void assemble_store(int m, double val, int j1, int j2
 // Inverse real transform along kx of 2*nt pairs (two real maps per complex
 // transform), then assembly for pair (Y1, Y2) and, when the pair table asks
 // for it, the mirrored pair (Y2, Y1) from r -> -r.
-__global__ __launch_bounds__(256) void k_fin_kx(const cx<double> *__restrict__ mid, Dims d,
-                                                Tables t, int p0, int ptot, int nt,
-                                                const double *__restrict__ prof, OutPtrs out)
+__global__ __launch_bounds__(FFT_BLOCK) void k_fin_kx(const cx<double> *__restrict__ mid, Dims d,
+                                                      Tables t, int p0, int ptot,
+                                                      const double *__restrict__ prof,
+                                                      OutPtrs out)
 {
     extern __shared__ cx<double> lds[];
-    const int nx = d.nx, nz = d.nz, nkx = d.nkx, ny = d.ny;
+    const int nx = d.nx, nz = d.nz, nkx = d.nkx, ny = d.ny, nt = d.ntx;
     const int npair = 2 * nt;
     const int pblk = blockIdx.x, rz = blockIdx.y, m = blockIdx.z;
     const int pl0 = pblk * npair;
     const int np = min(npair, ptot - pl0);
-    const int bs = nx + 1;
-    const int bsz = max(nt * bs, nkx * npair);
-    cx<double> *A = lds;
-    cx<double> *S = lds + nt * bs;   // staging, then FFT scratch
-    for (int e = threadIdx.x; e < nkx * npair; e += blockDim.x) {
-        const int kx = e / npair, b = e - kx * npair;
-        S[kx * npair + b] = (b < np) ? mid[(((size_t)m * nkx + kx) * nz + rz) * ptot + pl0 + b]
-                                     : cx<double>{0.0, 0.0};
-    }
+    const int bs = fft_stride(nx);
+    cx<double> *A = lds;                      // nt transforms of length nx
+    cx<double> *S = lds + nt * bs;            // staging [kx][pair]
+    cx<double> *tw = S + nkx * npair;         // twiddles
+    load_twiddles(tw, t.twx, nx);
+    gather_batched<4, FFT_BLOCK, cx<double>>(
+        nkx * npair,
+        [&](int e) {
+            const int kx = e / npair, b = e - kx * npair;
+            return (b < np) ? mid[(((size_t)m * nkx + kx) * nz + rz) * ptot + pl0 + b]
+                            : cx<double>{0.0, 0.0};
+        },
+        [&](int e, cx<double> x) { S[e] = x; });
     __syncthreads();
+    // consecutive threads take consecutive transforms: bank-friendly reads of S
     for (int e = threadIdx.x; e < nt * nx; e += blockDim.x) {
-        const int c = e / nx, n = e - c * nx;
+        const int n = e / nt, c = e - n * nt;
         cx<double> xa, xb;
         if (n <= nx / 2) {
             xa = S[n * npair + 2 * c];
@@ -172,11 +186,10 @@ __global__ __launch_bounds__(256) void k_fin_kx(const cx<double> *__restrict__ m
             xa = cconj(S[(nx - n) * npair + 2 * c]);
             xb = cconj(S[(nx - n) * npair + 2 * c + 1]);
         }
-        A[c * bs + n] = cx<double>{xa.x - xb.y, xa.y + xb.x};  // xa + i xb
+        A[c * bs + fft_pad(n)] = cx<double>{xa.x - xb.y, xa.y + xb.x};  // xa + i xb
     }
     __syncthreads();
-    const cx<double> *R = lds_fft<double>(A, S, nt, bs, t.px, t.twx, +1);
-    (void)bsz;
+    lds_fft_ip<double, FFT_CAP, FFT_BLOCK>(A, nt, bs, t.px, tw, +1);
     const double sig = map_sigma(m);
     const size_t plane = (size_t)nz * nkx;
     for (int e = threadIdx.x; e < np * nkx; e += blockDim.x) {
@@ -184,13 +197,13 @@ __global__ __launch_bounds__(256) void k_fin_kx(const cx<double> *__restrict__ m
         const int code = t.pairs[p0 + pl0 + b];
         const int j1 = pair_j1(code), j2 = pair_j2(code);
         const int c = b >> 1;
-        const cx<double> zv = R[c * bs + rx];
+        const cx<double> zv = A[c * bs + fft_pad(rx)];
         const double val = (b & 1) ? zv.y : zv.x;
         assemble_store(m, val, j1, j2, prof, ny, d.nu, out,
                        ((size_t)j1 * ny + j2) * plane + (size_t)rz * nkx + rx);
         if (pair_mirror(code)) {
             const int rxm = (rx == 0) ? 0 : nx - rx;
-            const cx<double> zm = R[c * bs + rxm];
+            const cx<double> zm = A[c * bs + fft_pad(rxm)];
             const double vm = sig * ((b & 1) ? zm.y : zm.x);
             const int rzm = (rz == 0) ? 0 : nz - rz;
             assemble_store(m, vm, j2, j1, prof, ny, d.nu, out,
@@ -204,16 +217,13 @@ hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
                          double *const *out)
 {
     const int ptot = p1 - p0;
-    int nt = 8;
-    auto need = [&](int n) {
-        return sizeof(cx<double>) * ((size_t)n * (d.nx + 1) +
-                                     std::max((size_t)n * (d.nx + 1), (size_t)d.nkx * 2 * n));
-    };
-    while (nt > 1 && need(nt) > 65536) nt >>= 1;
+    const size_t lds = sizeof(cx<double>) *
+                       ((size_t)d.ntx * fft_stride(d.nx) + (size_t)d.nkx * 2 * d.ntx + d.nx);
     OutPtrs op;
     for (int i = 0; i < 14; ++i) op.t[i] = out[i];
-    dim3 grid((ptot + 2 * nt - 1) / (2 * nt), d.nz, NMAP);
-    hipLaunchKernelGGL(k_fin_kx, grid, dim3(256), need(nt), st, mid, d, t, p0, ptot, nt, prof, op);
+    dim3 grid((ptot + 2 * d.ntx - 1) / (2 * d.ntx), d.nz, NMAP);
+    set_lds_limit(k_fin_kx);
+    hipLaunchKernelGGL(k_fin_kx, grid, dim3(FFT_BLOCK), lds, st, mid, d, t, p0, ptot, prof, op);
     return hipGetLastError();
 }
 

@@ -9,10 +9,11 @@
 // paper uses to defer derivatives, Section "General structure of the program").
 //
 // Per wavenumber k this is a complex rank-K update over the snapshots with the
-// wall-normal planes as rows and columns.  With q = u'_i u'_i and
-// Q_ij = 2 u'_i u'_j + delta_ij q, the eight term spectra needed per ordered
-// pair (Y1, Y2) are built from nine accumulators c0..c8 of products
-// conj(L(Y1)) R(Y2) (27 complex products per pair and snapshot):
+// wall-normal planes as rows and columns.  The spectra hold the fluctuations
+// and Q_ij = 2 u'_i u'_j + delta_ij q (q = u'_i u'_i = (Q_xx + Q_yy + Q_zz)/5);
+// the eight term spectra needed per ordered pair (Y1, Y2) are built from nine
+// accumulators c0..c8 of products conj(L(Y1)) R(Y2) (27 complex products per
+// pair and snapshot):
 //   c0 = sum_i (u_i, u_i)                          -> R^      (scale energy)
 //   c1 = sum_i (Q_ix, u_i) - (u_i, Q_ix)           -> <du^2 du>  spectrum
 //   c2 = sum_i (Q_iz, u_i) - (u_i, Q_iz)           -> <du^2 dw>  spectrum
@@ -38,7 +39,7 @@
 //   so sum_k A B = Re/Im of conj(L) R.
 //   D (lane l, register v): element (Y1 = 16a + l/16 + 4v, Y2 = 16b + l%16)
 //   (checked on the device: the f64 form strides the rows by 4 across registers).
-#include "gke_internal.h"
+#include "rankk_common.h"
 
 namespace gke {
 
@@ -49,41 +50,6 @@ typedef double d4 __attribute__((ext_vector_type(4)));
         ar[c] = __builtin_amdgcn_mfma_f64_16x16x4f64((a), (br), ar[c], 0, 0, 0); \
         ai[c] = __builtin_amdgcn_mfma_f64_16x16x4f64((a), (bi), ai[c], 0, 0, 0); \
     } while (0)
-
-// Store the eight term spectra of one element from the nine accumulators.
-__device__ __forceinline__ void store_spectra(cx<double> *acc, size_t sp_stride, size_t o,
-                                              const double *cr, const double *ci,
-                                              int accumulate)
-{
-    double sr[NSPEC], si[NSPEC];
-    sr[S_R] = cr[0];
-    si[S_R] = ci[0];
-    sr[S_FX] = cr[1];
-    si[S_FX] = ci[1];
-    sr[S_FY] = cr[3] - cr[4];
-    si[S_FY] = ci[3] - ci[4];
-    sr[S_FZ] = cr[2];
-    si[S_FZ] = ci[2];
-    sr[S_PHI] = 2.0 * cr[5] - cr[3] - cr[4];
-    si[S_PHI] = 2.0 * ci[5] - ci[3] - ci[4];
-    sr[S_PP] = cr[6];
-    si[S_PP] = ci[6];
-    sr[S_UVS] = cr[7] + cr[8];
-    si[S_UVS] = ci[7] + ci[8];
-    sr[S_UVA] = cr[8] - cr[7];
-    si[S_UVA] = ci[8] - ci[7];
-#pragma unroll
-    for (int sp = 0; sp < NSPEC; ++sp) {
-        cx<double> *dst = acc + sp * sp_stride + o;
-        cx<double> val = cx<double>{sr[sp], si[sp]};
-        if (accumulate) {
-            const cx<double> old = *dst;
-            val.x += old.x;
-            val.y += old.y;
-        }
-        *dst = val;
-    }
-}
 
 struct Operands {
     double L[NFIELD];
@@ -155,11 +121,9 @@ __global__ __launch_bounds__(64) void k_rankk_f64(const cx<double> *__restrict__
 #pragma unroll
         for (int f = 0; f < NFIELD; ++f) Lc[f] = ok ? cur.L[f] : 0.0;
         const double lu = Lc[F_U], lv = Lc[F_V], lw = Lc[F_W], lp = Lc[F_P];
-        const double lq = Lc[F_UU] + Lc[F_VV] + Lc[F_WW];
-        const double lQxx = 2.0 * Lc[F_UU] + lq, lQyy = 2.0 * Lc[F_VV] + lq;
-        const double lQzz = 2.0 * Lc[F_WW] + lq;
-        const double lQxy = 2.0 * Lc[F_UV], lQxz = 2.0 * Lc[F_UW];
-        const double lQyz = 2.0 * Lc[F_VW];
+        const double lQxx = Lc[F_QXX], lQyy = Lc[F_QYY], lQzz = Lc[F_QZZ];
+        const double lQxy = Lc[F_QXY], lQxz = Lc[F_QXZ], lQyz = Lc[F_QYZ];
+        const double lq = 0.2 * (lQxx + lQyy + lQzz);
         const double nu_ = -lu, nv = -lv, nw = -lw;
         // right operand (planes Y2): real-output and imaginary-output forms
         double br[NFIELD], bi[NFIELD];
@@ -168,14 +132,14 @@ __global__ __launch_bounds__(64) void k_rankk_f64(const cx<double> *__restrict__
             br[f] = ri ? cur.R[f].y : cur.R[f].x;
             bi[f] = ri ? -cur.R[f].x : cur.R[f].y;
         }
-        const double rqr = br[F_UU] + br[F_VV] + br[F_WW];
-        const double rqi = bi[F_UU] + bi[F_VV] + bi[F_WW];
-        const double rQxxr = 2.0 * br[F_UU] + rqr, rQxxi = 2.0 * bi[F_UU] + rqi;
-        const double rQyyr = 2.0 * br[F_VV] + rqr, rQyyi = 2.0 * bi[F_VV] + rqi;
-        const double rQzzr = 2.0 * br[F_WW] + rqr, rQzzi = 2.0 * bi[F_WW] + rqi;
-        const double rQxyr = 2.0 * br[F_UV], rQxyi = 2.0 * bi[F_UV];
-        const double rQxzr = 2.0 * br[F_UW], rQxzi = 2.0 * bi[F_UW];
-        const double rQyzr = 2.0 * br[F_VW], rQyzi = 2.0 * bi[F_VW];
+        const double rQxxr = br[F_QXX], rQxxi = bi[F_QXX];
+        const double rQyyr = br[F_QYY], rQyyi = bi[F_QYY];
+        const double rQzzr = br[F_QZZ], rQzzi = bi[F_QZZ];
+        const double rQxyr = br[F_QXY], rQxyi = bi[F_QXY];
+        const double rQxzr = br[F_QXZ], rQxzi = bi[F_QXZ];
+        const double rQyzr = br[F_QYZ], rQyzi = bi[F_QYZ];
+        const double rqr = 0.2 * (rQxxr + rQyyr + rQzzr);
+        const double rqi = 0.2 * (rQxxi + rQyyi + rQzzi);
         const double ur = br[F_U], ui = bi[F_U], vr = br[F_V], vi = bi[F_V];
         const double wr = br[F_W], wi = bi[F_W], pr = br[F_P], pi = bi[F_P];
 
@@ -225,65 +189,6 @@ __global__ __launch_bounds__(64) void k_rankk_f64(const cx<double> *__restrict__
     }
 }
 
-// Pairs that involve the last Ny mod 16 planes: one thread per (k, pair), FP64
-// vector arithmetic.  pairs[i] = j1 | j2 << 12 for compact index P = P0 + i.
-__global__ __launch_bounds__(64) void k_rankk_rem_f64(const cx<double> *__restrict__ spec, Dims d,
-                                                      const int *__restrict__ pairs, int nrem,
-                                                      int nsnap, int accumulate,
-                                                      cx<double> *__restrict__ acc)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
-    if (i >= nrem) return;
-    const int code = pairs[d.npair_tiles + i];
-    const int j1 = code & 4095, j2 = (code >> 12) & 4095;
-    const size_t fstride = (size_t)d.chunk * d.ny;
-    const cx<double> *kb = spec + (size_t)k * NFIELD * fstride;
-    double cr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ci[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int s = 0; s < nsnap; ++s) {
-        cx<double> A[NFIELD], B[NFIELD];
-#pragma unroll
-        for (int f = 0; f < NFIELD; ++f) {
-            A[f] = kb[f * fstride + (size_t)s * d.ny + j1];
-            B[f] = kb[f * fstride + (size_t)s * d.ny + j2];
-        }
-        auto derive = [](const cx<double> *F, cx<double> *q, cx<double> *Q) {
-            q->x = F[F_UU].x + F[F_VV].x + F[F_WW].x;
-            q->y = F[F_UU].y + F[F_VV].y + F[F_WW].y;
-            // Q: xx yy zz xy xz yz
-            Q[0] = cx<double>{2.0 * F[F_UU].x + q->x, 2.0 * F[F_UU].y + q->y};
-            Q[1] = cx<double>{2.0 * F[F_VV].x + q->x, 2.0 * F[F_VV].y + q->y};
-            Q[2] = cx<double>{2.0 * F[F_WW].x + q->x, 2.0 * F[F_WW].y + q->y};
-            Q[3] = cx<double>{2.0 * F[F_UV].x, 2.0 * F[F_UV].y};
-            Q[4] = cx<double>{2.0 * F[F_UW].x, 2.0 * F[F_UW].y};
-            Q[5] = cx<double>{2.0 * F[F_VW].x, 2.0 * F[F_VW].y};
-        };
-        cx<double> qa, qb, Qa[6], Qb[6];
-        derive(A, &qa, Qa);
-        derive(B, &qb, Qb);
-        // conj(a) b accumulated into channel c with sign sg
-        auto mac = [&](int c, cx<double> a, cx<double> b, double sg) {
-            cr[c] += sg * (a.x * b.x + a.y * b.y);
-            ci[c] += sg * (a.x * b.y - a.y * b.x);
-        };
-        const cx<double> ua = A[F_U], va = A[F_V], wa = A[F_W], pa = A[F_P];
-        const cx<double> ub = B[F_U], vb = B[F_V], wb = B[F_W], pb = B[F_P];
-        mac(0, ua, ub, 1.0); mac(0, va, vb, 1.0); mac(0, wa, wb, 1.0);
-        mac(1, Qa[0], ub, 1.0); mac(1, Qa[3], vb, 1.0); mac(1, Qa[4], wb, 1.0);
-        mac(1, ua, Qb[0], -1.0); mac(1, va, Qb[3], -1.0); mac(1, wa, Qb[4], -1.0);
-        mac(2, Qa[4], ub, 1.0); mac(2, Qa[5], vb, 1.0); mac(2, Qa[2], wb, 1.0);
-        mac(2, ua, Qb[4], -1.0); mac(2, va, Qb[5], -1.0); mac(2, wa, Qb[2], -1.0);
-        mac(3, Qa[3], ub, 1.0); mac(3, Qa[1], vb, 1.0); mac(3, Qa[5], wb, 1.0);
-        mac(4, ua, Qb[3], 1.0); mac(4, va, Qb[1], 1.0); mac(4, wa, Qb[5], 1.0);
-        mac(5, va, qb, 1.0); mac(5, qa, vb, 1.0);
-        mac(6, pa, vb, 1.0); mac(6, va, pb, 1.0);
-        mac(7, ua, vb, 1.0);
-        mac(8, va, ub, 1.0);
-    }
-    store_spectra(acc, (size_t)d.nk * d.npair, (size_t)k * d.npair + d.npair_tiles + i, cr, ci,
-                  accumulate);
-}
-
 hipError_t launch_rankk_f64(hipStream_t st, const Dims &d, const Tables &t,
                             const cx<double> *spec, int nsnap, int accumulate,
                             cx<double> *acc)
@@ -297,12 +202,7 @@ hipError_t launch_rankk_f64(hipStream_t st, const Dims &d, const Tables &t,
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const int nrem = d.npair - d.npair_tiles;
-    if (nrem > 0) {
-        hipLaunchKernelGGL(k_rankk_rem_f64, dim3((nrem + 63) / 64, d.nk), dim3(64), 0, st, spec,
-                           d, t.pairs, nrem, nsnap, accumulate, acc);
-    }
-    return hipGetLastError();
+    return launch_rankk_rem(st, d, t, spec, nsnap, accumulate, acc);
 }
 
 }  // namespace gke

@@ -11,23 +11,8 @@
 
 namespace gke {
 
-__device__ __forceinline__ double field_value(int f, double a, double b, double c, double d)
-{
-    switch (f) {
-    case F_U: return a;
-    case F_V: return b;
-    case F_W: return c;
-    case F_P: return d;
-    case F_UU: return a * a;
-    case F_VV: return b * b;
-    case F_WW: return c * c;
-    case F_UV: return a * b;
-    case F_UW: return a * c;
-    default: return b * c;  // F_VW
-    }
-}
-
-__device__ __forceinline__ double block_sum256(double v, double *sh)
+// Sum over the block in a fixed order; result valid on thread 0.
+__device__ __forceinline__ double block_sum_fixed(double v, double *sh)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -40,170 +25,226 @@ __device__ __forceinline__ double block_sum256(double v, double *sh)
     return r;
 }
 
-// One block = zb consecutive z rows of plane j.
-//   inter[j][f][kx][z]: x-transformed rows (unnormalised) of the ten fields
-//   momp[j][k][zblk]: FP64 partial sums of q uv pv qu qv qw and (dy u')^2
-template <typename TI>
-__global__ __launch_bounds__(256) void k_fluct_xfft(const TI *__restrict__ u,
-                                                    const TI *__restrict__ v,
-                                                    const TI *__restrict__ w,
-                                                    const TI *__restrict__ p,
-                                                    const double *__restrict__ prof, Dims d,
-                                                    Tables t, cx<double> *__restrict__ inter,
-                                                    double *__restrict__ momp)
+template <typename F>
+static void set_lds_limit(F *kernel)
 {
-    extern __shared__ cx<double> lds[];
-    __shared__ double sh[8];
+    (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)LDS_BUDGET);
+}
+
+// BF16 helpers for the split spectra: round to nearest even (finite inputs)
+__device__ __forceinline__ unsigned int bf16_rn_bits(float x)
+{
+    unsigned int u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_bits_to_float(unsigned int h) { return __uint_as_float(h << 16); }
+// x ~ hi + lo with hi = RN_bf16(x), lo = RN_bf16(x - hi); packed hi | lo << 16
+__device__ __forceinline__ unsigned int split_bf16(float x)
+{
+    const unsigned int h = bf16_rn_bits(x);
+    const unsigned int l = bf16_rn_bits(x - bf16_bits_to_float(h));
+    return h | (l << 16);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_spec(cx<double> *spec, size_t i, cx<T> X) { spec[i] = cx<double>{X.x, X.y}; }
+template <typename T>
+__device__ __forceinline__ void store_spec(bf16x4 *spec, size_t i, cx<T> X)
+{
+    spec[i] = bf16x4{split_bf16((float)X.x), split_bf16((float)X.y)};
+}
+
+// One block = zb consecutive z rows of plane j.  One pass over the inputs:
+// fluctuations (FP64), the ten real fields u v w p Qxx Qyy Qzz Qxy Qxz Qyz
+// packed two per complex row into LDS, FP64 one-point partial sums and the
+// wall-normal gradient energy; then one batched transform (type T) of the
+// 5 zb complex rows along x.
+//   inter[j][zblk][f][kx][row]: x-transformed rows (unnormalised); each block
+//   writes one contiguous chunk
+//   momp[j][k][zblk]: FP64 partial sums of q uv pv qu qv qw and (dy u')^2
+template <typename TI, typename T>
+__global__ __launch_bounds__(FFT_BLOCK) void k_fluct_xfft(const TI *__restrict__ u,
+                                                          const TI *__restrict__ v,
+                                                          const TI *__restrict__ w,
+                                                          const TI *__restrict__ p,
+                                                          const double *__restrict__ prof,
+                                                          Dims d, Tables t,
+                                                          cx<T> *__restrict__ inter,
+                                                          double *__restrict__ momp)
+{
+    extern __shared__ unsigned char lds_raw[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
+    __shared__ double sh[FFT_BLOCK / 64];
     const int nx = d.nx, ny = d.ny, nz = d.nz, nkx = d.nkx, zb = d.zb;
     const int zblk = blockIdx.x, j = blockIdx.y;
     const int z0 = zblk * zb;
-    const int bs = nx + 1;
-    cx<double> *A = lds;
-    cx<double> *B = lds + zb * bs;
+    const int bs = fft_stride(nx);
     const size_t npl = (size_t)nx * nz;
     const size_t off = (size_t)j * npl + (size_t)z0 * nx;
     const double U = prof[P_U * ny + j], V = prof[P_V * ny + j];
     const double W = prof[P_W * ny + j], P = prof[P_P * ny + j];
     const int nel = zb * nx;
-
-    // one-point moments and the wall-normal gradient energy (FP64)
-    {
-        const int js = t.j0[j];
-        double wt[5], Ms[3][5];
-        for (int a = 0; a < 5; ++a) {
-            wt[a] = t.w5[j * 5 + a];
-            Ms[0][a] = prof[P_U * ny + js + a];
-            Ms[1][a] = prof[P_V * ny + js + a];
-            Ms[2][a] = prof[P_W * ny + js + a];
-        }
-        double mq = 0, muv = 0, mpv = 0, mqu = 0, mqv = 0, mqw = 0, mgy = 0;
-        for (int e = threadIdx.x; e < nel; e += blockDim.x) {
-            const double a = (double)u[off + e] - U, b = (double)v[off + e] - V;
-            const double c = (double)w[off + e] - W, dd = (double)p[off + e] - P;
-            const double q = a * a + b * b + c * c;
-            mq += q;
-            muv += a * b;
-            mpv += dd * b;
-            mqu += q * a;
-            mqv += q * b;
-            mqw += q * c;
-            double gu = 0, gv = 0, gw = 0;
-            for (int k = 0; k < 5; ++k) {
-                const size_t o = (size_t)(js + k) * npl + (size_t)z0 * nx + e;
-                gu += wt[k] * ((double)u[o] - Ms[0][k]);
-                gv += wt[k] * ((double)v[o] - Ms[1][k]);
-                gw += wt[k] * ((double)w[o] - Ms[2][k]);
-            }
-            mgy += gu * gu + gv * gv + gw * gw;
-        }
-        const double parts[NMOMP] = {mq, muv, mpv, mqu, mqv, mqw, mgy};
-        for (int k = 0; k < NMOMP; ++k) {
-            const double r = block_sum256(parts[k], sh);
-            if (threadIdx.x == 0) momp[((size_t)j * NMOMP + k) * d.nzb + zblk] += r;
-        }
+    const int js = t.j0[j];
+    double wt[5], Ms[3][5];
+    for (int a = 0; a < 5; ++a) {
+        wt[a] = t.w5[j * 5 + a];
+        Ms[0][a] = prof[P_U * ny + js + a];
+        Ms[1][a] = prof[P_V * ny + js + a];
+        Ms[2][a] = prof[P_W * ny + js + a];
     }
-
-    // five complex pairs of real fields: (u,v) (w,p) (uu,vv) (ww,uv) (uw,vw)
-    for (int pr = 0; pr < NFIELD / 2; ++pr) {
-        const int fa = 2 * pr, fb = 2 * pr + 1;
-        for (int e = threadIdx.x; e < nel; e += blockDim.x) {
-            const double a = (double)u[off + e] - U, b = (double)v[off + e] - V;
-            const double c = (double)w[off + e] - W, dd = (double)p[off + e] - P;
-            const int row = e / nx, x = e - row * nx;
-            A[row * bs + x] = cx<double>{field_value(fa, a, b, c, dd), field_value(fb, a, b, c, dd)};
+    double mq = 0, muv = 0, mpv = 0, mqu = 0, mqv = 0, mqw = 0, mgy = 0;
+    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+        const double a = (double)u[off + e] - U, b = (double)v[off + e] - V;
+        const double c = (double)w[off + e] - W, dd = (double)p[off + e] - P;
+        const double q = a * a + b * b + c * c;
+        mq += q;
+        muv += a * b;
+        mpv += dd * b;
+        mqu += q * a;
+        mqv += q * b;
+        mqw += q * c;
+        double gu = 0, gv = 0, gw = 0;
+        for (int k = 0; k < 5; ++k) {
+            const size_t o = (size_t)(js + k) * npl + (size_t)z0 * nx + e;
+            gu += wt[k] * ((double)u[o] - Ms[0][k]);
+            gv += wt[k] * ((double)v[o] - Ms[1][k]);
+            gw += wt[k] * ((double)w[o] - Ms[2][k]);
         }
-        __syncthreads();
-        const cx<double> *R = lds_fft<double>(A, B, zb, bs, t.px, t.twx, -1);
-        // split the two real transforms: Fa = (Z(k) + conj Z(-k))/2, Fb = (Z(k) - conj Z(-k))/(2i)
-        for (int e = threadIdx.x; e < nkx * zb; e += blockDim.x) {
-            const int k = e / zb, row = e - k * zb;
-            const cx<double> Z = R[row * bs + k];
-            const cx<double> Zc = cconj(R[row * bs + (k == 0 ? 0 : nx - k)]);
-            const cx<double> Fa = cx<double>{0.5 * (Z.x + Zc.x), 0.5 * (Z.y + Zc.y)};
-            const cx<double> Fb = cx<double>{0.5 * (Z.y - Zc.y), -0.5 * (Z.x - Zc.x)};
-            inter[(((size_t)j * NFIELD + fa) * nkx + k) * nz + z0 + row] = Fa;
-            inter[(((size_t)j * NFIELD + fb) * nkx + k) * nz + z0 + row] = Fb;
-        }
-        __syncthreads();
+        mgy += gu * gu + gv * gv + gw * gw;
+        // (u,v) (w,p) (Qxx,Qyy) (Qzz,Qxy) (Qxz,Qyz), two real rows per complex row
+        const int row = e / nx, x = fft_pad(e - row * nx);
+        lds[(0 * zb + row) * bs + x] = cx<T>{(T)a, (T)b};
+        lds[(1 * zb + row) * bs + x] = cx<T>{(T)c, (T)dd};
+        lds[(2 * zb + row) * bs + x] = cx<T>{(T)(2.0 * a * a + q), (T)(2.0 * b * b + q)};
+        lds[(3 * zb + row) * bs + x] = cx<T>{(T)(2.0 * c * c + q), (T)(2.0 * a * b)};
+        lds[(4 * zb + row) * bs + x] = cx<T>{(T)(2.0 * a * c), (T)(2.0 * b * c)};
     }
+    const double parts[NMOMP] = {mq, muv, mpv, mqu, mqv, mqw, mgy};
+    for (int k = 0; k < NMOMP; ++k) {
+        const double r = block_sum_fixed(parts[k], sh);
+        if (threadIdx.x == 0) momp[((size_t)j * NMOMP + k) * d.nzb + zblk] += r;
+    }
+    cx<T> *tw = lds + 5 * zb * bs;
+    load_twiddles(tw, tw_of<T>(t, 0), nx);
+    __syncthreads();
+    lds_fft_ip<T, FFT_CAP, FFT_BLOCK>(lds, 5 * zb, bs, t.px, tw, -1);
+    // split the two real transforms: Fa = (Z(k) + conj Z(-k))/2, Fb = (Z(k) - conj Z(-k))/(2i)
+    cx<T> *dst = inter + ((size_t)j * d.nzb + zblk) * NFIELD * nkx * zb;
+    for (int e = threadIdx.x; e < 5 * nkx * zb; e += blockDim.x) {
+        const int pr = e / (nkx * zb);
+        const int r2 = e - pr * nkx * zb;
+        const int k = r2 / zb, row = r2 - k * zb;
+        const cx<T> *R = lds + (pr * zb + row) * bs;
+        const cx<T> Z = R[fft_pad(k)];
+        const cx<T> Zc = cconj(R[fft_pad(k == 0 ? 0 : nx - k)]);
+        const cx<T> Fa = cx<T>{T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y + Zc.y)};
+        const cx<T> Fb = cx<T>{T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
+        dst[((2 * pr) * nkx + k) * zb + row] = Fa;
+        dst[((2 * pr + 1) * nkx + k) * zb + row] = Fb;
+    }
+}
+
+template <typename TI, typename T>
+static void launch_fx(hipStream_t st, const Dims &d, const Tables &t, const void *u,
+                      const void *v, const void *w, const void *p, const double *prof,
+                      void *inter, double *momp)
+{
+    const size_t lds = sizeof(cx<T>) * (5 * (size_t)d.zb * fft_stride(d.nx) + d.nx);
+    set_lds_limit(k_fluct_xfft<TI, T>);
+    hipLaunchKernelGGL((k_fluct_xfft<TI, T>), dim3(d.nzb, d.ny), dim3(FFT_BLOCK), lds, st,
+                       (const TI *)u, (const TI *)v, (const TI *)w, (const TI *)p, prof, d, t,
+                       (cx<T> *)inter, momp);
 }
 
 hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int f32,
                              const void *u, const void *v, const void *w, const void *p,
-                             const double *prof, cx<double> *inter, double *momp)
+                             const double *prof, void *inter, double *momp)
 {
-    const size_t lds = sizeof(cx<double>) * 2 * (size_t)d.zb * (d.nx + 1);
-    dim3 grid(d.nzb, d.ny);
-    if (f32)
-        hipLaunchKernelGGL(k_fluct_xfft<float>, grid, dim3(256), lds, st, (const float *)u,
-                           (const float *)v, (const float *)w, (const float *)p, prof, d, t,
-                           inter, momp);
-    else
-        hipLaunchKernelGGL(k_fluct_xfft<double>, grid, dim3(256), lds, st, (const double *)u,
-                           (const double *)v, (const double *)w, (const double *)p, prof, d, t,
-                           inter, momp);
+    const bool sp = d.prec == PREC_BF16X3;
+    if (f32 && sp) launch_fx<float, float>(st, d, t, u, v, w, p, prof, inter, momp);
+    else if (f32) launch_fx<float, double>(st, d, t, u, v, w, p, prof, inter, momp);
+    else if (sp) launch_fx<double, float>(st, d, t, u, v, w, p, prof, inter, momp);
+    else launch_fx<double, double>(st, d, t, u, v, w, p, prof, inter, momp);
     return hipGetLastError();
 }
 
-// One block = jb consecutive planes of one field at one kx: transform along z,
-// scale, and store spec[k = kx*Nz + kz][f][slot][j] (planes contiguous).
-// For u, v, w also add sum_kz w_kx (alpha^2 + beta^2)|A^|^2 into momg[j][f][kx]
-// (the plane average of (dx u')^2 + (dz u')^2 by the Parseval identity).
-__global__ __launch_bounds__(256) void k_zfft_pack(const cx<double> *__restrict__ inter, Dims d,
-                                                   Tables t, int slot,
-                                                   cx<double> *__restrict__ spec,
-                                                   double *__restrict__ momg)
+// One block = jb consecutive planes of one field at one kx: transform along z
+// (type T), scale, and store spec[k = kx*Nz + kz][f][slot][j] (planes
+// contiguous) as FP64 complex or split BF16.  For u, v, w also add
+// sum_kz w_kx (alpha^2 + beta^2)|A^|^2 into momg[j][f][kx] (the plane average
+// of (dx u')^2 + (dz u')^2 by the Parseval identity).
+template <typename T, typename S>
+__global__ __launch_bounds__(FFT_BLOCK) void k_zfft_pack(const cx<T> *__restrict__ inter, Dims d,
+                                                         Tables t, int slot,
+                                                         S *__restrict__ spec,
+                                                         double *__restrict__ momg)
 {
-    extern __shared__ cx<double> lds[];
-    __shared__ double red[256];
+    extern __shared__ unsigned char lds_raw[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
     const int nx = d.nx, ny = d.ny, nz = d.nz, nkx = d.nkx, jb = d.jb;
     const int jblk = blockIdx.x, kx = blockIdx.y, f = blockIdx.z;
     const int j0 = jblk * jb;
     const int nb = min(jb, ny - j0);
-    const int bs = nz + 1;
-    cx<double> *A = lds;
-    cx<double> *B = lds + jb * bs;
-    for (int e = threadIdx.x; e < nb * nz; e += blockDim.x) {
-        const int b = e / nz, z = e - b * nz;
-        A[b * bs + z] = inter[(((size_t)(j0 + b) * NFIELD + f) * nkx + kx) * nz + z];
-    }
+    const int bs = fft_stride(nz);
+    const int zb = d.zb;
+    cx<T> *tw = lds + jb * bs;
+    load_twiddles(tw, tw_of<T>(t, 1), nz);
+    gather_batched<4, FFT_BLOCK, cx<T>>(
+        nb * nz,
+        [&](int e) {
+            const int b = e / nz, z = e - b * nz;
+            const int zblk = z / zb, row = z - zblk * zb;
+            return inter[((((size_t)(j0 + b) * d.nzb + zblk) * NFIELD + f) * nkx + kx) * zb + row];
+        },
+        [&](int e, cx<T> x) {
+            const int b = e / nz, z = e - b * nz;
+            lds[b * bs + fft_pad(z)] = x;
+        });
     __syncthreads();
-    const cx<double> *R = lds_fft<double>(A, B, nb, bs, t.pz, t.twz, -1);
+    lds_fft_ip<T, FFT_CAP, FFT_BLOCK>(lds, nb, bs, t.pz, tw, -1);
     const double scale = 1.0 / ((double)nx * (double)nz);
     const double two_pi = 6.283185307179586476925286766559;
     const double alpha = (2 * kx == nx) ? 0.0 : two_pi * kx / d.lx;
     const double wkx = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
-    double eg = 0.0;
-    for (int e = threadIdx.x; e < jb * nz; e += blockDim.x) {
-        const int kz = e / jb, b = e - kz * jb;
-        if (b < nb) {
-            const cx<double> X = cscale(R[b * bs + kz], scale);
-            spec[((((size_t)kx * nz + kz) * NFIELD + f) * d.chunk + slot) * ny + j0 + b] = X;
-            if (f < 3) {
-                const int kzs = (kz <= nz / 2) ? kz : kz - nz;
-                const double beta = (2 * kz == nz) ? 0.0 : two_pi * kzs / d.lz;
-                eg += wkx * (alpha * alpha + beta * beta) * (X.x * X.x + X.y * X.y);
-            }
+    for (int e = threadIdx.x; e < nb * nz; e += blockDim.x) {
+        const int kz = e / nb, b = e - kz * nb;
+        const cx<T> Y = lds[b * bs + fft_pad(kz)];
+        const cx<double> X = cx<double>{(double)Y.x * scale, (double)Y.y * scale};
+        store_spec<double>(spec, ((((size_t)kx * nz + kz) * NFIELD + f) * d.chunk + slot) * ny + j0 + b, X);
+        if (f < 3) {
+            const int kzs = (kz <= nz / 2) ? kz : kz - nz;
+            const double beta = (2 * kz == nz) ? 0.0 : two_pi * kzs / d.lz;
+            // the element is not read again: keep its gradient energy in place
+            lds[b * bs + fft_pad(kz)].x = (T)(wkx * (alpha * alpha + beta * beta) * (X.x * X.x + X.y * X.y));
         }
     }
     if (f < 3) {
-        // every thread works on one plane b = threadIdx.x % jb (blockDim % jb == 0)
-        red[threadIdx.x] = eg;
         __syncthreads();
         if ((int)threadIdx.x < nb) {
             double s = 0.0;
-            for (int i = threadIdx.x; i < (int)blockDim.x; i += jb) s += red[i];
+            for (int kz = 0; kz < nz; ++kz) s += (double)lds[threadIdx.x * bs + fft_pad(kz)].x;
             momg[((size_t)(j0 + threadIdx.x) * 3 + f) * nkx + kx] += s;
         }
     }
 }
 
-hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t,
-                            const cx<double> *inter, int slot, cx<double> *spec, double *momg)
+hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t, const void *inter,
+                            int slot, void *spec, double *momg)
 {
-    const size_t lds = sizeof(cx<double>) * 2 * (size_t)d.jb * (d.nz + 1);
-    dim3 grid((d.ny + d.jb - 1) / d.jb, d.nkx, NFIELD);
-    hipLaunchKernelGGL(k_zfft_pack, grid, dim3(256), lds, st, inter, d, t, slot, spec, momg);
+    dim3 grid(d.njb, d.nkx, NFIELD);
+    if (d.prec == PREC_BF16X3) {
+        const size_t lds = sizeof(cx<float>) * ((size_t)d.jb * fft_stride(d.nz) + d.nz);
+        set_lds_limit(k_zfft_pack<float, bf16x4>);
+        hipLaunchKernelGGL((k_zfft_pack<float, bf16x4>), grid, dim3(FFT_BLOCK), lds, st,
+                           (const cx<float> *)inter, d, t, slot, (bf16x4 *)spec, momg);
+    } else {
+        const size_t lds = sizeof(cx<double>) * ((size_t)d.jb * fft_stride(d.nz) + d.nz);
+        set_lds_limit(k_zfft_pack<double, cx<double>>);
+        hipLaunchKernelGGL((k_zfft_pack<double, cx<double>>), grid, dim3(FFT_BLOCK), lds, st,
+                           (const cx<double> *)inter, d, t, slot, (cx<double> *)spec, momg);
+    }
     return hipGetLastError();
 }
 

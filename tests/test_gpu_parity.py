@@ -196,3 +196,77 @@ def test_re200_full_size_sampled_pairs():
             scale = np.abs(g[t - 1]).max()   # norm-wise: the whole map
             assert abs(g[t - 1][j1, j2, q, p] - val) <= TOL_FP64 * scale, (j1, j2, p, q, t)
     say("re200 direct-sum points ok")
+
+
+# ---------------------------------------------------------------------------
+# split-BF16 three-term rank-k update (FP32 transforms, FP32 accumulation)
+# ---------------------------------------------------------------------------
+TOL_BF16 = 1e-5
+
+
+def term_errors(gpu_maps, ref, pairs, nx):
+    """Per-term norm-wise error max|gpu - oracle| / max|oracle| over the pairs."""
+    nkx = nx // 2 + 1
+    errs = []
+    for t in range(14):
+        if t == 13:
+            g = np.array([[gpu_maps[13][a, b]] for (a, b) in pairs])
+            r = ref[:, 13, 0, 0][:, None]
+        else:
+            g = np.array([gpu_maps[t][a, b] for (a, b) in pairs])
+            r = ref[:, t, :, :nkx]
+        m = np.abs(r).max()
+        errs.append(float(np.abs(g - r).max() / (m if m > 0 else 1.0)))
+    return errs
+
+
+def check_bf16(g, ref, pairs, nx, label):
+    errs = term_errors(g, ref, pairs, nx)
+    say(f"{label}: per-term norm-wise error " +
+        " ".join(f"T{t + 1}={e:.1e}" for t, e in enumerate(errs)))
+    for t, e in enumerate(errs):
+        assert e <= TOL_BF16, f"{label}: T{t + 1} norm-wise error {e:.3e} > {TOL_BF16:.0e}"
+    return errs
+
+
+def test_tiny_bf16x3(tiny):
+    w, y, snap = tiny
+    say("case tiny bf16x3")
+    g, prof = run_gpu(snap, w, y, precision="bf16x3")
+    pairs = oracle.all_pairs(w.ny)
+    ref = oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs)
+    errs = check_bf16(g, ref, pairs, w.nx, "tiny bf16x3")
+    # the split products are not exact: the error is above FP64 rounding
+    assert max(errs) > 1e-12
+    p_ref = oracle.step1(snap, y, w.lx, w.lz, w.nu)
+    # means and point moments stay in FP64 (eps takes the FP32 transforms)
+    assert np.abs(prof[:11] - p_ref[:11]).max() <= 1e-12 * np.abs(p_ref).max()
+
+
+def test_bf16x3_ragged_multi_chunk_f32_inputs():
+    # 24 x 21 x 20: radix 3 and 5, one full plane tile and a 5-plane tail;
+    # 7 snapshots in chunks of 4 (the second chunk partly filled)
+    w = synth.workload("tiny", nx=24, nz=20, ny=21, S=7, M=6, dtype="f32")
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 77)
+    say("case bf16x3 24x21x20 S=7 chunk=4 f32")
+    g, _ = run_gpu(snap, w, y, precision="bf16x3", chunk=4, pair_batch=61)
+    pairs = oracle.all_pairs(w.ny)
+    ref = oracle.pair_terms(snap.astype(np.float64), y, w.lx, w.lz, w.nu, pairs)
+    check_bf16(g, ref, pairs, w.nx, "bf16x3 24x21x20")
+
+
+@pytest.mark.timeout(900)
+def test_re200_grid_bf16x3_sampled_pairs():
+    """The Re_tau=200 grid with FP32 inputs and the split-BF16 update (64
+    snapshots, chunks of 32) on sampled pairs against the oracle."""
+    w = synth.workload("re200_bf16", S=64)
+    y = synth.y_grid(w)
+    say("case re200 grid bf16x3: generating", w.S, "snapshots")
+    snap = synth.snapshots(w, 512)
+    say("case re200 grid bf16x3: GPU run")
+    g, _ = run_gpu(snap, w, y, precision="bf16x3", chunk=32)
+    pairs = [(0, 0), (5, 127), (64, 64), (30, 95), (128, 1), (70, 71)]
+    say("case re200 grid bf16x3: oracle on", len(pairs), "pairs")
+    ref = oracle.pair_terms(snap.astype(np.float64), y, w.lx, w.lz, w.nu, pairs)
+    check_bf16(g, ref, pairs, w.nx, "re200 bf16x3 sampled pairs")
