@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GKE (y1,y2,rx,rz) term-map points/s; split-BF16 vs FP64 at stated rel. err"
 UNIT = "point-snapshots/s"
-PEAK = {"fp64_mfma": 78.6, "bf16_mfma": 2500.0, "hbm": 8000.0}   # TFLOP/s, TFLOP/s, GB/s
+# MI355X published peaks: dense MFMA (TFLOP/s), FP64 vector (TFLOP/s), HBM (GB/s)
+PEAK = {"fp64_mfma": 78.6, "bf16_mfma": 2500.0, "fp64_vector": 78.6, "hbm": 8000.0}
 
 
 def log(*a):
@@ -42,11 +43,15 @@ def kernel_work(w, chunk):
     c16 = 16  # complex FP64
     c8 = 8 if w.precision == "bf16x3" else 16  # x-transformed values and spectra
     npair_u = ny * (ny + 1) // 2
+    n16 = 16 * (ny // 16)                 # planes in full 16-plane tiles
+    pairs_tiles = n16 * (n16 + 1) // 2    # unordered pairs within them
     # 27 complex MACs (216 flops) per (snapshot, wavenumber, unordered pair
     # Y1 <= Y2); the split-BF16 form takes three real products for each one
     fl = 216.0 * (3 if w.precision == "bf16x3" else 1)
     return {
-        "rankk": ("flop", fl * chunk * nk * npair_u),
+        "rankk": ("flop", fl * chunk * nk * pairs_tiles),
+        # pairs with a plane of the last Ny mod 16 (FP64 vector arithmetic)
+        "rankk_rem": ("flop", 216.0 * chunk * nk * (npair_u - pairs_tiles)),
         # read the 4 input fields once, write the 10 x-transformed fields
         "fluct_xfft": ("byte", 4.0 * n_pts * b_in + 10.0 * ny * nkx * nz * c8),
         # read the x-transformed fields, write the 10 spectra
@@ -97,6 +102,9 @@ def main():
                     help="override the rank-k arithmetic of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device-to-device copy of MIB MiB three times "
+                         "(the known-size reference for HBM traffic counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -108,7 +116,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1910_06409_amd import gke, runner, synth
+    from paper_1910_06409_amd import profiling, runner, synth
 
     w = synth.workload(args.workload)
     if args.snapshots:
@@ -124,9 +132,10 @@ def main():
     log(f"[bench] generating {S} snapshots of {w.name} ({w.nx}x{w.ny}x{w.nz}, {w.dtype})")
     t0 = time.perf_counter()
     snaps = torch.empty((S, 4, w.ny, w.nz, w.nx), dtype=tdt, device=dev)
+    gen = synth.DeviceSnapshots(w, args.seed, dev)
     for s in range(S):
-        snaps[s].copy_(torch.from_numpy(synth.snapshot(w, args.seed, s)))
-        if (s + 1) % 20 == 0:
+        gen(s, out=snaps[s])
+        if (s + 1) % 100 == 0:
             log(f"[bench]   {s + 1}/{S} snapshots resident ({time.perf_counter() - t0:.0f} s)")
     torch.cuda.synchronize()
 
@@ -135,6 +144,16 @@ def main():
     outs = r.alloc_terms()
     log(f"[bench] workspace {r.workspace.numel() / 2**30:.1f} GiB, outputs "
         f"{sum(o.numel() for o in outs) * 8 / 2**30:.1f} GiB")
+
+    if args.calibrate_copy:
+        nb = args.calibrate_copy << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {nb} bytes done")
+        del src, dst
 
     def step():
         r.reset()
@@ -174,7 +193,7 @@ def main():
              "avg_launch_ms": avg}
         if name in work:
             kind, amount = work[name]
-            if name == "rankk":
+            if name in ("rankk", "rankk_rem"):
                 # the last launch of a step may hold fewer snapshots: use the mean
                 launches = n / args.steps
                 amount = amount * (S / chunk) / launches
@@ -185,13 +204,22 @@ def main():
         kernels[name] = k
     dom = max(kernels, key=lambda n: kernels[n]["ms_per_step"])
     dk = kernels[dom]
-    if "achieved_tflops" in dk:
+    if dom == "rankk_rem":
+        # FP64 vector arithmetic: the fp64 vector peak of the chip
+        ach, peak, unit, bound = dk["achieved_tflops"], PEAK["fp64_vector"], "TFLOP/s", "alu"
+    elif "achieved_tflops" in dk:
         peak = PEAK["bf16_mfma" if w.precision == "bf16x3" else "fp64_mfma"]
         ach, unit, bound = dk["achieved_tflops"], "TFLOP/s", "mfma"
     else:
         ach, peak, unit, bound = dk.get("achieved_gbs", 0.0), PEAK["hbm"], "GB/s", "hbm"
-    roof = {"kernel": dom, "bound": bound, "achieved": ach, "peak": peak, "unit": unit,
-            "frac": ach / peak, "traffic": None}
+    # HBM bytes per launch of that kernel from the committed counter summary,
+    # provided its sources are unchanged since the counters were taken
+    traffic = profiling.traffic_if_current(
+        os.path.join(ROOT, "profiles", f"traffic_{dom}_{w.name}_{w.precision}.txt"), dom,
+        w.precision) if S == synth.workload(w.name).S and args.chunk == 0 else None
+    roof = {"kernel": profiling.symbol(dom, w.precision) if dom in profiling.KERNELS else dom,
+            "bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+            "traffic": traffic}
 
     cpu = None
     if not args.no_cpu_baseline:

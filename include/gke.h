@@ -172,9 +172,11 @@ gke_status gke_get_profiles(gke_plan_t plan, double *out);
  * Errors: GKE_ERR_STATE (no workspace), GKE_ERR_HIP. */
 gke_status gke_reset(gke_plan_t plan);
 
-/* kernel families reported by gke_timings */
+/* kernel families reported by gke_timings (GKE_K_RANKK: the matrix-core
+ * update of full 16-plane tiles; GKE_K_RANKK_REM: the pairs that involve the
+ * last Ny mod 16 planes) */
 enum { GKE_K_PLANE_SUMS = 0, GKE_K_FLUCT_XFFT, GKE_K_ZFFT_PACK, GKE_K_RANKK, GKE_K_FIN_KZ,
-       GKE_K_FIN_KX, GKE_K_FD, GKE_K_SMALL, GKE_NKERNELS };
+       GKE_K_FIN_KX, GKE_K_FD, GKE_K_SMALL, GKE_K_RANKK_REM, GKE_NKERNELS };
 
 /* With GKE_OPT_TIMING set, HIP events bracket every kernel launch on the
  * plan's stream.  Synchronises the stream, then writes per kernel family the

@@ -117,7 +117,8 @@ hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int
 // cx<double> (FP64 path) or bf16x4 (split-BF16 path).
 hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t, const void *inter,
                             int slot, void *spec, double *momg);
-// cross-spectral rank-k update over the snapshots of one chunk (FP64 MFMA)
+// cross-spectral rank-k update over the snapshots of one chunk, pairs of full
+// plane tiles (FP64 MFMA)
 hipError_t launch_rankk_f64(hipStream_t st, const Dims &d, const Tables &t,
                             const cx<double> *spec, int nsnap, int accumulate,
                             cx<double> *acc);
@@ -125,6 +126,13 @@ hipError_t launch_rankk_f64(hipStream_t st, const Dims &d, const Tables &t,
 hipError_t launch_rankk_bf16x3(hipStream_t st, const Dims &d, const Tables &t,
                                const bf16x4 *spec, int nsnap, int accumulate,
                                cx<double> *acc);
+// the pairs that involve the last Ny mod 16 planes (FP64 vector arithmetic)
+hipError_t launch_rankk_rem_f64(hipStream_t st, const Dims &d, const Tables &t,
+                                const cx<double> *spec, int nsnap, int accumulate,
+                                cx<double> *acc);
+hipError_t launch_rankk_rem_bf16x3(hipStream_t st, const Dims &d, const Tables &t,
+                                   const bf16x4 *spec, int nsnap, int accumulate,
+                                   cx<double> *acc);
 // finalize: inverse transform along kz of the term spectra of the pairs
 // [p0, p1) of the compact pair index, scaled by 1/count
 hipError_t launch_fin_kz(hipStream_t st, const Dims &d, const Tables &t,

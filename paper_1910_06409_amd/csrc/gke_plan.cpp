@@ -212,14 +212,26 @@ size_t layout(gke_plan_t p, char *base)
 gke_status launch_flush(gke_plan_t p)
 {
     if (p->pending == 0) return GKE_OK;
-    GKE_HIP(p, timed(p, GKE_K_RANKK, [&] {
-        const int accumulate = p->chunks_done > 0 ? 1 : 0;
-        if (p->d.prec == gke::PREC_BF16X3)
-            return gke::launch_rankk_bf16x3(p->stream, p->d, p->tab, (const gke::bf16x4 *)p->spec,
-                                            p->pending, accumulate, p->acc);
-        return gke::launch_rankk_f64(p->stream, p->d, p->tab, (const cx<double> *)p->spec,
-                                     p->pending, accumulate, p->acc);
-    }));
+    const int accumulate = p->chunks_done > 0 ? 1 : 0;
+    const bool split = p->d.prec == gke::PREC_BF16X3;
+    const auto *s64 = (const cx<double> *)p->spec;
+    const auto *s16 = (const gke::bf16x4 *)p->spec;
+    if (p->d.ntp > 0) {
+        GKE_HIP(p, timed(p, GKE_K_RANKK, [&] {
+            return split ? gke::launch_rankk_bf16x3(p->stream, p->d, p->tab, s16, p->pending,
+                                                    accumulate, p->acc)
+                         : gke::launch_rankk_f64(p->stream, p->d, p->tab, s64, p->pending,
+                                                 accumulate, p->acc);
+        }));
+    }
+    if (p->d.npair > p->d.npair_tiles) {
+        GKE_HIP(p, timed(p, GKE_K_RANKK_REM, [&] {
+            return split ? gke::launch_rankk_rem_bf16x3(p->stream, p->d, p->tab, s16, p->pending,
+                                                        accumulate, p->acc)
+                         : gke::launch_rankk_rem_f64(p->stream, p->d, p->tab, s64, p->pending,
+                                                     accumulate, p->acc);
+        }));
+    }
     ++p->chunks_done;
     p->pending = 0;
     return GKE_OK;

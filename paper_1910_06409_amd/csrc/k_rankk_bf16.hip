@@ -222,9 +222,14 @@ hipError_t launch_rankk_bf16x3(hipStream_t st, const Dims &d, const Tables &t,
         const int G = (int)((total + 7) / 8 * 8);
         hipLaunchKernelGGL(k_rankk_bf16x3, dim3(G), dim3(64), 0, st, spec, d, t.tile_a, t.tile_b,
                            nsnap, accumulate, (int)total, acc);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_rankk_rem_bf16x3(hipStream_t st, const Dims &d, const Tables &t,
+                                   const bf16x4 *spec, int nsnap, int accumulate,
+                                   cx<double> *acc)
+{
     return launch_rankk_rem(st, d, t, spec, nsnap, accumulate, acc);
 }
 

@@ -24,7 +24,7 @@ TERM_NAMES = ["du2", "phix_t", "phix_m", "phix_v", "phiy_t", "phiy_v", "phiz_t",
               "phi_t", "phi_p", "phi_v", "xi_p1", "xi_p2", "xi_d"]
 PROFILE_NAMES = ["U", "V", "W", "P", "S", "q", "uv", "pv", "Tx", "Ty", "Tz", "eps"]
 KERNEL_NAMES = ["plane_sums", "fluct_xfft", "zfft_pack", "rankk", "fin_kz", "fin_kx", "fd_terms",
-                "small"]
+                "small", "rankk_rem"]
 GKE_NKERNELS = len(KERNEL_NAMES)
 
 

@@ -172,6 +172,33 @@ def _wavenumbers(w: Workload):
 _SCALE_CACHE: dict = {}
 
 
+def _coefficients(w: Workload, seed: int, s: int) -> np.ndarray:
+    """Seeded random stream-function and pressure coefficients [M][4 nb]
+    (Chebyshev mode x (field, band wavenumber)), amplitude law applied."""
+    _, _, band, amp = _wavenumbers(w)
+    iz, ix = np.nonzero(band)
+    nb = iz.size
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), int(s)]))
+    c = rng.standard_normal((4, w.M, nb)) + 1j * rng.standard_normal((4, w.M, nb))
+    c *= amp[iz, ix][None, None, :]
+    return c.transpose(1, 0, 2).reshape(w.M, 4 * nb)
+
+
+def _assemble(xp, w: Workload, cm, T, dT, f, fp, a, b):
+    """Velocity (curl of the enveloped stream function) and pressure
+    coefficients on the band wavenumbers, [4][ny][nb]; xp is numpy or torch."""
+    nb = a.shape[-1]
+    ps = (T @ cm).reshape(w.ny, 4, nb)
+    dps = (dT @ cm).reshape(w.ny, 4, nb)
+    F, Fp = f[:, None], fp[:, None]
+    px, py, pz, pp = ps[:, 0], ps[:, 1], ps[:, 2], ps[:, 3]
+    dpx, dpz = dps[:, 0], dps[:, 2]
+    uh = Fp * pz + F * dpz - 1j * b * F * py
+    vh = 1j * b * F * px - 1j * a * F * pz
+    wh = 1j * a * F * py - Fp * px - F * dpx
+    return xp.stack([uh, vh, wh, pp])
+
+
 def _raw_snapshot(w: Workload, seed: int, s: int) -> np.ndarray:
     """Unscaled fluctuation fields [4][ny][nz][nx] (u', v', w', p') in float64."""
     y = y_grid(w)
@@ -179,29 +206,10 @@ def _raw_snapshot(w: Workload, seed: int, s: int) -> np.ndarray:
     T, dT = _cheb(w.M, y)
     alpha, beta, band, amp = _wavenumbers(w)
     iz, ix = np.nonzero(band)
-    nb = iz.size
-    rng = np.random.default_rng(np.random.SeedSequence([int(seed), int(s)]))
-    c = rng.standard_normal((4, w.M, nb)) + 1j * rng.standard_normal((4, w.M, nb))
-    c *= amp[iz, ix][None, None, :]
-    cm = c.transpose(1, 0, 2).reshape(w.M, 4 * nb)
-    ps = T @ cm
-    dps = dT @ cm
-    ps = ps.reshape(w.ny, 4, nb)
-    dps = dps.reshape(w.ny, 4, nb)
-    a = alpha[ix][None, :]
-    b = beta[iz][None, :]
-    F = f[:, None]
-    Fp = fp[:, None]
-    px, py, pz, pp = ps[:, 0], ps[:, 1], ps[:, 2], ps[:, 3]
-    dpx, dpz = dps[:, 0], dps[:, 2]
-    uh = Fp * pz + F * dpz - 1j * b * F * py
-    vh = 1j * b * F * px - 1j * a * F * pz
-    wh = 1j * a * F * py - Fp * px - F * dpx
+    cm = _coefficients(w, seed, s)
+    co = _assemble(np, w, cm, T, dT, f, fp, alpha[ix][None, :], beta[iz][None, :])
     spec = np.zeros((4, w.ny, w.nz, w.nx // 2 + 1), dtype=np.complex128)
-    spec[0][:, iz, ix] = uh
-    spec[1][:, iz, ix] = vh
-    spec[2][:, iz, ix] = wh
-    spec[3][:, iz, ix] = pp
+    spec[:, :, iz, ix] = co
     workers = max(1, min(16, os.cpu_count() or 1))
     phys = scipy.fft.irfft2(spec, s=(w.nz, w.nx), axes=(-2, -1), norm="forward",
                             workers=workers)
@@ -234,6 +242,49 @@ def snapshot(w: Workload, seed: int, s: int) -> np.ndarray:
     if w.dtype == "f32":
         return r.astype(np.float32)
     return r
+
+
+class DeviceSnapshots:
+    """The same snapshots built on a torch device: the seeded coefficients are
+    drawn on the host exactly as in `snapshot`, the Chebyshev expansion and the
+    inverse transforms run on the device (for large ensembles: generation
+    speed only; values agree with `snapshot` to rounding)."""
+
+    def __init__(self, w: Workload, seed: int, device):
+        import torch
+        self.torch, self.w, self.seed, self.device = torch, w, int(seed), device
+        y = y_grid(w)
+        f, fp = _envelope(w, y)
+        T, dT = _cheb(w.M, y)
+        alpha, beta, band, _ = _wavenumbers(w)
+        iz, ix = np.nonzero(band)
+        c128 = torch.complex128
+        dev = lambda x, dt=c128: torch.as_tensor(x).to(device=device, dtype=dt)
+        self.T, self.dT = dev(T), dev(dT)
+        self.f, self.fp = dev(f), dev(fp)
+        self.a, self.b = dev(alpha[ix][None, :]), dev(beta[iz][None, :])
+        self.flat = dev(iz * (w.nx // 2 + 1) + ix, torch.int64)
+        self.su, self.sp = _scales(w, seed)
+        self.mean = dev(mean_profile(w, y), torch.float64)[:, None, None]
+
+    def __call__(self, s: int, out=None):
+        """Snapshot s as a device tensor [4][ny][nz][nx] (written into out if given)."""
+        torch, w = self.torch, self.w
+        cm = torch.from_numpy(_coefficients(w, self.seed, s)).to(self.device)
+        co = _assemble(torch, w, cm, self.T, self.dT, self.f, self.fp, self.a, self.b)
+        nkx = w.nx // 2 + 1
+        spec = torch.zeros((4, w.ny, w.nz * nkx), dtype=torch.complex128, device=self.device)
+        spec[:, :, self.flat] = co
+        spec = spec.view(4, w.ny, w.nz, nkx)
+        r = torch.fft.irfft2(spec, s=(w.nz, w.nx), norm="forward")
+        r[:3] *= self.su
+        r[3] *= self.sp
+        r[0] += self.mean
+        dt = torch.float32 if w.dtype == "f32" else torch.float64
+        if out is None:
+            return r.to(dt)
+        out.copy_(r)
+        return out
 
 
 def snapshots(w: Workload, seed: int, S: int | None = None) -> np.ndarray:

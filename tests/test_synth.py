@@ -1,0 +1,59 @@
+"""The seeded synthetic channel generator (no method arithmetic): shapes,
+determinism, the no-slip and divergence-free structure, and agreement of the
+device-side builder with the host one."""
+import numpy as np
+import pytest
+
+from paper_1910_06409_amd import synth
+
+
+def test_deterministic_and_seeded(tiny):
+    w, _, _ = tiny
+    a = synth.snapshot(w, 5, 2)
+    assert a.shape == (4, w.ny, w.nz, w.nx)
+    assert np.array_equal(a, synth.snapshot(w, 5, 2))
+    assert not np.array_equal(a, synth.snapshot(w, 5, 3))
+    assert not np.array_equal(a, synth.snapshot(w, 6, 2))
+
+
+def test_no_slip_and_mean(tiny):
+    w, y, _ = tiny
+    a = synth.snapshot(w, 1, 0)
+    U = synth.mean_profile(w, y)
+    # velocities vanish at the walls; u~ carries the mean profile
+    assert np.abs(a[:3, 0]).max() < 1e-12 and np.abs(a[:3, -1]).max() < 1e-12
+    assert abs(a[0].mean(axis=(1, 2)) - U).max() < 0.2
+
+
+def test_divergence_free_spectrally():
+    # i alpha u^ + d(v^)/dy + i beta w^ = 0 per wavenumber, with the exact y
+    # derivative of v^ = F (i beta psi_x - i alpha psi_z) from the expansion
+    w = synth.workload("tiny", ny=33)
+    y = synth.y_grid(w)
+    f, fp = synth._envelope(w, y)
+    T, dT = synth._cheb(w.M, y)
+    alpha, beta, band, _ = synth._wavenumbers(w)
+    iz, ix = np.nonzero(band)
+    cm = synth._coefficients(w, 3, 0)
+    co = synth._assemble(np, w, cm, T, dT, f, fp, alpha[ix][None, :], beta[iz][None, :])
+    nb = iz.size
+    ps = (T @ cm).reshape(w.ny, 4, nb)
+    dps = (dT @ cm).reshape(w.ny, 4, nb)
+    a, b = alpha[ix][None, :], beta[iz][None, :]
+    F, Fp = f[:, None], fp[:, None]
+    dv = 1j * b * (Fp * ps[:, 0] + F * dps[:, 0]) - 1j * a * (Fp * ps[:, 2] + F * dps[:, 2])
+    div = 1j * a * co[0] + dv + 1j * b * co[2]
+    assert np.abs(div).max() <= 1e-12 * np.abs(co[:3]).max() * max(alpha.max(), beta.max())
+
+
+@pytest.mark.parametrize("name", ["tiny", "re200_bf16"])
+def test_device_builder_matches_host(name):
+    torch = pytest.importorskip("torch")
+    w = synth.workload(name)
+    g = synth.DeviceSnapshots(w, 11, torch.device("cpu"))
+    for s in (0, 4):
+        a = synth.snapshot(w, 11, s)
+        b = g(s).numpy()
+        assert b.dtype == a.dtype
+        tol = 1e-13 if a.dtype == np.float64 else 1e-6
+        assert np.abs(a.astype(np.float64) - b).max() <= tol * np.abs(a).max()
