@@ -41,10 +41,24 @@ enum { MP_Q = 0, MP_UV, MP_PV, MP_QU, MP_QV, MP_QW, MP_GY, NMOMP };
 // pass-1 plane sums are split over this many blocks per plane
 constexpr int NSPLIT = 8;
 
-// LDS transforms: at most FFT_CAP complex FP64 elements per block (128 KiB of
-// the 160 KiB LDS of a gfx950 workgroup), FFT_BLOCK threads per block
-constexpr int FFT_CAP = 8192;
-constexpr int FFT_BLOCK = 1024;
+// LDS transforms: at most FFT_CAP complex elements per block and FFT_BLOCK
+// threads per block.  4096 FP64 elements (64 KiB) and 512 threads let two
+// blocks share a compute unit (160 KiB LDS, 128 VGPRs at 4 waves per SIMD),
+// so that one block's global loads overlap the other's transform.
+#ifndef GKE_FFT_CAP
+#define GKE_FFT_CAP 4096
+#endif
+#ifndef GKE_FFT_BLOCK
+#define GKE_FFT_BLOCK 512
+#endif
+#ifndef GKE_FFT_WAVES
+#define GKE_FFT_WAVES 4
+#endif
+constexpr int FFT_CAP = GKE_FFT_CAP;
+constexpr int FFT_BLOCK = GKE_FFT_BLOCK;
+// launch bounds of the transform kernels: FFT_BLOCK threads, at least
+// GKE_FFT_WAVES waves per SIMD (so that several blocks share a compute unit)
+#define GKE_FFT_BOUNDS __launch_bounds__(GKE_FFT_BLOCK, GKE_FFT_WAVES)
 constexpr size_t LDS_BUDGET = 156 * 1024;
 
 struct Dims {

@@ -24,7 +24,7 @@ static void set_lds_limit(F *kernel)
 
 // Inverse transform along kz for pb pairs of one term spectrum at one kx.
 // mid layout: [NMAP][nkx][nz (rz)][ptot (pairs of this batch)].
-__global__ __launch_bounds__(FFT_BLOCK) void k_fin_kz(const cx<double> *__restrict__ acc, Dims d,
+__global__ GKE_FFT_BOUNDS void k_fin_kz(const cx<double> *__restrict__ acc, Dims d,
                                                       Tables t, int p0, int ptot,
                                                       double inv_count,
                                                       cx<double> *__restrict__ mid)
@@ -150,7 +150,7 @@ __device__ __forceinline__ void assemble_store(int m, double val, int j1, int j2
 // Inverse real transform along kx of 2*nt pairs (two real maps per complex
 // transform), then assembly for pair (Y1, Y2) and, when the pair table asks
 // for it, the mirrored pair (Y2, Y1) from r -> -r.
-__global__ __launch_bounds__(FFT_BLOCK) void k_fin_kx(const cx<double> *__restrict__ mid, Dims d,
+__global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims d,
                                                       Tables t, int p0, int ptot,
                                                       const double *__restrict__ prof,
                                                       OutPtrs out)

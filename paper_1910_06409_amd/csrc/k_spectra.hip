@@ -65,7 +65,7 @@ __device__ __forceinline__ void store_spec(bf16x4 *spec, size_t i, cx<T> X)
 //   writes one contiguous chunk
 //   momp[j][k][zblk]: FP64 partial sums of q uv pv qu qv qw and (dy u')^2
 template <typename TI, typename T>
-__global__ __launch_bounds__(FFT_BLOCK) void k_fluct_xfft(const TI *__restrict__ u,
+__global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
                                                           const TI *__restrict__ v,
                                                           const TI *__restrict__ w,
                                                           const TI *__restrict__ p,
@@ -176,7 +176,7 @@ hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int
 // sum_kz w_kx (alpha^2 + beta^2)|A^|^2 into momg[j][f][kx] (the plane average
 // of (dx u')^2 + (dz u')^2 by the Parseval identity).
 template <typename T, typename S>
-__global__ __launch_bounds__(FFT_BLOCK) void k_zfft_pack(const cx<T> *__restrict__ inter, Dims d,
+__global__ GKE_FFT_BOUNDS void k_zfft_pack(const cx<T> *__restrict__ inter, Dims d,
                                                          Tables t, int slot,
                                                          S *__restrict__ spec,
                                                          double *__restrict__ momg)

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgke.so")
+# GKE_LIBRARY may name another build of the same library (other block shapes)
+LIB_PATH = os.environ.get("GKE_LIBRARY") or os.path.join(_HERE, "libgke.so")
 
 GKE_OK, GKE_ERR_ARG, GKE_ERR_STATE, GKE_ERR_OOM, GKE_ERR_HIP, GKE_ERR_UNSUPPORTED = range(6)
 GKE_OPT_DTYPE, GKE_OPT_PRECISION, GKE_OPT_CHUNK, GKE_OPT_PAIR_BATCH, GKE_OPT_TIMING = 1, 2, 3, 4, 5
