@@ -56,28 +56,105 @@ struct Operands {
     cx<double> R[NFIELD];
 };
 
-// Branch-free: a slot past the end reloads the last valid slot; the caller
+// Loads of one snapshot pair.  Addresses split into a wave-uniform part
+// (wavenumber, field, snapshot pair: scalar registers) and a 32-bit lane
+// offset (plane, snapshot within the pair, real/imaginary part).
+// Branch-free: a pair past the end reloads the last valid snapshot; the caller
 // zeroes the left operand of such a slot when it uses it (a zero left value
 // cancels every product of that snapshot), so the loads stay in flight.
-__device__ __forceinline__ void load_operands(Operands &op, const double *lbase,
-                                              const cx<double> *rbase, size_t fstride,
-                                              int ny, int s, int nsnap)
+__device__ __forceinline__ void load_operands(Operands &op, const char *kb, size_t fbytes,
+                                              unsigned loff, unsigned roff, unsigned sbytes,
+                                              int s0, int soff, int nsnap)
 {
-    const int sc = s < nsnap ? s : nsnap - 1;
+    const int s = s0 + soff < nsnap ? s0 + soff : nsnap - 1;
+    const unsigned so = (unsigned)(s - s0) * sbytes;
+    const char *base = kb + (size_t)s0 * sbytes;
 #pragma unroll
     for (int f = 0; f < NFIELD; ++f) {
-        const size_t o = f * fstride + (size_t)sc * ny;
-        op.L[f] = lbase[2 * o];
-        op.R[f] = rbase[o];
+        const char *bf = base + f * fbytes;
+        const unsigned lo = loff + so, ro = roff + so;
+        op.L[f] = *reinterpret_cast<const double *>(bf + lo);
+        op.R[f] = *reinterpret_cast<const cx<double> *>(bf + ro);
     }
 }
 
+// The products of one snapshot pair into the nine accumulators.
+__device__ __forceinline__ void rankk_f64_step(d4 *ar, d4 *ai, const Operands &cur, bool ok,
+                                               int ri)
+{
+    // left operand (planes Y1): fluctuations and Q_ij; zero past the end
+    double Lc[NFIELD];
+#pragma unroll
+    for (int f = 0; f < NFIELD; ++f) Lc[f] = ok ? cur.L[f] : 0.0;
+    const double lu = Lc[F_U], lv = Lc[F_V], lw = Lc[F_W], lp = Lc[F_P];
+    const double lQxx = Lc[F_QXX], lQyy = Lc[F_QYY], lQzz = Lc[F_QZZ];
+    const double lQxy = Lc[F_QXY], lQxz = Lc[F_QXZ], lQyz = Lc[F_QYZ];
+    const double lq = 0.2 * (lQxx + lQyy + lQzz);
+    const double nu_ = -lu, nv = -lv, nw = -lw;
+    // right operand (planes Y2): real-output and imaginary-output forms
+    double br[NFIELD], bi[NFIELD];
+#pragma unroll
+    for (int f = 0; f < NFIELD; ++f) {
+        br[f] = ri ? cur.R[f].y : cur.R[f].x;
+        bi[f] = ri ? -cur.R[f].x : cur.R[f].y;
+    }
+    const double rQxxr = br[F_QXX], rQxxi = bi[F_QXX];
+    const double rQyyr = br[F_QYY], rQyyi = bi[F_QYY];
+    const double rQzzr = br[F_QZZ], rQzzi = bi[F_QZZ];
+    const double rQxyr = br[F_QXY], rQxyi = bi[F_QXY];
+    const double rQxzr = br[F_QXZ], rQxzi = bi[F_QXZ];
+    const double rQyzr = br[F_QYZ], rQyzi = bi[F_QYZ];
+    const double rqr = 0.2 * (rQxxr + rQyyr + rQzzr);
+    const double rqi = 0.2 * (rQxxi + rQyyi + rQzzi);
+    const double ur = br[F_U], ui = bi[F_U], vr = br[F_V], vi = bi[F_V];
+    const double wr = br[F_W], wi = bi[F_W], pr = br[F_P], pi = bi[F_P];
+
+    // 27 products, ordered so that successive ones feed different accumulators
+    GKE_MFMA2(0, lu, ur, ui);
+    GKE_MFMA2(1, lQxx, ur, ui);
+    GKE_MFMA2(2, lQxz, ur, ui);
+    GKE_MFMA2(3, lQxy, ur, ui);
+    GKE_MFMA2(8, lv, ur, ui);
+    GKE_MFMA2(4, lu, rQxyr, rQxyi);
+    GKE_MFMA2(1, nu_, rQxxr, rQxxi);
+    GKE_MFMA2(2, nu_, rQxzr, rQxzi);
+    GKE_MFMA2(5, lv, rqr, rqi);
+    GKE_MFMA2(0, lv, vr, vi);
+    GKE_MFMA2(1, lQxy, vr, vi);
+    GKE_MFMA2(2, lQyz, vr, vi);
+    GKE_MFMA2(3, lQyy, vr, vi);
+    GKE_MFMA2(6, lp, vr, vi);
+    GKE_MFMA2(7, lu, vr, vi);
+    GKE_MFMA2(4, lv, rQyyr, rQyyi);
+    GKE_MFMA2(5, lq, vr, vi);
+    GKE_MFMA2(1, nv, rQxyr, rQxyi);
+    GKE_MFMA2(2, nv, rQyzr, rQyzi);
+    GKE_MFMA2(6, lv, pr, pi);
+    GKE_MFMA2(0, lw, wr, wi);
+    GKE_MFMA2(1, lQxz, wr, wi);
+    GKE_MFMA2(2, lQzz, wr, wi);
+    GKE_MFMA2(3, lQyz, wr, wi);
+    GKE_MFMA2(4, lw, rQyzr, rQyzi);
+    GKE_MFMA2(1, nw, rQxzr, rQxzi);
+    GKE_MFMA2(2, nw, rQzzr, rQzzi);
+}
+
+// Register prefetch of the next snapshot pair (1) or none (0), and the
+// minimum waves per SIMD.  Without the prefetch the kernel fits 2 waves per
+// SIMD (220 VGPRs), and each wave's MFMA chain covers the other's loads; this
+// measured about 1.35x faster than one wave with a prefetch.
+#ifndef GKE_RANKK_PF
+#define GKE_RANKK_PF 0
+#endif
+#ifndef GKE_RANKK_MINW
+#define GKE_RANKK_MINW 2
+#endif
+
 // acc layout: [NSPEC][nk][P] complex.
-__global__ __launch_bounds__(64) void k_rankk_f64(const cx<double> *__restrict__ spec, Dims d,
-                                                  const int *__restrict__ tile_a,
-                                                  const int *__restrict__ tile_b, int nsnap,
-                                                  int accumulate, int total,
-                                                  cx<double> *__restrict__ acc)
+__global__ __launch_bounds__(64, GKE_RANKK_MINW) void k_rankk_f64(
+    const cx<double> *__restrict__ spec, Dims d, const int *__restrict__ tile_a,
+    const int *__restrict__ tile_b, int nsnap, int accumulate, int total,
+    cx<double> *__restrict__ acc)
 {
     // XCD-aware order: workgroup i runs on XCD i % 8; give every XCD a
     // contiguous range of (k, tile pair) so the tiles of one wavenumber share
@@ -93,9 +170,11 @@ __global__ __launch_bounds__(64) void k_rankk_f64(const cx<double> *__restrict__
     const int lane = threadIdx.x;
     const int row = lane & 15, kq = lane >> 4, soff = kq >> 1, ri = kq & 1;
     const size_t fstride = (size_t)d.chunk * d.ny;  // complex elements per field
-    const cx<double> *kb = spec + (size_t)k * NFIELD * fstride;
-    const double *lbase = reinterpret_cast<const double *>(kb + ta * 16 + row) + ri;
-    const cx<double> *rbase = kb + tb * 16 + row;
+    const char *kb = reinterpret_cast<const char *>(spec + (size_t)k * NFIELD * fstride);
+    const size_t fbytes = fstride * sizeof(cx<double>);
+    const unsigned sbytes = (unsigned)d.ny * sizeof(cx<double>);
+    const unsigned loff = (unsigned)(ta * 16 + row) * sizeof(cx<double>) + ri * sizeof(double);
+    const unsigned roff = (unsigned)(tb * 16 + row) * sizeof(cx<double>);
 
     d4 ar[9], ai[9];
 #pragma unroll
@@ -104,76 +183,28 @@ __global__ __launch_bounds__(64) void k_rankk_f64(const cx<double> *__restrict__
         ai[c] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
+#if GKE_RANKK_PF
     Operands cur;
-    load_operands(cur, lbase, rbase, fstride, d.ny, soff, nsnap);
+    load_operands(cur, kb, fbytes, loff, roff, sbytes, 0, soff, nsnap);
     for (int s0 = 0; s0 < nsnap; s0 += 2) {
         // prefetch the next snapshot pair while this one is multiplied
         Operands nxt;
-        const int sn = s0 + 2 + soff;
-        load_operands(nxt, lbase, rbase, fstride, d.ny, sn, nsnap);
+        load_operands(nxt, kb, fbytes, loff, roff, sbytes, s0 + 2 < nsnap ? s0 + 2 : s0, soff,
+                      nsnap);
         // keep the scheduler from pulling the consumers of these loads into
         // this iteration: they are waited for only at the next one
         __builtin_amdgcn_sched_barrier(0);
-
-        // left operand (planes Y1): fluctuations and Q_ij; zero past the end
-        const bool ok = s0 + soff < nsnap;
-        double Lc[NFIELD];
-#pragma unroll
-        for (int f = 0; f < NFIELD; ++f) Lc[f] = ok ? cur.L[f] : 0.0;
-        const double lu = Lc[F_U], lv = Lc[F_V], lw = Lc[F_W], lp = Lc[F_P];
-        const double lQxx = Lc[F_QXX], lQyy = Lc[F_QYY], lQzz = Lc[F_QZZ];
-        const double lQxy = Lc[F_QXY], lQxz = Lc[F_QXZ], lQyz = Lc[F_QYZ];
-        const double lq = 0.2 * (lQxx + lQyy + lQzz);
-        const double nu_ = -lu, nv = -lv, nw = -lw;
-        // right operand (planes Y2): real-output and imaginary-output forms
-        double br[NFIELD], bi[NFIELD];
-#pragma unroll
-        for (int f = 0; f < NFIELD; ++f) {
-            br[f] = ri ? cur.R[f].y : cur.R[f].x;
-            bi[f] = ri ? -cur.R[f].x : cur.R[f].y;
-        }
-        const double rQxxr = br[F_QXX], rQxxi = bi[F_QXX];
-        const double rQyyr = br[F_QYY], rQyyi = bi[F_QYY];
-        const double rQzzr = br[F_QZZ], rQzzi = bi[F_QZZ];
-        const double rQxyr = br[F_QXY], rQxyi = bi[F_QXY];
-        const double rQxzr = br[F_QXZ], rQxzi = bi[F_QXZ];
-        const double rQyzr = br[F_QYZ], rQyzi = bi[F_QYZ];
-        const double rqr = 0.2 * (rQxxr + rQyyr + rQzzr);
-        const double rqi = 0.2 * (rQxxi + rQyyi + rQzzi);
-        const double ur = br[F_U], ui = bi[F_U], vr = br[F_V], vi = bi[F_V];
-        const double wr = br[F_W], wi = bi[F_W], pr = br[F_P], pi = bi[F_P];
-
-        // 27 products, ordered so that successive ones feed different accumulators
-        GKE_MFMA2(0, lu, ur, ui);
-        GKE_MFMA2(1, lQxx, ur, ui);
-        GKE_MFMA2(2, lQxz, ur, ui);
-        GKE_MFMA2(3, lQxy, ur, ui);
-        GKE_MFMA2(8, lv, ur, ui);
-        GKE_MFMA2(4, lu, rQxyr, rQxyi);
-        GKE_MFMA2(1, nu_, rQxxr, rQxxi);
-        GKE_MFMA2(2, nu_, rQxzr, rQxzi);
-        GKE_MFMA2(5, lv, rqr, rqi);
-        GKE_MFMA2(0, lv, vr, vi);
-        GKE_MFMA2(1, lQxy, vr, vi);
-        GKE_MFMA2(2, lQyz, vr, vi);
-        GKE_MFMA2(3, lQyy, vr, vi);
-        GKE_MFMA2(6, lp, vr, vi);
-        GKE_MFMA2(7, lu, vr, vi);
-        GKE_MFMA2(4, lv, rQyyr, rQyyi);
-        GKE_MFMA2(5, lq, vr, vi);
-        GKE_MFMA2(1, nv, rQxyr, rQxyi);
-        GKE_MFMA2(2, nv, rQyzr, rQyzi);
-        GKE_MFMA2(6, lv, pr, pi);
-        GKE_MFMA2(0, lw, wr, wi);
-        GKE_MFMA2(1, lQxz, wr, wi);
-        GKE_MFMA2(2, lQzz, wr, wi);
-        GKE_MFMA2(3, lQyz, wr, wi);
-        GKE_MFMA2(4, lw, rQyzr, rQyzi);
-        GKE_MFMA2(1, nw, rQxzr, rQxzi);
-        GKE_MFMA2(2, nw, rQzzr, rQzzi);
+        rankk_f64_step(ar, ai, cur, s0 + soff < nsnap, ri);
         __builtin_amdgcn_sched_barrier(0);
         cur = nxt;
     }
+#else
+    for (int s0 = 0; s0 < nsnap; s0 += 2) {
+        Operands cur;
+        load_operands(cur, kb, fbytes, loff, roff, sbytes, s0, soff, nsnap);
+        rankk_f64_step(ar, ai, cur, s0 + soff < nsnap, ri);
+    }
+#endif
 
     const size_t sp_stride = (size_t)d.nk * d.npair;
 #pragma unroll

@@ -92,24 +92,92 @@ __device__ __forceinline__ void make_q(const bf16x4 *F, unsigned int &re, unsign
         ai[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16((A).a, (B).im, ai[c], 0, 0, 0); \
     } while (0)
 
-__device__ __forceinline__ void load_raw(bf16x4 *L, bf16x4 *R, const bf16x4 *lbase,
-                                         const bf16x4 *rbase, size_t fstride, int ny, int s,
-                                         int nsnap)
+// Loads of one snapshot quad (lane group g takes snapshot s0 + g): a
+// wave-uniform base (wavenumber, field, quad) plus a 32-bit lane offset.  A
+// snapshot past the end reloads the last valid one (zeroed at use).
+__device__ __forceinline__ void load_raw(bf16x4 *L, bf16x4 *R, const char *kb, size_t fbytes,
+                                         unsigned loff, unsigned roff, unsigned sbytes, int s0,
+                                         int g, int nsnap)
 {
-    const int sc = s < nsnap ? s : nsnap - 1;
+    const int s = s0 + g < nsnap ? s0 + g : nsnap - 1;
+    const unsigned so = (unsigned)(s - s0) * sbytes;
+    const char *base = kb + (size_t)s0 * sbytes;
 #pragma unroll
     for (int f = 0; f < NFIELD; ++f) {
-        const size_t o = f * fstride + (size_t)sc * ny;
-        L[f] = lbase[o];
-        R[f] = rbase[o];
+        const char *bf = base + f * fbytes;
+        const unsigned lo = loff + so, ro = roff + so;
+        L[f] = *reinterpret_cast<const bf16x4 *>(bf + lo);
+        R[f] = *reinterpret_cast<const bf16x4 *>(bf + ro);
     }
 }
 
-__global__ __launch_bounds__(64) void k_rankk_bf16x3(const bf16x4 *__restrict__ spec, Dims d,
-                                                     const int *__restrict__ tile_a,
-                                                     const int *__restrict__ tile_b, int nsnap,
-                                                     int accumulate, int total,
-                                                     cx<double> *__restrict__ acc)
+// The split products of one snapshot quad into the nine accumulators.
+__device__ __forceinline__ void rankk_bf16_step(f4 *ar, f4 *ai, bf16x4 *Lc, const bf16x4 *Rc,
+                                                bool ok)
+{
+    // a snapshot past the end contributes nothing: zero its left operand
+#pragma unroll
+    for (int f = 0; f < NFIELD; ++f) {
+        Lc[f].re = ok ? Lc[f].re : 0u;
+        Lc[f].im = ok ? Lc[f].im : 0u;
+    }
+    unsigned int lqr, lqi, rqr, rqi;
+    make_q(Lc, lqr, lqi);
+    make_q(Rc, rqr, rqi);
+    const OpA u_ = make_a(Lc[F_U].re, Lc[F_U].im), v_ = make_a(Lc[F_V].re, Lc[F_V].im);
+    const OpA w_ = make_a(Lc[F_W].re, Lc[F_W].im), p_ = make_a(Lc[F_P].re, Lc[F_P].im);
+    const OpA q_ = make_a(lqr, lqi);
+    const OpA Qxx = make_a(Lc[F_QXX].re, Lc[F_QXX].im), Qyy = make_a(Lc[F_QYY].re, Lc[F_QYY].im);
+    const OpA Qzz = make_a(Lc[F_QZZ].re, Lc[F_QZZ].im), Qxy = make_a(Lc[F_QXY].re, Lc[F_QXY].im);
+    const OpA Qxz = make_a(Lc[F_QXZ].re, Lc[F_QXZ].im), Qyz = make_a(Lc[F_QYZ].re, Lc[F_QYZ].im);
+    const OpA nu_ = neg_a(u_), nv_ = neg_a(v_), nw_ = neg_a(w_);
+    const OpB U = make_b(Rc[F_U].re, Rc[F_U].im), V = make_b(Rc[F_V].re, Rc[F_V].im);
+    const OpB W = make_b(Rc[F_W].re, Rc[F_W].im), P = make_b(Rc[F_P].re, Rc[F_P].im);
+    const OpB Q = make_b(rqr, rqi);
+    const OpB RQxx = make_b(Rc[F_QXX].re, Rc[F_QXX].im), RQyy = make_b(Rc[F_QYY].re, Rc[F_QYY].im);
+    const OpB RQzz = make_b(Rc[F_QZZ].re, Rc[F_QZZ].im), RQxy = make_b(Rc[F_QXY].re, Rc[F_QXY].im);
+    const OpB RQxz = make_b(Rc[F_QXZ].re, Rc[F_QXZ].im), RQyz = make_b(Rc[F_QYZ].re, Rc[F_QYZ].im);
+
+    GKE_MFMA_BF(0, u_, U);
+    GKE_MFMA_BF(1, Qxx, U);
+    GKE_MFMA_BF(2, Qxz, U);
+    GKE_MFMA_BF(3, Qxy, U);
+    GKE_MFMA_BF(8, v_, U);
+    GKE_MFMA_BF(4, u_, RQxy);
+    GKE_MFMA_BF(1, nu_, RQxx);
+    GKE_MFMA_BF(2, nu_, RQxz);
+    GKE_MFMA_BF(5, v_, Q);
+    GKE_MFMA_BF(0, v_, V);
+    GKE_MFMA_BF(1, Qxy, V);
+    GKE_MFMA_BF(2, Qyz, V);
+    GKE_MFMA_BF(3, Qyy, V);
+    GKE_MFMA_BF(6, p_, V);
+    GKE_MFMA_BF(7, u_, V);
+    GKE_MFMA_BF(4, v_, RQyy);
+    GKE_MFMA_BF(5, q_, V);
+    GKE_MFMA_BF(1, nv_, RQxy);
+    GKE_MFMA_BF(2, nv_, RQyz);
+    GKE_MFMA_BF(6, v_, P);
+    GKE_MFMA_BF(0, w_, W);
+    GKE_MFMA_BF(1, Qxz, W);
+    GKE_MFMA_BF(2, Qzz, W);
+    GKE_MFMA_BF(3, Qyz, W);
+    GKE_MFMA_BF(4, w_, RQyz);
+    GKE_MFMA_BF(1, nw_, RQxz);
+    GKE_MFMA_BF(2, nw_, RQzz);
+}
+
+#ifndef GKE_RANKK16_PF
+#define GKE_RANKK16_PF 0
+#endif
+#ifndef GKE_RANKK16_MINW
+#define GKE_RANKK16_MINW 3
+#endif
+
+__global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
+    const bf16x4 *__restrict__ spec, Dims d, const int *__restrict__ tile_a,
+    const int *__restrict__ tile_b, int nsnap, int accumulate, int total,
+    cx<double> *__restrict__ acc)
 {
     const int G = gridDim.x;
     const int bid = blockIdx.x;
@@ -122,9 +190,11 @@ __global__ __launch_bounds__(64) void k_rankk_bf16x3(const bf16x4 *__restrict__ 
     const int lane = threadIdx.x;
     const int row = lane & 15, g = lane >> 4;
     const size_t fstride = (size_t)d.chunk * d.ny;
-    const bf16x4 *kb = spec + (size_t)k * NFIELD * fstride;
-    const bf16x4 *lbase = kb + ta * 16 + row;
-    const bf16x4 *rbase = kb + tb * 16 + row;
+    const char *kb = reinterpret_cast<const char *>(spec + (size_t)k * NFIELD * fstride);
+    const size_t fbytes = fstride * sizeof(bf16x4);
+    const unsigned sbytes = (unsigned)d.ny * sizeof(bf16x4);
+    const unsigned loff = (unsigned)(ta * 16 + row) * sizeof(bf16x4);
+    const unsigned roff = (unsigned)(tb * 16 + row) * sizeof(bf16x4);
 
     f4 ar[9], ai[9];
 #pragma unroll
@@ -133,64 +203,14 @@ __global__ __launch_bounds__(64) void k_rankk_bf16x3(const bf16x4 *__restrict__ 
         ai[c] = f4{0.f, 0.f, 0.f, 0.f};
     }
 
+#if GKE_RANKK16_PF
     bf16x4 Lc[NFIELD], Rc[NFIELD];
-    load_raw(Lc, Rc, lbase, rbase, fstride, d.ny, g, nsnap);
+    load_raw(Lc, Rc, kb, fbytes, loff, roff, sbytes, 0, g, nsnap);
     for (int s0 = 0; s0 < nsnap; s0 += 4) {
         bf16x4 Ln[NFIELD], Rn[NFIELD];
-        load_raw(Ln, Rn, lbase, rbase, fstride, d.ny, s0 + 4 + g, nsnap);
+        load_raw(Ln, Rn, kb, fbytes, loff, roff, sbytes, s0 + 4 < nsnap ? s0 + 4 : s0, g, nsnap);
         __builtin_amdgcn_sched_barrier(0);
-
-        // a snapshot past the end contributes nothing: zero its left operand
-        const bool ok = s0 + g < nsnap;
-#pragma unroll
-        for (int f = 0; f < NFIELD; ++f) {
-            Lc[f].re = ok ? Lc[f].re : 0u;
-            Lc[f].im = ok ? Lc[f].im : 0u;
-        }
-        unsigned int lqr, lqi, rqr, rqi;
-        make_q(Lc, lqr, lqi);
-        make_q(Rc, rqr, rqi);
-        const OpA u_ = make_a(Lc[F_U].re, Lc[F_U].im), v_ = make_a(Lc[F_V].re, Lc[F_V].im);
-        const OpA w_ = make_a(Lc[F_W].re, Lc[F_W].im), p_ = make_a(Lc[F_P].re, Lc[F_P].im);
-        const OpA q_ = make_a(lqr, lqi);
-        const OpA Qxx = make_a(Lc[F_QXX].re, Lc[F_QXX].im), Qyy = make_a(Lc[F_QYY].re, Lc[F_QYY].im);
-        const OpA Qzz = make_a(Lc[F_QZZ].re, Lc[F_QZZ].im), Qxy = make_a(Lc[F_QXY].re, Lc[F_QXY].im);
-        const OpA Qxz = make_a(Lc[F_QXZ].re, Lc[F_QXZ].im), Qyz = make_a(Lc[F_QYZ].re, Lc[F_QYZ].im);
-        const OpA nu_ = neg_a(u_), nv_ = neg_a(v_), nw_ = neg_a(w_);
-        const OpB U = make_b(Rc[F_U].re, Rc[F_U].im), V = make_b(Rc[F_V].re, Rc[F_V].im);
-        const OpB W = make_b(Rc[F_W].re, Rc[F_W].im), P = make_b(Rc[F_P].re, Rc[F_P].im);
-        const OpB Q = make_b(rqr, rqi);
-        const OpB RQxx = make_b(Rc[F_QXX].re, Rc[F_QXX].im), RQyy = make_b(Rc[F_QYY].re, Rc[F_QYY].im);
-        const OpB RQzz = make_b(Rc[F_QZZ].re, Rc[F_QZZ].im), RQxy = make_b(Rc[F_QXY].re, Rc[F_QXY].im);
-        const OpB RQxz = make_b(Rc[F_QXZ].re, Rc[F_QXZ].im), RQyz = make_b(Rc[F_QYZ].re, Rc[F_QYZ].im);
-
-        GKE_MFMA_BF(0, u_, U);
-        GKE_MFMA_BF(1, Qxx, U);
-        GKE_MFMA_BF(2, Qxz, U);
-        GKE_MFMA_BF(3, Qxy, U);
-        GKE_MFMA_BF(8, v_, U);
-        GKE_MFMA_BF(4, u_, RQxy);
-        GKE_MFMA_BF(1, nu_, RQxx);
-        GKE_MFMA_BF(2, nu_, RQxz);
-        GKE_MFMA_BF(5, v_, Q);
-        GKE_MFMA_BF(0, v_, V);
-        GKE_MFMA_BF(1, Qxy, V);
-        GKE_MFMA_BF(2, Qyz, V);
-        GKE_MFMA_BF(3, Qyy, V);
-        GKE_MFMA_BF(6, p_, V);
-        GKE_MFMA_BF(7, u_, V);
-        GKE_MFMA_BF(4, v_, RQyy);
-        GKE_MFMA_BF(5, q_, V);
-        GKE_MFMA_BF(1, nv_, RQxy);
-        GKE_MFMA_BF(2, nv_, RQyz);
-        GKE_MFMA_BF(6, v_, P);
-        GKE_MFMA_BF(0, w_, W);
-        GKE_MFMA_BF(1, Qxz, W);
-        GKE_MFMA_BF(2, Qzz, W);
-        GKE_MFMA_BF(3, Qyz, W);
-        GKE_MFMA_BF(4, w_, RQyz);
-        GKE_MFMA_BF(1, nw_, RQxz);
-        GKE_MFMA_BF(2, nw_, RQzz);
+        rankk_bf16_step(ar, ai, Lc, Rc, s0 + g < nsnap);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int f = 0; f < NFIELD; ++f) {
@@ -198,6 +218,13 @@ __global__ __launch_bounds__(64) void k_rankk_bf16x3(const bf16x4 *__restrict__ 
             Rc[f] = Rn[f];
         }
     }
+#else
+    for (int s0 = 0; s0 < nsnap; s0 += 4) {
+        bf16x4 Lc[NFIELD], Rc[NFIELD];
+        load_raw(Lc, Rc, kb, fbytes, loff, roff, sbytes, s0, g, nsnap);
+        rankk_bf16_step(ar, ai, Lc, Rc, s0 + g < nsnap);
+    }
+#endif
 
     const size_t sp_stride = (size_t)d.nk * d.npair;
 #pragma unroll
