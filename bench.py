@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--chunk", type=int, default=0, help="0: one chunk for the ensemble")
     ap.add_argument("--snapshots", type=int, default=0, help="override S (0: workload's)")
+    ap.add_argument("--pair-batch", type=int, default=0,
+                    help="pairs per finalize batch (0: all pairs at once)")
     ap.add_argument("--precision", default="", choices=["", "fp64", "bf16x3"],
                     help="override the rank-k arithmetic of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -140,7 +142,8 @@ def main():
     torch.cuda.synchronize()
 
     r = runner.GkeRun(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu, dtype=w.dtype,
-                      precision=w.precision, chunk=chunk, device=dev)
+                      precision=w.precision, chunk=chunk, pair_batch=args.pair_batch,
+                      device=dev)
     outs = r.alloc_terms()
     log(f"[bench] workspace {r.workspace.numel() / 2**30:.1f} GiB, outputs "
         f"{sum(o.numel() for o in outs) * 8 / 2**30:.1f} GiB")

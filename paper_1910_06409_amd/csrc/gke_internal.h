@@ -35,8 +35,8 @@ enum { M_R = 0, M_DRX, M_DRZ, M_FX, M_FY, M_FZ, M_PHI, M_PP, M_UVS, M_UVA, NMAP 
 // profile rows (same order as the public GKE_P_* rows)
 enum { P_U = 0, P_V, P_W, P_P, P_S, P_Q, P_UV, P_PV, P_TX, P_TY, P_TZ, P_EPS, NPROF };
 
-// physical-space moment partials per (plane, z block): q uv pv qu qv qw gy
-enum { MP_Q = 0, MP_UV, MP_PV, MP_QU, MP_QV, MP_QW, MP_GY, NMOMP };
+// physical-space moment partials per (plane, z block): q uv pv qu qv qw
+enum { MP_Q = 0, MP_UV, MP_PV, MP_QU, MP_QV, MP_QW, NMOMP };
 
 // pass-1 plane sums are split over this many blocks per plane
 constexpr int NSPLIT = 8;
@@ -93,6 +93,7 @@ struct Tables {
     const int *tile_a;       // [ntp] tile-pair rows
     const int *tile_b;       // [ntp] tile-pair columns (a <= b)
     const int *pairs;        // [npair] pair table
+    const int *pidx;         // [ny][ny] compact pair index of (Y1, Y2), either order
     FftPlanDev px, pz;
 };
 
@@ -118,19 +119,23 @@ hipError_t launch_means(hipStream_t st, const Dims &d, const Tables &t, const do
                         double count, double *prof);
 // S = D U only (means already in prof)
 hipError_t launch_shear(hipStream_t st, const Dims &d, const Tables &t, double *prof);
-// reduce moment partials into the remaining profile rows
-hipError_t launch_profiles(hipStream_t st, const Dims &d, const double *momp,
-                           const double *momg, double count, double *prof);
+// plane averages of u'_i(Y1) u'_i(Y2) for |Y1 - Y2| <= 4 (r0[Y1][Y2 - Y1]) and
+// of |grad_xz u'|^2 (gxz[Y]) from the scale-energy spectrum accumulators
+hipError_t launch_r0(hipStream_t st, const Dims &d, const Tables &t, const cx<double> *acc,
+                     double inv_count, double *r0, double *gxz);
+// reduce moment partials into the remaining profile rows; eps from r0, gxz
+hipError_t launch_profiles(hipStream_t st, const Dims &d, const Tables &t, const double *momp,
+                           const double *r0, const double *gxz, double count, double *prof);
 
 // pass 2, per snapshot: fluctuations, products, x transforms, moments.
 // inter holds cx<double> (FP64 path) or cx<float> (split-BF16 path).
 hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int f32,
                              const void *u, const void *v, const void *w, const void *p,
                              const double *prof, void *inter, double *momp);
-// z transforms, packing into the spectra slot, gradient energy.  spec holds
-// cx<double> (FP64 path) or bf16x4 (split-BF16 path).
+// z transforms and packing into the spectra slot.  spec holds cx<double>
+// (FP64 path) or bf16x4 (split-BF16 path).
 hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t, const void *inter,
-                            int slot, void *spec, double *momg);
+                            int slot, void *spec);
 // cross-spectral rank-k update over the snapshots of one chunk, pairs of full
 // plane tiles (FP64 MFMA)
 hipError_t launch_rankk_f64(hipStream_t st, const Dims &d, const Tables &t,

@@ -31,14 +31,14 @@ struct gke_plan_s {
     std::vector<cx<double>> h_twx, h_twz;
     std::vector<cx<float>> h_twx32, h_twz32;
     std::vector<double> h_w5;
-    std::vector<int> h_j0, h_ta, h_tb, h_pairs;
+    std::vector<int> h_j0, h_ta, h_tb, h_pairs, h_pidx;
 
     // carved device pointers
     cx<double> *twx = nullptr, *twz = nullptr;
     cx<float> *twx32 = nullptr, *twz32 = nullptr;
     double *w5 = nullptr;
-    int *j0 = nullptr, *ta = nullptr, *tb = nullptr, *pairs = nullptr;
-    double *sums1 = nullptr, *prof = nullptr, *momp = nullptr, *momg = nullptr;
+    int *j0 = nullptr, *ta = nullptr, *tb = nullptr, *pairs = nullptr, *pidx = nullptr;
+    double *sums1 = nullptr, *prof = nullptr, *momp = nullptr, *r0 = nullptr, *gxz = nullptr;
     void *inter = nullptr;  // cx<double> (FP64) or cx<float> (split-BF16)
     void *spec = nullptr;   // cx<double> (FP64) or gke::bf16x4 (split-BF16)
     cx<double> *acc = nullptr, *mid = nullptr;
@@ -196,10 +196,12 @@ size_t layout(gke_plan_t p, char *base)
     p->ta = (int *)take(sizeof(int) * std::max(d.ntp, 1));
     p->tb = (int *)take(sizeof(int) * std::max(d.ntp, 1));
     p->pairs = (int *)take(sizeof(int) * d.npair);
+    p->pidx = (int *)take(sizeof(int) * d.ny * d.ny);
     p->sums1 = (double *)take(sizeof(double) * 4 * d.ny * gke::NSPLIT);
     p->prof = (double *)take(sizeof(double) * gke::NPROF * d.ny);
     p->momp = (double *)take(sizeof(double) * d.ny * gke::NMOMP * d.nzb);
-    p->momg = (double *)take(sizeof(double) * d.ny * 3 * d.nkx);
+    p->r0 = (double *)take(sizeof(double) * d.ny * 5);
+    p->gxz = (double *)take(sizeof(double) * d.ny);
     // both split-BF16 buffers hold 8-byte elements (cx<float>, bf16x4)
     const size_t esz = d.prec == gke::PREC_BF16X3 ? 8 : sizeof(cx<double>);
     p->inter = take(esz * (size_t)d.ny * d.nzb * gke::NFIELD * d.nkx * d.zb);
@@ -334,6 +336,18 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
         delete p;
         return fail(nullptr, GKE_ERR_UNSUPPORTED, "internal pair count mismatch");
     }
+    // compact index of every plane pair, either order
+    p->h_pidx.assign((size_t)Ny * Ny, -1);
+    for (int P = 0; P < d.npair; ++P) {
+        const int j1 = gke::pair_j1(p->h_pairs[P]), j2 = gke::pair_j2(p->h_pairs[P]);
+        if (p->h_pidx[(size_t)j1 * Ny + j2] < 0) p->h_pidx[(size_t)j1 * Ny + j2] = P;
+        if (p->h_pidx[(size_t)j2 * Ny + j1] < 0) p->h_pidx[(size_t)j2 * Ny + j1] = P;
+    }
+    for (int v : p->h_pidx)
+        if (v < 0) {
+            delete p;
+            return fail(nullptr, GKE_ERR_UNSUPPORTED, "internal pair table incomplete");
+        }
     p->tab.px = radix_plan(Nx);
     p->tab.pz = radix_plan(Nz);
     *out = p;
@@ -405,6 +419,7 @@ gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
     GKE_HIP(p, hipMemcpyAsync(p->ta, p->h_ta.data(), sizeof(int) * p->h_ta.size(), hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->tb, p->h_tb.data(), sizeof(int) * p->h_tb.size(), hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->pairs, p->h_pairs.data(), sizeof(int) * d.npair, hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->pidx, p->h_pidx.data(), sizeof(int) * d.ny * d.ny, hipMemcpyHostToDevice, st));
     // sums, profiles and moment partials start at zero
     GKE_HIP(p, hipMemsetAsync(p->sums1, 0, (char *)p->inter - (char *)p->sums1, st));
     GKE_HIP(p, hipStreamSynchronize(st));
@@ -417,6 +432,7 @@ gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
     p->tab.tile_a = p->ta;
     p->tab.tile_b = p->tb;
     p->tab.pairs = p->pairs;
+    p->tab.pidx = p->pidx;
     return GKE_OK;
 }
 
@@ -446,8 +462,7 @@ gke_status gke_accumulate(gke_plan_t p, const void *u, const void *v, const void
                                       p->inter, p->momp);
     }));
     GKE_HIP(p, timed(p, GKE_K_ZFFT_PACK, [&] {
-        return gke::launch_zfft_pack(p->stream, p->d, p->tab, p->inter, p->pending, p->spec,
-                                     p->momg);
+        return gke::launch_zfft_pack(p->stream, p->d, p->tab, p->inter, p->pending, p->spec);
     }));
     ++p->pending;
     ++p->n2;
@@ -503,13 +518,17 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
     if (s != GKE_OK) return s;
     const gke::Dims &d = p->d;
     hipStream_t st = p->stream;
+    const double inv = 1.0 / (double)p->n2;
     GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {
-        return gke::launch_profiles(st, d, p->momp, p->momg, (double)p->n2, p->prof);
+        return gke::launch_r0(st, d, p->tab, p->acc, inv, p->r0, p->gxz);
+    }));
+    GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {
+        return gke::launch_profiles(st, d, p->tab, p->momp, p->r0, p->gxz, (double)p->n2,
+                                    p->prof);
     }));
     double *outp[14];
     for (int i = 0; i < 14; ++i) outp[i] = (double *)out->t[i];
     const int pbt = (p->pair_batch > 0 && p->pair_batch < d.npair) ? p->pair_batch : d.npair;
-    const double inv = 1.0 / (double)p->n2;
     for (int q0 = 0; q0 < d.npair; q0 += pbt) {
         const int q1 = std::min(d.npair, q0 + pbt);
         GKE_HIP(p, timed(p, GKE_K_FIN_KZ, [&] {

@@ -2,9 +2,8 @@
 // fluctuations about the Step-1 means (FP64), the in-plane products formed in
 // physical space (Section "Products instead of correlations"), and the 2-D
 // forward transform of every plane, written in the layout the cross-spectral
-// update reads.  Also the FP64 one-point moments and the pseudo-dissipation
-// pieces (x and z derivatives spectral, y derivative by the five-point
-// stencil).
+// update reads.  Also the FP64 one-point moments.  (The pseudo-dissipation is
+// formed at finalize from the scale-energy spectra, by the Parseval identity.)
 //
 // Normalisation: A^(kx,kz) = (1/(Nx Nz)) sum_{x,z} A e^{-i(alpha x + beta z)}.
 #include "gke_internal.h"
@@ -86,15 +85,7 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
     const double U = prof[P_U * ny + j], V = prof[P_V * ny + j];
     const double W = prof[P_W * ny + j], P = prof[P_P * ny + j];
     const int nel = zb * nx;
-    const int js = t.j0[j];
-    double wt[5], Ms[3][5];
-    for (int a = 0; a < 5; ++a) {
-        wt[a] = t.w5[j * 5 + a];
-        Ms[0][a] = prof[P_U * ny + js + a];
-        Ms[1][a] = prof[P_V * ny + js + a];
-        Ms[2][a] = prof[P_W * ny + js + a];
-    }
-    double mq = 0, muv = 0, mpv = 0, mqu = 0, mqv = 0, mqw = 0, mgy = 0;
+    double mq = 0, muv = 0, mpv = 0, mqu = 0, mqv = 0, mqw = 0;
     for (int e = threadIdx.x; e < nel; e += blockDim.x) {
         const double a = (double)u[off + e] - U, b = (double)v[off + e] - V;
         const double c = (double)w[off + e] - W, dd = (double)p[off + e] - P;
@@ -105,14 +96,6 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
         mqu += q * a;
         mqv += q * b;
         mqw += q * c;
-        double gu = 0, gv = 0, gw = 0;
-        for (int k = 0; k < 5; ++k) {
-            const size_t o = (size_t)(js + k) * npl + (size_t)z0 * nx + e;
-            gu += wt[k] * ((double)u[o] - Ms[0][k]);
-            gv += wt[k] * ((double)v[o] - Ms[1][k]);
-            gw += wt[k] * ((double)w[o] - Ms[2][k]);
-        }
-        mgy += gu * gu + gv * gv + gw * gw;
         // (u,v) (w,p) (Qxx,Qyy) (Qzz,Qxy) (Qxz,Qyz), two real rows per complex row
         const int row = e / nx, x = fft_pad(e - row * nx);
         lds[(0 * zb + row) * bs + x] = cx<T>{(T)a, (T)b};
@@ -121,7 +104,7 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
         lds[(3 * zb + row) * bs + x] = cx<T>{(T)(2.0 * c * c + q), (T)(2.0 * a * b)};
         lds[(4 * zb + row) * bs + x] = cx<T>{(T)(2.0 * a * c), (T)(2.0 * b * c)};
     }
-    const double parts[NMOMP] = {mq, muv, mpv, mqu, mqv, mqw, mgy};
+    const double parts[NMOMP] = {mq, muv, mpv, mqu, mqv, mqw};
     for (int k = 0; k < NMOMP; ++k) {
         const double r = block_sum_fixed(parts[k], sh);
         if (threadIdx.x == 0) momp[((size_t)j * NMOMP + k) * d.nzb + zblk] += r;
@@ -172,14 +155,11 @@ hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int
 
 // One block = jb consecutive planes of one field at one kx: transform along z
 // (type T), scale, and store spec[k = kx*Nz + kz][f][slot][j] (planes
-// contiguous) as FP64 complex or split BF16.  For u, v, w also add
-// sum_kz w_kx (alpha^2 + beta^2)|A^|^2 into momg[j][f][kx] (the plane average
-// of (dx u')^2 + (dz u')^2 by the Parseval identity).
+// contiguous) as FP64 complex or split BF16.
 template <typename T, typename S>
 __global__ GKE_FFT_BOUNDS void k_zfft_pack(const cx<T> *__restrict__ inter, Dims d,
                                                          Tables t, int slot,
-                                                         S *__restrict__ spec,
-                                                         double *__restrict__ momg)
+                                                         S *__restrict__ spec)
 {
     extern __shared__ unsigned char lds_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
@@ -205,45 +185,28 @@ __global__ GKE_FFT_BOUNDS void k_zfft_pack(const cx<T> *__restrict__ inter, Dims
     __syncthreads();
     lds_fft_ip<T, FFT_CAP, FFT_BLOCK>(lds, nb, bs, t.pz, tw, -1);
     const double scale = 1.0 / ((double)nx * (double)nz);
-    const double two_pi = 6.283185307179586476925286766559;
-    const double alpha = (2 * kx == nx) ? 0.0 : two_pi * kx / d.lx;
-    const double wkx = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
     for (int e = threadIdx.x; e < nb * nz; e += blockDim.x) {
         const int kz = e / nb, b = e - kz * nb;
         const cx<T> Y = lds[b * bs + fft_pad(kz)];
         const cx<double> X = cx<double>{(double)Y.x * scale, (double)Y.y * scale};
         store_spec<double>(spec, ((((size_t)kx * nz + kz) * NFIELD + f) * d.chunk + slot) * ny + j0 + b, X);
-        if (f < 3) {
-            const int kzs = (kz <= nz / 2) ? kz : kz - nz;
-            const double beta = (2 * kz == nz) ? 0.0 : two_pi * kzs / d.lz;
-            // the element is not read again: keep its gradient energy in place
-            lds[b * bs + fft_pad(kz)].x = (T)(wkx * (alpha * alpha + beta * beta) * (X.x * X.x + X.y * X.y));
-        }
-    }
-    if (f < 3) {
-        __syncthreads();
-        if ((int)threadIdx.x < nb) {
-            double s = 0.0;
-            for (int kz = 0; kz < nz; ++kz) s += (double)lds[threadIdx.x * bs + fft_pad(kz)].x;
-            momg[((size_t)(j0 + threadIdx.x) * 3 + f) * nkx + kx] += s;
-        }
     }
 }
 
 hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t, const void *inter,
-                            int slot, void *spec, double *momg)
+                            int slot, void *spec)
 {
     dim3 grid(d.njb, d.nkx, NFIELD);
     if (d.prec == PREC_BF16X3) {
         const size_t lds = sizeof(cx<float>) * ((size_t)d.jb * fft_stride(d.nz) + d.nz);
         set_lds_limit(k_zfft_pack<float, bf16x4>);
         hipLaunchKernelGGL((k_zfft_pack<float, bf16x4>), grid, dim3(FFT_BLOCK), lds, st,
-                           (const cx<float> *)inter, d, t, slot, (bf16x4 *)spec, momg);
+                           (const cx<float> *)inter, d, t, slot, (bf16x4 *)spec);
     } else {
         const size_t lds = sizeof(cx<double>) * ((size_t)d.jb * fft_stride(d.nz) + d.nz);
         set_lds_limit(k_zfft_pack<double, cx<double>>);
         hipLaunchKernelGGL((k_zfft_pack<double, cx<double>>), grid, dim3(FFT_BLOCK), lds, st,
-                           (const cx<double> *)inter, d, t, slot, (cx<double> *)spec, momg);
+                           (const cx<double> *)inter, d, t, slot, (cx<double> *)spec);
     }
     return hipGetLastError();
 }

@@ -106,10 +106,63 @@ hipError_t launch_shear(hipStream_t st, const Dims &d, const Tables &t, double *
     return hipGetLastError();
 }
 
-// One block per plane: reduce the per-block partials of the moment kernels.
-__global__ void k_profiles(int ny, int nzb, int nkx, const double *__restrict__ momp,
-                           const double *__restrict__ momg, double inv_pts, double inv_count,
-                           double nu, double *__restrict__ prof)
+// One block per (plane Y, offset a = 0..4): the plane average of
+// u'_i(Y) u'_i(Y + a), which by the Parseval identity over the stored half
+// spectrum (weight 1 at kx = 0 and Nx/2, 2 otherwise) is
+//   sum_k w_kx Re S_R(k; Y, Y + a) / count,
+// and for a = 0 also the plane average of (d_x u'_i)^2 + (d_z u'_i)^2,
+//   sum_k w_kx (alpha^2 + beta^2) S_R(k; Y, Y) / count
+// (spectral derivatives, zero multiplier at the Nyquist wavenumbers).  These
+// give the pseudo-dissipation (Section "Step 2") without further passes over
+// the fields.  r0[Y][a], gxz[Y]; a fixed summation order.
+__global__ __launch_bounds__(256) void k_r0(const cx<double> *__restrict__ acc, Dims d,
+                                            Tables t, double inv_count, double *__restrict__ r0,
+                                            double *__restrict__ gxz)
+{
+    __shared__ double sh[8];
+    const int y = blockIdx.x, a = blockIdx.y;
+    if (y + a >= d.ny) {
+        if (threadIdx.x == 0) r0[y * 5 + a] = 0.0;
+        return;
+    }
+    const int P = t.pidx[y * d.ny + y + a];
+    const cx<double> *s = acc + (size_t)S_R * d.nk * d.npair + P;
+    const double two_pi = 6.283185307179586476925286766559;
+    double r = 0.0, g = 0.0;
+    for (int k = threadIdx.x; k < d.nk; k += blockDim.x) {
+        const int kx = k / d.nz, kz = k - kx * d.nz;
+        const double w = (kx == 0 || 2 * kx == d.nx) ? 1.0 : 2.0;
+        const double v = w * s[(size_t)k * d.npair].x;
+        r += v;
+        if (a == 0) {
+            const int kzs = (kz <= d.nz / 2) ? kz : kz - d.nz;
+            const double al = (2 * kx == d.nx) ? 0.0 : two_pi * kx / d.lx;
+            const double be = (2 * kz == d.nz) ? 0.0 : two_pi * kzs / d.lz;
+            g += (al * al + be * be) * v;
+        }
+    }
+    r = block_sum(r, sh);
+    g = block_sum(g, sh);
+    if (threadIdx.x == 0) {
+        r0[y * 5 + a] = r * inv_count;
+        if (a == 0) gxz[y] = g * inv_count;
+    }
+}
+
+hipError_t launch_r0(hipStream_t st, const Dims &d, const Tables &t, const cx<double> *acc,
+                     double inv_count, double *r0, double *gxz)
+{
+    hipLaunchKernelGGL(k_r0, dim3(d.ny, 5), dim3(256), 0, st, acc, d, t, inv_count, r0, gxz);
+    return hipGetLastError();
+}
+
+// One block per plane: reduce the per-block partials of the moment kernel;
+// eps = nu (<(d_x u')^2 + (d_z u')^2> + <(D u')^2>) with D the five-point
+// wall-normal weights: <(D u')^2> = sum_ab w_a w_b <u'(Y_a) u'(Y_b)>.
+__global__ void k_profiles(int ny, int nzb, const double *__restrict__ momp,
+                           const double *__restrict__ w5, const int *__restrict__ j0,
+                           const double *__restrict__ r0, const double *__restrict__ gxz,
+                           double inv_pts, double nu, double *__restrict__ prof)
 {
     const int j = blockIdx.x;
     if (threadIdx.x != 0) return;
@@ -120,25 +173,29 @@ __global__ void k_profiles(int ny, int nzb, int nkx, const double *__restrict__ 
         for (int b = 0; b < nzb; ++b) a += mp[k * nzb + b];
         s[k] = a * inv_pts;
     }
-    double g = 0.0;
-    const double *mg = momg + (size_t)j * 3 * nkx;
-    for (int i = 0; i < 3 * nkx; ++i) g += mg[i];
+    double gy = 0.0;
+    const int js = j0[j];
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b) {
+            const int ya = js + a, yb = js + b;
+            const int lo = ya < yb ? ya : yb, df = ya < yb ? yb - ya : ya - yb;
+            gy += w5[j * 5 + a] * w5[j * 5 + b] * r0[lo * 5 + df];
+        }
     prof[P_Q * ny + j] = s[MP_Q];
     prof[P_UV * ny + j] = s[MP_UV];
     prof[P_PV * ny + j] = s[MP_PV];
     prof[P_TX * ny + j] = s[MP_QU];
     prof[P_TY * ny + j] = s[MP_QV];
     prof[P_TZ * ny + j] = s[MP_QW];
-    prof[P_EPS * ny + j] = nu * (s[MP_GY] + g * inv_count);
+    prof[P_EPS * ny + j] = nu * (gy + gxz[j]);
 }
 
-hipError_t launch_profiles(hipStream_t st, const Dims &d, const double *momp,
-                           const double *momg, double count, double *prof)
+hipError_t launch_profiles(hipStream_t st, const Dims &d, const Tables &t, const double *momp,
+                           const double *r0, const double *gxz, double count, double *prof)
 {
-    const double inv_count = 1.0 / count;
-    const double inv_pts = inv_count / ((double)d.nx * (double)d.nz);
-    hipLaunchKernelGGL(k_profiles, dim3(d.ny), dim3(64), 0, st, d.ny, d.nzb, d.nkx, momp, momg,
-                       inv_pts, inv_count, d.nu, prof);
+    const double inv_pts = 1.0 / (count * (double)d.nx * (double)d.nz);
+    hipLaunchKernelGGL(k_profiles, dim3(d.ny), dim3(64), 0, st, d.ny, d.nzb, momp, t.w5, t.j0,
+                       r0, gxz, inv_pts, d.nu, prof);
     return hipGetLastError();
 }
 
