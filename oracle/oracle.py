@@ -191,5 +191,30 @@ def pair_terms(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float,
     return out
 
 
+# Sign of each term under the statistical reflection about the centreline,
+# (u, v, w, p)(x, y, z) -> (u, -v, w, p)(x, 2h - y, z), at fixed (rx, rz):
+#   T_i(Y1, Y2) = SIGMA_Y[i] * T_i(2h - Y1, 2h - Y2)
+# (Section "Exploiting symmetries": every term is symmetric or antisymmetric
+# under the inversion of y).  A term flips when it carries an odd number of
+# wall-normal components (v, d/dy or r_y): the r_y fluxes T5, T6 and the
+# Y fluxes T9, T10, T11.
+SIGMA_Y = np.array([+1, +1, +1, +1, -1, -1, +1, +1, -1, -1, -1, +1, +1, +1], dtype=np.float64)
+
+
+def mirror_terms(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float,
+                 pairs, prof: np.ndarray | None = None, nthreads: int | None = None):
+    """Terms of each ordered pair averaged with those of the reflected pair
+    (Section "Step 2": the other half of the channel doubles the sample):
+        Tbar(Y1, Y2) = (T(Y1, Y2) + SIGMA_Y * T(2h - Y1, 2h - Y2)) / 2,
+    same (rx, rz).  The y grid must be symmetric about the centreline, so the
+    reflected plane of index j is Ny - 1 - j.  Returns [npairs][14][nz][nx]."""
+    ny = _as_snap(snap).shape[2]
+    pairs = [tuple(int(v) for v in p) for p in np.asarray(pairs).reshape(-1, 2)]
+    refl = [(ny - 1 - a, ny - 1 - b) for (a, b) in pairs]
+    t = pair_terms(snap, y, lx, lz, nu, pairs + refl, prof=prof, nthreads=nthreads)
+    n = len(pairs)
+    return 0.5 * (t[:n] + SIGMA_Y[None, :, None, None] * t[n:])
+
+
 def all_pairs(ny: int):
     return [(a, b) for a in range(ny) for b in range(ny)]

@@ -325,3 +325,42 @@ def test_mirror_sign_table_from_paper():
         lhs, rhs = agg[:n], sign * _neg_r(agg[n:])
         assert nerr(lhs, rhs) < 1e-11, name
         assert np.abs(lhs).max() > 1e-8, name   # non-trivial
+
+
+def test_reflection_sign_of_every_term():
+    """On an ensemble closed under the reflection about the centreline, every
+    term of (Y1, Y2) equals SIGMA_Y times the term of the reflected pair
+    (2h - Y1, 2h - Y2) at the same (rx, rz), exactly; the wrong sign on any
+    term fails."""
+    w = synth.workload("tiny", S=3)
+    y = synth.y_grid(w)
+    assert np.allclose(y, -y[::-1], atol=1e-15)
+    base = synth.snapshots(w, 5)
+    ens = np.concatenate([base, synth.mirror(base)], axis=0)
+    ny = w.ny
+    pairs = [(1, 4), (3, 12), (6, 6), (2, 16), (9, 3), (0, 8)]
+    refl = [(ny - 1 - a, ny - 1 - b) for (a, b) in pairs]
+    o = oracle.pair_terms(ens, y, w.lx, w.lz, w.nu, pairs + refl)
+    n = len(pairs)
+    for t in range(14):
+        lhs, rhs = o[:n, t], oracle.SIGMA_Y[t] * o[n:, t]
+        assert np.abs(lhs).max() > 1e-8, t
+        assert nerr(lhs, rhs) < 1e-11, (t, nerr(lhs, rhs))
+        assert nerr(lhs, -rhs) > 0.1, t
+
+
+def test_mirror_average_on_reflection_closed_ensemble():
+    """The mirror average changes nothing on a reflection-closed ensemble and
+    is an even/odd split otherwise: Tbar(p) = SIGMA_Y Tbar(reflected p)."""
+    w = synth.workload("tiny", S=2)
+    y = synth.y_grid(w)
+    base = synth.snapshots(w, 8)
+    ens = np.concatenate([base, synth.mirror(base)], axis=0)
+    pairs = [(2, 7), (5, 5), (1, 15)]
+    m = oracle.mirror_terms(ens, y, w.lx, w.lz, w.nu, pairs)
+    p = oracle.pair_terms(ens, y, w.lx, w.lz, w.nu, pairs)
+    assert nerr(m, p) < 1e-11
+    ny = w.ny
+    mb = oracle.mirror_terms(base, y, w.lx, w.lz, w.nu, pairs)
+    mr = oracle.mirror_terms(base, y, w.lx, w.lz, w.nu, [(ny - 1 - a, ny - 1 - b) for a, b in pairs])
+    assert nerr(mb, oracle.SIGMA_Y[None, :, None, None] * mr) < 1e-12
