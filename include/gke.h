@@ -64,10 +64,37 @@ enum {
     GKE_OPT_PRECISION = 2,    /* rank-k arithmetic: GKE_PREC_FP64 (default) or GKE_PREC_BF16X3 */
     GKE_OPT_CHUNK = 3,        /* snapshots per cross-spectral batch, even, 2..4096 (default 64) */
     GKE_OPT_PAIR_BATCH = 4,   /* plane pairs per finalize batch, 0 = all at once (default) */
-    GKE_OPT_TIMING = 5        /* 1: record HIP events around every kernel launch (any time) */
+    GKE_OPT_TIMING = 5,       /* 1: record HIP events around every kernel launch (any time) */
+    GKE_OPT_MIRROR = 6,       /* 1: average every term with the reflected pair (below) */
+    GKE_OPT_DOMAIN = 7,       /* output domain, GKE_DOMAIN_* (default ALLPAIRS_HALFRX) */
+    GKE_OPT_SLAB = 8          /* output Y1 rows per slab, 0 = all rows in one slab (default) */
 };
 enum { GKE_DTYPE_F64 = 0, GKE_DTYPE_F32 = 1 };
 enum { GKE_PREC_FP64 = 0, GKE_PREC_BF16X3 = 1 };
+
+/* Mirror average (GKE_OPT_MIRROR = 1; Section "Step 2": one half of the
+ * channel is used to double the sample, with the sign of each term set by its
+ * symmetry under the inversion of y, Section "Exploiting symmetries"):
+ *   Tbar(Y1, Y2; rx, rz) = (T(Y1, Y2) + sigma_y T(2h - Y1, 2h - Y2)) / 2,
+ * sigma_y = -1 for T5, T6, T9, T10, T11 (an odd number of wall-normal
+ * components) and +1 for the others.  Needs a y grid symmetric about its
+ * centre to 1e-13 of its length; plane j reflects to Ny - 1 - j.
+ *
+ * Output domains (GKE_OPT_DOMAIN), for the pairs of one slab:
+ *   GKE_DOMAIN_ALLPAIRS_HALFRX   Y1 in the slab, every Y2, rx >= 0 (Nx/2 + 1 columns);
+ *   GKE_DOMAIN_Y1LEY2_FULLR      Y1 in the slab, Y2 >= Y1, every rx (Nx columns);
+ *   GKE_DOMAIN_FUNDAMENTAL_FULLR Y1 <= h (index <= (Ny - 1)/2) in the slab,
+ *                                Y1 <= Y2 <= 2h - Y1, every rx; needs MIRROR = 1
+ *                                (Section "Exploiting symmetries": the terms
+ *                                outside follow from the symmetries).
+ * Slabs (GKE_OPT_SLAB = R > 0): the output rows of the domain are cut into
+ * slabs of R rows (Section "Undersampling and parallelisation": the result
+ * space split into wall-normal slices, independent thanks to the local
+ * finite-difference stencil); each slab needs its own second scan, see
+ * gke_begin_slab.  The accumulators then cover only the slab's rows, their
+ * five-point neighbours and (mirror) the reflected rows. */
+enum { GKE_DOMAIN_ALLPAIRS_HALFRX = 0, GKE_DOMAIN_Y1LEY2_FULLR = 1,
+       GKE_DOMAIN_FUNDAMENTAL_FULLR = 2 };
 
 /* term slots: the fourteen components of the budget, T1..T14 -> 0..13
  *   GKE_T_DU2      <du_i du_i>                    (eq. du2)
@@ -93,11 +120,15 @@ enum {
 };
 
 /* Output of gke_finalize.  Each non-NULL t[i] is a caller-owned FP64 device
- * array.  Maps T1..T13 are laid out [Y1 0..Ny)[Y2 0..Ny)[q 0..Nz)[p 0..Nx/2]
- * (all ordered pairs, the half plane rx >= 0; the half rx <= 0 of pair
- * (Y1,Y2) is the half rx >= 0 of pair (Y2,Y1) by the r-inversion symmetry of
- * Section "Exploiting symmetries").  T14 does not depend on r and is laid out
- * [Y1][Y2].  on_device must be 1. */
+ * array.  Default (no mirror, all-pairs domain, one slab): maps T1..T13 are
+ * laid out [Y1 0..Ny)[Y2 0..Ny)[q 0..Nz)[p 0..Nx/2] (all ordered pairs, the
+ * half plane rx >= 0; the half rx <= 0 of pair (Y1,Y2) is the half rx >= 0 of
+ * pair (Y2,Y1) by the r-inversion symmetry of Section "Exploiting
+ * symmetries"), and T14, which does not depend on r, is laid out [Y1][Y2].
+ * With mirror, another domain or slabs: the maps of the current slab are laid
+ * out [n 0..npairs)[q 0..Nz)[p 0..width) with the slab's output pairs in the
+ * order of gke_slab_pairs, width = Nx/2 + 1 (ALLPAIRS_HALFRX) or Nx (FULLR
+ * domains), and T14 is laid out [n].  on_device must be 1. */
 typedef struct {
     void *t[GKE_NTERMS];
     int on_device;
@@ -162,6 +193,22 @@ gke_status gke_set_means(gke_plan_t plan, const double *U, const double *V, cons
  * GKE_ERR_STATE (no second-scan snapshot, or the two scans have different
  * snapshot counts), GKE_ERR_ARG, GKE_ERR_UNSUPPORTED (host outputs), GKE_ERR_HIP. */
 gke_status gke_finalize(gke_plan_t plan, const gke_terms *out);
+
+/* Number of slabs (after gke_set_workspace): 1 unless GKE_OPT_SLAB cuts the
+ * output rows.  Errors: GKE_ERR_STATE (no workspace). */
+gke_status gke_slab_count(gke_plan_t plan, int *count);
+
+/* Output pairs of slab `slab` in layout order: *count receives their number
+ * and, when pairs is not NULL, pairs[2 n] = Y1 index, pairs[2 n + 1] = Y2
+ * index (host array of 2 * count ints).  Errors: GKE_ERR_ARG, GKE_ERR_STATE. */
+gke_status gke_slab_pairs(gke_plan_t plan, int slab, int *count, int *pairs);
+
+/* Start the second scan of slab `slab` (after gke_begin_stats or
+ * gke_set_means, which start slab 0): forgets the second-scan snapshots of
+ * the previous slab; the caller then accumulates every snapshot again and
+ * calls gke_finalize for this slab's maps.  Enqueued on the plan's stream.
+ * Errors: GKE_ERR_ARG (slab out of range), GKE_ERR_STATE (means not known). */
+gke_status gke_begin_slab(gke_plan_t plan, int slab);
 
 /* Copy the GKE_NPROF x Ny profile block (row-major, FP64) to host memory
  * `out`.  Valid after gke_finalize (rows U..S after gke_begin_stats). */

@@ -32,6 +32,10 @@ enum { S_R = 0, S_FX, S_FY, S_FZ, S_PHI, S_PP, S_UVS, S_UVA, NSPEC };
 // r-space maps produced by the inverse transforms in finalize
 enum { M_R = 0, M_DRX, M_DRZ, M_FX, M_FY, M_FZ, M_PHI, M_PP, M_UVS, M_UVA, NMAP };
 
+// terms kept as full-plane maps per slab in the general output modes:
+// T1-T5, T7-T10, T12, T13 (T6, T11 and T14 are formed from them at output)
+constexpr int NSTORED = 11;
+
 // profile rows (same order as the public GKE_P_* rows)
 enum { P_U = 0, P_V, P_W, P_P, P_S, P_Q, P_UV, P_PV, P_TX, P_TY, P_TZ, P_EPS, NPROF };
 
@@ -90,8 +94,10 @@ struct Tables {
     const cx<float> *twz32;
     const double *w5;        // [ny][5] five-point weights
     const int *j0;           // [ny] first stencil node
-    const int *tile_a;       // [ntp] tile-pair rows
-    const int *tile_b;       // [ntp] tile-pair columns (a <= b)
+    const int *tile_a;       // [ntp] tile-pair row tiles (index into rowplane / 16)
+    const int *tile_b;       // [ntp] tile-pair column tiles (planes 16 b .. 16 b + 15)
+    const int *rowplane;     // [16 * row tiles] plane of each row of the row tiles
+    const int *rowidx;       // [ny] row of plane Y1 in the full-plane map buffer, or -1
     const int *pairs;        // [npair] pair table
     const int *pidx;         // [ny][ny] compact pair index of (Y1, Y2), either order
     FftPlanDev px, pz;
@@ -157,10 +163,25 @@ hipError_t launch_rankk_rem_bf16x3(hipStream_t st, const Dims &d, const Tables &
 hipError_t launch_fin_kz(hipStream_t st, const Dims &d, const Tables &t,
                          const cx<double> *acc, int p0, int p1, double inv_count,
                          cx<double> *mid);
-// finalize: inverse real transform along kx, FP64 assembly, both orientations
+// finalize: inverse real transform along kx, FP64 assembly.  full = 0: both
+// orientations into the all-pairs half-plane maps out[t][Y1][Y2][rz][rx <= Nx/2];
+// full = 1: orientation (Y1, Y2) of the pair code only, every rx, into
+// out[t][rowidx[Y1]][Y2][rz][rx < Nx]
 hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
                          const cx<double> *mid, int p0, int p1, const double *prof,
-                         double *const *out);
+                         double *const *out, int full);
+// general output modes: mirror average, output domain, T6/T11/T14, from the
+// full-plane map buffer of the slab rows (see k_final.hip)
+hipError_t launch_slab_out(hipStream_t st, const Dims &d, const Tables &t, const double *mf,
+                           size_t mstride, const int *opairs, int nopairs, const double *prof,
+                           int mirror, int width, double *const *out);
+// band accumulators for eps in the general modes: band[a][Y][k] += sum over the
+// chunk of sum_i Re conj(u_i^(k; Y)) u_i^(k; Y + a), a = 0..4
+hipError_t launch_band(hipStream_t st, const Dims &d, const void *spec, int nsnap,
+                       int accumulate, double *band);
+// r0, gxz (as launch_r0) from the band accumulators
+hipError_t launch_r0_band(hipStream_t st, const Dims &d, const double *band, double inv_count,
+                          double *r0, double *gxz);
 // Step 3: T6 and T11 from T1 along Y1 and Y2
 hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const double *t1,
                            double *t6, double *t11);

@@ -16,6 +16,19 @@
 
 using gke::cx;
 
+// Tables of one slab of output rows in the general modes (mirror average,
+// FULLR domains or slabs).
+struct SlabTables {
+    int y1b = 0, y1e = 0;          // output rows [y1b, y1e)
+    std::vector<int> rows;         // planes with accumulators (sorted, unique)
+    std::vector<int> rowplane;     // rows padded to a multiple of 16 (row tiles)
+    std::vector<int> rowidx;       // [ny] index in rows, -1 if absent
+    std::vector<int> ta, tb;       // tile pairs (row tile, column tile)
+    std::vector<int> pairs;        // pair codes in compact order
+    std::vector<int> opairs;       // output pairs Y1 | Y2 << 16 in layout order
+    int ntp = 0, npair_tiles = 0, npair = 0;
+};
+
 struct gke_plan_s {
     gke::Dims d{};
     std::vector<double> y;
@@ -23,6 +36,11 @@ struct gke_plan_s {
     int prec = GKE_PREC_FP64;
     int chunk = 64;
     int pair_batch = 0;  // pairs per finalize batch (0 = all)
+    int mirror = 0, domain = GKE_DOMAIN_ALLPAIRS_HALFRX, slab_rows = 0;
+    bool general = false;          // mirror, a FULLR domain or slabs
+    std::vector<SlabTables> slabs;
+    int cur_slab = 0;
+    std::vector<int> h_rowplane;   // identity row planes of the all-pairs mode
     hipStream_t stream = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -38,6 +56,9 @@ struct gke_plan_s {
     cx<float> *twx32 = nullptr, *twz32 = nullptr;
     double *w5 = nullptr;
     int *j0 = nullptr, *ta = nullptr, *tb = nullptr, *pairs = nullptr, *pidx = nullptr;
+    int *rowplane = nullptr, *rowidx = nullptr, *opairs = nullptr;
+    double *mf = nullptr, *band = nullptr;
+    size_t mstride = 0;            // doubles per term map in mf
     double *sums1 = nullptr, *prof = nullptr, *momp = nullptr, *r0 = nullptr, *gxz = nullptr;
     void *inter = nullptr;  // cx<double> (FP64) or cx<float> (split-BF16)
     void *spec = nullptr;   // cx<double> (FP64) or gke::bf16x4 (split-BF16)
@@ -176,6 +197,76 @@ hipError_t collect_timings(gke_plan_t p)
     return hipSuccess;
 }
 
+// Output rows and the Y2 range of row j1 in the plan's domain.
+int domain_rows(gke_plan_t p)
+{
+    return p->domain == GKE_DOMAIN_FUNDAMENTAL_FULLR ? (p->d.ny - 1) / 2 + 1 : p->d.ny;
+}
+void domain_cols(gke_plan_t p, int j1, int &c0, int &c1)
+{
+    const int ny = p->d.ny;
+    c0 = p->domain == GKE_DOMAIN_ALLPAIRS_HALFRX ? 0 : j1;
+    c1 = p->domain == GKE_DOMAIN_FUNDAMENTAL_FULLR ? ny - j1 : ny;
+}
+
+// Tables of every slab (general modes): rows with accumulators = the slab's
+// output rows, their five-point stencil rows and, with the mirror average,
+// the reflections of both; tile pairs = every row tile against every column
+// tile (ordered pairs); remainder pairs = every row against the last
+// Ny mod 16 planes.
+void build_slabs(gke_plan_t p)
+{
+    const gke::Dims &d = p->d;
+    const int ny = d.ny, nrows = domain_rows(p);
+    const int R = p->slab_rows > 0 ? std::min(p->slab_rows, nrows) : nrows;
+    p->slabs.clear();
+    for (int y1b = 0; y1b < nrows; y1b += R) {
+        SlabTables t;
+        t.y1b = y1b;
+        t.y1e = std::min(nrows, y1b + R);
+        std::vector<char> in(ny, 0);
+        for (int j = t.y1b; j < t.y1e; ++j) {
+            in[j] = 1;
+            for (int a = 0; a < 5; ++a) in[p->h_j0[j] + a] = 1;
+        }
+        if (p->mirror)
+            for (int j = 0; j < ny; ++j)
+                if (in[j]) in[ny - 1 - j] = 2 | in[ny - 1 - j];
+        t.rowidx.assign(ny, -1);
+        for (int j = 0; j < ny; ++j)
+            if (in[j]) {
+                t.rowidx[j] = (int)t.rows.size();
+                t.rows.push_back(j);
+            }
+        t.rowplane = t.rows;
+        while (t.rowplane.size() % 16) t.rowplane.push_back(t.rows.back());
+        const int nrt = d.ntile > 0 ? (int)t.rowplane.size() / 16 : 0;
+        for (int rt = 0; rt < nrt; ++rt)
+            for (int ct = 0; ct < d.ntile; ++ct) {
+                t.ta.push_back(rt);
+                t.tb.push_back(ct);
+                for (int i = 0; i < 16; ++i)
+                    for (int k = 0; k < 16; ++k)
+                        t.pairs.push_back(t.rowplane[16 * rt + i] | (16 * ct + k) << 12);
+            }
+        t.ntp = (int)t.ta.size();
+        t.npair_tiles = 256 * t.ntp;
+        for (int r : t.rows)
+            for (int c = 16 * d.ntile; c < ny; ++c) t.pairs.push_back(r | c << 12);
+        t.npair = (int)t.pairs.size();
+        if (t.ta.empty()) {
+            t.ta.push_back(0);
+            t.tb.push_back(0);
+        }
+        for (int j1 = t.y1b; j1 < t.y1e; ++j1) {
+            int c0, c1;
+            domain_cols(p, j1, c0, c1);
+            for (int j2 = c0; j2 < c1; ++j2) t.opairs.push_back(j1 | j2 << 16);
+        }
+        p->slabs.push_back(std::move(t));
+    }
+}
+
 // Workspace layout; with base != nullptr also assigns the pointers.
 size_t layout(gke_plan_t p, char *base)
 {
@@ -186,17 +277,33 @@ size_t layout(gke_plan_t p, char *base)
         off = align256(off + bytes);
         return base ? base + o : nullptr;
     };
-    const int pbt = (p->pair_batch > 0 && p->pair_batch < d.npair) ? p->pair_batch : d.npair;
+    // table and accumulator extents: all pairs, or the largest slab
+    size_t ntp = std::max(d.ntp, 1), npair = d.npair, nrowp = p->h_rowplane.size();
+    size_t nrows = 0, nopairs = 1;
+    if (p->general) {
+        ntp = npair = nrowp = 1;
+        for (const auto &t : p->slabs) {
+            ntp = std::max(ntp, t.ta.size());
+            npair = std::max(npair, (size_t)t.npair);
+            nrowp = std::max(nrowp, t.rowplane.size());
+            nrows = std::max(nrows, t.rows.size());
+            nopairs = std::max(nopairs, t.opairs.size());
+        }
+    }
+    const size_t pbt = (p->pair_batch > 0 && (size_t)p->pair_batch < npair) ? p->pair_batch : npair;
     p->twx = (cx<double> *)take(sizeof(cx<double>) * d.nx);
     p->twz = (cx<double> *)take(sizeof(cx<double>) * d.nz);
     p->twx32 = (cx<float> *)take(sizeof(cx<float>) * d.nx);
     p->twz32 = (cx<float> *)take(sizeof(cx<float>) * d.nz);
     p->w5 = (double *)take(sizeof(double) * 5 * d.ny);
     p->j0 = (int *)take(sizeof(int) * d.ny);
-    p->ta = (int *)take(sizeof(int) * std::max(d.ntp, 1));
-    p->tb = (int *)take(sizeof(int) * std::max(d.ntp, 1));
-    p->pairs = (int *)take(sizeof(int) * d.npair);
+    p->ta = (int *)take(sizeof(int) * ntp);
+    p->tb = (int *)take(sizeof(int) * ntp);
+    p->pairs = (int *)take(sizeof(int) * npair);
     p->pidx = (int *)take(sizeof(int) * d.ny * d.ny);
+    p->rowplane = (int *)take(sizeof(int) * nrowp);
+    p->rowidx = (int *)take(sizeof(int) * d.ny);
+    p->opairs = (int *)take(sizeof(int) * nopairs);
     p->sums1 = (double *)take(sizeof(double) * 4 * d.ny * gke::NSPLIT);
     p->prof = (double *)take(sizeof(double) * gke::NPROF * d.ny);
     p->momp = (double *)take(sizeof(double) * d.ny * gke::NMOMP * d.nzb);
@@ -206,9 +313,33 @@ size_t layout(gke_plan_t p, char *base)
     const size_t esz = d.prec == gke::PREC_BF16X3 ? 8 : sizeof(cx<double>);
     p->inter = take(esz * (size_t)d.ny * d.nzb * gke::NFIELD * d.nkx * d.zb);
     p->spec = take(esz * (size_t)d.nk * gke::NFIELD * d.chunk * d.ny);
-    p->acc = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NSPEC * d.nk * d.npair);
+    p->acc = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NSPEC * d.nk * npair);
     p->mid = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NMAP * d.nkx * d.nz * pbt);
+    p->mstride = nrows * d.ny * (size_t)d.nz * d.nx;
+    p->mf = (double *)take(sizeof(double) * gke::NSTORED * p->mstride);
+    p->band = (double *)take(p->general ? sizeof(double) * (size_t)d.nk * 5 * d.ny : 0);
     return off;
+}
+
+// Make slab s current: upload its tables, set the pair extents.
+gke_status select_slab(gke_plan_t p, int s)
+{
+    const SlabTables &t = p->slabs[s];
+    hipStream_t st = p->stream;
+    GKE_HIP(p, hipMemcpyAsync(p->rowplane, t.rowplane.data(), sizeof(int) * t.rowplane.size(), hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->rowidx, t.rowidx.data(), sizeof(int) * t.rowidx.size(), hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->ta, t.ta.data(), sizeof(int) * t.ta.size(), hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->tb, t.tb.data(), sizeof(int) * t.tb.size(), hipMemcpyHostToDevice, st));
+    if (t.npair > 0)
+        GKE_HIP(p, hipMemcpyAsync(p->pairs, t.pairs.data(), sizeof(int) * t.npair, hipMemcpyHostToDevice, st));
+    if (!t.opairs.empty())
+        GKE_HIP(p, hipMemcpyAsync(p->opairs, t.opairs.data(), sizeof(int) * t.opairs.size(), hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipStreamSynchronize(st));
+    p->d.ntp = t.ntp;
+    p->d.npair_tiles = t.npair_tiles;
+    p->d.npair = t.npair;
+    p->cur_slab = s;
+    return GKE_OK;
 }
 
 gke_status launch_flush(gke_plan_t p)
@@ -234,6 +365,10 @@ gke_status launch_flush(gke_plan_t p)
                                                      accumulate, p->acc);
         }));
     }
+    if (p->general)  // eps needs the band pairs of every plane, not only the slab's
+        GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {
+            return gke::launch_band(p->stream, p->d, p->spec, p->pending, accumulate, p->band);
+        }));
     ++p->chunks_done;
     p->pending = 0;
     return GKE_OK;
@@ -348,6 +483,7 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
             delete p;
             return fail(nullptr, GKE_ERR_UNSUPPORTED, "internal pair table incomplete");
         }
+    for (int i = 0; i < std::max(16 * d.ntile, 1); ++i) p->h_rowplane.push_back(i);
     p->tab.px = radix_plan(Nx);
     p->tab.pz = radix_plan(Nz);
     *out = p;
@@ -385,14 +521,51 @@ gke_status gke_set_option(gke_plan_t p, int key, int64_t value)
         if (value < 0 || value > 1000000) return fail(p, GKE_ERR_ARG, "bad pair batch");
         p->pair_batch = (int)value;
         return GKE_OK;
+    case GKE_OPT_MIRROR: {
+        if (value != 0 && value != 1) return fail(p, GKE_ERR_ARG, "mirror must be 0 or 1");
+        if (value == 1) {
+            const int ny = p->d.ny;
+            const double span = p->y[ny - 1] - p->y[0], c = p->y[0] + p->y[ny - 1];
+            for (int j = 0; j < ny; ++j)
+                if (std::fabs(p->y[ny - 1 - j] - (c - p->y[j])) > 1e-13 * span)
+                    return fail(p, GKE_ERR_ARG, "mirror needs a y grid symmetric about its centre");
+        }
+        p->mirror = (int)value;
+        return GKE_OK;
+    }
+    case GKE_OPT_DOMAIN:
+        if (value != GKE_DOMAIN_ALLPAIRS_HALFRX && value != GKE_DOMAIN_Y1LEY2_FULLR &&
+            value != GKE_DOMAIN_FUNDAMENTAL_FULLR)
+            return fail(p, GKE_ERR_ARG, "unknown output domain");
+        p->domain = (int)value;
+        return GKE_OK;
+    case GKE_OPT_SLAB:
+        if (value < 0 || value > 4096) return fail(p, GKE_ERR_ARG, "slab rows must be in [0, 4096]");
+        p->slab_rows = (int)value;
+        return GKE_OK;
     default:
         return fail(p, GKE_ERR_ARG, "unknown option key");
     }
 }
 
+// Fix the output mode from the options (before sizing the workspace).
+gke_status prepare_mode(gke_plan_t p)
+{
+    if (p->domain == GKE_DOMAIN_FUNDAMENTAL_FULLR && !p->mirror)
+        return fail(p, GKE_ERR_ARG, "the fundamental domain needs GKE_OPT_MIRROR = 1");
+    p->general = p->mirror || p->domain != GKE_DOMAIN_ALLPAIRS_HALFRX || p->slab_rows > 0;
+    if (p->general) build_slabs(p);
+    else p->slabs.clear();
+    return GKE_OK;
+}
+
 gke_status gke_workspace_size(gke_plan_t p, size_t *bytes)
 {
     if (!p || !bytes) return fail(p, GKE_ERR_ARG, "NULL argument");
+    if (!p->ws) {
+        gke_status s = prepare_mode(p);
+        if (s != GKE_OK) return s;
+    }
     *bytes = layout(p, nullptr);
     return GKE_OK;
 }
@@ -402,6 +575,10 @@ gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
     if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
     if (p->ws) return fail(p, GKE_ERR_STATE, "workspace already set");
     if (!dev || ((uintptr_t)dev & 255)) return fail(p, GKE_ERR_ARG, "workspace NULL or not 256-byte aligned");
+    {
+        gke_status s = prepare_mode(p);
+        if (s != GKE_OK) return s;
+    }
     const size_t need = layout(p, nullptr);
     if (bytes < need)
         return fail(p, GKE_ERR_OOM, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -416,9 +593,12 @@ gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
     GKE_HIP(p, hipMemcpyAsync(p->twz32, p->h_twz32.data(), sizeof(cx<float>) * d.nz, hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->w5, p->h_w5.data(), sizeof(double) * 5 * d.ny, hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->j0, p->h_j0.data(), sizeof(int) * d.ny, hipMemcpyHostToDevice, st));
-    GKE_HIP(p, hipMemcpyAsync(p->ta, p->h_ta.data(), sizeof(int) * p->h_ta.size(), hipMemcpyHostToDevice, st));
-    GKE_HIP(p, hipMemcpyAsync(p->tb, p->h_tb.data(), sizeof(int) * p->h_tb.size(), hipMemcpyHostToDevice, st));
-    GKE_HIP(p, hipMemcpyAsync(p->pairs, p->h_pairs.data(), sizeof(int) * d.npair, hipMemcpyHostToDevice, st));
+    if (!p->general) {  // all-pairs tables (a slab uploads its own)
+        GKE_HIP(p, hipMemcpyAsync(p->ta, p->h_ta.data(), sizeof(int) * p->h_ta.size(), hipMemcpyHostToDevice, st));
+        GKE_HIP(p, hipMemcpyAsync(p->tb, p->h_tb.data(), sizeof(int) * p->h_tb.size(), hipMemcpyHostToDevice, st));
+        GKE_HIP(p, hipMemcpyAsync(p->pairs, p->h_pairs.data(), sizeof(int) * d.npair, hipMemcpyHostToDevice, st));
+        GKE_HIP(p, hipMemcpyAsync(p->rowplane, p->h_rowplane.data(), sizeof(int) * p->h_rowplane.size(), hipMemcpyHostToDevice, st));
+    }
     GKE_HIP(p, hipMemcpyAsync(p->pidx, p->h_pidx.data(), sizeof(int) * d.ny * d.ny, hipMemcpyHostToDevice, st));
     // sums, profiles and moment partials start at zero
     GKE_HIP(p, hipMemsetAsync(p->sums1, 0, (char *)p->inter - (char *)p->sums1, st));
@@ -433,6 +613,9 @@ gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
     p->tab.tile_b = p->tb;
     p->tab.pairs = p->pairs;
     p->tab.pidx = p->pidx;
+    p->tab.rowplane = p->rowplane;
+    p->tab.rowidx = p->rowidx;
+    if (p->general) return select_slab(p, 0);
     return GKE_OK;
 }
 
@@ -512,7 +695,7 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
     if (!p->second_scan || p->n2 == 0) return fail(p, GKE_ERR_STATE, "no second-scan snapshot");
     if (!p->means_from_host && p->n1 != p->n2)
         return fail(p, GKE_ERR_STATE, "the two scans saw different snapshot counts");
-    if ((out->t[GKE_T_PHIY_V] || out->t[GKE_T_PHI_V]) && !out->t[GKE_T_DU2])
+    if (!p->general && (out->t[GKE_T_PHIY_V] || out->t[GKE_T_PHI_V]) && !out->t[GKE_T_DU2])
         return fail(p, GKE_ERR_ARG, "the Y-derivative terms need the <du^2> output buffer");
     gke_status s = launch_flush(p);
     if (s != GKE_OK) return s;
@@ -520,7 +703,8 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
     hipStream_t st = p->stream;
     const double inv = 1.0 / (double)p->n2;
     GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {
-        return gke::launch_r0(st, d, p->tab, p->acc, inv, p->r0, p->gxz);
+        return p->general ? gke::launch_r0_band(st, d, p->band, inv, p->r0, p->gxz)
+                          : gke::launch_r0(st, d, p->tab, p->acc, inv, p->r0, p->gxz);
     }));
     GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {
         return gke::launch_profiles(st, d, p->tab, p->momp, p->r0, p->gxz, (double)p->n2,
@@ -529,13 +713,37 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
     double *outp[14];
     for (int i = 0; i < 14; ++i) outp[i] = (double *)out->t[i];
     const int pbt = (p->pair_batch > 0 && p->pair_batch < d.npair) ? p->pair_batch : d.npair;
+    if (p->general) {
+        // every transformed term of the slab's rows into the full-plane buffer,
+        // then mirror average, domain, T6 / T11 / T14 into the caller's maps
+        static const int kslot[14] = {0, 1, 2, 3, 4, -1, 5, 6, 7, 8, -1, 9, 10, -1};
+        double *mfp[14];
+        for (int i = 0; i < 14; ++i) mfp[i] = kslot[i] >= 0 ? p->mf + kslot[i] * p->mstride : nullptr;
+        for (int q0 = 0; q0 < d.npair; q0 += pbt) {
+            const int q1 = std::min(d.npair, q0 + pbt);
+            GKE_HIP(p, timed(p, GKE_K_FIN_KZ, [&] {
+                return gke::launch_fin_kz(st, d, p->tab, p->acc, q0, q1, inv, p->mid);
+            }));
+            GKE_HIP(p, timed(p, GKE_K_FIN_KX, [&] {
+                return gke::launch_fin_kx(st, d, p->tab, p->mid, q0, q1, p->prof, mfp, 1);
+            }));
+        }
+        const SlabTables &t = p->slabs[p->cur_slab];
+        const int width = p->domain == GKE_DOMAIN_ALLPAIRS_HALFRX ? d.nkx : d.nx;
+        GKE_HIP(p, timed(p, GKE_K_FD, [&] {
+            return gke::launch_slab_out(st, d, p->tab, p->mf, p->mstride, p->opairs,
+                                        (int)t.opairs.size(), p->prof, p->mirror, width, outp);
+        }));
+        GKE_HIP(p, hipStreamSynchronize(st));
+        return GKE_OK;
+    }
     for (int q0 = 0; q0 < d.npair; q0 += pbt) {
         const int q1 = std::min(d.npair, q0 + pbt);
         GKE_HIP(p, timed(p, GKE_K_FIN_KZ, [&] {
             return gke::launch_fin_kz(st, d, p->tab, p->acc, q0, q1, inv, p->mid);
         }));
         GKE_HIP(p, timed(p, GKE_K_FIN_KX, [&] {
-            return gke::launch_fin_kx(st, d, p->tab, p->mid, q0, q1, p->prof, outp);
+            return gke::launch_fin_kx(st, d, p->tab, p->mid, q0, q1, p->prof, outp, 0);
         }));
     }
     if (outp[GKE_T_PHIY_V] || outp[GKE_T_PHI_V])
@@ -548,6 +756,58 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
             return gke::launch_t14(st, d, p->prof, outp[GKE_T_XI_D]);
         }));
     GKE_HIP(p, hipStreamSynchronize(st));
+    return GKE_OK;
+}
+
+gke_status gke_slab_count(gke_plan_t p, int *count)
+{
+    if (!p || !count) return fail(p, GKE_ERR_ARG, "NULL argument");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    *count = p->general ? (int)p->slabs.size() : 1;
+    return GKE_OK;
+}
+
+gke_status gke_slab_pairs(gke_plan_t p, int slab, int *count, int *pairs)
+{
+    if (!p || !count) return fail(p, GKE_ERR_ARG, "NULL argument");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    const int ns = p->general ? (int)p->slabs.size() : 1;
+    if (slab < 0 || slab >= ns) return fail(p, GKE_ERR_ARG, "slab out of range");
+    const int ny = p->d.ny;
+    if (!p->general) {
+        *count = ny * ny;
+        if (pairs)
+            for (int n = 0; n < ny * ny; ++n) {
+                pairs[2 * n] = n / ny;
+                pairs[2 * n + 1] = n % ny;
+            }
+        return GKE_OK;
+    }
+    const SlabTables &t = p->slabs[slab];
+    *count = (int)t.opairs.size();
+    if (pairs)
+        for (size_t n = 0; n < t.opairs.size(); ++n) {
+            pairs[2 * n] = t.opairs[n] & 0xffff;
+            pairs[2 * n + 1] = t.opairs[n] >> 16;
+        }
+    return GKE_OK;
+}
+
+gke_status gke_begin_slab(gke_plan_t p, int slab)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    const int ns = p->general ? (int)p->slabs.size() : 1;
+    if (slab < 0 || slab >= ns) return fail(p, GKE_ERR_ARG, "slab out of range");
+    if (!p->second_scan) return fail(p, GKE_ERR_STATE, "the means are not known yet");
+    // forget the second scan of the previous slab: moments restart, the
+    // accumulators are overwritten by the first chunk
+    GKE_HIP(p, hipMemsetAsync(p->momp, 0, sizeof(double) * p->d.ny * gke::NMOMP * p->d.nzb, p->stream));
+    p->n2 = 0;
+    p->pending = 0;
+    p->chunks_done = 0;
+    if (p->general) return select_slab(p, slab);
+    GKE_HIP(p, hipStreamSynchronize(p->stream));
     return GKE_OK;
 }
 
@@ -572,6 +832,7 @@ gke_status gke_reset(gke_plan_t p)
     p->chunks_done = 0;
     p->second_scan = false;
     p->means_from_host = false;
+    if (p->general && p->cur_slab != 0) return select_slab(p, 0);
     return GKE_OK;
 }
 

@@ -153,7 +153,7 @@ __device__ __forceinline__ void assemble_store(int m, double val, int j1, int j2
 __global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims d,
                                                       Tables t, int p0, int ptot,
                                                       const double *__restrict__ prof,
-                                                      OutPtrs out)
+                                                      OutPtrs out, int full)
 {
     extern __shared__ cx<double> lds[];
     const int nx = d.nx, nz = d.nz, nkx = d.nkx, ny = d.ny, nt = d.ntx;
@@ -190,6 +190,19 @@ __global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims
     }
     __syncthreads();
     lds_fft_ip<double, FFT_CAP, FFT_BLOCK>(A, nt, bs, t.px, tw, +1);
+    if (full) {
+        // one orientation, every rx, rows of the full-plane buffer
+        for (int e = threadIdx.x; e < np * nx; e += blockDim.x) {
+            const int b = e / nx, rx = e - b * nx;
+            const int code = t.pairs[p0 + pl0 + b];
+            const int j1 = pair_j1(code), j2 = pair_j2(code);
+            const cx<double> zv = A[(b >> 1) * bs + fft_pad(rx)];
+            const double val = (b & 1) ? zv.y : zv.x;
+            assemble_store(m, val, j1, j2, prof, ny, d.nu, out,
+                           (((size_t)t.rowidx[j1] * ny + j2) * nz + rz) * nx + rx);
+        }
+        return;
+    }
     const double sig = map_sigma(m);
     const size_t plane = (size_t)nz * nkx;
     for (int e = threadIdx.x; e < np * nkx; e += blockDim.x) {
@@ -214,7 +227,7 @@ __global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims
 
 hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
                          const cx<double> *mid, int p0, int p1, const double *prof,
-                         double *const *out)
+                         double *const *out, int full)
 {
     const int ptot = p1 - p0;
     const size_t lds = sizeof(cx<double>) *
@@ -223,7 +236,8 @@ hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
     for (int i = 0; i < 14; ++i) op.t[i] = out[i];
     dim3 grid((ptot + 2 * d.ntx - 1) / (2 * d.ntx), d.nz, NMAP);
     set_lds_limit(k_fin_kx);
-    hipLaunchKernelGGL(k_fin_kx, grid, dim3(FFT_BLOCK), lds, st, mid, d, t, p0, ptot, prof, op);
+    hipLaunchKernelGGL(k_fin_kx, grid, dim3(FFT_BLOCK), lds, st, mid, d, t, p0, ptot, prof, op,
+                       full);
     return hipGetLastError();
 }
 
@@ -256,6 +270,84 @@ hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const
     const size_t plane = (size_t)d.nz * d.nkx;
     dim3 grid((unsigned)((plane + 255) / 256), d.ny, d.ny);
     hipLaunchKernelGGL(k_fd_terms, grid, dim3(256), 0, st, t1, d, t, t6, t11);
+    return hipGetLastError();
+}
+
+// Output of one slab in the general modes.  The maps of the slab's rows, of
+// their five-point neighbours and (with the mirror average) of the reflected
+// rows sit in the full-plane buffer mf[slot][row][Y2][rz][rx < Nx] for the
+// eleven terms that come from the transforms (slot k of term t: kslot below).
+// For every output pair (Y1, Y2) of the slab (opairs[q] = Y1 | Y2 << 16) and
+// every (rz, rx < width):
+//   mirror = 1: the average with the reflected pair,
+//     (T(Y1, Y2) + sigma_y T(2h - Y1, 2h - Y2)) / 2   (Section "Step 2": the
+//     other half of the channel doubles the sample; sigma_y = sign of the term
+//     under the reflection, Section "Exploiting symmetries");
+//   T6, T11 from the five-point Y1 and Y2 derivatives of the (averaged) <du^2>
+//   (Section "Step 3"), T14 from eps.
+// out[t][(q Nz + rz) width + rx]; T14 out[13][q].
+struct OutPtrs14 {
+    double *t[14];
+};
+
+__global__ __launch_bounds__(256) void k_slab_out(const double *__restrict__ mf, size_t mstride,
+                                                  Dims d, Tables t,
+                                                  const int *__restrict__ opairs,
+                                                  const double *__restrict__ prof, int mirror,
+                                                  int width, OutPtrs14 out)
+{
+    // slot of each term in mf (-1: not a transformed map)
+    constexpr int kslot[14] = {0, 1, 2, 3, 4, -1, 5, 6, 7, 8, -1, 9, 10, -1};
+    constexpr double sig[14] = {1, 1, 1, 1, -1, -1, 1, 1, -1, -1, -1, 1, 1, 1};
+    const int ny = d.ny, nz = d.nz, nx = d.nx;
+    const int q = blockIdx.x, rz = blockIdx.y;
+    const int code = opairs[q];
+    const int j1 = code & 0xffff, j2 = code >> 16;
+    const size_t plane = (size_t)nz * nx;
+    auto M = [&](int slot, int r, int c, size_t ofs) {
+        return mf[slot * mstride + ((size_t)t.rowidx[r] * ny + c) * plane + ofs];
+    };
+    auto Tb = [&](int slot, int r, int c, size_t ofs, double sg) {
+        double v = M(slot, r, c, ofs);
+        if (mirror) v = 0.5 * (v + sg * M(slot, ny - 1 - r, ny - 1 - c, ofs));
+        return v;
+    };
+    const bool fd = out.t[5] || out.t[10];
+    const int a1 = t.j0[j1], a2 = t.j0[j2];
+    for (int rx = threadIdx.x; rx < width; rx += blockDim.x) {
+        const size_t ofs = (size_t)rz * nx + rx;
+        const size_t o = ((size_t)q * nz + rz) * width + rx;
+#pragma unroll
+        for (int k = 0; k < 14; ++k)
+            if (kslot[k] >= 0 && out.t[k]) out.t[k][o] = Tb(kslot[k], j1, j2, ofs, sig[k]);
+        if (fd) {
+            double d1 = 0.0, d2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                d1 += t.w5[j1 * 5 + a] * Tb(0, a1 + a, j2, ofs, 1.0);
+                d2 += t.w5[j2 * 5 + a] * Tb(0, j1, a2 + a, ofs, 1.0);
+            }
+            if (out.t[5]) out.t[5][o] = -d.nu * (d2 - d1);
+            if (out.t[10]) out.t[10][o] = -0.5 * d.nu * (d1 + d2);
+        }
+    }
+    if (out.t[13] && rz == 0 && threadIdx.x == 0) {
+        const double *eps = prof + P_EPS * ny;
+        double v = -2.0 * (eps[j1] + eps[j2]);
+        if (mirror) v = 0.5 * (v - 2.0 * (eps[ny - 1 - j1] + eps[ny - 1 - j2]));
+        out.t[13][q] = v;
+    }
+}
+
+hipError_t launch_slab_out(hipStream_t st, const Dims &d, const Tables &t, const double *mf,
+                           size_t mstride, const int *opairs, int nopairs, const double *prof,
+                           int mirror, int width, double *const *out)
+{
+    OutPtrs14 op;
+    for (int i = 0; i < 14; ++i) op.t[i] = out[i];
+    if (nopairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slab_out, dim3(nopairs, d.nz), dim3(256), 0, st, mf, mstride, d, t,
+                       opairs, prof, mirror, width, op);
     return hipGetLastError();
 }
 

@@ -26,18 +26,22 @@
 // r-inversion symmetry (Section "Exploiting symmetries") at finalize.
 //
 // The planes split into full 16-plane tiles, handled on the matrix cores by
-// tile pairs (a <= b), and the remaining Ny mod 16 planes, whose pairs go to a
-// small FP64 vector kernel.  Accumulators are indexed by a compact pair index
-// P: tile pair tp covers P = 256 tp + 16 (Y1 offset) + (Y2 offset), the
-// remainder pairs follow in the order of the host-built pair table.
+// tile pairs, and the remaining Ny mod 16 planes, whose pairs go to a small
+// FP64 vector kernel.  A tile pair (a, b) takes its 16 rows (planes Y1) from
+// the row-plane table at 16 a .. 16 a + 15 and its 16 columns (planes Y2) from
+// 16 b .. 16 b + 15: for all pairs the row table is the identity and a <= b;
+// for a subset of rows (a slab of Y1 planes) it lists those planes.
+// Accumulators are indexed by a compact pair index P: tile pair tp covers
+// P = 256 tp + 16 (row offset) + (column offset), the remainder pairs follow in
+// the order of the host-built pair table.
 //
 // MFMA mapping (v_mfma_f64_16x16x4f64, one wave per 16x16 output tile):
 //   K index = (snapshot pair s0, s0+1) x (real, imaginary part);
-//   A (lane l): Re/Im of L[Y1 = 16a + l%16][s0 + (l/16)/2], picked by (l/16)%2;
+//   A (lane l): Re/Im of L[Y1 = row plane 16a + l%16][s0 + (l/16)/2], picked by (l/16)%2;
 //   B (lane l): for the real output (Rr, Ri), for the imaginary output
 //               (Ri, -Rr) of R[Y2 = 16b + l%16][s0 + (l/16)/2];
 //   so sum_k A B = Re/Im of conj(L) R.
-//   D (lane l, register v): element (Y1 = 16a + l/16 + 4v, Y2 = 16b + l%16)
+//   D (lane l, register v): element (row l/16 + 4v, Y2 = 16b + l%16)
 //   (checked on the device: the f64 form strides the rows by 4 across registers).
 #include "rankk_common.h"
 
@@ -153,8 +157,8 @@ __device__ __forceinline__ void rankk_f64_step(d4 *ar, d4 *ai, const Operands &c
 // acc layout: [NSPEC][nk][P] complex.
 __global__ __launch_bounds__(64, GKE_RANKK_MINW) void k_rankk_f64(
     const cx<double> *__restrict__ spec, Dims d, const int *__restrict__ tile_a,
-    const int *__restrict__ tile_b, int nsnap, int accumulate, int total,
-    cx<double> *__restrict__ acc)
+    const int *__restrict__ tile_b, const int *__restrict__ t_rowplane, int nsnap,
+    int accumulate, int total, cx<double> *__restrict__ acc)
 {
     // XCD-aware order: workgroup i runs on XCD i % 8; give every XCD a
     // contiguous range of (k, tile pair) so the tiles of one wavenumber share
@@ -173,7 +177,8 @@ __global__ __launch_bounds__(64, GKE_RANKK_MINW) void k_rankk_f64(
     const char *kb = reinterpret_cast<const char *>(spec + (size_t)k * NFIELD * fstride);
     const size_t fbytes = fstride * sizeof(cx<double>);
     const unsigned sbytes = (unsigned)d.ny * sizeof(cx<double>);
-    const unsigned loff = (unsigned)(ta * 16 + row) * sizeof(cx<double>) + ri * sizeof(double);
+    const unsigned loff =
+        (unsigned)t_rowplane[ta * 16 + row] * sizeof(cx<double>) + ri * sizeof(double);
     const unsigned roff = (unsigned)(tb * 16 + row) * sizeof(cx<double>);
 
     d4 ar[9], ai[9];
@@ -229,7 +234,7 @@ hipError_t launch_rankk_f64(hipStream_t st, const Dims &d, const Tables &t,
         if (total >= (1LL << 31) - 8) return hipErrorInvalidValue;
         const int G = (int)((total + 7) / 8 * 8);
         hipLaunchKernelGGL(k_rankk_f64, dim3(G), dim3(64), 0, st, spec, d, t.tile_a, t.tile_b,
-                           nsnap, accumulate, (int)total, acc);
+                           t.rowplane, nsnap, accumulate, (int)total, acc);
     }
     return hipGetLastError();
 }

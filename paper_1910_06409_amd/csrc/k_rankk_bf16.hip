@@ -176,8 +176,8 @@ __device__ __forceinline__ void rankk_bf16_step(f4 *ar, f4 *ai, bf16x4 *Lc, cons
 
 __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
     const bf16x4 *__restrict__ spec, Dims d, const int *__restrict__ tile_a,
-    const int *__restrict__ tile_b, int nsnap, int accumulate, int total,
-    cx<double> *__restrict__ acc)
+    const int *__restrict__ tile_b, const int *__restrict__ t_rowplane, int nsnap,
+    int accumulate, int total, cx<double> *__restrict__ acc)
 {
     const int G = gridDim.x;
     const int bid = blockIdx.x;
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
     const char *kb = reinterpret_cast<const char *>(spec + (size_t)k * NFIELD * fstride);
     const size_t fbytes = fstride * sizeof(bf16x4);
     const unsigned sbytes = (unsigned)d.ny * sizeof(bf16x4);
-    const unsigned loff = (unsigned)(ta * 16 + row) * sizeof(bf16x4);
+    const unsigned loff = (unsigned)t_rowplane[ta * 16 + row] * sizeof(bf16x4);
     const unsigned roff = (unsigned)(tb * 16 + row) * sizeof(bf16x4);
 
     f4 ar[9], ai[9];
@@ -248,7 +248,7 @@ hipError_t launch_rankk_bf16x3(hipStream_t st, const Dims &d, const Tables &t,
         if (total >= (1LL << 31) - 8) return hipErrorInvalidValue;
         const int G = (int)((total + 7) / 8 * 8);
         hipLaunchKernelGGL(k_rankk_bf16x3, dim3(G), dim3(64), 0, st, spec, d, t.tile_a, t.tile_b,
-                           nsnap, accumulate, (int)total, acc);
+                           t.rowplane, nsnap, accumulate, (int)total, acc);
     }
     return hipGetLastError();
 }

@@ -199,6 +199,93 @@ hipError_t launch_profiles(hipStream_t st, const Dims &d, const Tables &t, const
     return hipGetLastError();
 }
 
+// Band accumulators for the general modes (where the accumulators hold only
+// the rows of one slab): for every wavenumber k, plane Y and offset a = 0..4,
+//   band[k][a][Y] (+)= sum over the chunk of sum_i Re conj(u_i^(k;Y)) u_i^(k;Y+a),
+// the same scale-energy products k_r0 reads from the full accumulators.
+__device__ __forceinline__ cx<double> band_value(const cx<double> *s, size_t i) { return s[i]; }
+__device__ __forceinline__ cx<double> band_value(const bf16x4 *s, size_t i)
+{
+    const bf16x4 v = s[i];
+    return cx<double>{(double)__uint_as_float(v.re << 16) + (double)__uint_as_float(v.re & 0xffff0000u),
+                      (double)__uint_as_float(v.im << 16) + (double)__uint_as_float(v.im & 0xffff0000u)};
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_band(const S *__restrict__ spec, Dims d, int nsnap,
+                                              int accumulate, double *__restrict__ band)
+{
+    const int k = blockIdx.x, ny = d.ny;
+    const size_t fstride = (size_t)d.chunk * ny;
+    const S *kb = spec + (size_t)k * NFIELD * fstride;
+    for (int e = threadIdx.x; e < 5 * ny; e += blockDim.x) {
+        const int a = e / ny, j = e - a * ny;
+        double s = 0.0;
+        if (j + a < ny) {
+            for (int sl = 0; sl < nsnap; ++sl)
+                for (int f = F_U; f <= F_W; ++f) {
+                    const size_t o = f * fstride + (size_t)sl * ny + j;
+                    const cx<double> x = band_value(kb, o), y = band_value(kb, o + a);
+                    s += x.x * y.x + x.y * y.y;
+                }
+        }
+        double *dst = band + (size_t)k * 5 * ny + e;
+        *dst = accumulate ? *dst + s : s;
+    }
+}
+
+hipError_t launch_band(hipStream_t st, const Dims &d, const void *spec, int nsnap,
+                       int accumulate, double *band)
+{
+    if (d.prec == PREC_BF16X3)
+        hipLaunchKernelGGL(k_band<bf16x4>, dim3(d.nk), dim3(256), 0, st, (const bf16x4 *)spec, d,
+                           nsnap, accumulate, band);
+    else
+        hipLaunchKernelGGL(k_band<cx<double>>, dim3(d.nk), dim3(256), 0, st,
+                           (const cx<double> *)spec, d, nsnap, accumulate, band);
+    return hipGetLastError();
+}
+
+// r0 and gxz of k_r0 from the band accumulators (one block per (Y, a)).
+__global__ __launch_bounds__(256) void k_r0_band(const double *__restrict__ band, Dims d,
+                                                 double inv_count, double *__restrict__ r0,
+                                                 double *__restrict__ gxz)
+{
+    __shared__ double sh[8];
+    const int y = blockIdx.x, a = blockIdx.y, ny = d.ny;
+    if (y + a >= ny) {
+        if (threadIdx.x == 0) r0[y * 5 + a] = 0.0;
+        return;
+    }
+    const double two_pi = 6.283185307179586476925286766559;
+    double r = 0.0, g = 0.0;
+    for (int k = threadIdx.x; k < d.nk; k += blockDim.x) {
+        const int kx = k / d.nz, kz = k - kx * d.nz;
+        const double w = (kx == 0 || 2 * kx == d.nx) ? 1.0 : 2.0;
+        const double v = w * band[(size_t)k * 5 * ny + a * ny + y];
+        r += v;
+        if (a == 0) {
+            const int kzs = (kz <= d.nz / 2) ? kz : kz - d.nz;
+            const double al = (2 * kx == d.nx) ? 0.0 : two_pi * kx / d.lx;
+            const double be = (2 * kz == d.nz) ? 0.0 : two_pi * kzs / d.lz;
+            g += (al * al + be * be) * v;
+        }
+    }
+    r = block_sum(r, sh);
+    g = block_sum(g, sh);
+    if (threadIdx.x == 0) {
+        r0[y * 5 + a] = r * inv_count;
+        if (a == 0) gxz[y] = g * inv_count;
+    }
+}
+
+hipError_t launch_r0_band(hipStream_t st, const Dims &d, const double *band, double inv_count,
+                          double *r0, double *gxz)
+{
+    hipLaunchKernelGGL(k_r0_band, dim3(d.ny, 5), dim3(256), 0, st, band, d, inv_count, r0, gxz);
+    return hipGetLastError();
+}
+
 __global__ void k_t14(int ny, const double *__restrict__ prof, double *__restrict__ t14)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -17,6 +17,8 @@ LIB_PATH = os.environ.get("GKE_LIBRARY") or os.path.join(_HERE, "libgke.so")
 
 GKE_OK, GKE_ERR_ARG, GKE_ERR_STATE, GKE_ERR_OOM, GKE_ERR_HIP, GKE_ERR_UNSUPPORTED = range(6)
 GKE_OPT_DTYPE, GKE_OPT_PRECISION, GKE_OPT_CHUNK, GKE_OPT_PAIR_BATCH, GKE_OPT_TIMING = 1, 2, 3, 4, 5
+GKE_OPT_MIRROR, GKE_OPT_DOMAIN, GKE_OPT_SLAB = 6, 7, 8
+GKE_DOMAIN_ALLPAIRS_HALFRX, GKE_DOMAIN_Y1LEY2_FULLR, GKE_DOMAIN_FUNDAMENTAL_FULLR = 0, 1, 2
 GKE_DTYPE_F64, GKE_DTYPE_F32 = 0, 1
 GKE_PREC_FP64, GKE_PREC_BF16X3 = 0, 1
 GKE_NTERMS = 14
@@ -70,6 +72,9 @@ def lib() -> ctypes.CDLL:
         "gke_set_means": ([vp, dp, dp, dp, dp], i32),
         "gke_finalize": ([vp, ctypes.POINTER(gke_terms)], i32),
         "gke_get_profiles": ([vp, dp], i32),
+        "gke_slab_count": ([vp, ctypes.POINTER(i32)], i32),
+        "gke_slab_pairs": ([vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "gke_begin_slab": ([vp, i32], i32),
         "gke_reset": ([vp], i32),
         "gke_timings": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                          i32], i32),
@@ -156,6 +161,26 @@ def gke_get_profiles(plan, ny: int) -> np.ndarray:
     out = np.zeros((GKE_NPROF, ny))
     _check(lib().gke_get_profiles(plan, _dp(out)), plan)
     return out
+
+
+def gke_slab_count(plan) -> int:
+    n = ctypes.c_int()
+    _check(lib().gke_slab_count(plan, ctypes.byref(n)), plan)
+    return n.value
+
+
+def gke_slab_pairs(plan, slab: int) -> np.ndarray:
+    """Output pairs of a slab in layout order, int array [n][2] of (Y1, Y2)."""
+    n = ctypes.c_int()
+    _check(lib().gke_slab_pairs(plan, slab, ctypes.byref(n), None), plan)
+    out = np.zeros((n.value, 2), dtype=np.int32)
+    _check(lib().gke_slab_pairs(plan, slab, ctypes.byref(n),
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))), plan)
+    return out
+
+
+def gke_begin_slab(plan, slab: int) -> None:
+    _check(lib().gke_begin_slab(plan, slab), plan)
 
 
 def gke_reset(plan) -> None:

@@ -17,7 +17,8 @@ class GkeRun:
     """
 
     def __init__(self, nx, ny, nz, y, lx, lz, nu, *, dtype="f64", precision="fp64",
-                 chunk=64, pair_batch=0, device="cuda", stream=None):
+                 chunk=64, pair_batch=0, mirror=0, domain=0, slab=0, device="cuda",
+                 stream=None):
         self.nx, self.ny, self.nz = nx, ny, nz
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
@@ -31,6 +32,11 @@ class GkeRun:
                            gke.GKE_PREC_BF16X3 if precision == "bf16x3" else gke.GKE_PREC_FP64)
         gke.gke_set_option(self.plan, gke.GKE_OPT_CHUNK, int(chunk))
         gke.gke_set_option(self.plan, gke.GKE_OPT_PAIR_BATCH, int(pair_batch))
+        gke.gke_set_option(self.plan, gke.GKE_OPT_MIRROR, int(mirror))
+        gke.gke_set_option(self.plan, gke.GKE_OPT_DOMAIN, int(domain))
+        gke.gke_set_option(self.plan, gke.GKE_OPT_SLAB, int(slab))
+        self.domain = int(domain)
+        self.general = bool(mirror or domain or slab)
         gke.gke_set_stream(self.plan, self.stream.cuda_stream)
         nbytes = gke.gke_workspace_size(self.plan)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -57,14 +63,29 @@ class GkeRun:
     def set_means(self, U, V, W, P):
         gke.gke_set_means(self.plan, U, V, W, P)
 
-    def alloc_terms(self, which=None):
+    def alloc_terms(self, which=None, slab=0):
+        """Output maps for gke_finalize (of `slab` in the general modes)."""
         which = range(gke.GKE_NTERMS) if which is None else which
-        shape = (self.ny, self.ny, self.nz, self.nx // 2 + 1)
+        if self.general:
+            n = len(gke.gke_slab_pairs(self.plan, slab))
+            width = self.nx // 2 + 1 if self.domain == gke.GKE_DOMAIN_ALLPAIRS_HALFRX else self.nx
+            shape, s14 = (n, self.nz, width), (n,)
+        else:
+            shape, s14 = (self.ny, self.ny, self.nz, self.nx // 2 + 1), (self.ny, self.ny)
         out = [None] * gke.GKE_NTERMS
         for i in which:
-            shp = (self.ny, self.ny) if i == 13 else shape
-            out[i] = torch.empty(shp, dtype=torch.float64, device=self.device)
+            out[i] = torch.empty(s14 if i == 13 else shape, dtype=torch.float64,
+                                 device=self.device)
         return out
+
+    def slab_count(self) -> int:
+        return gke.gke_slab_count(self.plan)
+
+    def slab_pairs(self, slab: int) -> np.ndarray:
+        return gke.gke_slab_pairs(self.plan, slab)
+
+    def begin_slab(self, slab: int):
+        gke.gke_begin_slab(self.plan, slab)
 
     def finalize(self, out=None):
         if out is None:
@@ -111,3 +132,28 @@ def run_snapshots(snaps_dev, y, lx, lz, nu, *, dtype="f64", precision="fp64", ch
     prof = r.profiles()
     r.close()
     return out, prof
+
+
+def run_slabs(snaps_dev, y, lx, lz, nu, *, dtype="f64", precision="fp64", chunk=64,
+              pair_batch=0, mirror=0, domain=0, slab=0, which=None):
+    """Both scans, then one second scan and finalize per slab.  Returns
+    ([(pairs [n][2], maps of the slab)], profiles); maps as gke_finalize lays
+    them out for the general modes."""
+    S, _, ny, nz, nx = snaps_dev.shape
+    r = GkeRun(nx, ny, nz, y, lx, lz, nu, dtype=dtype, precision=precision, chunk=chunk,
+               pair_batch=pair_batch, mirror=mirror, domain=domain, slab=slab,
+               device=snaps_dev.device)
+    for s in range(S):
+        r.accumulate_snapshot(snaps_dev[s])
+    r.begin_stats()
+    res = []
+    for sl in range(r.slab_count()):
+        if sl > 0:
+            r.begin_slab(sl)
+        for s in range(S):
+            r.accumulate_snapshot(snaps_dev[s])
+        out = r.finalize(r.alloc_terms(which, slab=sl))
+        res.append((r.slab_pairs(sl), out))
+    prof = r.profiles()
+    r.close()
+    return res, prof

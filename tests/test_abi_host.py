@@ -84,6 +84,42 @@ def test_options_and_state_errors():
         gke.gke_destroy(p)
 
 
+def test_general_mode_options():
+    y = np.linspace(-1, 1, 17)
+    p = gke.gke_plan(16, 17, 16, y, 2 * np.pi, np.pi, 0.005)
+    try:
+        n_all = gke.gke_workspace_size(p)
+        for key, bad in [(gke.GKE_OPT_MIRROR, 2), (gke.GKE_OPT_DOMAIN, 5), (gke.GKE_OPT_SLAB, -1)]:
+            with pytest.raises(gke.GkeError) as e:
+                gke.gke_set_option(p, key, bad)
+            assert e.value.status == gke.GKE_ERR_ARG
+        # the fundamental domain needs the mirror average
+        gke.gke_set_option(p, gke.GKE_OPT_DOMAIN, gke.GKE_DOMAIN_FUNDAMENTAL_FULLR)
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_workspace_size(p)
+        assert e.value.status == gke.GKE_ERR_ARG
+        gke.gke_set_option(p, gke.GKE_OPT_MIRROR, 1)
+        gke.gke_set_option(p, gke.GKE_OPT_SLAB, 2)
+        n_slab = gke.gke_workspace_size(p)
+        assert 0 < n_slab
+        with pytest.raises(gke.GkeError) as e:   # slab queries need the workspace
+            gke.gke_slab_count(p)
+        assert e.value.status == gke.GKE_ERR_STATE
+        del n_all
+    finally:
+        gke.gke_destroy(p)
+    # a grid that is not symmetric about its centre refuses the mirror average
+    ya = np.linspace(-1, 1, 17) ** 3 + 0.01 * np.linspace(-1, 1, 17) ** 2
+    p = gke.gke_plan(16, 17, 16, ya, 1.0, 1.0, 0.01)
+    try:
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_set_option(p, gke.GKE_OPT_MIRROR, 1)
+        assert e.value.status == gke.GKE_ERR_ARG
+        assert "symmetric" in gke.gke_last_error(p)
+    finally:
+        gke.gke_destroy(p)
+
+
 def test_workspace_scales_with_grid():
     from paper_1910_06409_amd import synth
     w = synth.workload("re200")
