@@ -39,8 +39,9 @@ constexpr int NSTORED = 11;
 // profile rows (same order as the public GKE_P_* rows)
 enum { P_U = 0, P_V, P_W, P_P, P_S, P_Q, P_UV, P_PV, P_TX, P_TY, P_TZ, P_EPS, NPROF };
 
-// physical-space moment partials per (plane, z block): q uv pv qu qv qw
-enum { MP_Q = 0, MP_UV, MP_PV, MP_QU, MP_QV, MP_QW, NMOMP };
+// physical-space moment partials per (plane, z block): q uv pv qu qv qw and,
+// on the split-BF16 path, the wall-normal gradient energy gy
+enum { MP_Q = 0, MP_UV, MP_PV, MP_QU, MP_QV, MP_QW, MP_GY, NMOMP };
 
 // pass-1 plane sums are split over this many blocks per plane
 constexpr int NSPLIT = 8;

@@ -3,7 +3,10 @@
 // physical space (Section "Products instead of correlations"), and the 2-D
 // forward transform of every plane, written in the layout the cross-spectral
 // update reads.  Also the FP64 one-point moments.  (The pseudo-dissipation is
-// formed at finalize from the scale-energy spectra, by the Parseval identity.)
+// formed at finalize from the scale-energy spectra, by the Parseval identity;
+// on the split-BF16 path its wall-normal part is summed here instead, from FP64
+// five-point differences of the fluctuations: forming it from the split
+// spectra, sum_ab w_a w_b <u'(Y_a) u'(Y_b)>, would lose digits to cancellation.)
 //
 // Normalisation: A^(kx,kz) = (1/(Nx Nz)) sum_{x,z} A e^{-i(alpha x + beta z)}.
 #include "gke_internal.h"
@@ -85,7 +88,16 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
     const double U = prof[P_U * ny + j], V = prof[P_V * ny + j];
     const double W = prof[P_W * ny + j], P = prof[P_P * ny + j];
     const int nel = zb * nx;
-    double mq = 0, muv = 0, mpv = 0, mqu = 0, mqv = 0, mqw = 0;
+    constexpr bool kGy = sizeof(T) == sizeof(float);   // split-BF16 path
+    const int js = t.j0[j];
+    double wt[5], Ms[3][5];
+    for (int a = 0; a < 5; ++a) {
+        wt[a] = kGy ? t.w5[j * 5 + a] : 0.0;
+        Ms[0][a] = kGy ? prof[P_U * ny + js + a] : 0.0;
+        Ms[1][a] = kGy ? prof[P_V * ny + js + a] : 0.0;
+        Ms[2][a] = kGy ? prof[P_W * ny + js + a] : 0.0;
+    }
+    double mq = 0, muv = 0, mpv = 0, mqu = 0, mqv = 0, mqw = 0, mgy = 0;
     for (int e = threadIdx.x; e < nel; e += blockDim.x) {
         const double a = (double)u[off + e] - U, b = (double)v[off + e] - V;
         const double c = (double)w[off + e] - W, dd = (double)p[off + e] - P;
@@ -96,6 +108,16 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
         mqu += q * a;
         mqv += q * b;
         mqw += q * c;
+        if (kGy) {
+            double gu = 0, gv = 0, gw = 0;
+            for (int k = 0; k < 5; ++k) {
+                const size_t o = (size_t)(js + k) * npl + (size_t)z0 * nx + e;
+                gu += wt[k] * ((double)u[o] - Ms[0][k]);
+                gv += wt[k] * ((double)v[o] - Ms[1][k]);
+                gw += wt[k] * ((double)w[o] - Ms[2][k]);
+            }
+            mgy += gu * gu + gv * gv + gw * gw;
+        }
         // (u,v) (w,p) (Qxx,Qyy) (Qzz,Qxy) (Qxz,Qyz), two real rows per complex row
         const int row = e / nx, x = fft_pad(e - row * nx);
         lds[(0 * zb + row) * bs + x] = cx<T>{(T)a, (T)b};
@@ -104,7 +126,7 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
         lds[(3 * zb + row) * bs + x] = cx<T>{(T)(2.0 * c * c + q), (T)(2.0 * a * b)};
         lds[(4 * zb + row) * bs + x] = cx<T>{(T)(2.0 * a * c), (T)(2.0 * b * c)};
     }
-    const double parts[NMOMP] = {mq, muv, mpv, mqu, mqv, mqw};
+    const double parts[NMOMP] = {mq, muv, mpv, mqu, mqv, mqw, mgy};
     for (int k = 0; k < NMOMP; ++k) {
         const double r = block_sum_fixed(parts[k], sh);
         if (threadIdx.x == 0) momp[((size_t)j * NMOMP + k) * d.nzb + zblk] += r;

@@ -162,7 +162,8 @@ hipError_t launch_r0(hipStream_t st, const Dims &d, const Tables &t, const cx<do
 __global__ void k_profiles(int ny, int nzb, const double *__restrict__ momp,
                            const double *__restrict__ w5, const int *__restrict__ j0,
                            const double *__restrict__ r0, const double *__restrict__ gxz,
-                           double inv_pts, double nu, double *__restrict__ prof)
+                           double inv_pts, double nu, int gy_direct,
+                           double *__restrict__ prof)
 {
     const int j = blockIdx.x;
     if (threadIdx.x != 0) return;
@@ -187,6 +188,8 @@ __global__ void k_profiles(int ny, int nzb, const double *__restrict__ momp,
     prof[P_TX * ny + j] = s[MP_QU];
     prof[P_TY * ny + j] = s[MP_QV];
     prof[P_TZ * ny + j] = s[MP_QW];
+    // the split-BF16 path sums the wall-normal part in physical space (FP64)
+    if (gy_direct) gy = s[MP_GY];
     prof[P_EPS * ny + j] = nu * (gy + gxz[j]);
 }
 
@@ -195,7 +198,7 @@ hipError_t launch_profiles(hipStream_t st, const Dims &d, const Tables &t, const
 {
     const double inv_pts = 1.0 / (count * (double)d.nx * (double)d.nz);
     hipLaunchKernelGGL(k_profiles, dim3(d.ny), dim3(64), 0, st, d.ny, d.nzb, momp, t.w5, t.j0,
-                       r0, gxz, inv_pts, d.nu, prof);
+                       r0, gxz, inv_pts, d.nu, d.prec == PREC_BF16X3 ? 1 : 0, prof);
     return hipGetLastError();
 }
 
