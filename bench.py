@@ -104,6 +104,10 @@ def main():
                     help="override the rank-k arithmetic of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--also", default="re200_bf16",
+                    help="comma-separated workloads measured after the main one (speed-up per "
+                         "snapshot reported under 'extra'); empty for none")
+    ap.add_argument("--also-steps", type=int, default=2)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device-to-device copy of MIB MiB three times "
                          "(the known-size reference for HBM traffic counters)")
@@ -115,138 +119,168 @@ def main():
               "the multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1910_06409_amd import profiling, runner, synth
 
-    w = synth.workload(args.workload)
-    if args.snapshots:
-        w = synth.workload(args.workload, S=args.snapshots)
-    if args.precision:
-        w = synth.workload(args.workload, S=w.S, precision=args.precision)
-    S = w.S
-    chunk = args.chunk or (S + (S & 1))
-    y = synth.y_grid(w)
+    def load_workload(name, snapshots=0, precision=""):
+        w = synth.workload(name)
+        if snapshots:
+            w = synth.workload(name, S=snapshots)
+        if precision:
+            w = synth.workload(name, S=w.S, precision=precision)
+        return w
+
     dev = torch.device("cuda", 0)
-    tdt = torch.float64 if w.dtype == "f64" else torch.float32
 
-    log(f"[bench] generating {S} snapshots of {w.name} ({w.nx}x{w.ny}x{w.nz}, {w.dtype})")
-    t0 = time.perf_counter()
-    snaps = torch.empty((S, 4, w.ny, w.nz, w.nx), dtype=tdt, device=dev)
-    gen = synth.DeviceSnapshots(w, args.seed, dev)
-    for s in range(S):
-        gen(s, out=snaps[s])
-        if (s + 1) % 100 == 0:
-            log(f"[bench]   {s + 1}/{S} snapshots resident ({time.perf_counter() - t0:.0f} s)")
-    torch.cuda.synchronize()
-
-    r = runner.GkeRun(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu, dtype=w.dtype,
-                      precision=w.precision, chunk=chunk, pair_batch=args.pair_batch,
-                      device=dev)
-    outs = r.alloc_terms()
-    log(f"[bench] workspace {r.workspace.numel() / 2**30:.1f} GiB, outputs "
-        f"{sum(o.numel() for o in outs) * 8 / 2**30:.1f} GiB")
-
-    if args.calibrate_copy:
-        nb = args.calibrate_copy << 20
-        src = torch.ones(nb, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
+    def measure(w, steps, warmup, chunk_arg, calibrate=0):
+        """Time `steps` whole-path steps of workload w; returns a result dict."""
+        S = w.S
+        # one batch for the whole ensemble when it is small, else the library's
+        # automatic chunk (largest batch whose spectra fit its memory budget)
+        chunk = chunk_arg if chunk_arg else (S + (S & 1) if S <= 128 else 0)
+        y = synth.y_grid(w)
+        tdt = torch.float64 if w.dtype == "f64" else torch.float32
+        log(f"[bench] generating {S} snapshots of {w.name} ({w.nx}x{w.ny}x{w.nz}, {w.dtype})")
+        t0 = time.perf_counter()
+        snaps = torch.empty((S, 4, w.ny, w.nz, w.nx), dtype=tdt, device=dev)
+        gen = synth.DeviceSnapshots(w, args.seed, dev)
+        for s in range(S):
+            gen(s, out=snaps[s])
+            if (s + 1) % 100 == 0:
+                log(f"[bench]   {s + 1}/{S} snapshots resident ({time.perf_counter() - t0:.0f} s)")
         torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {nb} bytes done")
-        del src, dst
+        del gen
+        r = runner.GkeRun(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu, dtype=w.dtype,
+                          precision=w.precision, chunk=chunk, pair_batch=args.pair_batch,
+                          device=dev)
+        chunk_used = r.chunk()
+        outs = r.alloc_terms()
+        log(f"[bench] workspace {r.workspace.numel() / 2**30:.1f} GiB, outputs "
+            f"{sum(o.numel() for o in outs) * 8 / 2**30:.1f} GiB, chunk {chunk_used}")
+        if calibrate:
+            nb = calibrate << 20
+            src = torch.ones(nb, dtype=torch.uint8, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"[bench] calibration copy of {nb} bytes done")
+            del src, dst
 
-    def step():
-        r.reset()
-        for s in range(S):
-            r.accumulate_snapshot(snaps[s])
-        r.begin_stats()
-        for s in range(S):
-            r.accumulate_snapshot(snaps[s])
-        r.finalize(outs)
+        def step():
+            r.reset()
+            for s in range(S):
+                r.accumulate_snapshot(snaps[s])
+            r.begin_stats()
+            for s in range(S):
+                r.accumulate_snapshot(snaps[s])
+            r.finalize(outs)
 
-    for i in range(args.warmup):
-        step()
-        log(f"[bench] warmup step {i + 1}/{args.warmup} done")
-    r.set_timing(True)
-    r.timings(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-        log(f"[bench] timed step {i + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    tm = r.timings(reset=True)
-    r.set_timing(False)
+        for i in range(warmup):
+            step()
+            log(f"[bench] warmup step {i + 1}/{warmup} done")
+        r.set_timing(True)
+        r.timings(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step()
+            log(f"[bench] timed step {i + 1}/{steps} done")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        tm = r.timings(reset=True)
+        r.set_timing(False)
+        r.close()
+        del outs, snaps, r
+        torch.cuda.empty_cache()
 
-    ms_step = 1e3 * elapsed / args.steps
-    p_out = w.points_out
-    value = p_out * S / (elapsed / args.steps)
+        t_step = elapsed / steps
+        work = kernel_work(w, chunk_used)
+        kernels = {}
+        for name, (ms, n) in tm.items():
+            if n == 0:
+                continue
+            avg = ms / n
+            k = {"ms_per_step": ms / steps, "launches_per_step": n / steps, "avg_launch_ms": avg}
+            if name in work:
+                kind, amount = work[name]
+                if name in ("rankk", "rankk_rem"):
+                    # the last launch of a step may hold fewer snapshots: use the mean
+                    amount = amount * (S / chunk_used) / (n / steps)
+                if kind == "flop":
+                    k["achieved_tflops"] = amount / (avg * 1e-3) / 1e12
+                else:
+                    k["achieved_gbs"] = amount / (avg * 1e-3) / 1e9
+            kernels[name] = k
+        dom = max(kernels, key=lambda n: kernels[n]["ms_per_step"])
+        dk = kernels[dom]
+        if dom == "rankk_rem":
+            # FP64 vector arithmetic: the fp64 vector peak of the chip
+            ach, peak, unit, bound = dk["achieved_tflops"], PEAK["fp64_vector"], "TFLOP/s", "alu"
+        elif "achieved_tflops" in dk:
+            peak = PEAK["bf16_mfma" if w.precision == "bf16x3" else "fp64_mfma"]
+            ach, unit, bound = dk["achieved_tflops"], "TFLOP/s", "mfma"
+        else:
+            ach, peak, unit, bound = dk.get("achieved_gbs", 0.0), PEAK["hbm"], "GB/s", "hbm"
+        # HBM bytes per launch of that kernel from the committed counter summary,
+        # provided its sources are unchanged since the counters were taken
+        traffic = profiling.traffic_if_current(
+            os.path.join(ROOT, "profiles", f"traffic_{dom}_{w.name}_{w.precision}.txt"), dom,
+            w.precision) if S == synth.workload(w.name).S and chunk_arg == 0 else None
+        roof = {"kernel": profiling.symbol(dom, w.precision) if dom in profiling.KERNELS else dom,
+                "bound": bound, "achieved": ach, "peak": peak, "unit": unit,
+                "frac": ach / peak, "traffic": traffic}
+        return {"w": w, "S": S, "chunk": chunk_used, "t_step": t_step, "kernels": kernels,
+                "roofline": roof, "value": w.points_out * S / t_step}
 
-    work = kernel_work(w, chunk)
-    kernels = {}
-    for name, (ms, n) in tm.items():
-        if n == 0:
-            continue
-        avg = ms / n
-        k = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
-             "avg_launch_ms": avg}
-        if name in work:
-            kind, amount = work[name]
-            if name in ("rankk", "rankk_rem"):
-                # the last launch of a step may hold fewer snapshots: use the mean
-                launches = n / args.steps
-                amount = amount * (S / chunk) / launches
-            if kind == "flop":
-                k["achieved_tflops"] = amount / (avg * 1e-3) / 1e12
-            else:
-                k["achieved_gbs"] = amount / (avg * 1e-3) / 1e9
-        kernels[name] = k
-    dom = max(kernels, key=lambda n: kernels[n]["ms_per_step"])
-    dk = kernels[dom]
-    if dom == "rankk_rem":
-        # FP64 vector arithmetic: the fp64 vector peak of the chip
-        ach, peak, unit, bound = dk["achieved_tflops"], PEAK["fp64_vector"], "TFLOP/s", "alu"
-    elif "achieved_tflops" in dk:
-        peak = PEAK["bf16_mfma" if w.precision == "bf16x3" else "fp64_mfma"]
-        ach, unit, bound = dk["achieved_tflops"], "TFLOP/s", "mfma"
-    else:
-        ach, peak, unit, bound = dk.get("achieved_gbs", 0.0), PEAK["hbm"], "GB/s", "hbm"
-    # HBM bytes per launch of that kernel from the committed counter summary,
-    # provided its sources are unchanged since the counters were taken
-    traffic = profiling.traffic_if_current(
-        os.path.join(ROOT, "profiles", f"traffic_{dom}_{w.name}_{w.precision}.txt"), dom,
-        w.precision) if S == synth.workload(w.name).S and args.chunk == 0 else None
-    roof = {"kernel": profiling.symbol(dom, w.precision) if dom in profiling.KERNELS else dom,
-            "bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-            "traffic": traffic}
+    w = load_workload(args.workload, args.snapshots, args.precision)
+    main_res = measure(w, args.steps, args.warmup, args.chunk, args.calibrate_copy)
+    S = w.S
+
+    extra = {}
+    for name in [n for n in args.also.split(",") if n]:
+        we = load_workload(name)
+        er = measure(we, args.also_steps, 1, 0)
+        per_snap_main = main_res["t_step"] / S
+        per_snap = er["t_step"] / we.S
+        extra[name] = {
+            "value": er["value"], "unit": UNIT, "ms_per_step": 1e3 * er["t_step"],
+            "snapshots": we.S, "chunk": er["chunk"], "dtype": we.dtype,
+            "precision": we.precision, "steps": args.also_steps,
+            "speedup_per_snapshot_vs_main": per_snap_main / per_snap,
+            "roofline": er["roofline"],
+            "kernels_ms_per_step": {k: v["ms_per_step"] for k, v in er["kernels"].items()},
+        }
+        log(f"[bench] {name}: {1e3 * er['t_step']:.1f} ms/step, "
+            f"{per_snap_main / per_snap:.2f}x per snapshot vs {w.name}")
 
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(w, y, args.seed, args.cpu_threads, s_sample=min(30, S), j1=w.ny // 2 - 4)
+        cpu = cpu_baseline(w, synth.y_grid(w), args.seed, args.cpu_threads, s_sample=min(30, S),
+                           j1=w.ny // 2 - 4)
         log(f"[bench] oracle sample took {cpu['seconds']:.1f} s")
 
+    t_step = main_res["t_step"]
     res = {
-        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
+        "metric": METRIC, "value": main_res["value"], "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if w.precision == "fp64" else "bf16x3",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} channel grid, {S} "
                                f"{w.dtype} snapshots, all (Y1,Y2) pairs, rx>=0 half plane, "
                                f"14 term maps", "grid": [w.nx, w.ny, w.nz], "snapshots": S,
-                   "precision": w.precision, "chunk": chunk, "points_out": p_out},
-        "points_per_s": p_out / (elapsed / args.steps),
-        "roofline": roof,
+                   "precision": w.precision, "chunk": main_res["chunk"],
+                   "points_out": w.points_out},
+        "points_per_s": w.points_out / t_step,
+        "roofline": main_res["roofline"],
         "cpu_baseline": cpu,
-        "kernels": kernels,
+        "kernels": main_res["kernels"],
+        "extra": extra,
     }
     print(json.dumps(res), flush=True)
-    r.close()
 
 
 if __name__ == "__main__":

@@ -62,7 +62,8 @@ typedef enum {
 enum {
     GKE_OPT_DTYPE = 1,        /* input storage: GKE_DTYPE_F64 (default) or GKE_DTYPE_F32 */
     GKE_OPT_PRECISION = 2,    /* rank-k arithmetic: GKE_PREC_FP64 (default) or GKE_PREC_BF16X3 */
-    GKE_OPT_CHUNK = 3,        /* snapshots per cross-spectral batch, even, 2..4096 (default 64) */
+    GKE_OPT_CHUNK = 3,        /* snapshots per cross-spectral batch, even, 2..4096 (default 64);
+                                 0: the most whose spectra fit 16 GiB, in [8, 512] */
     GKE_OPT_PAIR_BATCH = 4,   /* plane pairs per finalize batch, 0 = all at once (default) */
     GKE_OPT_TIMING = 5,       /* 1: record HIP events around every kernel launch (any time) */
     GKE_OPT_MIRROR = 6,       /* 1: average every term with the reflected pair (below) */
@@ -155,6 +156,11 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
  * Errors: GKE_ERR_ARG (unknown key, bad value), GKE_ERR_STATE (too late),
  * GKE_ERR_UNSUPPORTED (value not built). */
 gke_status gke_set_option(gke_plan_t plan, int key, int64_t value);
+
+/* Value of an option in effect: after gke_workspace_size or
+ * gke_set_workspace, GKE_OPT_CHUNK reports the chunk chosen for 0.
+ * Errors: GKE_ERR_ARG (NULL, unknown key). */
+gke_status gke_get_option(gke_plan_t plan, int key, int64_t *value);
 
 /* Device workspace bytes the plan needs with its current options. */
 gke_status gke_workspace_size(gke_plan_t plan, size_t *bytes);

@@ -512,8 +512,8 @@ gke_status gke_set_option(gke_plan_t p, int key, int64_t value)
         p->d.prec = value == GKE_PREC_BF16X3 ? gke::PREC_BF16X3 : gke::PREC_FP64;
         return GKE_OK;
     case GKE_OPT_CHUNK:
-        if (value < 2 || value > 4096 || value % 2)
-            return fail(p, GKE_ERR_ARG, "chunk must be even and in [2, 4096]");
+        if (value != 0 && (value < 2 || value > 4096 || value % 2))
+            return fail(p, GKE_ERR_ARG, "chunk must be 0 or even and in [2, 4096]");
         p->chunk = (int)value;
         p->d.chunk = (int)value;
         return GKE_OK;
@@ -548,15 +548,42 @@ gke_status gke_set_option(gke_plan_t p, int key, int64_t value)
     }
 }
 
-// Fix the output mode from the options (before sizing the workspace).
+// Fix the output mode and the automatic chunk from the options (before sizing
+// the workspace).  Chunk 0: the most snapshots per cross-spectral batch whose
+// spectra fit kAutoChunkBytes (every batch re-reads and re-writes the
+// accumulators, so fewer, larger batches move fewer bytes), in [8, 512].
+constexpr size_t kAutoChunkBytes = (size_t)16 << 30;
 gke_status prepare_mode(gke_plan_t p)
 {
+    if (p->chunk == 0) {
+        const size_t esz = p->d.prec == gke::PREC_BF16X3 ? 8 : 16;
+        const size_t per = esz * (size_t)p->d.nk * gke::NFIELD * p->d.ny;
+        size_t c = kAutoChunkBytes / per;
+        c = std::max<size_t>(8, std::min<size_t>(512, c)) & ~(size_t)1;
+        p->d.chunk = (int)c;
+    }
     if (p->domain == GKE_DOMAIN_FUNDAMENTAL_FULLR && !p->mirror)
         return fail(p, GKE_ERR_ARG, "the fundamental domain needs GKE_OPT_MIRROR = 1");
     p->general = p->mirror || p->domain != GKE_DOMAIN_ALLPAIRS_HALFRX || p->slab_rows > 0;
     if (p->general) build_slabs(p);
     else p->slabs.clear();
     return GKE_OK;
+}
+
+gke_status gke_get_option(gke_plan_t p, int key, int64_t *value)
+{
+    if (!p || !value) return fail(p, GKE_ERR_ARG, "NULL argument");
+    switch (key) {
+    case GKE_OPT_DTYPE: *value = p->dtype; return GKE_OK;
+    case GKE_OPT_PRECISION: *value = p->prec; return GKE_OK;
+    case GKE_OPT_CHUNK: *value = p->d.chunk; return GKE_OK;
+    case GKE_OPT_PAIR_BATCH: *value = p->pair_batch; return GKE_OK;
+    case GKE_OPT_TIMING: *value = p->timing ? 1 : 0; return GKE_OK;
+    case GKE_OPT_MIRROR: *value = p->mirror; return GKE_OK;
+    case GKE_OPT_DOMAIN: *value = p->domain; return GKE_OK;
+    case GKE_OPT_SLAB: *value = p->slab_rows; return GKE_OK;
+    default: return fail(p, GKE_ERR_ARG, "unknown option key");
+    }
 }
 
 gke_status gke_workspace_size(gke_plan_t p, size_t *bytes)

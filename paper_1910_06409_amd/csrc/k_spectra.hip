@@ -9,6 +9,8 @@
 // spectra, sum_ab w_a w_b <u'(Y_a) u'(Y_b)>, would lose digits to cancellation.)
 //
 // Normalisation: A^(kx,kz) = (1/(Nx Nz)) sum_{x,z} A e^{-i(alpha x + beta z)}.
+#include <algorithm>
+
 #include "gke_internal.h"
 
 namespace gke {
@@ -175,11 +177,11 @@ hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int
     return hipGetLastError();
 }
 
-// One block = jb consecutive planes of one field at one kx: transform along z
-// (type T), scale, and store spec[k = kx*Nz + kz][f][slot][j] (planes
-// contiguous) as FP64 complex or split BF16.
+// One block = jb consecutive planes of one field at one kx (FP64 path; two
+// blocks share a compute unit): transform along z, scale, and store
+// spec[k = kx*Nz + kz][f][slot][j] (planes contiguous).
 template <typename T, typename S>
-__global__ GKE_FFT_BOUNDS void k_zfft_pack(const cx<T> *__restrict__ inter, Dims d,
+__global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, Dims d,
                                                          Tables t, int slot,
                                                          S *__restrict__ spec)
 {
@@ -215,20 +217,112 @@ __global__ GKE_FFT_BOUNDS void k_zfft_pack(const cx<T> *__restrict__ inter, Dims
     }
 }
 
+// Split-BF16 path.  Work item = jb consecutive planes of one field at one kx:
+// transform along z (FP32), scale, and store spec[k = kx*Nz + kz][f][slot][j] (planes
+// contiguous) as FP64 complex or split BF16.  Persistent blocks: each XCD
+// (workgroup i runs on XCD i % 8) takes a contiguous range of items, so items
+// that share cache lines of inter (neighbouring kx) meet in one L2; a block
+// gathers its next item into registers while it transforms and stores the
+// current one.
+constexpr int ZBLOCK = 1024;   // threads of the persistent z-pass blocks
+
+template <typename T, typename S>
+__global__ __launch_bounds__(ZBLOCK) void k_zfft_pack(const cx<T> *__restrict__ inter, Dims d,
+                                                      Tables t, int slot, S *__restrict__ spec,
+                                                      int nitems)
+{
+    constexpr int MAXE = (FFT_CAP + ZBLOCK - 1) / ZBLOCK;
+    extern __shared__ unsigned char lds_raw[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
+    const int ny = d.ny, nz = d.nz, nkx = d.nkx, jb = d.jb, zb = d.zb, njb = d.njb;
+    const int bs = fft_stride(nz);
+    cx<T> *tw = lds + jb * bs;
+    load_twiddles(tw, tw_of<T>(t, 1), nz);
+    const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3, gb = gridDim.x >> 3;
+    const int per = (nitems + 7) >> 3;
+    const int i0 = xcd * per, i1 = min(nitems, i0 + per);
+    const double scale = 1.0 / ((double)d.nx * (double)nz);
+    cx<T> pf[MAXE];
+    // item -> (f, kx, jblk), jblk fastest
+    auto gather = [&](int item) {
+        const int jblk = item % njb, t2 = item / njb;
+        const int kx = t2 % nkx, f = t2 / nkx;
+        const int j0 = jblk * jb, nb = min(jb, ny - j0);
+#pragma unroll
+        for (int q = 0; q < MAXE; ++q) {
+            const int e = threadIdx.x + q * ZBLOCK;
+            if (e < nb * nz) {
+                const int b = e / nz, z = e - b * nz;
+                const int zblk = z / zb, row = z - zblk * zb;
+                pf[q] = inter[((((size_t)(j0 + b) * d.nzb + zblk) * NFIELD + f) * nkx + kx) * zb + row];
+            }
+        }
+    };
+    int item = i0 + lb;
+    if (item < i1) gather(item);
+    for (; item < i1; item += gb) {
+        const int jblk = item % njb, t2 = item / njb;
+        const int kx = t2 % nkx, f = t2 / nkx;
+        const int j0 = jblk * jb, nb = min(jb, ny - j0);
+        __syncthreads();   // the previous item's LDS reads are done
+#pragma unroll
+        for (int q = 0; q < MAXE; ++q) {
+            const int e = threadIdx.x + q * ZBLOCK;
+            if (e < nb * nz) {
+                const int b = e / nz, z = e - b * nz;
+                lds[b * bs + fft_pad(z)] = pf[q];
+            }
+        }
+        if (item + gb < i1) gather(item + gb);   // in flight during this item
+        __syncthreads();
+        lds_fft_ip<T, FFT_CAP, ZBLOCK>(lds, nb, bs, t.pz, tw, -1);
+        for (int e = threadIdx.x; e < nb * nz; e += blockDim.x) {
+            const int kz = e / nb, b = e - kz * nb;
+            const cx<T> Y = lds[b * bs + fft_pad(kz)];
+            const cx<double> X = cx<double>{(double)Y.x * scale, (double)Y.y * scale};
+            store_spec<double>(spec, ((((size_t)kx * nz + kz) * NFIELD + f) * d.chunk + slot) * ny + j0 + b, X);
+        }
+    }
+}
+
+// persistent grid: the resident blocks of every compute unit, a multiple of 8
+template <typename K>
+static int persistent_grid(K kernel, int block, size_t lds, int nitems)
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    int g = cus * per_cu;
+    g = std::min(g, (nitems + 7) / 8 * 8);
+    return std::max(8, g / 8 * 8);
+}
+
 hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t, const void *inter,
                             int slot, void *spec)
 {
-    dim3 grid(d.njb, d.nkx, NFIELD);
+    const int nitems = d.njb * d.nkx * NFIELD;
     if (d.prec == PREC_BF16X3) {
         const size_t lds = sizeof(cx<float>) * ((size_t)d.jb * fft_stride(d.nz) + d.nz);
-        set_lds_limit(k_zfft_pack<float, bf16x4>);
-        hipLaunchKernelGGL((k_zfft_pack<float, bf16x4>), grid, dim3(FFT_BLOCK), lds, st,
-                           (const cx<float> *)inter, d, t, slot, (bf16x4 *)spec);
+        auto k = k_zfft_pack<float, bf16x4>;
+        set_lds_limit(k);
+        hipLaunchKernelGGL(k, dim3(persistent_grid(k, ZBLOCK, lds, nitems)), dim3(ZBLOCK), lds,
+                           st, (const cx<float> *)inter, d, t, slot, (bf16x4 *)spec, nitems);
     } else {
+        // FP64: the persistent form measured slower (one block per compute
+        // unit, register spills); two plain blocks per compute unit
         const size_t lds = sizeof(cx<double>) * ((size_t)d.jb * fft_stride(d.nz) + d.nz);
-        set_lds_limit(k_zfft_pack<double, cx<double>>);
-        hipLaunchKernelGGL((k_zfft_pack<double, cx<double>>), grid, dim3(FFT_BLOCK), lds, st,
-                           (const cx<double> *)inter, d, t, slot, (cx<double> *)spec);
+        set_lds_limit(k_zfft_pack_blk<double, cx<double>>);
+        hipLaunchKernelGGL((k_zfft_pack_blk<double, cx<double>>), dim3(d.njb, d.nkx, NFIELD),
+                           dim3(FFT_BLOCK), lds, st, (const cx<double> *)inter, d, t, slot,
+                           (cx<double> *)spec);
     }
     return hipGetLastError();
 }

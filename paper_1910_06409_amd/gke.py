@@ -64,6 +64,7 @@ def lib() -> ctypes.CDLL:
         "gke_plan": ([i32, i32, i32, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                       ctypes.POINTER(vp)], i32),
         "gke_set_option": ([vp, i32, i64], i32),
+        "gke_get_option": ([vp, i32, ctypes.POINTER(i64)], i32),
         "gke_workspace_size": ([vp, ctypes.POINTER(sz)], i32),
         "gke_set_workspace": ([vp, vp, sz], i32),
         "gke_set_stream": ([vp, vp], i32),
@@ -119,6 +120,12 @@ def gke_plan(Nx: int, Ny: int, Nz: int, y, Lx: float, Lz: float, nu: float):
 
 def gke_set_option(plan, key: int, value: int) -> None:
     _check(lib().gke_set_option(plan, key, value), plan)
+
+
+def gke_get_option(plan, key: int) -> int:
+    v = ctypes.c_int64()
+    _check(lib().gke_get_option(plan, key, ctypes.byref(v)), plan)
+    return v.value
 
 
 def gke_workspace_size(plan) -> int:

@@ -78,6 +78,10 @@ class GkeRun:
                                  device=self.device)
         return out
 
+    def chunk(self) -> int:
+        """Snapshots per cross-spectral batch in effect (resolves chunk 0)."""
+        return gke.gke_get_option(self.plan, gke.GKE_OPT_CHUNK)
+
     def slab_count(self) -> int:
         return gke.gke_slab_count(self.plan)
 

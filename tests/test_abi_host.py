@@ -63,6 +63,12 @@ def test_options_and_state_errors():
         gke.gke_set_option(p, gke.GKE_OPT_CHUNK, 8)
         n8 = gke.gke_workspace_size(p)
         assert n64 > n8 > 0
+        assert gke.gke_get_option(p, gke.GKE_OPT_CHUNK) == 8
+        # chunk 0: the library picks the largest batch within its memory budget
+        gke.gke_set_option(p, gke.GKE_OPT_CHUNK, 0)
+        gke.gke_workspace_size(p)
+        assert gke.gke_get_option(p, gke.GKE_OPT_CHUNK) == 512
+        gke.gke_set_option(p, gke.GKE_OPT_CHUNK, 64)
         # no workspace yet: every device step is refused with a state error
         with pytest.raises(gke.GkeError) as e:
             gke.gke_accumulate(p, 1, 1, 1, 1)
