@@ -59,6 +59,10 @@ constexpr int NSPLIT = 8;
 #ifndef GKE_FFT_WAVES
 #define GKE_FFT_WAVES 4
 #endif
+// loads a thread keeps in flight in the gathers of the transform kernels
+#ifndef GKE_GATHER
+#define GKE_GATHER 4
+#endif
 constexpr int FFT_CAP = GKE_FFT_CAP;
 constexpr int FFT_BLOCK = GKE_FFT_BLOCK;
 // launch bounds of the transform kernels: FFT_BLOCK threads, at least

@@ -43,7 +43,7 @@ __global__ GKE_FFT_BOUNDS void k_fin_kz(const cx<double> *__restrict__ acc, Dims
     cx<double> *tw = lds + pb * bs;
     load_twiddles(tw, t.twz, nz);
     for (int tr = 0; tr < nout_tr; ++tr) {
-        gather_batched<4, FFT_BLOCK, cx<double>>(
+        gather_batched<GKE_GATHER, FFT_BLOCK, cx<double>>(
             nz * np,
             [&](int e) {
                 const int kz = e / np, b = e - kz * np;
@@ -166,7 +166,7 @@ __global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims
     cx<double> *S = lds + nt * bs;            // staging [kx][pair]
     cx<double> *tw = S + nkx * npair;         // twiddles
     load_twiddles(tw, t.twx, nx);
-    gather_batched<4, FFT_BLOCK, cx<double>>(
+    gather_batched<GKE_GATHER, FFT_BLOCK, cx<double>>(
         nkx * npair,
         [&](int e) {
             const int kx = e / npair, b = e - kx * npair;

@@ -195,7 +195,7 @@ __global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, 
     const int zb = d.zb;
     cx<T> *tw = lds + jb * bs;
     load_twiddles(tw, tw_of<T>(t, 1), nz);
-    gather_batched<4, FFT_BLOCK, cx<T>>(
+    gather_batched<GKE_GATHER, FFT_BLOCK, cx<T>>(
         nb * nz,
         [&](int e) {
             const int b = e / nz, z = e - b * nz;
