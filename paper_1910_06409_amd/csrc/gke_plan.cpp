@@ -552,7 +552,7 @@ gke_status gke_set_option(gke_plan_t p, int key, int64_t value)
 // the workspace).  Chunk 0: the most snapshots per cross-spectral batch whose
 // spectra fit kAutoChunkBytes (every batch re-reads and re-writes the
 // accumulators, so fewer, larger batches move fewer bytes), in [8, 512].
-constexpr size_t kAutoChunkBytes = (size_t)16 << 30;
+constexpr size_t kAutoChunkBytes = (size_t)48 << 30;
 gke_status prepare_mode(gke_plan_t p)
 {
     if (p->chunk == 0) {

@@ -261,13 +261,14 @@ def test_bf16x3_ragged_multi_chunk_f32_inputs():
 @pytest.mark.timeout(900)
 def test_re200_grid_bf16x3_sampled_pairs():
     """The Re_tau=200 grid with FP32 inputs and the split-BF16 update (64
-    snapshots, chunks of 32) on sampled pairs against the oracle."""
+    snapshots, the automatic chunk: one FP32-accumulated batch of 64) on
+    sampled pairs against the oracle."""
     w = synth.workload("re200_bf16", S=64)
     y = synth.y_grid(w)
     say("case re200 grid bf16x3: generating", w.S, "snapshots")
     snap = synth.snapshots(w, 512)
     say("case re200 grid bf16x3: GPU run")
-    g, _ = run_gpu(snap, w, y, precision="bf16x3", chunk=32)
+    g, _ = run_gpu(snap, w, y, precision="bf16x3", chunk=0)
     pairs = [(0, 0), (5, 127), (64, 64), (30, 95), (128, 1), (70, 71)]
     say("case re200 grid bf16x3: oracle on", len(pairs), "pairs")
     ref = oracle.pair_terms(snap.astype(np.float64), y, w.lx, w.lz, w.nu, pairs)
