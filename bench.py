@@ -104,6 +104,9 @@ def main():
                     help="override the rank-k arithmetic of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--slab-rows", type=int, default=0,
+                    help="config-5 path: mirror average, fundamental domain, Y1 slabs of this "
+                         "many rows (one timed pass over all slabs)")
     ap.add_argument("--also", default="re200_bf16",
                     help="comma-separated workloads measured after the main one (speed-up per "
                          "snapshot reported under 'extra'); empty for none")
@@ -119,6 +122,7 @@ def main():
               "the multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     from paper_1910_06409_amd import profiling, runner, synth
@@ -234,7 +238,87 @@ def main():
         return {"w": w, "S": S, "chunk": chunk_used, "t_step": t_step, "kernels": kernels,
                 "roofline": roof, "value": w.points_out * S / t_step}
 
+    def measure_slabs(w, slab_rows, chunk, pair_batch):
+        """The config-5 path: mirror average, fundamental domain, Y1 slabs (one
+        second scan per slab).  One timed pass over every slab; device time
+        only (the caller would stream each slab's maps to the host)."""
+        S = w.S
+        y = synth.y_grid(w)
+        tdt = torch.float64 if w.dtype == "f64" else torch.float32
+        log(f"[bench] generating {S} snapshots of {w.name} ({w.nx}x{w.ny}x{w.nz}, {w.dtype})")
+        snaps = torch.empty((S, 4, w.ny, w.nz, w.nx), dtype=tdt, device=dev)
+        gen = synth.DeviceSnapshots(w, args.seed, dev)
+        for s in range(S):
+            gen(s, out=snaps[s])
+        torch.cuda.synchronize()
+        del gen
+        from paper_1910_06409_amd import gke
+        r = runner.GkeRun(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu, dtype=w.dtype,
+                          precision=w.precision, chunk=chunk, pair_batch=pair_batch,
+                          mirror=1, domain=gke.GKE_DOMAIN_FUNDAMENTAL_FULLR, slab=slab_rows,
+                          device=dev)
+        nslab = r.slab_count()
+        npairs = [len(r.slab_pairs(sl)) for sl in range(nslab)]
+        outs = r.alloc_terms(slab=int(np.argmax(npairs)))
+        log(f"[bench] workspace {r.workspace.numel() / 2**30:.1f} GiB, {nslab} slabs, "
+            f"slab outputs {sum(o.numel() for o in outs) * 8 / 2**30:.1f} GiB, chunk {r.chunk()}")
+
+        def views(sl):
+            n = npairs[sl]
+            return [o[:n] if o is not None else None for o in outs]
+
+        r.set_timing(True)
+        r.timings(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(S):
+            r.accumulate_snapshot(snaps[s])
+        r.begin_stats()
+        for sl in range(nslab):
+            if sl > 0:
+                r.begin_slab(sl)
+            for s in range(S):
+                r.accumulate_snapshot(snaps[s])
+            r.finalize(views(sl))
+            if (sl + 1) % 8 == 0 or sl + 1 == nslab:
+                log(f"[bench] slab {sl + 1}/{nslab} done ({time.perf_counter() - t0:.1f} s)")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        tm = r.timings(reset=True)
+        # device-to-host rate of one slab's maps into pinned memory
+        n0 = npairs[0]
+        host = torch.empty(n0 * w.nz * w.nx, dtype=torch.float64, pin_memory=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for o in outs[:13]:
+            host.copy_(o[:n0].reshape(-1))
+        torch.cuda.synchronize()
+        d2h = 13 * host.numel() * 8 / (time.perf_counter() - t1)
+        r.close()
+        del outs, snaps, r
+        torch.cuda.empty_cache()
+        p_out = sum(npairs) * w.nz * w.nx
+        return {"w": w, "S": S, "t": elapsed, "nslab": nslab, "p_out": p_out,
+                "value": p_out * S / elapsed, "d2h_gbs": d2h / 1e9,
+                "kernels_ms": {k: v[0] for k, v in tm.items() if v[1]}}
+
     w = load_workload(args.workload, args.snapshots, args.precision)
+    if args.slab_rows:
+        sr = measure_slabs(w, args.slab_rows, args.chunk or 8, args.pair_batch or 1024)
+        res = {
+            "metric": METRIC, "value": sr["value"], "unit": UNIT, "n_gpus": 1, "steps": 1,
+            "warmup": 0, "ms_per_step": 1e3 * sr["t"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if w.precision == "fp64" else "bf16x3", "data": "synthetic",
+            "config": {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} channel grid, {sr['S']} "
+                                   f"{w.dtype} snapshots, mirror average, fundamental domain "
+                                   f"(full r), {sr['nslab']} Y1 slabs of {args.slab_rows} rows, "
+                                   f"14 term maps", "points_out": sr["p_out"]},
+            "d2h_gbs_pinned": sr["d2h_gbs"],
+            "kernels_ms": sr["kernels_ms"],
+        }
+        print(json.dumps(res), flush=True)
+        return
     main_res = measure(w, args.steps, args.warmup, args.chunk, args.calibrate_copy)
     S = w.S
 

@@ -148,3 +148,50 @@ def test_re200_grid_mirror_fundamental_first_slab():
         rr = ref[:, t, 0, 0] if t == 13 else ref[:, t]
         e = np.abs(g - rr).max() / np.abs(rr).max()
         assert e <= TOL_FP64, (t, e)
+
+
+@pytest.mark.timeout(900)
+def test_re1000_grid_split_mirror_slab_sampled():
+    """Config 5's shape: the Re_tau=1000 grid (512 x 257 x 384), FP32 inputs,
+    split-BF16 update, mirror average, fundamental domain, slabs of 4 rows;
+    the first slab (the wall rows) and one interior slab on sampled pairs
+    against the oracle; 3 snapshots."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_06409_amd import runner
+    w = synth.workload("re1000", S=3)
+    y = synth.y_grid(w)
+    print("case re1000 mirror fundamental slabs: generating", flush=True)
+    snap = synth.snapshots(w, 91)
+    dev = torch.from_numpy(snap).cuda()
+    r = runner.GkeRun(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu, dtype="f32", precision="bf16x3",
+                      chunk=4, pair_batch=1024, mirror=1,
+                      domain=gke.GKE_DOMAIN_FUNDAMENTAL_FULLR, slab=4)
+    for s in range(w.S):
+        r.accumulate_snapshot(dev[s])
+    r.begin_stats()
+    got = {}
+    for sl in (0, 20):
+        if sl:
+            r.begin_slab(sl)
+        for s in range(w.S):
+            r.accumulate_snapshot(dev[s])
+        print("case re1000: finalize slab", sl, flush=True)
+        maps = r.finalize(r.alloc_terms(slab=sl))
+        pairs = [tuple(p) for p in r.slab_pairs(sl)]
+        pick = [0, len(pairs) // 3, len(pairs) - 1]
+        got[sl] = ([pairs[i] for i in pick], [m[pick].cpu().numpy() for m in maps])
+        del maps
+    r.close()
+    for sl, (sel, maps) in got.items():
+        print("case re1000: oracle on", sel, flush=True)
+        ref = oracle.mirror_terms(snap.astype(np.float64), y, w.lx, w.lz, w.nu, sel)
+        errs = []
+        for t in range(14):
+            rr = ref[:, t, 0, 0] if t == 13 else ref[:, t]
+            e = np.abs(maps[t] - rr).max() / np.abs(rr).max()
+            errs.append(e)
+        print(f"re1000 slab {sl}: " + " ".join(f"T{t + 1}={e:.1e}" for t, e in enumerate(errs)),
+              flush=True)
+        assert max(errs) <= TOL_BF16, (sl, errs)
