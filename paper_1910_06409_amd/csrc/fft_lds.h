@@ -67,6 +67,28 @@ __device__ __forceinline__ int div_small(int a, int d, float inv_d)
     return q;
 }
 
+// e = hi * n + lo for e = start, start + step, start + 2 step, ... with one
+// division at the start and none per step (step < n or any step >= 0).
+struct Walk2 {
+    int hi, lo, dhi, dlo, n;
+    __device__ __forceinline__ Walk2(int start, int step, int n_) : n(n_)
+    {
+        hi = start / n;
+        lo = start - hi * n;
+        dhi = step / n;
+        dlo = step - dhi * n;
+    }
+    __device__ __forceinline__ void next()
+    {
+        hi += dhi;
+        lo += dlo;
+        if (lo >= n) {
+            lo -= n;
+            ++hi;
+        }
+    }
+};
+
 template <int R, typename T>
 struct Dft;
 

@@ -42,12 +42,15 @@ __global__ GKE_FFT_BOUNDS void k_fin_kz(const cx<double> *__restrict__ acc, Dims
     const int nout_tr = (sp == S_R) ? 2 : 1;
     cx<double> *tw = lds + pb * bs;
     load_twiddles(tw, t.twz, nz);
+    const cx<double> *ab = acc + ((size_t)sp * d.nk + (size_t)kx * nz) * pall + pg0;
+    const int cnt = nz * np;
     for (int tr = 0; tr < nout_tr; ++tr) {
+        // e = kz np + b: pairs contiguous in acc
         gather_batched<GKE_GATHER, FFT_BLOCK, cx<double>>(
-            nz * np,
+            cnt,
             [&](int e) {
                 const int kz = e / np, b = e - kz * np;
-                return acc[((size_t)sp * d.nk + (size_t)kx * nz + kz) * pall + pg0 + b];
+                return ab[kz * pall + b];
             },
             [&](int e, cx<double> X) {
                 const int kz = e / np, b = e - kz * np;
@@ -64,8 +67,10 @@ __global__ GKE_FFT_BOUNDS void k_fin_kz(const cx<double> *__restrict__ acc, Dims
         int m0;
         if (sp == S_R) m0 = (tr == 0) ? M_R : M_DRZ;
         else m0 = M_FX + (sp - S_FX);  // FX FY FZ PHI PP UVS UVA map one to one
-        for (int e = threadIdx.x; e < nz * np; e += blockDim.x) {
-            const int rz = e / np, b = e - rz * np;
+        Walk2 ws(threadIdx.x, FFT_BLOCK, np);   // (rz, b)
+        for (int e = threadIdx.x; e < cnt; e += FFT_BLOCK) {
+            const int rz = ws.hi, b = ws.lo;
+            ws.next();
             const cx<double> Y = lds[b * bs + fft_pad(rz)];
             const size_t o = ((size_t)kx * nz + rz) * ptot + pl0 + b;
             mid[(size_t)m0 * nkx * nz * ptot + o] = Y;
@@ -166,18 +171,34 @@ __global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims
     cx<double> *S = lds + nt * bs;            // staging [kx][pair]
     cx<double> *tw = S + nkx * npair;         // twiddles
     load_twiddles(tw, t.twx, nx);
-    gather_batched<GKE_GATHER, FFT_BLOCK, cx<double>>(
-        nkx * npair,
-        [&](int e) {
-            const int kx = e / npair, b = e - kx * npair;
-            return (b < np) ? mid[(((size_t)m * nkx + kx) * nz + rz) * ptot + pl0 + b]
-                            : cx<double>{0.0, 0.0};
-        },
-        [&](int e, cx<double> x) { S[e] = x; });
+    {
+        // e = kx npair + b: the pairs of one (map, kx, rz) are contiguous in mid
+        const cx<double> *mb = mid + ((size_t)m * nkx * nz + rz) * ptot + pl0;
+        const size_t skx = (size_t)nz * ptot;
+        const int cnt = nkx * npair;
+        for (int base = 0; base < cnt; base += GKE_GATHER * FFT_BLOCK) {
+            Walk2 w(base + threadIdx.x, FFT_BLOCK, npair);   // (kx, b)
+            cx<double> v[GKE_GATHER];
+#pragma unroll
+            for (int q = 0; q < GKE_GATHER; ++q) {
+                v[q] = cx<double>{0.0, 0.0};
+                if (base + (int)threadIdx.x + q * FFT_BLOCK < cnt && w.lo < np)
+                    v[q] = mb[w.hi * skx + w.lo];
+                w.next();
+            }
+#pragma unroll
+            for (int q = 0; q < GKE_GATHER; ++q) {
+                const int e = base + threadIdx.x + q * FFT_BLOCK;
+                if (e < cnt) S[e] = v[q];
+            }
+        }
+    }
     __syncthreads();
     // consecutive threads take consecutive transforms: bank-friendly reads of S
-    for (int e = threadIdx.x; e < nt * nx; e += blockDim.x) {
-        const int n = e / nt, c = e - n * nt;
+    Walk2 wn(threadIdx.x, FFT_BLOCK, nt);   // (n, c)
+    for (int e = threadIdx.x; e < nt * nx; e += FFT_BLOCK) {
+        const int n = wn.hi, c = wn.lo;
+        wn.next();
         cx<double> xa, xb;
         if (n <= nx / 2) {
             xa = S[n * npair + 2 * c];
@@ -192,8 +213,10 @@ __global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims
     lds_fft_ip<double, FFT_CAP, FFT_BLOCK>(A, nt, bs, t.px, tw, +1);
     if (full) {
         // one orientation, every rx, rows of the full-plane buffer
-        for (int e = threadIdx.x; e < np * nx; e += blockDim.x) {
-            const int b = e / nx, rx = e - b * nx;
+        Walk2 wb(threadIdx.x, FFT_BLOCK, nx);   // (b, rx)
+        for (int e = threadIdx.x; e < np * nx; e += FFT_BLOCK) {
+            const int b = wb.hi, rx = wb.lo;
+            wb.next();
             const int code = t.pairs[p0 + pl0 + b];
             const int j1 = pair_j1(code), j2 = pair_j2(code);
             const cx<double> zv = A[(b >> 1) * bs + fft_pad(rx)];
@@ -205,8 +228,10 @@ __global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims
     }
     const double sig = map_sigma(m);
     const size_t plane = (size_t)nz * nkx;
-    for (int e = threadIdx.x; e < np * nkx; e += blockDim.x) {
-        const int b = e / nkx, rx = e - b * nkx;
+    Walk2 wb(threadIdx.x, FFT_BLOCK, nkx);   // (b, rx)
+    for (int e = threadIdx.x; e < np * nkx; e += FFT_BLOCK) {
+        const int b = wb.hi, rx = wb.lo;
+        wb.next();
         const int code = t.pairs[p0 + pl0 + b];
         const int j1 = pair_j1(code), j2 = pair_j2(code);
         const int c = b >> 1;

@@ -15,20 +15,6 @@
 
 namespace gke {
 
-// Sum over the block in a fixed order; result valid on thread 0.
-__device__ __forceinline__ double block_sum_fixed(double v, double *sh)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
-    return r;
-}
-
 template <typename F>
 static void set_lds_limit(F *kernel)
 {
@@ -80,7 +66,7 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
 {
     extern __shared__ unsigned char lds_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
-    __shared__ double sh[FFT_BLOCK / 64];
+    __shared__ double shm[NMOMP * (FFT_BLOCK / 64)];
     const int nx = d.nx, ny = d.ny, nz = d.nz, nkx = d.nkx, zb = d.zb;
     const int zblk = blockIdx.x, j = blockIdx.y;
     const int z0 = zblk * zb;
@@ -100,7 +86,8 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
         Ms[2][a] = kGy ? prof[P_W * ny + js + a] : 0.0;
     }
     double mq = 0, muv = 0, mpv = 0, mqu = 0, mqv = 0, mqw = 0, mgy = 0;
-    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+    Walk2 wr(threadIdx.x, FFT_BLOCK, nx);   // (row, x)
+    for (int e = threadIdx.x; e < nel; e += FFT_BLOCK) {
         const double a = (double)u[off + e] - U, b = (double)v[off + e] - V;
         const double c = (double)w[off + e] - W, dd = (double)p[off + e] - P;
         const double q = a * a + b * b + c * c;
@@ -121,17 +108,29 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
             mgy += gu * gu + gv * gv + gw * gw;
         }
         // (u,v) (w,p) (Qxx,Qyy) (Qzz,Qxy) (Qxz,Qyz), two real rows per complex row
-        const int row = e / nx, x = fft_pad(e - row * nx);
+        const int row = wr.hi, x = fft_pad(wr.lo);
+        wr.next();
         lds[(0 * zb + row) * bs + x] = cx<T>{(T)a, (T)b};
         lds[(1 * zb + row) * bs + x] = cx<T>{(T)c, (T)dd};
         lds[(2 * zb + row) * bs + x] = cx<T>{(T)(2.0 * a * a + q), (T)(2.0 * b * b + q)};
         lds[(3 * zb + row) * bs + x] = cx<T>{(T)(2.0 * c * c + q), (T)(2.0 * a * b)};
         lds[(4 * zb + row) * bs + x] = cx<T>{(T)(2.0 * a * c), (T)(2.0 * b * c)};
     }
-    const double parts[NMOMP] = {mq, muv, mpv, mqu, mqv, mqw, mgy};
-    for (int k = 0; k < NMOMP; ++k) {
-        const double r = block_sum_fixed(parts[k], sh);
-        if (threadIdx.x == 0) momp[((size_t)j * NMOMP + k) * d.nzb + zblk] += r;
+    // the seven partial sums in one fixed-order block reduction
+    double parts[NMOMP] = {mq, muv, mpv, mqu, mqv, mqw, mgy};
+#pragma unroll
+    for (int k = 0; k < NMOMP; ++k)
+        for (int off = 32; off > 0; off >>= 1) parts[k] += __shfl_down(parts[k], off, 64);
+    {
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        if (lane == 0)
+            for (int k = 0; k < NMOMP; ++k) shm[k * (FFT_BLOCK / 64) + wid] = parts[k];
+        __syncthreads();
+        if ((int)threadIdx.x < NMOMP) {
+            double r = 0.0;
+            for (int i = 0; i < FFT_BLOCK / 64; ++i) r += shm[threadIdx.x * (FFT_BLOCK / 64) + i];
+            momp[((size_t)j * NMOMP + threadIdx.x) * d.nzb + zblk] += r;
+        }
     }
     cx<T> *tw = lds + 5 * zb * bs;
     load_twiddles(tw, tw_of<T>(t, 0), nx);
@@ -139,10 +138,12 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
     lds_fft_ip<T, FFT_CAP, FFT_BLOCK>(lds, 5 * zb, bs, t.px, tw, -1);
     // split the two real transforms: Fa = (Z(k) + conj Z(-k))/2, Fb = (Z(k) - conj Z(-k))/(2i)
     cx<T> *dst = inter + ((size_t)j * d.nzb + zblk) * NFIELD * nkx * zb;
-    for (int e = threadIdx.x; e < 5 * nkx * zb; e += blockDim.x) {
-        const int pr = e / (nkx * zb);
-        const int r2 = e - pr * nkx * zb;
-        const int k = r2 / zb, row = r2 - k * zb;
+    // e = (pr nkx + k) zb + row; zb divides the block size, so row is fixed
+    const int lzb = __builtin_ctz(zb), row = threadIdx.x & (zb - 1);
+    Walk2 wk(threadIdx.x >> lzb, FFT_BLOCK >> lzb, nkx);   // (pr, k)
+    for (int e = threadIdx.x; e < 5 * nkx * zb; e += FFT_BLOCK) {
+        const int pr = wk.hi, k = wk.lo;
+        wk.next();
         const cx<T> *R = lds + (pr * zb + row) * bs;
         const cx<T> Z = R[fft_pad(k)];
         const cx<T> Zc = cconj(R[fft_pad(k == 0 ? 0 : nx - k)]);
@@ -192,15 +193,19 @@ __global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, 
     const int j0 = jblk * jb;
     const int nb = min(jb, ny - j0);
     const int bs = fft_stride(nz);
-    const int zb = d.zb;
+    const int zb = d.zb, lzb = __builtin_ctz(zb), zm = zb - 1;
     cx<T> *tw = lds + jb * bs;
     load_twiddles(tw, tw_of<T>(t, 1), nz);
+    // inter[((((j0 + b) nzb + zblk) NFIELD + f) nkx + kx) zb + row], z = zblk zb + row
+    // offsets within a block stay below 2^31 (jb planes of inter)
+    const int szb = NFIELD * nkx * zb, sb = d.nzb * szb;
+    const cx<T> *ib = inter + (size_t)j0 * sb + ((size_t)f * nkx + kx) * zb;
+    const int cnt = nb * nz;
     gather_batched<GKE_GATHER, FFT_BLOCK, cx<T>>(
-        nb * nz,
+        cnt,
         [&](int e) {
             const int b = e / nz, z = e - b * nz;
-            const int zblk = z / zb, row = z - zblk * zb;
-            return inter[((((size_t)(j0 + b) * d.nzb + zblk) * NFIELD + f) * nkx + kx) * zb + row];
+            return ib[b * sb + (z >> lzb) * szb + (z & zm)];
         },
         [&](int e, cx<T> x) {
             const int b = e / nz, z = e - b * nz;
@@ -209,11 +214,15 @@ __global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, 
     __syncthreads();
     lds_fft_ip<T, FFT_CAP, FFT_BLOCK>(lds, nb, bs, t.pz, tw, -1);
     const double scale = 1.0 / ((double)nx * (double)nz);
-    for (int e = threadIdx.x; e < nb * nz; e += blockDim.x) {
-        const int kz = e / nb, b = e - kz * nb;
-        const cx<T> Y = lds[b * bs + fft_pad(kz)];
+    // spec[(((kx nz + kz) NFIELD + f) chunk + slot) ny + j0 + b]; nz * skz < 2^31
+    const int skz = NFIELD * d.chunk * ny;
+    S *sp = spec + (size_t)kx * nz * skz + ((size_t)f * d.chunk + slot) * ny + j0;
+    Walk2 ws(threadIdx.x, FFT_BLOCK, nb);   // (kz, b)
+    for (int e = threadIdx.x; e < cnt; e += FFT_BLOCK) {
+        const cx<T> Y = lds[ws.lo * bs + fft_pad(ws.hi)];
         const cx<double> X = cx<double>{(double)Y.x * scale, (double)Y.y * scale};
-        store_spec<double>(spec, ((((size_t)kx * nz + kz) * NFIELD + f) * d.chunk + slot) * ny + j0 + b, X);
+        store_spec<double>(sp, ws.hi * skz + ws.lo, X);
+        ws.next();
     }
 }
 
@@ -234,7 +243,8 @@ __global__ __launch_bounds__(ZBLOCK) void k_zfft_pack(const cx<T> *__restrict__ 
     constexpr int MAXE = (FFT_CAP + ZBLOCK - 1) / ZBLOCK;
     extern __shared__ unsigned char lds_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
-    const int ny = d.ny, nz = d.nz, nkx = d.nkx, jb = d.jb, zb = d.zb, njb = d.njb;
+    const int ny = d.ny, nz = d.nz, nkx = d.nkx, jb = d.jb, njb = d.njb;
+    const int zb = d.zb, lzb = __builtin_ctz(zb), zm = zb - 1;
     const int bs = fft_stride(nz);
     cx<T> *tw = lds + jb * bs;
     load_twiddles(tw, tw_of<T>(t, 1), nz);
@@ -242,20 +252,22 @@ __global__ __launch_bounds__(ZBLOCK) void k_zfft_pack(const cx<T> *__restrict__ 
     const int per = (nitems + 7) >> 3;
     const int i0 = xcd * per, i1 = min(nitems, i0 + per);
     const double scale = 1.0 / ((double)d.nx * (double)nz);
+    const size_t szb = (size_t)NFIELD * nkx * zb, sb = (size_t)d.nzb * szb;
+    const size_t skz = (size_t)NFIELD * d.chunk * ny;
+    // this thread's (b, z) for the gathers; nb * nz <= MAXE * ZBLOCK
+    const Walk2 wg(threadIdx.x, ZBLOCK, nz);
     cx<T> pf[MAXE];
     // item -> (f, kx, jblk), jblk fastest
     auto gather = [&](int item) {
         const int jblk = item % njb, t2 = item / njb;
         const int kx = t2 % nkx, f = t2 / nkx;
         const int j0 = jblk * jb, nb = min(jb, ny - j0);
+        const cx<T> *ib = inter + (size_t)j0 * sb + ((size_t)f * nkx + kx) * zb;
+        Walk2 w = wg;
 #pragma unroll
         for (int q = 0; q < MAXE; ++q) {
-            const int e = threadIdx.x + q * ZBLOCK;
-            if (e < nb * nz) {
-                const int b = e / nz, z = e - b * nz;
-                const int zblk = z / zb, row = z - zblk * zb;
-                pf[q] = inter[((((size_t)(j0 + b) * d.nzb + zblk) * NFIELD + f) * nkx + kx) * zb + row];
-            }
+            if (w.hi < nb) pf[q] = ib[w.hi * sb + (size_t)(w.lo >> lzb) * szb + (w.lo & zm)];
+            w.next();
         }
     };
     int item = i0 + lb;
@@ -265,22 +277,24 @@ __global__ __launch_bounds__(ZBLOCK) void k_zfft_pack(const cx<T> *__restrict__ 
         const int kx = t2 % nkx, f = t2 / nkx;
         const int j0 = jblk * jb, nb = min(jb, ny - j0);
         __syncthreads();   // the previous item's LDS reads are done
+        {
+            Walk2 w = wg;
 #pragma unroll
-        for (int q = 0; q < MAXE; ++q) {
-            const int e = threadIdx.x + q * ZBLOCK;
-            if (e < nb * nz) {
-                const int b = e / nz, z = e - b * nz;
-                lds[b * bs + fft_pad(z)] = pf[q];
+            for (int q = 0; q < MAXE; ++q) {
+                if (w.hi < nb) lds[w.hi * bs + fft_pad(w.lo)] = pf[q];
+                w.next();
             }
         }
         if (item + gb < i1) gather(item + gb);   // in flight during this item
         __syncthreads();
         lds_fft_ip<T, FFT_CAP, ZBLOCK>(lds, nb, bs, t.pz, tw, -1);
-        for (int e = threadIdx.x; e < nb * nz; e += blockDim.x) {
-            const int kz = e / nb, b = e - kz * nb;
-            const cx<T> Y = lds[b * bs + fft_pad(kz)];
+        S *sp = spec + (size_t)kx * nz * skz + ((size_t)f * d.chunk + slot) * ny + j0;
+        Walk2 w(threadIdx.x, ZBLOCK, nb);   // (kz, b)
+        for (int e = threadIdx.x; e < nb * nz; e += ZBLOCK) {
+            const cx<T> Y = lds[w.lo * bs + fft_pad(w.hi)];
             const cx<double> X = cx<double>{(double)Y.x * scale, (double)Y.y * scale};
-            store_spec<double>(spec, ((((size_t)kx * nz + kz) * NFIELD + f) * d.chunk + slot) * ny + j0 + b, X);
+            store_spec<double>(sp, w.hi * skz + w.lo, X);
+            w.next();
         }
     }
 }
