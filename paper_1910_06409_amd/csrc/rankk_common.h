@@ -54,26 +54,39 @@ __device__ __forceinline__ cx<double> spec_value(const bf16x4 *s, size_t i)
     return cx<double>{rh + rl, ih + il};
 }
 
+// The loads of snapshot s + 1 are issued before the products of snapshot s.
 template <typename S>
-__global__ __launch_bounds__(64) void k_rankk_rem(const S *__restrict__ spec, Dims d,
-                                                  const int *__restrict__ pairs, int nrem,
-                                                  int nsnap, int accumulate,
-                                                  cx<double> *__restrict__ acc)
+__global__ __launch_bounds__(64, 2) void k_rankk_rem(const S *__restrict__ spec, Dims d,
+                                                     const int *__restrict__ pairs, int nrem,
+                                                     int nsnap, int accumulate,
+                                                     cx<double> *__restrict__ acc)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y;
     if (i >= nrem) return;
     const int code = pairs[d.npair_tiles + i];
     const int j1 = pair_j1(code), j2 = pair_j2(code);
-    const size_t fstride = (size_t)d.chunk * d.ny;
+    const int fstride = d.chunk * d.ny;   // offsets within one wavenumber stay below 2^31
     const S *kb = spec + (size_t)k * NFIELD * fstride;
     double cr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ci[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    S An[NFIELD], Bn[NFIELD];
+#pragma unroll
+    for (int f = 0; f < NFIELD; ++f) {
+        An[f] = kb[f * fstride + j1];
+        Bn[f] = kb[f * fstride + j2];
+    }
     for (int s = 0; s < nsnap; ++s) {
         cx<double> A[NFIELD], B[NFIELD];
 #pragma unroll
         for (int f = 0; f < NFIELD; ++f) {
-            A[f] = spec_value(kb, f * fstride + (size_t)s * d.ny + j1);
-            B[f] = spec_value(kb, f * fstride + (size_t)s * d.ny + j2);
+            A[f] = spec_value(An, f);
+            B[f] = spec_value(Bn, f);
+        }
+        const int sn = (s + 1 < nsnap ? s + 1 : s) * d.ny;
+#pragma unroll
+        for (int f = 0; f < NFIELD; ++f) {
+            An[f] = kb[f * fstride + sn + j1];
+            Bn[f] = kb[f * fstride + sn + j2];
         }
         const cx<double> qa = cx<double>{0.2 * (A[F_QXX].x + A[F_QYY].x + A[F_QZZ].x),
                                          0.2 * (A[F_QXX].y + A[F_QYY].y + A[F_QZZ].y)};
