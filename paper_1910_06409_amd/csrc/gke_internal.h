@@ -19,11 +19,13 @@ enum { F_U = 0, F_V, F_W, F_P, F_QXX, F_QYY, F_QZZ, F_QXY, F_QXZ, F_QYZ, NFIELD 
 // precision of the cross-spectral update (GKE_PREC_*)
 enum { PREC_FP64 = 0, PREC_BF16X3 = 1 };
 
-// one complex spectral value split for the three-term BF16 products:
-// (re_hi, re_lo, im_hi, im_lo) as BF16 bit patterns, lo = RN(x - hi)
+// one complex spectral value split for the three-term BF16 products, as BF16
+// bit patterns with hi = RN(x), lo = RN(x - hi) for x = re, im; the two high
+// parts share one dword and the two low parts the other (the operand layout
+// of the matrix-core update, k_rankk_bf16.hip)
 struct bf16x4 {
-    unsigned int re;  // re_hi | re_lo << 16
-    unsigned int im;  // im_hi | im_lo << 16
+    unsigned int hi;  // re_hi | im_hi << 16
+    unsigned int lo;  // re_lo | im_lo << 16
 };
 
 // term spectra accumulated per unordered pair tile (see k_rankk.hip)

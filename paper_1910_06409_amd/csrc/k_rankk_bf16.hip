@@ -2,18 +2,23 @@
 // three-term MFMA products and FP32 accumulation.
 //
 // Every spectral value x is stored as x ~ hi + lo with hi = RN_bf16(x) and
-// lo = RN_bf16(x - hi).  A real product a b is taken as ah bh + ah bl + al bh
-// (the al bl term, below 2^-16 |a b|, is dropped).  For the complex product
-// conj(L) R of one snapshot the six real terms of each output part form one
-// group of eight K entries (two zero):
-//   A    = [Lrh, Lrh, Lrl, Lih, Lih, Lil, 0, 0]
-//   B_re = [Rrh, Rrl, Rrh, Rih, Ril, Rih, 0, 0]   -> sum = Re conj(L) R
-//   B_im = [Rih, Ril, Rih,-Rrh,-Rrl,-Rrh, 0, 0]   -> sum = Im conj(L) R
+// lo = RN_bf16(x - hi); a real product a b is taken as ah bh + ah bl + al bh
+// (the al bl term, below 2^-16 |a b|, is dropped).  The stored dwords are
+// h = (re_hi, im_hi) and l = (re_lo, im_lo) (bf16x4).  For conj(L) R of one
+// snapshot the six real terms of each output part form one group of eight K
+// entries (two zero), built from the dwords without arithmetic:
+//   A    = [Lh, Lh, Ll, 0]           = [Lrh, Lih, Lrh, Lih, Lrl, Lil, 0, 0]
+//   B_re = [Rh, Rl, Rh, 0]           = [Rrh, Rih, Rrl, Ril, Rrh, Rih, 0, 0]
+//   B_im = [s(Rh), s(Rl), s(Rh), 0]  = [Rih,-Rrh, Ril,-Rrl, Rih,-Rrh, 0, 0]
+// (s(x) swaps the two halves and negates the new upper one):
+//   A . B_re = Re conj(L) R,  A . B_im = Im conj(L) R  (three terms each).
 // v_mfma_f32_16x16x32_bf16 takes K = 32: lane l carries K entries 8(l/16)..+7,
 // so lane group g = l/16 carries snapshot s0 + g and one MFMA covers four
 // snapshots.  Rows (Y1) and columns (Y2) are planes, l%16 within the tile.
 // Output (checked on the device): lane l, register v -> (row 4(l/16) + v, col l%16).
-// The 27 products and nine accumulators are those of k_rankk.hip.
+// The nine accumulators are those of k_rankk.hip; q never enters as a field:
+// c5 = (v, q) + (q, v) = 0.2 sum_i [(v, Q_ii) + (Q_ii, v)], 31 products per
+// snapshot, which costs four MFMA pairs and saves forming q from split values.
 #include "rankk_common.h"
 
 namespace gke {
@@ -22,74 +27,21 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ bf8 as_bf8(unsigned int d0, unsigned int d1, unsigned int d2)
+__device__ __forceinline__ bf8 op3(unsigned int d0, unsigned int d1, unsigned int d2)
 {
     return __builtin_bit_cast(bf8, u4{d0, d1, d2, 0u});
 }
+// swap the BF16 halves, negate the new upper one: (a, b) -> (b, -a)
+__device__ __forceinline__ unsigned int swapneg(unsigned int x)
+{
+    return ((x >> 16) | (x << 16)) ^ 0x80000000u;
+}
+constexpr unsigned int NEG2 = 0x80008000u;   // negate both halves
 
-// the three operand forms of one stored value (re = rh | rl<<16, im = ih | il<<16)
-struct OpA {
-    bf8 a;
-};
-struct OpB {
-    bf8 re, im;
-};
-
-__device__ __forceinline__ OpA make_a(unsigned int re, unsigned int im)
-{
-    // [rh, rh, rl, ih, ih, il, 0, 0]
-    return OpA{as_bf8((re & 0xffffu) | (re << 16), (re >> 16) | (im << 16), im)};
-}
-__device__ __forceinline__ OpA neg_a(OpA x)
-{
-    u4 v = __builtin_bit_cast(u4, x.a);
-    v.x ^= 0x80008000u;
-    v.y ^= 0x80008000u;
-    v.z ^= 0x80008000u;
-    return OpA{__builtin_bit_cast(bf8, v)};
-}
-__device__ __forceinline__ OpB make_b(unsigned int re, unsigned int im)
-{
-    const unsigned int rre = (re >> 16) | (re << 16);  // [rl, rh]
-    const unsigned int rim = (im >> 16) | (im << 16);  // [il, ih]
-    OpB b;
-    // [rh, rl, rh, ih, il, ih, 0, 0]
-    b.re = as_bf8(re, (re & 0xffffu) | (im << 16), rim);
-    // [ih, il, ih, -rh, -rl, -rh, 0, 0]
-    b.im = as_bf8(im, (im & 0xffffu) | ((re ^ 0x8000u) << 16), rre ^ 0x80008000u);
-    return b;
-}
-
-__device__ __forceinline__ float hi_f(unsigned int w) { return __uint_as_float(w << 16); }
-__device__ __forceinline__ float lo_f(unsigned int w) { return __uint_as_float(w & 0xffff0000u); }
-__device__ __forceinline__ unsigned int bf16_rn(float x)
-{
-    unsigned int u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
-}
-__device__ __forceinline__ unsigned int split_f(float x)
-{
-    const unsigned int h = bf16_rn(x);
-    return h | (bf16_rn(x - __uint_as_float(h << 16)) << 16);
-}
-// q = (Qxx + Qyy + Qzz) / 5 from the stored hi + lo values, split again
-__device__ __forceinline__ void make_q(const bf16x4 *F, unsigned int &re, unsigned int &im)
-{
-    const float qr = 0.2f * ((hi_f(F[F_QXX].re) + lo_f(F[F_QXX].re)) +
-                             (hi_f(F[F_QYY].re) + lo_f(F[F_QYY].re)) +
-                             (hi_f(F[F_QZZ].re) + lo_f(F[F_QZZ].re)));
-    const float qi = 0.2f * ((hi_f(F[F_QXX].im) + lo_f(F[F_QXX].im)) +
-                             (hi_f(F[F_QYY].im) + lo_f(F[F_QYY].im)) +
-                             (hi_f(F[F_QZZ].im) + lo_f(F[F_QZZ].im)));
-    re = split_f(qr);
-    im = split_f(qi);
-}
-
-#define GKE_MFMA_BF(c, A, B)                                                          \
-    do {                                                                              \
-        ar[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16((A).a, (B).re, ar[c], 0, 0, 0); \
-        ai[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16((A).a, (B).im, ai[c], 0, 0, 0); \
+#define GKE_MFMA_BF(c, A, BRE, BIM)                                                \
+    do {                                                                           \
+        ar[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16((A), (BRE), ar[c], 0, 0, 0); \
+        ai[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16((A), (BIM), ai[c], 0, 0, 0); \
     } while (0)
 
 // Loads of one snapshot quad (lane group g takes snapshot s0 + g): a
@@ -112,66 +64,79 @@ __device__ __forceinline__ void load_raw(bf16x4 *L, bf16x4 *R, const char *kb, s
 }
 
 // The split products of one snapshot quad into the nine accumulators.
-__device__ __forceinline__ void rankk_bf16_step(f4 *ar, f4 *ai, bf16x4 *Lc, const bf16x4 *Rc,
-                                                bool ok)
+__device__ __forceinline__ void rankk_bf16_step(f4 *ar, f4 *ai, const bf16x4 *L,
+                                                const bf16x4 *R)
 {
-    // a snapshot past the end contributes nothing: zero its left operand
-#pragma unroll
-    for (int f = 0; f < NFIELD; ++f) {
-        Lc[f].re = ok ? Lc[f].re : 0u;
-        Lc[f].im = ok ? Lc[f].im : 0u;
-    }
-    unsigned int lqr, lqi, rqr, rqi;
-    make_q(Lc, lqr, lqi);
-    make_q(Rc, rqr, rqi);
-    const OpA u_ = make_a(Lc[F_U].re, Lc[F_U].im), v_ = make_a(Lc[F_V].re, Lc[F_V].im);
-    const OpA w_ = make_a(Lc[F_W].re, Lc[F_W].im), p_ = make_a(Lc[F_P].re, Lc[F_P].im);
-    const OpA q_ = make_a(lqr, lqi);
-    const OpA Qxx = make_a(Lc[F_QXX].re, Lc[F_QXX].im), Qyy = make_a(Lc[F_QYY].re, Lc[F_QYY].im);
-    const OpA Qzz = make_a(Lc[F_QZZ].re, Lc[F_QZZ].im), Qxy = make_a(Lc[F_QXY].re, Lc[F_QXY].im);
-    const OpA Qxz = make_a(Lc[F_QXZ].re, Lc[F_QXZ].im), Qyz = make_a(Lc[F_QYZ].re, Lc[F_QYZ].im);
-    const OpA nu_ = neg_a(u_), nv_ = neg_a(v_), nw_ = neg_a(w_);
-    const OpB U = make_b(Rc[F_U].re, Rc[F_U].im), V = make_b(Rc[F_V].re, Rc[F_V].im);
-    const OpB W = make_b(Rc[F_W].re, Rc[F_W].im), P = make_b(Rc[F_P].re, Rc[F_P].im);
-    const OpB Q = make_b(rqr, rqi);
-    const OpB RQxx = make_b(Rc[F_QXX].re, Rc[F_QXX].im), RQyy = make_b(Rc[F_QYY].re, Rc[F_QYY].im);
-    const OpB RQzz = make_b(Rc[F_QZZ].re, Rc[F_QZZ].im), RQxy = make_b(Rc[F_QXY].re, Rc[F_QXY].im);
-    const OpB RQxz = make_b(Rc[F_QXZ].re, Rc[F_QXZ].im), RQyz = make_b(Rc[F_QYZ].re, Rc[F_QYZ].im);
-
-    GKE_MFMA_BF(0, u_, U);
-    GKE_MFMA_BF(1, Qxx, U);
-    GKE_MFMA_BF(2, Qxz, U);
-    GKE_MFMA_BF(3, Qxy, U);
-    GKE_MFMA_BF(8, v_, U);
-    GKE_MFMA_BF(4, u_, RQxy);
-    GKE_MFMA_BF(1, nu_, RQxx);
-    GKE_MFMA_BF(2, nu_, RQxz);
-    GKE_MFMA_BF(5, v_, Q);
-    GKE_MFMA_BF(0, v_, V);
-    GKE_MFMA_BF(1, Qxy, V);
-    GKE_MFMA_BF(2, Qyz, V);
-    GKE_MFMA_BF(3, Qyy, V);
-    GKE_MFMA_BF(6, p_, V);
-    GKE_MFMA_BF(7, u_, V);
-    GKE_MFMA_BF(4, v_, RQyy);
-    GKE_MFMA_BF(5, q_, V);
-    GKE_MFMA_BF(1, nv_, RQxy);
-    GKE_MFMA_BF(2, nv_, RQyz);
-    GKE_MFMA_BF(6, v_, P);
-    GKE_MFMA_BF(0, w_, W);
-    GKE_MFMA_BF(1, Qxz, W);
-    GKE_MFMA_BF(2, Qzz, W);
-    GKE_MFMA_BF(3, Qyz, W);
-    GKE_MFMA_BF(4, w_, RQyz);
-    GKE_MFMA_BF(1, nw_, RQxz);
-    GKE_MFMA_BF(2, nw_, RQzz);
+    // left operands (planes Y1) and the negated u, v, w
+    const bf8 u_ = op3(L[F_U].hi, L[F_U].hi, L[F_U].lo);
+    const bf8 v_ = op3(L[F_V].hi, L[F_V].hi, L[F_V].lo);
+    const bf8 w_ = op3(L[F_W].hi, L[F_W].hi, L[F_W].lo);
+    const bf8 p_ = op3(L[F_P].hi, L[F_P].hi, L[F_P].lo);
+    const bf8 xx = op3(L[F_QXX].hi, L[F_QXX].hi, L[F_QXX].lo);
+    const bf8 yy = op3(L[F_QYY].hi, L[F_QYY].hi, L[F_QYY].lo);
+    const bf8 zz = op3(L[F_QZZ].hi, L[F_QZZ].hi, L[F_QZZ].lo);
+    const bf8 xy = op3(L[F_QXY].hi, L[F_QXY].hi, L[F_QXY].lo);
+    const bf8 xz = op3(L[F_QXZ].hi, L[F_QXZ].hi, L[F_QXZ].lo);
+    const bf8 yz = op3(L[F_QYZ].hi, L[F_QYZ].hi, L[F_QYZ].lo);
+    const bf8 nu_ = op3(L[F_U].hi ^ NEG2, L[F_U].hi ^ NEG2, L[F_U].lo ^ NEG2);
+    const bf8 nv_ = op3(L[F_V].hi ^ NEG2, L[F_V].hi ^ NEG2, L[F_V].lo ^ NEG2);
+    const bf8 nw_ = op3(L[F_W].hi ^ NEG2, L[F_W].hi ^ NEG2, L[F_W].lo ^ NEG2);
+    // right operands (planes Y2): real-output and imaginary-output forms
+#define GKE_B(f, re, im)                                                     \
+    const bf8 re = op3(R[f].hi, R[f].lo, R[f].hi);                           \
+    const unsigned int im##h = swapneg(R[f].hi), im##l = swapneg(R[f].lo);   \
+    const bf8 im = op3(im##h, im##l, im##h)
+    GKE_B(F_U, Ur, Ui);
+    GKE_B(F_V, Vr, Vi);
+    GKE_B(F_W, Wr, Wi);
+    GKE_B(F_P, Pr, Pi);
+    GKE_B(F_QXX, XXr, XXi);
+    GKE_B(F_QYY, YYr, YYi);
+    GKE_B(F_QZZ, ZZr, ZZi);
+    GKE_B(F_QXY, XYr, XYi);
+    GKE_B(F_QXZ, XZr, XZi);
+    GKE_B(F_QYZ, YZr, YZi);
+#undef GKE_B
+    // 31 products, ordered so that successive ones feed different accumulators
+    GKE_MFMA_BF(0, u_, Ur, Ui);
+    GKE_MFMA_BF(1, xx, Ur, Ui);
+    GKE_MFMA_BF(2, xz, Ur, Ui);
+    GKE_MFMA_BF(3, xy, Ur, Ui);
+    GKE_MFMA_BF(8, v_, Ur, Ui);
+    GKE_MFMA_BF(5, v_, XXr, XXi);
+    GKE_MFMA_BF(4, u_, XYr, XYi);
+    GKE_MFMA_BF(1, nu_, XXr, XXi);
+    GKE_MFMA_BF(2, nu_, XZr, XZi);
+    GKE_MFMA_BF(0, v_, Vr, Vi);
+    GKE_MFMA_BF(5, xx, Vr, Vi);
+    GKE_MFMA_BF(1, xy, Vr, Vi);
+    GKE_MFMA_BF(2, yz, Vr, Vi);
+    GKE_MFMA_BF(3, yy, Vr, Vi);
+    GKE_MFMA_BF(6, p_, Vr, Vi);
+    GKE_MFMA_BF(7, u_, Vr, Vi);
+    GKE_MFMA_BF(5, yy, Vr, Vi);
+    GKE_MFMA_BF(4, v_, YYr, YYi);
+    GKE_MFMA_BF(1, nv_, XYr, XYi);
+    GKE_MFMA_BF(2, nv_, YZr, YZi);
+    GKE_MFMA_BF(6, v_, Pr, Pi);
+    GKE_MFMA_BF(5, v_, YYr, YYi);
+    GKE_MFMA_BF(0, w_, Wr, Wi);
+    GKE_MFMA_BF(1, xz, Wr, Wi);
+    GKE_MFMA_BF(2, zz, Wr, Wi);
+    GKE_MFMA_BF(3, yz, Wr, Wi);
+    GKE_MFMA_BF(5, zz, Vr, Vi);
+    GKE_MFMA_BF(4, w_, YZr, YZi);
+    GKE_MFMA_BF(1, nw_, XZr, XZi);
+    GKE_MFMA_BF(2, nw_, ZZr, ZZi);
+    GKE_MFMA_BF(5, v_, ZZr, ZZi);
 }
 
+// register prefetch of the next snapshot quad (1) or none (0); waves per SIMD
 #ifndef GKE_RANKK16_PF
-#define GKE_RANKK16_PF 0
+#define GKE_RANKK16_PF 1
 #endif
 #ifndef GKE_RANKK16_MINW
-#define GKE_RANKK16_MINW 3
+#define GKE_RANKK16_MINW 2
 #endif
 
 __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
@@ -204,27 +169,33 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
     }
 
 #if GKE_RANKK16_PF
-    bf16x4 Lc[NFIELD], Rc[NFIELD];
-    load_raw(Lc, Rc, kb, fbytes, loff, roff, sbytes, 0, g, nsnap);
+    bf16x4 Ln[NFIELD], Rn[NFIELD];
+    load_raw(Ln, Rn, kb, fbytes, loff, roff, sbytes, 0, g, nsnap);
+#endif
     for (int s0 = 0; s0 < nsnap; s0 += 4) {
-        bf16x4 Ln[NFIELD], Rn[NFIELD];
-        load_raw(Ln, Rn, kb, fbytes, loff, roff, sbytes, s0 + 4 < nsnap ? s0 + 4 : s0, g, nsnap);
-        __builtin_amdgcn_sched_barrier(0);
-        rankk_bf16_step(ar, ai, Lc, Rc, s0 + g < nsnap);
-        __builtin_amdgcn_sched_barrier(0);
+        bf16x4 L[NFIELD], R[NFIELD];
+#if GKE_RANKK16_PF
 #pragma unroll
         for (int f = 0; f < NFIELD; ++f) {
-            Lc[f] = Ln[f];
-            Rc[f] = Rn[f];
+            L[f] = Ln[f];
+            R[f] = Rn[f];
         }
-    }
+        load_raw(Ln, Rn, kb, fbytes, loff, roff, sbytes, s0 + 4 < nsnap ? s0 + 4 : s0, g, nsnap);
+        __builtin_amdgcn_sched_barrier(0);
 #else
-    for (int s0 = 0; s0 < nsnap; s0 += 4) {
-        bf16x4 Lc[NFIELD], Rc[NFIELD];
-        load_raw(Lc, Rc, kb, fbytes, loff, roff, sbytes, s0, g, nsnap);
-        rankk_bf16_step(ar, ai, Lc, Rc, s0 + g < nsnap);
-    }
+        load_raw(L, R, kb, fbytes, loff, roff, sbytes, s0, g, nsnap);
 #endif
+        if (s0 + 4 > nsnap) {
+            // a snapshot past the end contributes nothing: zero its left operand
+            const bool ok = s0 + g < nsnap;
+#pragma unroll
+            for (int f = 0; f < NFIELD; ++f) {
+                L[f].hi = ok ? L[f].hi : 0u;
+                L[f].lo = ok ? L[f].lo : 0u;
+            }
+        }
+        rankk_bf16_step(ar, ai, L, R);
+    }
 
     const size_t sp_stride = (size_t)d.nk * d.npair;
 #pragma unroll
@@ -236,6 +207,8 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
             cr[c] = (double)ar[c][v];
             ci[c] = (double)ai[c][v];
         }
+        cr[5] *= 0.2;   // (v, q) + (q, v) from the 0.2 (Q_xx + Q_yy + Q_zz) products
+        ci[5] *= 0.2;
         store_spectra(acc, sp_stride, o, cr, ci, accumulate);
     }
 }

@@ -43,7 +43,8 @@ __device__ __forceinline__ void store_spec(cx<double> *spec, size_t i, cx<T> X) 
 template <typename T>
 __device__ __forceinline__ void store_spec(bf16x4 *spec, size_t i, cx<T> X)
 {
-    spec[i] = bf16x4{split_bf16((float)X.x), split_bf16((float)X.y)};
+    const unsigned int r = split_bf16((float)X.x), m = split_bf16((float)X.y);
+    spec[i] = bf16x4{(r & 0xffffu) | (m << 16), (r >> 16) | (m & 0xffff0000u)};
 }
 
 // One block = zb consecutive z rows of plane j.  One pass over the inputs:

@@ -210,8 +210,9 @@ __device__ __forceinline__ cx<double> band_value(const cx<double> *s, size_t i) 
 __device__ __forceinline__ cx<double> band_value(const bf16x4 *s, size_t i)
 {
     const bf16x4 v = s[i];
-    return cx<double>{(double)__uint_as_float(v.re << 16) + (double)__uint_as_float(v.re & 0xffff0000u),
-                      (double)__uint_as_float(v.im << 16) + (double)__uint_as_float(v.im & 0xffff0000u)};
+    return cx<double>{(double)__uint_as_float(v.hi << 16) + (double)__uint_as_float(v.lo << 16),
+                      (double)__uint_as_float(v.hi & 0xffff0000u) +
+                          (double)__uint_as_float(v.lo & 0xffff0000u)};
 }
 
 template <typename S>

@@ -49,8 +49,8 @@ __device__ __forceinline__ cx<double> spec_value(const cx<double> *s, size_t i) 
 __device__ __forceinline__ cx<double> spec_value(const bf16x4 *s, size_t i)
 {
     const bf16x4 v = s[i];
-    const double rh = __uint_as_float(v.re << 16), rl = __uint_as_float(v.re & 0xffff0000u);
-    const double ih = __uint_as_float(v.im << 16), il = __uint_as_float(v.im & 0xffff0000u);
+    const double rh = __uint_as_float(v.hi << 16), rl = __uint_as_float(v.lo << 16);
+    const double ih = __uint_as_float(v.hi & 0xffff0000u), il = __uint_as_float(v.lo & 0xffff0000u);
     return cx<double>{rh + rl, ih + il};
 }
 
