@@ -301,6 +301,27 @@ __device__ __forceinline__ void load_twiddles(cx<T> *dst, const cx<T> *src, int 
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
+// The same copy in two steps, for a caller that issues it among its other
+// loads: load() reads two entries per thread, unconditionally (a thread past
+// the end reads the last entry), store() writes them to LDS (a thread past the
+// end writes the last entry onto itself); entries beyond 2 * BLOCK are copied
+// by a loop in store().  No branch holds a load and its wait.
+template <typename T, int BLOCK>
+struct TwiddleCopy {
+    cx<T> v[2];
+    __device__ __forceinline__ void load(const cx<T> *src, int n)
+    {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) v[q] = src[min((int)threadIdx.x + q * BLOCK, n - 1)];
+    }
+    __device__ __forceinline__ void store(cx<T> *dst, const cx<T> *src, int n) const
+    {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) dst[min((int)threadIdx.x + q * BLOCK, n - 1)] = v[q];
+        for (int i = threadIdx.x + 2 * BLOCK; i < n; i += BLOCK) dst[i] = src[i];
+    }
+};
+
 // Gather `count` elements, MAXE per thread at a time: the loads of a group are
 // all issued before any is consumed, so a thread keeps MAXE loads in flight.
 // get(e) loads element e, put(e, v) stores it.

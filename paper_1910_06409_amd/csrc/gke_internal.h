@@ -46,7 +46,7 @@ enum { P_U = 0, P_V, P_W, P_P, P_S, P_Q, P_UV, P_PV, P_TX, P_TY, P_TZ, P_EPS, NP
 enum { MP_Q = 0, MP_UV, MP_PV, MP_QU, MP_QV, MP_QW, MP_GY, NMOMP };
 
 // pass-1 plane sums are split over this many blocks per plane
-constexpr int NSPLIT = 8;
+constexpr int NSPLIT = 32;
 
 // LDS transforms: at most FFT_CAP complex elements per block and FFT_BLOCK
 // threads per block.  4096 FP64 elements (64 KiB) and 512 threads let two
@@ -66,6 +66,7 @@ constexpr int NSPLIT = 8;
 #define GKE_GATHER 4
 #endif
 constexpr int FFT_CAP = GKE_FFT_CAP;
+constexpr int MAX_NTX = 16;   // complex transforms (two pairs each) per kx-pass block
 constexpr int FFT_BLOCK = GKE_FFT_BLOCK;
 // launch bounds of the transform kernels: FFT_BLOCK threads, at least
 // GKE_FFT_WAVES waves per SIMD (so that several blocks share a compute unit)
@@ -80,6 +81,7 @@ struct Dims {
     int ntp;          // ntile (ntile + 1) / 2 unordered tile pairs
     int npair_tiles;  // 256 ntp pairs handled on the matrix cores
     int npair;        // all unordered pairs (tile pairs + remainder pairs)
+    int pstr;         // pair stride of the accumulators: npair rounded up to 8 (128-byte rows)
     int zb, nzb;      // z rows per block in the x pass, number of blocks
     int jb, njb;      // planes per block in the z pass, number of blocks
     int pbz;          // pairs per block in the finalize kz pass

@@ -159,6 +159,9 @@ void fornberg_d1(double x0, const double *x, int n, double *w)
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+// pair extents of acc and mid rows: whole 128-byte lines of complex FP64
+template <typename I>
+I round8(I n) { return (n + 7) & ~(I)7; }
 
 // Bracket one launch with HIP events when timing is on.
 template <typename F>
@@ -313,8 +316,8 @@ size_t layout(gke_plan_t p, char *base)
     const size_t esz = d.prec == gke::PREC_BF16X3 ? 8 : sizeof(cx<double>);
     p->inter = take(esz * (size_t)d.ny * d.nzb * gke::NFIELD * d.nkx * d.zb);
     p->spec = take(esz * (size_t)d.nk * gke::NFIELD * d.chunk * d.ny);
-    p->acc = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NSPEC * d.nk * npair);
-    p->mid = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NMAP * d.nkx * d.nz * pbt);
+    p->acc = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NSPEC * d.nk * round8(npair));
+    p->mid = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NMAP * d.nkx * d.nz * round8(pbt));
     p->mstride = nrows * d.ny * (size_t)d.nz * d.nx;
     p->mf = (double *)take(sizeof(double) * gke::NSTORED * p->mstride);
     p->band = (double *)take(p->general ? sizeof(double) * (size_t)d.nk * 5 * d.ny : 0);
@@ -338,6 +341,7 @@ gke_status select_slab(gke_plan_t p, int s)
     p->d.ntp = t.ntp;
     p->d.npair_tiles = t.npair_tiles;
     p->d.npair = t.npair;
+    p->d.pstr = round8(t.npair);
     p->cur_slab = s;
     return GKE_OK;
 }
@@ -408,6 +412,7 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
     d.npair_tiles = 256 * d.ntp;
     // tile entries (diagonal tiles hold both orientations) + remainder pairs
     d.npair = d.npair_tiles + Ny * (Ny + 1) / 2 - (16 * d.ntile) * (16 * d.ntile + 1) / 2;
+    d.pstr = round8(d.npair);
     d.lx = Lx;
     d.lz = Lz;
     d.nu = nu;
@@ -430,10 +435,13 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
         d.njb = (Ny + jmax - 1) / jmax;
         d.jb = (Ny + d.njb - 1) / d.njb;
     }
-    // finalize: pairs per kz block, complex transforms (2 pairs) per kx block
+    // finalize: pairs per kz block, complex transforms (2 pairs each) per kx block
+    // (kz pass: multiples of 8 pairs where possible, 128-byte runs of acc and mid)
     d.pbz = (int)std::min<size_t>(48, cap / sz);
-    d.ntx = (int)std::min<size_t>(16, cap / (sx + 2 * (size_t)d.nkx));
-    if (d.zb < 1 || d.jb < 1 || d.pbz < 1 || d.ntx < 1) {
+    d.pbz &= d.pbz >= 8 ? ~7 : ~1;   // even: the R blocks split it in halves
+    d.ntx = (int)std::min<size_t>(gke::MAX_NTX, cap / sx);
+    // 32-bit element offsets within one wavenumber row of acc (kz pass)
+    if (d.zb < 1 || d.jb < 1 || d.pbz < 2 || d.ntx < 1 || (size_t)Nz * d.pstr >= ((size_t)1 << 31)) {
         delete p;
         return fail(nullptr, GKE_ERR_UNSUPPORTED, "grid too large for the LDS transforms");
     }

@@ -22,62 +22,87 @@ static void set_lds_limit(F *kernel)
                               (int)LDS_BUDGET);
 }
 
-// Inverse transform along kz for pb pairs of one term spectrum at one kx.
-// mid layout: [NMAP][nkx][nz (rz)][ptot (pairs of this batch)].
+__host__ __device__ inline int mid_stride(int ptot) { return (ptot + 7) & ~7; }
+
+// Inverse transform along kz of the pairs of one term spectrum at one kx.
+// Blocks z = 0, 1 take the two halves of a block of pb pairs of the R spectrum
+// and transform R^ and i beta R^ together (2 * pb/2 transforms); blocks z >= 2
+// take pb pairs of spectrum z - 1.  Every block reads its part of acc once.
+// mid layout: [NMAP][nkx][nz (rz)][mid_stride(ptot)] (the pairs of this batch,
+// rows padded to whole 128-byte lines).
 __global__ GKE_FFT_BOUNDS void k_fin_kz(const cx<double> *__restrict__ acc, Dims d,
                                                       Tables t, int p0, int ptot,
                                                       double inv_count,
                                                       cx<double> *__restrict__ mid)
 {
     extern __shared__ cx<double> lds[];
-    const int nz = d.nz, nkx = d.nkx, pb = d.pbz;
-    const int pblk = blockIdx.x, kx = blockIdx.y, sp = blockIdx.z;
-    const int pl0 = pblk * pb;                       // first pair within the batch
-    const int np = min(pb, ptot - pl0);
-    const size_t pall = (size_t)d.npair;
-    const size_t pg0 = (size_t)p0 + pl0;             // first pair within acc
+    const int nz = d.nz, nkx = d.nkx, pb = d.pbz;   // pb even (host)
+    const int kx = blockIdx.y;
+    const bool isr = blockIdx.z < 2;
+    const int sp = isr ? (int)S_R : (int)blockIdx.z - 1;
+    const int pl0 = blockIdx.x * pb + (isr ? (int)blockIdx.z * (pb >> 1) : 0);
+    const int np = min(isr ? pb >> 1 : pb, ptot - pl0);   // pairs of this block
+    if (np <= 0) return;                                   // whole block
+    const size_t pall = (size_t)d.pstr;
+    const size_t mst = (size_t)mid_stride(ptot);
     const int bs = fft_stride(nz);
     const double two_pi = 6.283185307179586476925286766559;
     const double alpha = (2 * kx == d.nx) ? 0.0 : two_pi * kx / d.lx;
-    const int nout_tr = (sp == S_R) ? 2 : 1;
     cx<double> *tw = lds + pb * bs;
-    load_twiddles(tw, t.twz, nz);
-    const cx<double> *ab = acc + ((size_t)sp * d.nk + (size_t)kx * nz) * pall + pg0;
+    const cx<double> *ab = acc + ((size_t)sp * d.nk + (size_t)kx * nz) * pall + p0 + pl0;
     const int cnt = nz * np;
-    for (int tr = 0; tr < nout_tr; ++tr) {
-        // e = kz np + b: pairs contiguous in acc
-        gather_batched<GKE_GATHER, FFT_BLOCK, cx<double>>(
-            cnt,
-            [&](int e) {
-                const int kz = e / np, b = e - kz * np;
-                return ab[kz * pall + b];
-            },
-            [&](int e, cx<double> X) {
-                const int kz = e / np, b = e - kz * np;
-                X = cscale(X, inv_count);
-                if (tr == 1) {  // i beta R^
-                    const int kzs = (kz <= nz / 2) ? kz : kz - nz;
-                    const double beta = (2 * kz == nz) ? 0.0 : two_pi * kzs / d.lz;
-                    X = cx<double>{-beta * X.y, beta * X.x};
-                }
-                lds[b * bs + fft_pad(kz)] = X;
-            });
-        __syncthreads();
-        lds_fft_ip<double, FFT_CAP, FFT_BLOCK>(lds, np, bs, t.pz, tw, +1);
-        int m0;
-        if (sp == S_R) m0 = (tr == 0) ? M_R : M_DRZ;
-        else m0 = M_FX + (sp - S_FX);  // FX FY FZ PHI PP UVS UVA map one to one
-        Walk2 ws(threadIdx.x, FFT_BLOCK, np);   // (rz, b)
-        for (int e = threadIdx.x; e < cnt; e += FFT_BLOCK) {
-            const int rz = ws.hi, b = ws.lo;
-            ws.next();
-            const cx<double> Y = lds[b * bs + fft_pad(rz)];
-            const size_t o = ((size_t)kx * nz + rz) * ptot + pl0 + b;
-            mid[(size_t)m0 * nkx * nz * ptot + o] = Y;
-            if (sp == S_R && tr == 0)  // i alpha R^: alpha is constant along kz
-                mid[(size_t)M_DRX * nkx * nz * ptot + o] = cx<double>{-alpha * Y.y, alpha * Y.x};
+    {
+        // nz * np <= FFT_CAP: every load of this thread is in flight at once.
+        // Loads and LDS stores are unconditional (no branch holds a load and
+        // its wait): a slot past the end takes element (nz - 1, 0) and stores
+        // it where that element goes.  e = kz np + b (pairs contiguous in acc),
+        // walked without divisions.
+        constexpr int MAXE = (FFT_CAP + FFT_BLOCK - 1) / FFT_BLOCK;
+        cx<double> x[MAXE];
+        const int ps = (int)pall;   // nz * pall < 2^31 (host)
+        Walk2 w(threadIdx.x, FFT_BLOCK, np);   // (kz, b)
+#pragma unroll
+        for (int q = 0; q < MAXE; ++q) {
+            const bool ok = w.hi < nz;
+            x[q] = ab[(ok ? w.hi : nz - 1) * ps + (ok ? w.lo : 0)];
+            w.next();
         }
-        __syncthreads();
+        TwiddleCopy<double, FFT_BLOCK> twc;   // in flight with the gathers
+        twc.load(t.twz, nz);
+        twc.store(tw, t.twz, nz);
+        w = Walk2(threadIdx.x, FFT_BLOCK, np);
+        const double bscale = two_pi / d.lz;
+#pragma unroll
+        for (int q = 0; q < MAXE; ++q) {
+            const bool ok = w.hi < nz;
+            const int kz = ok ? w.hi : nz - 1, b = ok ? w.lo : 0;
+            w.next();
+            const cx<double> X = cscale(x[q], inv_count);
+            lds[b * bs + fft_pad(kz)] = X;
+            if (isr) {   // i beta R^ as transform np + b
+                const int kzs = (kz <= nz / 2) ? kz : kz - nz;
+                const double beta = (2 * kz == nz) ? 0.0 : bscale * kzs;
+                lds[(np + b) * bs + fft_pad(kz)] = cx<double>{-beta * X.y, beta * X.x};
+            }
+        }
+    }
+    __syncthreads();
+    lds_fft_ip<double, FFT_CAP, FFT_BLOCK>(lds, isr ? 2 * np : np, bs, t.pz, tw, +1);
+    const size_t mplane = (size_t)nkx * nz * mst;
+    Walk2 ws(threadIdx.x, FFT_BLOCK, np);   // (rz, b)
+    for (int e = threadIdx.x; e < cnt; e += FFT_BLOCK) {
+        const int rz = ws.hi, b = ws.lo;
+        ws.next();
+        const cx<double> Y = lds[b * bs + fft_pad(rz)];
+        const size_t o = ((size_t)kx * nz + rz) * mst + pl0 + b;
+        if (isr) {
+            mid[(size_t)M_R * mplane + o] = Y;
+            // i alpha R^: alpha is constant along kz
+            mid[(size_t)M_DRX * mplane + o] = cx<double>{-alpha * Y.y, alpha * Y.x};
+            mid[(size_t)M_DRZ * mplane + o] = lds[(np + b) * bs + fft_pad(rz)];
+        } else {
+            mid[(size_t)(M_FX + (sp - S_FX)) * mplane + o] = Y;   // FX .. UVA one to one
+        }
     }
 }
 
@@ -87,7 +112,7 @@ hipError_t launch_fin_kz(hipStream_t st, const Dims &d, const Tables &t,
 {
     const int ptot = p1 - p0;
     const size_t lds = sizeof(cx<double>) * ((size_t)d.pbz * fft_stride(d.nz) + d.nz);
-    dim3 grid((ptot + d.pbz - 1) / d.pbz, d.nkx, NSPEC);
+    dim3 grid((ptot + d.pbz - 1) / d.pbz, d.nkx, NSPEC + 1);
     set_lds_limit(k_fin_kz);
     hipLaunchKernelGGL(k_fin_kz, grid, dim3(FFT_BLOCK), lds, st, acc, d, t, p0, ptot, inv_count,
                        mid);
@@ -107,17 +132,32 @@ __device__ __forceinline__ double map_sigma(int m)
     }
 }
 
-// Assemble the terms that use map m at (j1, j2) and store them at index o.
-__device__ __forceinline__ void assemble_store(int m, double val, int j1, int j2,
-                                               const double *prof, int ny, double nu,
+// One-point profile rows that map m combines with: a (and b) at Y1 and Y2.
+__device__ __forceinline__ void map_rows(int m, int &ra, int &rb)
+{
+    rb = -1;
+    switch (m) {
+    case M_R: ra = P_Q; rb = P_U; break;
+    case M_FX: ra = P_TX; break;
+    case M_FY: case M_PHI: ra = P_TY; break;
+    case M_FZ: ra = P_TZ; break;
+    case M_PP: ra = P_PV; break;
+    case M_UVS: case M_UVA: ra = P_UV; rb = P_S; break;
+    default: ra = -1; break;   // M_DRX, M_DRZ
+    }
+}
+
+// Assemble the terms that use map m and store them at index o; a1 a2 (b1 b2)
+// are the profile rows of map_rows at the first and the second plane.
+__device__ __forceinline__ void assemble_store(int m, double val, double a1, double a2,
+                                               double b1, double b2, double nu,
                                                const OutPtrs &out, size_t o)
 {
-#define PR(row, j) prof[(row) * ny + (j)]
     switch (m) {
     case M_R: {
-        const double t1 = PR(P_Q, j1) + PR(P_Q, j2) - 2.0 * val;       // <du^2>
+        const double t1 = a1 + a2 - 2.0 * val;                // <du^2>
         if (out.t[0]) out.t[0][o] = t1;
-        if (out.t[2]) out.t[2][o] = (PR(P_U, j2) - PR(P_U, j1)) * t1;  // <du^2 dU>
+        if (out.t[2]) out.t[2][o] = (b2 - b1) * t1;            // <du^2 dU>
         break;
     }
     case M_DRX:
@@ -127,34 +167,44 @@ __device__ __forceinline__ void assemble_store(int m, double val, int j1, int j2
         if (out.t[7]) out.t[7][o] = 4.0 * nu * val;
         break;
     case M_FX:
-        if (out.t[1]) out.t[1][o] = PR(P_TX, j2) - PR(P_TX, j1) + val;
+        if (out.t[1]) out.t[1][o] = a2 - a1 + val;
         break;
     case M_FY:
-        if (out.t[4]) out.t[4][o] = PR(P_TY, j2) - PR(P_TY, j1) + val;
+        if (out.t[4]) out.t[4][o] = a2 - a1 + val;
         break;
     case M_FZ:
-        if (out.t[6]) out.t[6][o] = PR(P_TZ, j2) - PR(P_TZ, j1) + val;
+        if (out.t[6]) out.t[6][o] = a2 - a1 + val;
         break;
     case M_PHI:
-        if (out.t[8]) out.t[8][o] = 0.5 * (PR(P_TY, j1) + PR(P_TY, j2) + val);
+        if (out.t[8]) out.t[8][o] = 0.5 * (a1 + a2 + val);
         break;
     case M_PP:
-        if (out.t[9]) out.t[9][o] = 2.0 * (PR(P_PV, j1) + PR(P_PV, j2) - val);
+        if (out.t[9]) out.t[9][o] = 2.0 * (a1 + a2 - val);
         break;
     case M_UVS:
-        if (out.t[11])
-            out.t[11][o] = -2.0 * (PR(P_UV, j1) + PR(P_UV, j2) - val) * 0.5 * (PR(P_S, j1) + PR(P_S, j2));
+        if (out.t[11]) out.t[11][o] = -2.0 * (a1 + a2 - val) * 0.5 * (b1 + b2);
         break;
     default:  // M_UVA
-        if (out.t[12]) out.t[12][o] = -(PR(P_UV, j2) - PR(P_UV, j1) + val) * (PR(P_S, j2) - PR(P_S, j1));
+        if (out.t[12]) out.t[12][o] = -(a2 - a1 + val) * (b2 - b1);
         break;
     }
-#undef PR
 }
+
+// per-pair data of a kx block, staged in LDS before the transform
+struct PairInfo {
+    int j1, j2, mirror, row1;   // row1: output row of j1 in the full-plane mode
+    double a1, a2, b1, b2;
+};
 
 // Inverse real transform along kx of 2*nt pairs (two real maps per complex
 // transform), then assembly for pair (Y1, Y2) and, when the pair table asks
 // for it, the mirrored pair (Y2, Y1) from r -> -r.
+//   Transform c packs pairs 2c and 2c + 1: A_c[n] = X_2c[n] + i X_2c+1[n] with
+//   X[n] for n > Nx/2 from Hermitian symmetry, X[Nx - kx] = conj X[kx]; the
+//   real and imaginary parts of its inverse are the two maps.  A thread loads
+//   both pairs of (kx, c) (adjacent in mid) and writes A_c[kx] and A_c[Nx - kx].
+//   Output: a group of tpp consecutive threads per pair, consecutive threads
+//   on consecutive rx.
 __global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims d,
                                                       Tables t, int p0, int ptot,
                                                       const double *__restrict__ prof,
@@ -167,85 +217,98 @@ __global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims
     const int pl0 = pblk * npair;
     const int np = min(npair, ptot - pl0);
     const int bs = fft_stride(nx);
-    cx<double> *A = lds;                      // nt transforms of length nx
-    cx<double> *S = lds + nt * bs;            // staging [kx][pair]
-    cx<double> *tw = S + nkx * npair;         // twiddles
-    load_twiddles(tw, t.twx, nx);
+    cx<double> *A = lds;            // nt transforms of length nx
+    cx<double> *tw = lds + nt * bs;   // twiddles
+    __shared__ PairInfo pinfo[2 * MAX_NTX];
+    // Every global load is issued before the first LDS store, so that the
+    // block waits about two round trips (pair code, then everything else).
+    // Loads and stores are unconditional at clamped indices (no branch holds
+    // a load and its wait): a slot past the end repeats the last element,
+    // which writes the same values to the same place.
+    const int code = t.pairs[p0 + pl0 + min((int)threadIdx.x, np - 1)];
+    // nkx * nt <= FFT_CAP / 2 + MAX_NTX (nt * fft_stride(nx) <= FFT_CAP, host)
+    constexpr int MAXG = (FFT_CAP / 2 + MAX_NTX + FFT_BLOCK - 1) / FFT_BLOCK;
+    const int cnt = nkx * nt;
+    cx<double> xa[MAXG], xb[MAXG];
+    const size_t mst = (size_t)mid_stride(ptot);
     {
-        // e = kx npair + b: the pairs of one (map, kx, rz) are contiguous in mid
-        const cx<double> *mb = mid + ((size_t)m * nkx * nz + rz) * ptot + pl0;
-        const size_t skx = (size_t)nz * ptot;
-        const int cnt = nkx * npair;
-        for (int base = 0; base < cnt; base += GKE_GATHER * FFT_BLOCK) {
-            Walk2 w(base + threadIdx.x, FFT_BLOCK, npair);   // (kx, b)
-            cx<double> v[GKE_GATHER];
+        const cx<double> *mb = mid + ((size_t)m * nkx * nz + rz) * mst + pl0;
+        const size_t skx = (size_t)nz * mst;
+        Walk2 w(threadIdx.x, FFT_BLOCK, nt);   // (kx, c)
 #pragma unroll
-            for (int q = 0; q < GKE_GATHER; ++q) {
-                v[q] = cx<double>{0.0, 0.0};
-                if (base + (int)threadIdx.x + q * FFT_BLOCK < cnt && w.lo < np)
-                    v[q] = mb[w.hi * skx + w.lo];
-                w.next();
-            }
-#pragma unroll
-            for (int q = 0; q < GKE_GATHER; ++q) {
-                const int e = base + threadIdx.x + q * FFT_BLOCK;
-                if (e < cnt) S[e] = v[q];
-            }
+        for (int q = 0; q < MAXG; ++q) {
+            const bool ok = w.hi < nkx;
+            const cx<double> *src = mb + (ok ? w.hi : nkx - 1) * skx;
+            const int c = ok ? w.lo : nt - 1;
+            xa[q] = src[min(2 * c, np - 1)];
+            xb[q] = src[min(2 * c + 1, np - 1)];
+            w.next();
         }
     }
-    __syncthreads();
-    // consecutive threads take consecutive transforms: bank-friendly reads of S
-    Walk2 wn(threadIdx.x, FFT_BLOCK, nt);   // (n, c)
-    for (int e = threadIdx.x; e < nt * nx; e += FFT_BLOCK) {
-        const int n = wn.hi, c = wn.lo;
-        wn.next();
-        cx<double> xa, xb;
-        if (n <= nx / 2) {
-            xa = S[n * npair + 2 * c];
-            xb = S[n * npair + 2 * c + 1];
-        } else {
-            xa = cconj(S[(nx - n) * npair + 2 * c]);
-            xb = cconj(S[(nx - n) * npair + 2 * c + 1]);
-        }
-        A[c * bs + fft_pad(n)] = cx<double>{xa.x - xb.y, xa.y + xb.x};  // xa + i xb
+    PairInfo pi;
+    pi.j1 = pair_j1(code);
+    pi.j2 = pair_j2(code);
+    pi.mirror = pair_mirror(code);
+    pi.row1 = full ? t.rowidx[pi.j1] : 0;
+    {
+        int ra, rb;
+        map_rows(m, ra, rb);
+        pi.a1 = ra >= 0 ? prof[ra * ny + pi.j1] : 0.0;
+        pi.a2 = ra >= 0 ? prof[ra * ny + pi.j2] : 0.0;
+        pi.b1 = rb >= 0 ? prof[rb * ny + pi.j1] : 0.0;
+        pi.b2 = rb >= 0 ? prof[rb * ny + pi.j2] : 0.0;
     }
+    {
+        TwiddleCopy<double, FFT_BLOCK> twc;
+        twc.load(t.twx, nx);
+        twc.store(tw, t.twx, nx);
+    }
+    {
+        Walk2 w(threadIdx.x, FFT_BLOCK, nt);   // (kx, c)
+#pragma unroll
+        for (int q = 0; q < MAXG; ++q) {
+            const bool ok = w.hi < nkx;
+            const int kx = ok ? w.hi : nkx - 1, c = ok ? w.lo : nt - 1;
+            w.next();
+            const cx<double> zero = cx<double>{0.0, 0.0};
+            const cx<double> a = 2 * c < np ? xa[q] : zero;      // padding pairs read 0
+            const cx<double> b = 2 * c + 1 < np ? xb[q] : zero;
+            cx<double> *Ac = A + c * bs;
+            Ac[fft_pad(kx)] = cx<double>{a.x - b.y, a.y + b.x};  // a + i b
+            const int kn = (kx == 0 || 2 * kx == nx) ? kx : nx - kx;
+            Ac[fft_pad(kn)] = kn == kx ? cx<double>{a.x - b.y, a.y + b.x}
+                                       : cx<double>{a.x + b.y, b.x - a.y};   // conj a + i conj b
+        }
+    }
+    if ((int)threadIdx.x < np) pinfo[threadIdx.x] = pi;
     __syncthreads();
     lds_fft_ip<double, FFT_CAP, FFT_BLOCK>(A, nt, bs, t.px, tw, +1);
+    const int tpp = FFT_BLOCK / npair;            // threads per pair
+    const int b = threadIdx.x / tpp, lane = threadIdx.x - b * tpp;
+    if (b >= np) return;
+    const PairInfo p = pinfo[b];
+    const cx<double> *Ac = A + (b >> 1) * bs;
     if (full) {
         // one orientation, every rx, rows of the full-plane buffer
-        Walk2 wb(threadIdx.x, FFT_BLOCK, nx);   // (b, rx)
-        for (int e = threadIdx.x; e < np * nx; e += FFT_BLOCK) {
-            const int b = wb.hi, rx = wb.lo;
-            wb.next();
-            const int code = t.pairs[p0 + pl0 + b];
-            const int j1 = pair_j1(code), j2 = pair_j2(code);
-            const cx<double> zv = A[(b >> 1) * bs + fft_pad(rx)];
-            const double val = (b & 1) ? zv.y : zv.x;
-            assemble_store(m, val, j1, j2, prof, ny, d.nu, out,
-                           (((size_t)t.rowidx[j1] * ny + j2) * nz + rz) * nx + rx);
+        const size_t o0 = (((size_t)p.row1 * ny + p.j2) * nz + rz) * nx;
+        for (int rx = lane; rx < nx; rx += tpp) {
+            const cx<double> zv = Ac[fft_pad(rx)];
+            assemble_store(m, (b & 1) ? zv.y : zv.x, p.a1, p.a2, p.b1, p.b2, d.nu, out, o0 + rx);
         }
         return;
     }
     const double sig = map_sigma(m);
     const size_t plane = (size_t)nz * nkx;
-    Walk2 wb(threadIdx.x, FFT_BLOCK, nkx);   // (b, rx)
-    for (int e = threadIdx.x; e < np * nkx; e += FFT_BLOCK) {
-        const int b = wb.hi, rx = wb.lo;
-        wb.next();
-        const int code = t.pairs[p0 + pl0 + b];
-        const int j1 = pair_j1(code), j2 = pair_j2(code);
-        const int c = b >> 1;
-        const cx<double> zv = A[c * bs + fft_pad(rx)];
-        const double val = (b & 1) ? zv.y : zv.x;
-        assemble_store(m, val, j1, j2, prof, ny, d.nu, out,
-                       ((size_t)j1 * ny + j2) * plane + (size_t)rz * nkx + rx);
-        if (pair_mirror(code)) {
-            const int rxm = (rx == 0) ? 0 : nx - rx;
-            const cx<double> zm = A[c * bs + fft_pad(rxm)];
+    const size_t o0 = ((size_t)p.j1 * ny + p.j2) * plane + (size_t)rz * nkx;
+    const int rzm = (rz == 0) ? 0 : nz - rz;
+    const size_t om = ((size_t)p.j2 * ny + p.j1) * plane + (size_t)rzm * nkx;
+    for (int rx = lane; rx < nkx; rx += tpp) {
+        const cx<double> zv = Ac[fft_pad(rx)];
+        assemble_store(m, (b & 1) ? zv.y : zv.x, p.a1, p.a2, p.b1, p.b2, d.nu, out, o0 + rx);
+        if (p.mirror) {   // (Y2, Y1) at -r: the profile roles swap
+            const cx<double> zm = Ac[fft_pad(rx == 0 ? 0 : nx - rx)];
             const double vm = sig * ((b & 1) ? zm.y : zm.x);
-            const int rzm = (rz == 0) ? 0 : nz - rz;
-            assemble_store(m, vm, j2, j1, prof, ny, d.nu, out,
-                           ((size_t)j2 * ny + j1) * plane + (size_t)rzm * nkx + rx);
+            assemble_store(m, vm, p.a2, p.a1, p.b2, p.b1, d.nu, out, om + rx);
         }
     }
 }
@@ -255,8 +318,7 @@ hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
                          double *const *out, int full)
 {
     const int ptot = p1 - p0;
-    const size_t lds = sizeof(cx<double>) *
-                       ((size_t)d.ntx * fft_stride(d.nx) + (size_t)d.nkx * 2 * d.ntx + d.nx);
+    const size_t lds = sizeof(cx<double>) * ((size_t)d.ntx * fft_stride(d.nx) + d.nx);
     OutPtrs op;
     for (int i = 0; i < 14; ++i) op.t[i] = out[i];
     dim3 grid((ptot + 2 * d.ntx - 1) / (2 * d.ntx), d.nz, NMAP);
@@ -268,14 +330,20 @@ hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
 
 // Step 3: d/dY1 and d/dY2 of <du^2> with the five-point weights;
 // T6 = -2 nu d/dry = -nu (d/dY2 - d/dY1), T11 = -(nu/2)(d/dY1 + d/dY2).
+// Blocks in the order (Y1, Y2, chunk of the plane), chunk fastest; the blocks
+// of one XCD (workgroup i runs on XCD i mod 8) take a contiguous range of that
+// order, so the Y2 neighbours of a block were read into the same L2 shortly
+// before.
 __global__ __launch_bounds__(256) void k_fd_terms(const double *__restrict__ t1, Dims d,
                                                   Tables t, double *__restrict__ t6,
-                                                  double *__restrict__ t11)
+                                                  double *__restrict__ t11, int nchunk)
 {
     const int ny = d.ny;
     const size_t plane = (size_t)d.nz * d.nkx;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int j2 = blockIdx.y, j1 = blockIdx.z;
+    const int nb = (int)gridDim.x, q8 = nb >> 3, r8 = nb & 7, xcd = blockIdx.x & 7;
+    const int item = xcd * q8 + min(xcd, r8) + (int)(blockIdx.x >> 3);
+    const int chunk = item % nchunk, j2 = (item / nchunk) % ny, j1 = item / (nchunk * ny);
+    const size_t i = (size_t)chunk * blockDim.x + threadIdx.x;
     if (i >= plane) return;
     const int a1 = t.j0[j1], a2 = t.j0[j2];
     double d1 = 0.0, d2 = 0.0;
@@ -293,8 +361,11 @@ hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const
                            double *t6, double *t11)
 {
     const size_t plane = (size_t)d.nz * d.nkx;
-    dim3 grid((unsigned)((plane + 255) / 256), d.ny, d.ny);
-    hipLaunchKernelGGL(k_fd_terms, grid, dim3(256), 0, st, t1, d, t, t6, t11);
+    const int nchunk = (int)((plane + 255) / 256);
+    const size_t nblk = (size_t)nchunk * d.ny * d.ny;
+    if (nblk >= ((size_t)1 << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fd_terms, dim3((unsigned)nblk), dim3(256), 0, st, t1, d, t, t6, t11,
+                       nchunk);
     return hipGetLastError();
 }
 

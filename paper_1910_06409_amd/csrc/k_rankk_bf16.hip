@@ -197,10 +197,10 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
         rankk_bf16_step(ar, ai, L, R);
     }
 
-    const size_t sp_stride = (size_t)d.nk * d.npair;
+    const size_t sp_stride = (size_t)d.nk * d.pstr;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const size_t o = (size_t)k * d.npair + (size_t)tp * 256 + (4 * g + v) * 16 + row;
+        const size_t o = (size_t)k * d.pstr + (size_t)tp * 256 + (4 * g + v) * 16 + row;
         double cr[9], ci[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) {

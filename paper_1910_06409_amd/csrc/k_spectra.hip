@@ -78,63 +78,87 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
     const double W = prof[P_W * ny + j], P = prof[P_P * ny + j];
     const int nel = zb * nx;
     constexpr bool kGy = sizeof(T) == sizeof(float);   // split-BF16 path
+    // zb nx and nx stay below FFT_CAP / 5 (host check): NI elements per thread
+    constexpr int NI = (FFT_CAP / 5 + FFT_BLOCK - 1) / FFT_BLOCK;
+    constexpr int NG = kGy ? NI : 1;
     const int js = t.j0[j];
-    double wt[5], Ms[3][5];
-    for (int a = 0; a < 5; ++a) {
-        wt[a] = kGy ? t.w5[j * 5 + a] : 0.0;
-        Ms[0][a] = kGy ? prof[P_U * ny + js + a] : 0.0;
-        Ms[1][a] = kGy ? prof[P_V * ny + js + a] : 0.0;
-        Ms[2][a] = kGy ? prof[P_W * ny + js + a] : 0.0;
+    // every load of this thread is issued before any is consumed: the
+    // twiddles, the four inputs and, on the split path, the five-plane stencil
+    // (unconditional loads at clamped indices, so that no branch separates
+    // them; the extra values are dropped)
+    TwiddleCopy<T, FFT_BLOCK> twc;
+    twc.load(tw_of<T>(t, 0), nx);
+    TI in[NI][4];
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+        const int e = min((int)threadIdx.x + q * FFT_BLOCK, nel - 1);
+        in[q][0] = u[off + e];
+        in[q][1] = v[off + e];
+        in[q][2] = w[off + e];
+        in[q][3] = p[off + e];
     }
-    double mq = 0, muv = 0, mpv = 0, mqu = 0, mqv = 0, mqw = 0, mgy = 0;
-    Walk2 wr(threadIdx.x, FFT_BLOCK, nx);   // (row, x)
-    for (int e = threadIdx.x; e < nel; e += FFT_BLOCK) {
-        const double a = (double)u[off + e] - U, b = (double)v[off + e] - V;
-        const double c = (double)w[off + e] - W, dd = (double)p[off + e] - P;
-        const double q = a * a + b * b + c * c;
-        mq += q;
-        muv += a * b;
-        mpv += dd * b;
-        mqu += q * a;
-        mqv += q * b;
-        mqw += q * c;
-        if (kGy) {
-            double gu = 0, gv = 0, gw = 0;
+    cx<T> *tw = lds + 5 * zb * bs;
+    twc.store(tw, tw_of<T>(t, 0), nx);   // the twiddle loads were issued first
+    TI st[NG][3][5];
+    if (kGy) {
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            const int e = min((int)threadIdx.x + q * FFT_BLOCK, nel - 1);
+#pragma unroll
             for (int k = 0; k < 5; ++k) {
                 const size_t o = (size_t)(js + k) * npl + (size_t)z0 * nx + e;
-                gu += wt[k] * ((double)u[o] - Ms[0][k]);
-                gv += wt[k] * ((double)v[o] - Ms[1][k]);
-                gw += wt[k] * ((double)w[o] - Ms[2][k]);
+                st[q][0][k] = u[o];
+                st[q][1][k] = v[o];
+                st[q][2][k] = w[o];
             }
-            mgy += gu * gu + gv * gv + gw * gw;
+        }
+    }
+    // every slot is processed; a slot past the end (clamped to the last
+    // element) adds nothing to the sums and rewrites the last element's LDS
+    // entries with the same values
+    double mq = 0, muv = 0, mpv = 0, mqu = 0, mqv = 0, mqw = 0, mgy = 0;
+    Walk2 wr(threadIdx.x, FFT_BLOCK, nx);   // (row, x)
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+        const bool ok = (int)threadIdx.x + q * FFT_BLOCK < nel;
+        const double a = (double)in[q][0] - U, b = (double)in[q][1] - V;
+        const double c = (double)in[q][2] - W, dd = (double)in[q][3] - P;
+        const double qq = a * a + b * b + c * c;
+        mq += ok ? qq : 0.0;
+        muv += ok ? a * b : 0.0;
+        mpv += ok ? dd * b : 0.0;
+        mqu += ok ? qq * a : 0.0;
+        mqv += ok ? qq * b : 0.0;
+        mqw += ok ? qq * c : 0.0;
+        if (kGy) {
+            double gu = 0, gv = 0, gw = 0;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const double wk = t.w5[j * 5 + k];
+                gu += wk * ((double)st[q < NG ? q : 0][0][k] - prof[P_U * ny + js + k]);
+                gv += wk * ((double)st[q < NG ? q : 0][1][k] - prof[P_V * ny + js + k]);
+                gw += wk * ((double)st[q < NG ? q : 0][2][k] - prof[P_W * ny + js + k]);
+            }
+            mgy += ok ? gu * gu + gv * gv + gw * gw : 0.0;
         }
         // (u,v) (w,p) (Qxx,Qyy) (Qzz,Qxy) (Qxz,Qyz), two real rows per complex row
-        const int row = wr.hi, x = fft_pad(wr.lo);
+        const int row = ok ? wr.hi : zb - 1, x = fft_pad(ok ? wr.lo : nx - 1);
         wr.next();
         lds[(0 * zb + row) * bs + x] = cx<T>{(T)a, (T)b};
         lds[(1 * zb + row) * bs + x] = cx<T>{(T)c, (T)dd};
-        lds[(2 * zb + row) * bs + x] = cx<T>{(T)(2.0 * a * a + q), (T)(2.0 * b * b + q)};
-        lds[(3 * zb + row) * bs + x] = cx<T>{(T)(2.0 * c * c + q), (T)(2.0 * a * b)};
+        lds[(2 * zb + row) * bs + x] = cx<T>{(T)(2.0 * a * a + qq), (T)(2.0 * b * b + qq)};
+        lds[(3 * zb + row) * bs + x] = cx<T>{(T)(2.0 * c * c + qq), (T)(2.0 * a * b)};
         lds[(4 * zb + row) * bs + x] = cx<T>{(T)(2.0 * a * c), (T)(2.0 * b * c)};
     }
-    // the seven partial sums in one fixed-order block reduction
+    // the seven partial sums: wave reductions now, the fixed-order sum over
+    // the waves and the update of momp after the transform, so that no global
+    // round trip sits before the barrier
     double parts[NMOMP] = {mq, muv, mpv, mqu, mqv, mqw, mgy};
 #pragma unroll
     for (int k = 0; k < NMOMP; ++k)
-        for (int off = 32; off > 0; off >>= 1) parts[k] += __shfl_down(parts[k], off, 64);
-    {
-        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-        if (lane == 0)
-            for (int k = 0; k < NMOMP; ++k) shm[k * (FFT_BLOCK / 64) + wid] = parts[k];
-        __syncthreads();
-        if ((int)threadIdx.x < NMOMP) {
-            double r = 0.0;
-            for (int i = 0; i < FFT_BLOCK / 64; ++i) r += shm[threadIdx.x * (FFT_BLOCK / 64) + i];
-            momp[((size_t)j * NMOMP + threadIdx.x) * d.nzb + zblk] += r;
-        }
-    }
-    cx<T> *tw = lds + 5 * zb * bs;
-    load_twiddles(tw, tw_of<T>(t, 0), nx);
+        for (int o = 32; o > 0; o >>= 1) parts[k] += __shfl_down(parts[k], o, 64);
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < NMOMP; ++k) shm[k * (FFT_BLOCK / 64) + (threadIdx.x >> 6)] = parts[k];
     __syncthreads();
     lds_fft_ip<T, FFT_CAP, FFT_BLOCK>(lds, 5 * zb, bs, t.px, tw, -1);
     // split the two real transforms: Fa = (Z(k) + conj Z(-k))/2, Fb = (Z(k) - conj Z(-k))/(2i)
@@ -152,6 +176,11 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
         const cx<T> Fb = cx<T>{T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
         dst[((2 * pr) * nkx + k) * zb + row] = Fa;
         dst[((2 * pr + 1) * nkx + k) * zb + row] = Fb;
+    }
+    if ((int)threadIdx.x < NMOMP) {   // shm was written before the first barrier
+        double r = 0.0;
+        for (int i = 0; i < FFT_BLOCK / 64; ++i) r += shm[threadIdx.x * (FFT_BLOCK / 64) + i];
+        momp[((size_t)j * NMOMP + threadIdx.x) * d.nzb + zblk] += r;
     }
 }
 
@@ -181,7 +210,11 @@ hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int
 
 // One block = jb consecutive planes of one field at one kx (FP64 path; two
 // blocks share a compute unit): transform along z, scale, and store
-// spec[k = kx*Nz + kz][f][slot][j] (planes contiguous).
+// spec[k = kx*Nz + kz][f][slot][j] (planes contiguous).  Work items in the order
+// (f, kx, jblk), jblk fastest; the workgroups of one XCD (workgroup i runs on
+// XCD i mod 8) take a contiguous range of items, so the items of neighbouring
+// kx, which read the two halves of the same cache lines of inter, meet in one
+// L2 a few items apart.
 template <typename T, typename S>
 __global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, Dims d,
                                                          Tables t, int slot,
@@ -190,28 +223,46 @@ __global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, 
     extern __shared__ unsigned char lds_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
     const int nx = d.nx, ny = d.ny, nz = d.nz, nkx = d.nkx, jb = d.jb;
-    const int jblk = blockIdx.x, kx = blockIdx.y, f = blockIdx.z;
+    const int nitem = (int)gridDim.x, q8 = nitem >> 3, r8 = nitem & 7, xcd = blockIdx.x & 7;
+    const int item = xcd * q8 + min(xcd, r8) + (int)(blockIdx.x >> 3);
+    const int jblk = item % d.njb, kx = (item / d.njb) % nkx, f = item / (d.njb * nkx);
     const int j0 = jblk * jb;
     const int nb = min(jb, ny - j0);
     const int bs = fft_stride(nz);
     const int zb = d.zb, lzb = __builtin_ctz(zb), zm = zb - 1;
     cx<T> *tw = lds + jb * bs;
-    load_twiddles(tw, tw_of<T>(t, 1), nz);
     // inter[((((j0 + b) nzb + zblk) NFIELD + f) nkx + kx) zb + row], z = zblk zb + row
     // offsets within a block stay below 2^31 (jb planes of inter)
     const int szb = NFIELD * nkx * zb, sb = d.nzb * szb;
     const cx<T> *ib = inter + (size_t)j0 * sb + ((size_t)f * nkx + kx) * zb;
     const int cnt = nb * nz;
-    gather_batched<GKE_GATHER, FFT_BLOCK, cx<T>>(
-        cnt,
-        [&](int e) {
-            const int b = e / nz, z = e - b * nz;
-            return ib[b * sb + (z >> lzb) * szb + (z & zm)];
-        },
-        [&](int e, cx<T> x) {
-            const int b = e / nz, z = e - b * nz;
-            lds[b * bs + fft_pad(z)] = x;
-        });
+    {
+        // nb * nz <= FFT_CAP: every load of this thread is in flight at once.
+        // Loads and LDS stores are unconditional, so that no branch holds a
+        // load and its wait: a slot past the end takes the last plane's first
+        // element and stores it where that element goes (the same value as
+        // its own thread stores).  Element e = b nz + z walked without divisions.
+        constexpr int MAXE = (FFT_CAP + FFT_BLOCK - 1) / FFT_BLOCK;
+        cx<T> x[MAXE];
+        Walk2 w(threadIdx.x, FFT_BLOCK, nz);   // (b, z)
+#pragma unroll
+        for (int q = 0; q < MAXE; ++q) {
+            const bool ok = w.hi < nb;
+            const int b = ok ? w.hi : nb - 1, z = ok ? w.lo : 0;
+            x[q] = ib[b * sb + (z >> lzb) * szb + (z & zm)];
+            w.next();
+        }
+        TwiddleCopy<T, FFT_BLOCK> twc;   // in flight with the gathers
+        twc.load(tw_of<T>(t, 1), nz);
+        twc.store(tw, tw_of<T>(t, 1), nz);
+        w = Walk2(threadIdx.x, FFT_BLOCK, nz);
+#pragma unroll
+        for (int q = 0; q < MAXE; ++q) {
+            const bool ok = w.hi < nb;
+            lds[(ok ? w.hi : nb - 1) * bs + fft_pad(ok ? w.lo : 0)] = x[q];
+            w.next();
+        }
+    }
     __syncthreads();
     lds_fft_ip<T, FFT_CAP, FFT_BLOCK>(lds, nb, bs, t.pz, tw, -1);
     const double scale = 1.0 / ((double)nx * (double)nz);
@@ -266,8 +317,10 @@ __global__ __launch_bounds__(ZBLOCK) void k_zfft_pack(const cx<T> *__restrict__ 
         const cx<T> *ib = inter + (size_t)j0 * sb + ((size_t)f * nkx + kx) * zb;
         Walk2 w = wg;
 #pragma unroll
-        for (int q = 0; q < MAXE; ++q) {
-            if (w.hi < nb) pf[q] = ib[w.hi * sb + (size_t)(w.lo >> lzb) * szb + (w.lo & zm)];
+        for (int q = 0; q < MAXE; ++q) {   // unconditional loads (see k_zfft_pack_blk)
+            const bool ok = w.hi < nb;
+            const int b = ok ? w.hi : nb - 1, z = ok ? w.lo : 0;
+            pf[q] = ib[b * sb + (size_t)(z >> lzb) * szb + (z & zm)];
             w.next();
         }
     };
@@ -335,7 +388,7 @@ hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t, cons
         // unit, register spills); two plain blocks per compute unit
         const size_t lds = sizeof(cx<double>) * ((size_t)d.jb * fft_stride(d.nz) + d.nz);
         set_lds_limit(k_zfft_pack_blk<double, cx<double>>);
-        hipLaunchKernelGGL((k_zfft_pack_blk<double, cx<double>>), dim3(d.njb, d.nkx, NFIELD),
+        hipLaunchKernelGGL((k_zfft_pack_blk<double, cx<double>>), dim3(nitems),
                            dim3(FFT_BLOCK), lds, st, (const cx<double> *)inter, d, t, slot,
                            (cx<double> *)spec);
     }

@@ -35,11 +35,25 @@ __global__ __launch_bounds__(256) void k_plane_sums(const TI *__restrict__ u,
     const int i0 = part * len, i1 = min(npl, i0 + len);
     const size_t off = (size_t)j * npl;
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        a[0] += (double)u[off + i];
-        a[1] += (double)v[off + i];
-        a[2] += (double)w[off + i];
-        a[3] += (double)p[off + i];
+    // four elements per field in flight per thread: unconditional loads at
+    // clamped indices, the ones past the end add nothing
+    constexpr int U = 4;
+    for (int i = i0 + threadIdx.x; i < i1; i += U * blockDim.x) {
+        TI x[U][4];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const size_t ik = off + min(i + k * (int)blockDim.x, i1 - 1);
+            x[k][0] = u[ik];
+            x[k][1] = v[ik];
+            x[k][2] = w[ik];
+            x[k][3] = p[ik];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const bool ok = i + k * (int)blockDim.x < i1;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) a[f] += ok ? (double)x[k][f] : 0.0;
+        }
     }
     for (int f = 0; f < 4; ++f) {
         const double r = block_sum(a[f], sh);
@@ -126,13 +140,13 @@ __global__ __launch_bounds__(256) void k_r0(const cx<double> *__restrict__ acc, 
         return;
     }
     const int P = t.pidx[y * d.ny + y + a];
-    const cx<double> *s = acc + (size_t)S_R * d.nk * d.npair + P;
+    const cx<double> *s = acc + (size_t)S_R * d.nk * d.pstr + P;
     const double two_pi = 6.283185307179586476925286766559;
     double r = 0.0, g = 0.0;
     for (int k = threadIdx.x; k < d.nk; k += blockDim.x) {
         const int kx = k / d.nz, kz = k - kx * d.nz;
         const double w = (kx == 0 || 2 * kx == d.nx) ? 1.0 : 2.0;
-        const double v = w * s[(size_t)k * d.npair].x;
+        const double v = w * s[(size_t)k * d.pstr].x;
         r += v;
         if (a == 0) {
             const int kzs = (kz <= d.nz / 2) ? kz : kz - d.nz;

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(64, 2) void k_rankk_rem(const S *__restrict__ spec,
         mac(7, ua, vb, 1.0);
         mac(8, va, ub, 1.0);
     }
-    store_spectra(acc, (size_t)d.nk * d.npair, (size_t)k * d.npair + d.npair_tiles + i, cr, ci,
+    store_spectra(acc, (size_t)d.nk * d.pstr, (size_t)k * d.pstr + d.npair_tiles + i, cr, ci,
                   accumulate);
 }
 
