@@ -35,127 +35,155 @@
 // P = 256 tp + 16 (row offset) + (column offset), the remainder pairs follow in
 // the order of the host-built pair table.
 //
-// MFMA mapping (v_mfma_f64_16x16x4f64, one wave per 16x16 output tile):
-//   K index = (snapshot pair s0, s0+1) x (real, imaginary part);
-//   A (lane l): Re/Im of L[Y1 = row plane 16a + l%16][s0 + (l/16)/2], picked by (l/16)%2;
-//   B (lane l): for the real output (Rr, Ri), for the imaginary output
-//               (Ri, -Rr) of R[Y2 = 16b + l%16][s0 + (l/16)/2];
-//   so sum_k A B = Re/Im of conj(L) R.
+// MFMA mapping (v_mfma_f64_16x16x4f64, K = four snapshots s0 .. s0+3):
+//   A (lane l): L[Y1 = row plane 16a + l%16][s0 + l/16],
+//   B (lane l): R[Y2 = 16b + l%16][s0 + l/16],
 //   D (lane l, register v): element (row l/16 + 4v, Y2 = 16b + l%16)
 //   (checked on the device: the f64 form strides the rows by 4 across registers).
+// Each complex product conj(L) R = (Lr - i Li)(Rr + i Ri) takes three real
+// products (the three-multiplication form of a complex product):
+//   K1 = (Lr - Li) Rr,  K2 = Lr (Ri - Rr),  K3 = -Li (Rr + Ri),
+//   Re = K1 - K3,  Im = K1 + K2,
+// so 27 complex products cost 81 MFMAs per four snapshots instead of 108.
+// The three real accumulators per complex accumulator do not fit one wave, so
+// a tile pair takes three waves, each with three complex accumulators and
+// loading only the fields they need: wave 0 holds c3 c4 c5 (8 products),
+// wave 1 c1 c7 c8 (8 products), wave 2 c0 c2 c6 (11 products); every term
+// spectrum is formed from one wave's accumulators.
 #include "rankk_common.h"
 
 namespace gke {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-#define GKE_MFMA2(c, a, br, bi)                                                   \
-    do {                                                                         \
-        ar[c] = __builtin_amdgcn_mfma_f64_16x16x4f64((a), (br), ar[c], 0, 0, 0); \
-        ai[c] = __builtin_amdgcn_mfma_f64_16x16x4f64((a), (bi), ai[c], 0, 0, 0); \
-    } while (0)
-
-struct Operands {
-    double L[NFIELD];
-    cx<double> R[NFIELD];
+// Loads of four snapshots (one per lane group) of the fields a wave uses.
+// Addresses split into a wave-uniform part (wavenumber, field, snapshot group:
+// scalar registers) and a 32-bit lane offset (plane, snapshot within the
+// group).  Branch-free: a snapshot past the end reloads the last valid one and
+// its left operand is zeroed (a zero left value cancels every product of that
+// snapshot), so the loads stay in flight.
+struct Loader {
+    const char *kb;
+    size_t fbytes;
+    unsigned loff, roff, sbytes;
+    __device__ __forceinline__ cx<double> get(int f, unsigned off, int s0, unsigned so) const
+    {
+        return *reinterpret_cast<const cx<double> *>(kb + (size_t)s0 * sbytes + f * fbytes +
+                                                     off + so);
+    }
 };
 
-// Loads of one snapshot pair.  Addresses split into a wave-uniform part
-// (wavenumber, field, snapshot pair: scalar registers) and a 32-bit lane
-// offset (plane, snapshot within the pair, real/imaginary part).
-// Branch-free: a pair past the end reloads the last valid snapshot; the caller
-// zeroes the left operand of such a slot when it uses it (a zero left value
-// cancels every product of that snapshot), so the loads stay in flight.
-__device__ __forceinline__ void load_operands(Operands &op, const char *kb, size_t fbytes,
-                                              unsigned loff, unsigned roff, unsigned sbytes,
-                                              int s0, int soff, int nsnap)
+// acc[3c + 0..2] += K1, K2, K3 of sg conj(l) r  (sg = -1 when neg, folded into
+// A); the right-hand forms Rr, Ri - Rr, Rr + Ri are formed here, so that only
+// the complex values stay live between products
+__device__ __forceinline__ void mac3(d4 *acc, int c, cx<double> l, cx<double> r, bool neg)
 {
-    const int s = s0 + soff < nsnap ? s0 + soff : nsnap - 1;
-    const unsigned so = (unsigned)(s - s0) * sbytes;
-    const char *base = kb + (size_t)s0 * sbytes;
+    const double a1 = neg ? l.y - l.x : l.x - l.y;
+    const double a2 = neg ? -l.x : l.x;
+    const double a3 = neg ? l.y : -l.y;
+    acc[3 * c + 0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, r.x, acc[3 * c + 0], 0, 0, 0);
+    acc[3 * c + 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, r.y - r.x, acc[3 * c + 1], 0, 0, 0);
+    acc[3 * c + 2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, r.x + r.y, acc[3 * c + 2], 0, 0, 0);
+}
+
+// fields of each wave, left and right
+constexpr int W0F[8] = {F_U, F_V, F_W, F_QXX, F_QYY, F_QZZ, F_QXY, F_QYZ};   // c3 c4 c5
+constexpr int W1F[6] = {F_U, F_V, F_W, F_QXX, F_QXY, F_QXZ};                 // c1 c7 c8
+constexpr int W2F[7] = {F_U, F_V, F_W, F_P, F_QXZ, F_QYZ, F_QZZ};            // c0 c2 c6
+
+template <int N>
+__device__ __forceinline__ void load_fields(cx<double> *L, cx<double> *R, const int (&fl)[N],
+                                            const Loader &ld, int s0, unsigned so, bool ok)
+{
 #pragma unroll
-    for (int f = 0; f < NFIELD; ++f) {
-        const char *bf = base + f * fbytes;
-        const unsigned lo = loff + so, ro = roff + so;
-        op.L[f] = *reinterpret_cast<const double *>(bf + lo);
-        op.R[f] = *reinterpret_cast<const cx<double> *>(bf + ro);
+    for (int i = 0; i < N; ++i) {
+        L[i] = ld.get(fl[i], ld.loff, s0, so);
+        R[i] = ld.get(fl[i], ld.roff, s0, so);
+    }
+    if (!ok) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) L[i] = cx<double>{0.0, 0.0};
     }
 }
 
-// The products of one snapshot pair into the nine accumulators.
-__device__ __forceinline__ void rankk_f64_step(d4 *ar, d4 *ai, const Operands &cur, bool ok,
-                                               int ri)
+// wave 0: acc slots 0 1 2 = c3 c4 c5; L, R in W0F order
+__device__ __forceinline__ void step_w0(d4 *acc, const cx<double> *L, const cx<double> *R)
 {
-    // left operand (planes Y1): fluctuations and Q_ij; zero past the end
-    double Lc[NFIELD];
-#pragma unroll
-    for (int f = 0; f < NFIELD; ++f) Lc[f] = ok ? cur.L[f] : 0.0;
-    const double lu = Lc[F_U], lv = Lc[F_V], lw = Lc[F_W], lp = Lc[F_P];
-    const double lQxx = Lc[F_QXX], lQyy = Lc[F_QYY], lQzz = Lc[F_QZZ];
-    const double lQxy = Lc[F_QXY], lQxz = Lc[F_QXZ], lQyz = Lc[F_QYZ];
-    const double lq = 0.2 * (lQxx + lQyy + lQzz);
-    const double nu_ = -lu, nv = -lv, nw = -lw;
-    // right operand (planes Y2): real-output and imaginary-output forms
-    double br[NFIELD], bi[NFIELD];
-#pragma unroll
-    for (int f = 0; f < NFIELD; ++f) {
-        br[f] = ri ? cur.R[f].y : cur.R[f].x;
-        bi[f] = ri ? -cur.R[f].x : cur.R[f].y;
-    }
-    const double rQxxr = br[F_QXX], rQxxi = bi[F_QXX];
-    const double rQyyr = br[F_QYY], rQyyi = bi[F_QYY];
-    const double rQzzr = br[F_QZZ], rQzzi = bi[F_QZZ];
-    const double rQxyr = br[F_QXY], rQxyi = bi[F_QXY];
-    const double rQxzr = br[F_QXZ], rQxzi = bi[F_QXZ];
-    const double rQyzr = br[F_QYZ], rQyzi = bi[F_QYZ];
-    const double rqr = 0.2 * (rQxxr + rQyyr + rQzzr);
-    const double rqi = 0.2 * (rQxxi + rQyyi + rQzzi);
-    const double ur = br[F_U], ui = bi[F_U], vr = br[F_V], vi = bi[F_V];
-    const double wr = br[F_W], wi = bi[F_W], pr = br[F_P], pi = bi[F_P];
-
-    // 27 products, ordered so that successive ones feed different accumulators
-    GKE_MFMA2(0, lu, ur, ui);
-    GKE_MFMA2(1, lQxx, ur, ui);
-    GKE_MFMA2(2, lQxz, ur, ui);
-    GKE_MFMA2(3, lQxy, ur, ui);
-    GKE_MFMA2(8, lv, ur, ui);
-    GKE_MFMA2(4, lu, rQxyr, rQxyi);
-    GKE_MFMA2(1, nu_, rQxxr, rQxxi);
-    GKE_MFMA2(2, nu_, rQxzr, rQxzi);
-    GKE_MFMA2(5, lv, rqr, rqi);
-    GKE_MFMA2(0, lv, vr, vi);
-    GKE_MFMA2(1, lQxy, vr, vi);
-    GKE_MFMA2(2, lQyz, vr, vi);
-    GKE_MFMA2(3, lQyy, vr, vi);
-    GKE_MFMA2(6, lp, vr, vi);
-    GKE_MFMA2(7, lu, vr, vi);
-    GKE_MFMA2(4, lv, rQyyr, rQyyi);
-    GKE_MFMA2(5, lq, vr, vi);
-    GKE_MFMA2(1, nv, rQxyr, rQxyi);
-    GKE_MFMA2(2, nv, rQyzr, rQyzi);
-    GKE_MFMA2(6, lv, pr, pi);
-    GKE_MFMA2(0, lw, wr, wi);
-    GKE_MFMA2(1, lQxz, wr, wi);
-    GKE_MFMA2(2, lQzz, wr, wi);
-    GKE_MFMA2(3, lQyz, wr, wi);
-    GKE_MFMA2(4, lw, rQyzr, rQyzi);
-    GKE_MFMA2(1, nw, rQxzr, rQxzi);
-    GKE_MFMA2(2, nw, rQzzr, rQzzi);
+    enum { u, v, w, xx, yy, zz, xy, yz };
+    const cx<double> lq = cx<double>{0.2 * (L[xx].x + L[yy].x + L[zz].x),
+                                     0.2 * (L[xx].y + L[yy].y + L[zz].y)};
+    const cx<double> rq = cx<double>{0.2 * (R[xx].x + R[yy].x + R[zz].x),
+                                     0.2 * (R[xx].y + R[yy].y + R[zz].y)};
+    mac3(acc, 0, L[xy], R[u], false);   // c3
+    mac3(acc, 1, L[u], R[xy], false);   // c4
+    mac3(acc, 2, lq, R[v], false);      // c5
+    mac3(acc, 0, L[yy], R[v], false);   // c3
+    mac3(acc, 1, L[v], R[yy], false);   // c4
+    mac3(acc, 2, L[v], rq, false);      // c5
+    mac3(acc, 0, L[yz], R[w], false);   // c3
+    mac3(acc, 1, L[w], R[yz], false);   // c4
 }
 
-// Register prefetch of the next snapshot pair (1) or none (0), and the
-// minimum waves per SIMD.  Without the prefetch the kernel fits 2 waves per
-// SIMD (220 VGPRs), and each wave's MFMA chain covers the other's loads; this
-// measured about 1.35x faster than one wave with a prefetch.
-#ifndef GKE_RANKK_PF
-#define GKE_RANKK_PF 0
-#endif
+// wave 1: acc slots 0 1 2 = c1 c7 c8; L, R in W1F order
+__device__ __forceinline__ void step_w1(d4 *acc, const cx<double> *L, const cx<double> *R)
+{
+    enum { u, v, w, xx, xy, xz };
+    mac3(acc, 0, L[xx], R[u], false);
+    mac3(acc, 1, L[u], R[v], false);    // c7
+    mac3(acc, 2, L[v], R[u], false);    // c8
+    mac3(acc, 0, L[xy], R[v], false);
+    mac3(acc, 0, L[xz], R[w], false);
+    mac3(acc, 0, L[u], R[xx], true);
+    mac3(acc, 0, L[v], R[xy], true);
+    mac3(acc, 0, L[w], R[xz], true);
+}
+
+// wave 2: acc slots 0 1 2 = c0 c2 c6; L, R in W2F order
+__device__ __forceinline__ void step_w2(d4 *acc, const cx<double> *L, const cx<double> *R)
+{
+    enum { u, v, w, p, xz, yz, zz };
+    mac3(acc, 0, L[u], R[u], false);    // c0
+    mac3(acc, 1, L[xz], R[u], false);   // c2
+    mac3(acc, 2, L[p], R[v], false);    // c6
+    mac3(acc, 0, L[v], R[v], false);
+    mac3(acc, 1, L[yz], R[v], false);
+    mac3(acc, 2, L[v], R[p], false);
+    mac3(acc, 0, L[w], R[w], false);
+    mac3(acc, 1, L[zz], R[w], false);
+    mac3(acc, 1, L[u], R[xz], true);
+    mac3(acc, 1, L[v], R[yz], true);
+    mac3(acc, 1, L[w], R[zz], true);
+}
+
+// all snapshots, four at a time, for wave kind W
+template <int W>
+__device__ __forceinline__ void snapshot_loop(d4 *ac, const Loader &ld, int nsnap, int kq)
+{
+    constexpr int N = W == 0 ? 8 : W == 1 ? 6 : 7;
+    for (int s0 = 0; s0 < nsnap; s0 += 4) {
+        const bool ok = s0 + kq < nsnap;
+        const unsigned so = (unsigned)((ok ? kq : nsnap - 1 - s0)) * ld.sbytes;
+        cx<double> L[N], R[N];
+        if (W == 0) {
+            load_fields(L, R, W0F, ld, s0, so, ok);
+            step_w0(ac, L, R);
+        } else if (W == 1) {
+            load_fields(L, R, W1F, ld, s0, so, ok);
+            step_w1(ac, L, R);
+        } else {
+            load_fields(L, R, W2F, ld, s0, so, ok);
+            step_w2(ac, L, R);
+        }
+    }
+}
+
+// minimum waves per SIMD (register budget)
 #ifndef GKE_RANKK_MINW
-#define GKE_RANKK_MINW 2
+#define GKE_RANKK_MINW 3
 #endif
 
-// acc layout: [NSPEC][nk][P] complex.
-__global__ __launch_bounds__(64, GKE_RANKK_MINW) void k_rankk_f64(
+// acc layout: [NSPEC][nk][P] complex.  One block (three waves) per (k, tile pair).
+__global__ __launch_bounds__(192, GKE_RANKK_MINW) void k_rankk_f64(
     const cx<double> *__restrict__ spec, Dims d, const int *__restrict__ tile_a,
     const int *__restrict__ tile_b, const int *__restrict__ t_rowplane, int nsnap,
     int accumulate, int total, cx<double> *__restrict__ acc)
@@ -171,57 +199,52 @@ __global__ __launch_bounds__(64, GKE_RANKK_MINW) void k_rankk_f64(
     const int tp = L - k * d.ntp;
     const int ta = tile_a[tp], tb = tile_b[tp];
 
-    const int lane = threadIdx.x;
-    const int row = lane & 15, kq = lane >> 4, soff = kq >> 1, ri = kq & 1;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kq = lane >> 4;
     const size_t fstride = (size_t)d.chunk * d.ny;  // complex elements per field
-    const char *kb = reinterpret_cast<const char *>(spec + (size_t)k * NFIELD * fstride);
-    const size_t fbytes = fstride * sizeof(cx<double>);
-    const unsigned sbytes = (unsigned)d.ny * sizeof(cx<double>);
-    const unsigned loff =
-        (unsigned)t_rowplane[ta * 16 + row] * sizeof(cx<double>) + ri * sizeof(double);
-    const unsigned roff = (unsigned)(tb * 16 + row) * sizeof(cx<double>);
+    Loader ld;
+    ld.kb = reinterpret_cast<const char *>(spec + (size_t)k * NFIELD * fstride);
+    ld.fbytes = fstride * sizeof(cx<double>);
+    ld.sbytes = (unsigned)d.ny * sizeof(cx<double>);
+    ld.loff = (unsigned)t_rowplane[ta * 16 + row] * sizeof(cx<double>);
+    ld.roff = (unsigned)(tb * 16 + row) * sizeof(cx<double>);
 
-    d4 ar[9], ai[9];
+    d4 ac[9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
-        ar[c] = d4{0.0, 0.0, 0.0, 0.0};
-        ai[c] = d4{0.0, 0.0, 0.0, 0.0};
-    }
+    for (int c = 0; c < 9; ++c) ac[c] = d4{0.0, 0.0, 0.0, 0.0};
 
-#if GKE_RANKK_PF
-    Operands cur;
-    load_operands(cur, kb, fbytes, loff, roff, sbytes, 0, soff, nsnap);
-    for (int s0 = 0; s0 < nsnap; s0 += 2) {
-        // prefetch the next snapshot pair while this one is multiplied
-        Operands nxt;
-        load_operands(nxt, kb, fbytes, loff, roff, sbytes, s0 + 2 < nsnap ? s0 + 2 : s0, soff,
-                      nsnap);
-        // keep the scheduler from pulling the consumers of these loads into
-        // this iteration: they are waited for only at the next one
-        __builtin_amdgcn_sched_barrier(0);
-        rankk_f64_step(ar, ai, cur, s0 + soff < nsnap, ri);
-        __builtin_amdgcn_sched_barrier(0);
-        cur = nxt;
-    }
-#else
-    for (int s0 = 0; s0 < nsnap; s0 += 2) {
-        Operands cur;
-        load_operands(cur, kb, fbytes, loff, roff, sbytes, s0, soff, nsnap);
-        rankk_f64_step(ar, ai, cur, s0 + soff < nsnap, ri);
-    }
-#endif
+    // one loop per wave kind, so that each keeps only its own loop invariants
+    if (wv == 0) snapshot_loop<0>(ac, ld, nsnap, kq);
+    else if (wv == 1) snapshot_loop<1>(ac, ld, nsnap, kq);
+    else snapshot_loop<2>(ac, ld, nsnap, kq);
 
     const size_t sp_stride = (size_t)d.nk * d.pstr;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const size_t o = (size_t)k * d.pstr + (size_t)tp * 256 + (kq + 4 * v) * 16 + row;
+        // Re = K1 - K3, Im = K1 + K2 of each accumulator of this wave
         double cr[9], ci[9];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-            cr[c] = ar[c][v];
-            ci[c] = ai[c][v];
+        for (int c = 0; c < 9; ++c) cr[c] = ci[c] = 0.0;
+        auto put = [&](int slot, int c) {
+            cr[c] = ac[3 * slot][v] - ac[3 * slot + 2][v];
+            ci[c] = ac[3 * slot][v] + ac[3 * slot + 1][v];
+        };
+        if (wv == 0) {
+            put(0, 3);
+            put(1, 4);
+            put(2, 5);
+        } else if (wv == 1) {
+            put(0, 1);
+            put(1, 7);
+            put(2, 8);
+        } else {
+            put(0, 0);
+            put(1, 2);
+            put(2, 6);
         }
-        store_spectra(acc, sp_stride, o, cr, ci, accumulate);
+        store_spectra_part(acc, sp_stride, o, cr, ci, accumulate, wv);
     }
 }
 
@@ -233,7 +256,7 @@ hipError_t launch_rankk_f64(hipStream_t st, const Dims &d, const Tables &t,
         const long long total = (long long)d.nk * d.ntp;
         if (total >= (1LL << 31) - 8) return hipErrorInvalidValue;
         const int G = (int)((total + 7) / 8 * 8);
-        hipLaunchKernelGGL(k_rankk_f64, dim3(G), dim3(64), 0, st, spec, d, t.tile_a, t.tile_b,
+        hipLaunchKernelGGL(k_rankk_f64, dim3(G), dim3(192), 0, st, spec, d, t.tile_a, t.tile_b,
                            t.rowplane, nsnap, accumulate, (int)total, acc);
     }
     return hipGetLastError();

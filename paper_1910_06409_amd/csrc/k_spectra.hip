@@ -38,6 +38,33 @@ __device__ __forceinline__ unsigned int split_bf16(float x)
     return h | (l << 16);
 }
 
+// Sums each of eight values over the 64 lanes of a wave in a fixed order: on
+// return, every lane of the group of eight lanes g = lane / 8 holds the sum of
+// v[g].  Each step halves the values a lane keeps and sends the other half to
+// its partner (lanes 32, 16, 8 apart), then the last three steps finish the
+// sum within the group: 10 exchanges instead of 8 x 6.
+__device__ __forceinline__ double wave_sum8(const double (&v)[8])
+{
+    const int lane = threadIdx.x & 63;
+    double a[4], b[2];
+    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double keep = h5 ? v[4 + i] : v[i], send = h5 ? v[i] : v[4 + i];
+        a[i] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double keep = h4 ? a[2 + i] : a[i], send = h4 ? a[i] : a[2 + i];
+        b[i] = keep + __shfl_xor(send, 16, 64);
+    }
+    double c = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8, 64);
+    c += __shfl_xor(c, 4, 64);
+    c += __shfl_xor(c, 2, 64);
+    c += __shfl_xor(c, 1, 64);
+    return c;
+}
+
 template <typename T>
 __device__ __forceinline__ void store_spec(cx<double> *spec, size_t i, cx<T> X) { spec[i] = cx<double>{X.x, X.y}; }
 template <typename T>
@@ -153,12 +180,13 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
     // the seven partial sums: wave reductions now, the fixed-order sum over
     // the waves and the update of momp after the transform, so that no global
     // round trip sits before the barrier
-    double parts[NMOMP] = {mq, muv, mpv, mqu, mqv, mqw, mgy};
-#pragma unroll
-    for (int k = 0; k < NMOMP; ++k)
-        for (int o = 32; o > 0; o >>= 1) parts[k] += __shfl_down(parts[k], o, 64);
-    if ((threadIdx.x & 63) == 0)
-        for (int k = 0; k < NMOMP; ++k) shm[k * (FFT_BLOCK / 64) + (threadIdx.x >> 6)] = parts[k];
+    static_assert(NMOMP <= 8, "wave_sum8 reduces eight values");
+    const double parts[8] = {mq, muv, mpv, mqu, mqv, mqw, mgy, 0.0};
+    const double ws = wave_sum8(parts);
+    {
+        const int lane = threadIdx.x & 63, g = lane >> 3;
+        if ((lane & 7) == 0 && g < NMOMP) shm[g * (FFT_BLOCK / 64) + (threadIdx.x >> 6)] = ws;
+    }
     __syncthreads();
     lds_fft_ip<T, FFT_CAP, FFT_BLOCK>(lds, 5 * zb, bs, t.px, tw, -1);
     // split the two real transforms: Fa = (Z(k) + conj Z(-k))/2, Fb = (Z(k) - conj Z(-k))/(2i)
@@ -208,9 +236,10 @@ hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int
     return hipGetLastError();
 }
 
-// One block = jb consecutive planes of one field at one kx (FP64 path; two
-// blocks share a compute unit): transform along z, scale, and store
-// spec[k = kx*Nz + kz][f][slot][j] (planes contiguous).  Work items in the order
+// One block = jb consecutive planes of one field at one kx (two blocks share
+// a compute unit): transform along z (type T), scale, and store
+// spec[k = kx*Nz + kz][f][slot][j] (planes contiguous) as FP64 complex or split
+// BF16.  Work items in the order
 // (f, kx, jblk), jblk fastest; the workgroups of one XCD (workgroup i runs on
 // XCD i mod 8) take a contiguous range of items, so the items of neighbouring
 // kx, which read the two halves of the same cache lines of inter, meet in one
@@ -278,119 +307,22 @@ __global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, 
     }
 }
 
-// Split-BF16 path.  Work item = jb consecutive planes of one field at one kx:
-// transform along z (FP32), scale, and store spec[k = kx*Nz + kz][f][slot][j] (planes
-// contiguous) as FP64 complex or split BF16.  Persistent blocks: each XCD
-// (workgroup i runs on XCD i % 8) takes a contiguous range of items, so items
-// that share cache lines of inter (neighbouring kx) meet in one L2; a block
-// gathers its next item into registers while it transforms and stores the
-// current one.
-constexpr int ZBLOCK = 1024;   // threads of the persistent z-pass blocks
-
-template <typename T, typename S>
-__global__ __launch_bounds__(ZBLOCK) void k_zfft_pack(const cx<T> *__restrict__ inter, Dims d,
-                                                      Tables t, int slot, S *__restrict__ spec,
-                                                      int nitems)
-{
-    constexpr int MAXE = (FFT_CAP + ZBLOCK - 1) / ZBLOCK;
-    extern __shared__ unsigned char lds_raw[];
-    cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
-    const int ny = d.ny, nz = d.nz, nkx = d.nkx, jb = d.jb, njb = d.njb;
-    const int zb = d.zb, lzb = __builtin_ctz(zb), zm = zb - 1;
-    const int bs = fft_stride(nz);
-    cx<T> *tw = lds + jb * bs;
-    load_twiddles(tw, tw_of<T>(t, 1), nz);
-    const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3, gb = gridDim.x >> 3;
-    const int per = (nitems + 7) >> 3;
-    const int i0 = xcd * per, i1 = min(nitems, i0 + per);
-    const double scale = 1.0 / ((double)d.nx * (double)nz);
-    const size_t szb = (size_t)NFIELD * nkx * zb, sb = (size_t)d.nzb * szb;
-    const size_t skz = (size_t)NFIELD * d.chunk * ny;
-    // this thread's (b, z) for the gathers; nb * nz <= MAXE * ZBLOCK
-    const Walk2 wg(threadIdx.x, ZBLOCK, nz);
-    cx<T> pf[MAXE];
-    // item -> (f, kx, jblk), jblk fastest
-    auto gather = [&](int item) {
-        const int jblk = item % njb, t2 = item / njb;
-        const int kx = t2 % nkx, f = t2 / nkx;
-        const int j0 = jblk * jb, nb = min(jb, ny - j0);
-        const cx<T> *ib = inter + (size_t)j0 * sb + ((size_t)f * nkx + kx) * zb;
-        Walk2 w = wg;
-#pragma unroll
-        for (int q = 0; q < MAXE; ++q) {   // unconditional loads (see k_zfft_pack_blk)
-            const bool ok = w.hi < nb;
-            const int b = ok ? w.hi : nb - 1, z = ok ? w.lo : 0;
-            pf[q] = ib[b * sb + (size_t)(z >> lzb) * szb + (z & zm)];
-            w.next();
-        }
-    };
-    int item = i0 + lb;
-    if (item < i1) gather(item);
-    for (; item < i1; item += gb) {
-        const int jblk = item % njb, t2 = item / njb;
-        const int kx = t2 % nkx, f = t2 / nkx;
-        const int j0 = jblk * jb, nb = min(jb, ny - j0);
-        __syncthreads();   // the previous item's LDS reads are done
-        {
-            Walk2 w = wg;
-#pragma unroll
-            for (int q = 0; q < MAXE; ++q) {
-                if (w.hi < nb) lds[w.hi * bs + fft_pad(w.lo)] = pf[q];
-                w.next();
-            }
-        }
-        if (item + gb < i1) gather(item + gb);   // in flight during this item
-        __syncthreads();
-        lds_fft_ip<T, FFT_CAP, ZBLOCK>(lds, nb, bs, t.pz, tw, -1);
-        S *sp = spec + (size_t)kx * nz * skz + ((size_t)f * d.chunk + slot) * ny + j0;
-        Walk2 w(threadIdx.x, ZBLOCK, nb);   // (kz, b)
-        for (int e = threadIdx.x; e < nb * nz; e += ZBLOCK) {
-            const cx<T> Y = lds[w.lo * bs + fft_pad(w.hi)];
-            const cx<double> X = cx<double>{(double)Y.x * scale, (double)Y.y * scale};
-            store_spec<double>(sp, w.hi * skz + w.lo, X);
-            w.next();
-        }
-    }
-}
-
-// persistent grid: the resident blocks of every compute unit, a multiple of 8
-template <typename K>
-static int persistent_grid(K kernel, int block, size_t lds, int nitems)
-{
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            cus = 256;
-    }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    int g = cus * per_cu;
-    g = std::min(g, (nitems + 7) / 8 * 8);
-    return std::max(8, g / 8 * 8);
-}
-
 hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t, const void *inter,
                             int slot, void *spec)
 {
+    // two blocks per compute unit (a persistent form with a register prefetch
+    // of the next item measured slower on both paths)
     const int nitems = d.njb * d.nkx * NFIELD;
     if (d.prec == PREC_BF16X3) {
         const size_t lds = sizeof(cx<float>) * ((size_t)d.jb * fft_stride(d.nz) + d.nz);
-        auto k = k_zfft_pack<float, bf16x4>;
-        set_lds_limit(k);
-        hipLaunchKernelGGL(k, dim3(persistent_grid(k, ZBLOCK, lds, nitems)), dim3(ZBLOCK), lds,
-                           st, (const cx<float> *)inter, d, t, slot, (bf16x4 *)spec, nitems);
+        set_lds_limit(k_zfft_pack_blk<float, bf16x4>);
+        hipLaunchKernelGGL((k_zfft_pack_blk<float, bf16x4>), dim3(nitems), dim3(FFT_BLOCK), lds,
+                           st, (const cx<float> *)inter, d, t, slot, (bf16x4 *)spec);
     } else {
-        // FP64: the persistent form measured slower (one block per compute
-        // unit, register spills); two plain blocks per compute unit
         const size_t lds = sizeof(cx<double>) * ((size_t)d.jb * fft_stride(d.nz) + d.nz);
         set_lds_limit(k_zfft_pack_blk<double, cx<double>>);
-        hipLaunchKernelGGL((k_zfft_pack_blk<double, cx<double>>), dim3(nitems),
-                           dim3(FFT_BLOCK), lds, st, (const cx<double> *)inter, d, t, slot,
-                           (cx<double> *)spec);
+        hipLaunchKernelGGL((k_zfft_pack_blk<double, cx<double>>), dim3(nitems), dim3(FFT_BLOCK),
+                           lds, st, (const cx<double> *)inter, d, t, slot, (cx<double> *)spec);
     }
     return hipGetLastError();
 }

@@ -7,10 +7,12 @@
 
 namespace gke {
 
-// Store the eight term spectra of one element from the nine accumulators.
-__device__ __forceinline__ void store_spectra(cx<double> *acc, size_t sp_stride, size_t o,
-                                              const double *cr, const double *ci,
-                                              int accumulate)
+// Store the eight term spectra of one element from the nine accumulators
+// (part < 0: all of them; part 0: S_FY S_PHI from c3 c4 c5; part 1: S_FX
+// S_UVS S_UVA from c1 c7 c8; part 2: S_R S_FZ S_PP from c0 c2 c6).
+__device__ __forceinline__ void store_spectra_part(cx<double> *acc, size_t sp_stride, size_t o,
+                                                   const double *cr, const double *ci,
+                                                   int accumulate, int part)
 {
     double sr[NSPEC], si[NSPEC];
     sr[S_R] = cr[0];
@@ -31,6 +33,9 @@ __device__ __forceinline__ void store_spectra(cx<double> *acc, size_t sp_stride,
     si[S_UVA] = ci[8] - ci[7];
 #pragma unroll
     for (int sp = 0; sp < NSPEC; ++sp) {
+        const int owner = (sp == S_FY || sp == S_PHI) ? 0
+                          : (sp == S_FX || sp == S_UVS || sp == S_UVA) ? 1 : 2;
+        if (part >= 0 && owner != part) continue;
         cx<double> *dst = acc + sp * sp_stride + o;
         cx<double> val = cx<double>{sr[sp], si[sp]};
         if (accumulate) {
@@ -40,6 +45,13 @@ __device__ __forceinline__ void store_spectra(cx<double> *acc, size_t sp_stride,
         }
         *dst = val;
     }
+}
+
+__device__ __forceinline__ void store_spectra(cx<double> *acc, size_t sp_stride, size_t o,
+                                              const double *cr, const double *ci,
+                                              int accumulate)
+{
+    store_spectra_part(acc, sp_stride, o, cr, ci, accumulate, -1);
 }
 
 // Pairs that involve the last Ny mod 16 planes: one thread per (k, pair), FP64
