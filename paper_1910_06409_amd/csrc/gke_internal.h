@@ -72,6 +72,13 @@ constexpr int FFT_BLOCK = GKE_FFT_BLOCK;
 // GKE_FFT_WAVES waves per SIMD (so that several blocks share a compute unit)
 #define GKE_FFT_BOUNDS __launch_bounds__(GKE_FFT_BLOCK, GKE_FFT_WAVES)
 constexpr size_t LDS_BUDGET = 156 * 1024;
+// The x pass and the kx finalize also come in a smaller shape, 256 threads and
+// 2048 elements per block (four blocks per compute unit), used when the grid
+// still gives each block at least two z rows (x pass) or eight transforms (kx
+// finalize); measured faster for both at the re200 size.
+constexpr int SMALL_BLOCK = 256, SMALL_CAP = 2048;
+template <int BLOCK>
+constexpr int cap_of() { return BLOCK == SMALL_BLOCK ? SMALL_CAP : FFT_CAP; }
 
 struct Dims {
     int nx, ny, nz;
@@ -82,7 +89,10 @@ struct Dims {
     int npair_tiles;  // 256 ntp pairs handled on the matrix cores
     int npair;        // all unordered pairs (tile pairs + remainder pairs)
     int pstr;         // pair stride of the accumulators: npair rounded up to 8 (128-byte rows)
+    int xblk;         // threads of an x-pass block (SMALL_BLOCK or FFT_BLOCK)
+    int kxblk;        // threads of a kx-finalize block (SMALL_BLOCK or FFT_BLOCK)
     int zb, nzb;      // z rows per block in the x pass, number of blocks
+    int zg, nzg;      // z rows per group of the x-transformed layout (a multiple of zb)
     int jb, njb;      // planes per block in the z pass, number of blocks
     int pbz;          // pairs per block in the finalize kz pass
     int ntx;          // complex transforms (two pairs each) per block in the kx pass

@@ -314,7 +314,7 @@ size_t layout(gke_plan_t p, char *base)
     p->gxz = (double *)take(sizeof(double) * d.ny);
     // both split-BF16 buffers hold 8-byte elements (cx<float>, bf16x4)
     const size_t esz = d.prec == gke::PREC_BF16X3 ? 8 : sizeof(cx<double>);
-    p->inter = take(esz * (size_t)d.ny * d.nzb * gke::NFIELD * d.nkx * d.zb);
+    p->inter = take(esz * (size_t)d.ny * d.nzg * gke::NFIELD * d.nkx * d.zg);
     p->spec = take(esz * (size_t)d.nk * gke::NFIELD * d.chunk * d.ny);
     p->acc = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NSPEC * d.nk * round8(npair));
     p->mid = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NMAP * d.nkx * d.nz * round8(pbt));
@@ -425,10 +425,22 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
         delete p;
         return fail(nullptr, GKE_ERR_UNSUPPORTED, "transform length too large for one block");
     }
+    // the smaller block shape of the x pass and the kx finalize when its cap
+    // still holds two z rows (x pass) or eight transforms (kx finalize)
+    const size_t cap_small = std::min<size_t>(cap, gke::SMALL_CAP);
+    d.xblk = (size_t)10 * sx <= cap_small && Nz % 2 == 0 ? gke::SMALL_BLOCK : gke::FFT_BLOCK;
+    d.kxblk = cap_small / sx >= 8 ? gke::SMALL_BLOCK : gke::FFT_BLOCK;
+    const size_t capx = d.xblk == gke::SMALL_BLOCK ? cap_small : cap;
+    const size_t capkx = d.kxblk == gke::SMALL_BLOCK ? cap_small : cap;
     // x pass: 5 complex rows per z row (ten real fields), zb | Nz
     d.zb = 16;
-    while (d.zb > 1 && (Nz % d.zb || (size_t)5 * d.zb * sx > cap)) d.zb >>= 1;
+    while (d.zb > 1 && (Nz % d.zb || (size_t)5 * d.zb * sx > capx)) d.zb >>= 1;
     d.nzb = Nz / d.zb;
+    // rows of one run of the x-transformed layout: at least 4 (64-byte runs of
+    // FP64 complex for the z pass) even when an x-pass block holds fewer
+    d.zg = d.zb;
+    while (d.zg < 4 && Nz % (2 * d.zg) == 0) d.zg *= 2;
+    d.nzg = Nz / d.zg;
     // z pass: planes per block, spread evenly over the blocks
     {
         const int jmax = (int)std::min<size_t>(64, cap / sz);
@@ -439,7 +451,7 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
     // (kz pass: multiples of 8 pairs where possible, 128-byte runs of acc and mid)
     d.pbz = (int)std::min<size_t>(48, cap / sz);
     d.pbz &= d.pbz >= 8 ? ~7 : ~1;   // even: the R blocks split it in halves
-    d.ntx = (int)std::min<size_t>(gke::MAX_NTX, cap / sx);
+    d.ntx = (int)std::min<size_t>(gke::MAX_NTX, capkx / sx);
     // 32-bit element offsets within one wavenumber row of acc (kz pass)
     if (d.zb < 1 || d.jb < 1 || d.pbz < 2 || d.ntx < 1 || (size_t)Nz * d.pstr >= ((size_t)1 << 31)) {
         delete p;

@@ -205,11 +205,13 @@ struct PairInfo {
 //   both pairs of (kx, c) (adjacent in mid) and writes A_c[kx] and A_c[Nx - kx].
 //   Output: a group of tpp consecutive threads per pair, consecutive threads
 //   on consecutive rx.
-__global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims d,
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fin_kx(const cx<double> *__restrict__ mid, Dims d,
                                                       Tables t, int p0, int ptot,
                                                       const double *__restrict__ prof,
                                                       OutPtrs out, int full)
 {
+    constexpr int CAP = cap_of<BLOCK>();
     extern __shared__ cx<double> lds[];
     const int nx = d.nx, nz = d.nz, nkx = d.nkx, ny = d.ny, nt = d.ntx;
     const int npair = 2 * nt;
@@ -226,15 +228,15 @@ __global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims
     // a load and its wait): a slot past the end repeats the last element,
     // which writes the same values to the same place.
     const int code = t.pairs[p0 + pl0 + min((int)threadIdx.x, np - 1)];
-    // nkx * nt <= FFT_CAP / 2 + MAX_NTX (nt * fft_stride(nx) <= FFT_CAP, host)
-    constexpr int MAXG = (FFT_CAP / 2 + MAX_NTX + FFT_BLOCK - 1) / FFT_BLOCK;
+    // nkx * nt <= CAP / 2 + MAX_NTX (nt * fft_stride(nx) <= CAP, host)
+    constexpr int MAXG = (CAP / 2 + MAX_NTX + BLOCK - 1) / BLOCK;
     const int cnt = nkx * nt;
     cx<double> xa[MAXG], xb[MAXG];
     const size_t mst = (size_t)mid_stride(ptot);
     {
         const cx<double> *mb = mid + ((size_t)m * nkx * nz + rz) * mst + pl0;
         const size_t skx = (size_t)nz * mst;
-        Walk2 w(threadIdx.x, FFT_BLOCK, nt);   // (kx, c)
+        Walk2 w(threadIdx.x, BLOCK, nt);   // (kx, c)
 #pragma unroll
         for (int q = 0; q < MAXG; ++q) {
             const bool ok = w.hi < nkx;
@@ -259,12 +261,12 @@ __global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims
         pi.b2 = rb >= 0 ? prof[rb * ny + pi.j2] : 0.0;
     }
     {
-        TwiddleCopy<double, FFT_BLOCK> twc;
+        TwiddleCopy<double, BLOCK> twc;
         twc.load(t.twx, nx);
         twc.store(tw, t.twx, nx);
     }
     {
-        Walk2 w(threadIdx.x, FFT_BLOCK, nt);   // (kx, c)
+        Walk2 w(threadIdx.x, BLOCK, nt);   // (kx, c)
 #pragma unroll
         for (int q = 0; q < MAXG; ++q) {
             const bool ok = w.hi < nkx;
@@ -282,8 +284,8 @@ __global__ GKE_FFT_BOUNDS void k_fin_kx(const cx<double> *__restrict__ mid, Dims
     }
     if ((int)threadIdx.x < np) pinfo[threadIdx.x] = pi;
     __syncthreads();
-    lds_fft_ip<double, FFT_CAP, FFT_BLOCK>(A, nt, bs, t.px, tw, +1);
-    const int tpp = FFT_BLOCK / npair;            // threads per pair
+    lds_fft_ip<double, CAP, BLOCK>(A, nt, bs, t.px, tw, +1);
+    const int tpp = BLOCK / npair;            // threads per pair
     const int b = threadIdx.x / tpp, lane = threadIdx.x - b * tpp;
     if (b >= np) return;
     const PairInfo p = pinfo[b];
@@ -322,9 +324,15 @@ hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
     OutPtrs op;
     for (int i = 0; i < 14; ++i) op.t[i] = out[i];
     dim3 grid((ptot + 2 * d.ntx - 1) / (2 * d.ntx), d.nz, NMAP);
-    set_lds_limit(k_fin_kx);
-    hipLaunchKernelGGL(k_fin_kx, grid, dim3(FFT_BLOCK), lds, st, mid, d, t, p0, ptot, prof, op,
-                       full);
+    if (d.kxblk == SMALL_BLOCK) {
+        set_lds_limit(k_fin_kx<SMALL_BLOCK>);
+        hipLaunchKernelGGL(k_fin_kx<SMALL_BLOCK>, grid, dim3(SMALL_BLOCK), lds, st, mid, d, t, p0,
+                           ptot, prof, op, full);
+    } else {
+        set_lds_limit(k_fin_kx<FFT_BLOCK>);
+        hipLaunchKernelGGL(k_fin_kx<FFT_BLOCK>, grid, dim3(FFT_BLOCK), lds, st, mid, d, t, p0,
+                           ptot, prof, op, full);
+    }
     return hipGetLastError();
 }
 

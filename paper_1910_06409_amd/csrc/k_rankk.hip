@@ -155,26 +155,57 @@ __device__ __forceinline__ void step_w2(d4 *acc, const cx<double> *L, const cx<d
     mac3(acc, 1, L[w], R[zz], true);
 }
 
+// register prefetch of the next four snapshots (1) or none (0)
+#ifndef GKE_RANKK_PF
+#define GKE_RANKK_PF 0
+#endif
+
+template <int W, int N>
+__device__ __forceinline__ void load_kind(cx<double> *L, cx<double> *R, const Loader &ld, int s0,
+                                          int kq, int nsnap)
+{
+    const bool ok = s0 + kq < nsnap;
+    const unsigned so = (unsigned)((ok ? kq : nsnap - 1 - s0)) * ld.sbytes;
+    if (W == 0) load_fields(L, R, W0F, ld, s0, so, ok);
+    else if (W == 1) load_fields(L, R, W1F, ld, s0, so, ok);
+    else load_fields(L, R, W2F, ld, s0, so, ok);
+}
+
+template <int W>
+__device__ __forceinline__ void step_kind(d4 *ac, const cx<double> *L, const cx<double> *R)
+{
+    if (W == 0) step_w0(ac, L, R);
+    else if (W == 1) step_w1(ac, L, R);
+    else step_w2(ac, L, R);
+}
+
 // all snapshots, four at a time, for wave kind W
 template <int W>
 __device__ __forceinline__ void snapshot_loop(d4 *ac, const Loader &ld, int nsnap, int kq)
 {
     constexpr int N = W == 0 ? 8 : W == 1 ? 6 : 7;
+#if GKE_RANKK_PF
+    cx<double> L[N], R[N];
+    load_kind<W, N>(L, R, ld, 0, kq, nsnap);
     for (int s0 = 0; s0 < nsnap; s0 += 4) {
-        const bool ok = s0 + kq < nsnap;
-        const unsigned so = (unsigned)((ok ? kq : nsnap - 1 - s0)) * ld.sbytes;
-        cx<double> L[N], R[N];
-        if (W == 0) {
-            load_fields(L, R, W0F, ld, s0, so, ok);
-            step_w0(ac, L, R);
-        } else if (W == 1) {
-            load_fields(L, R, W1F, ld, s0, so, ok);
-            step_w1(ac, L, R);
-        } else {
-            load_fields(L, R, W2F, ld, s0, so, ok);
-            step_w2(ac, L, R);
+        cx<double> Ln[N], Rn[N];
+        load_kind<W, N>(Ln, Rn, ld, s0 + 4 < nsnap ? s0 + 4 : s0, kq, nsnap);
+        __builtin_amdgcn_sched_barrier(0);
+        step_kind<W>(ac, L, R);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            L[i] = Ln[i];
+            R[i] = Rn[i];
         }
     }
+#else
+    for (int s0 = 0; s0 < nsnap; s0 += 4) {
+        cx<double> L[N], R[N];
+        load_kind<W, N>(L, R, ld, s0, kq, nsnap);
+        step_kind<W>(ac, L, R);
+    }
+#endif
 }
 
 // minimum waves per SIMD (register budget)

@@ -79,11 +79,11 @@ __device__ __forceinline__ void store_spec(bf16x4 *spec, size_t i, cx<T> X)
 // packed two per complex row into LDS, FP64 one-point partial sums and the
 // wall-normal gradient energy; then one batched transform (type T) of the
 // 5 zb complex rows along x.
-//   inter[j][zblk][f][kx][row]: x-transformed rows (unnormalised); each block
-//   writes one contiguous chunk
+//   inter[j][g][f][kx][row]: x-transformed rows (unnormalised) in groups of zg
+//   rows (z = g zg + row); a block writes its zb rows of one group
 //   momp[j][k][zblk]: FP64 partial sums of q uv pv qu qv qw and (dy u')^2
-template <typename TI, typename T>
-__global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
+template <typename TI, typename T, int BLOCK>
+__global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fluct_xfft(const TI *__restrict__ u,
                                                           const TI *__restrict__ v,
                                                           const TI *__restrict__ w,
                                                           const TI *__restrict__ p,
@@ -92,11 +92,17 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
                                                           cx<T> *__restrict__ inter,
                                                           double *__restrict__ momp)
 {
+    constexpr int CAP = cap_of<BLOCK>();
     extern __shared__ unsigned char lds_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
-    __shared__ double shm[NMOMP * (FFT_BLOCK / 64)];
+    __shared__ double shm[NMOMP * (BLOCK / 64)];
     const int nx = d.nx, ny = d.ny, nz = d.nz, nkx = d.nkx, zb = d.zb;
-    const int zblk = blockIdx.x, j = blockIdx.y;
+    // blocks in the order (j, zblk), zblk fastest; the blocks of one XCD
+    // (workgroup i runs on XCD i mod 8) take a contiguous range of it, so the
+    // blocks that share a row group of inter write it through one L2
+    const int nblk = (int)gridDim.x, q8 = nblk >> 3, r8 = nblk & 7, xcd = blockIdx.x & 7;
+    const int item = xcd * q8 + min(xcd, r8) + (int)(blockIdx.x >> 3);
+    const int zblk = item % d.nzb, j = item / d.nzb;
     const int z0 = zblk * zb;
     const int bs = fft_stride(nx);
     const size_t npl = (size_t)nx * nz;
@@ -105,20 +111,20 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
     const double W = prof[P_W * ny + j], P = prof[P_P * ny + j];
     const int nel = zb * nx;
     constexpr bool kGy = sizeof(T) == sizeof(float);   // split-BF16 path
-    // zb nx and nx stay below FFT_CAP / 5 (host check): NI elements per thread
-    constexpr int NI = (FFT_CAP / 5 + FFT_BLOCK - 1) / FFT_BLOCK;
+    // zb nx and nx stay below CAP / 5 (host check): NI elements per thread
+    constexpr int NI = (CAP / 5 + BLOCK - 1) / BLOCK;
     constexpr int NG = kGy ? NI : 1;
     const int js = t.j0[j];
     // every load of this thread is issued before any is consumed: the
     // twiddles, the four inputs and, on the split path, the five-plane stencil
     // (unconditional loads at clamped indices, so that no branch separates
     // them; the extra values are dropped)
-    TwiddleCopy<T, FFT_BLOCK> twc;
+    TwiddleCopy<T, BLOCK> twc;
     twc.load(tw_of<T>(t, 0), nx);
     TI in[NI][4];
 #pragma unroll
     for (int q = 0; q < NI; ++q) {
-        const int e = min((int)threadIdx.x + q * FFT_BLOCK, nel - 1);
+        const int e = min((int)threadIdx.x + q * BLOCK, nel - 1);
         in[q][0] = u[off + e];
         in[q][1] = v[off + e];
         in[q][2] = w[off + e];
@@ -130,7 +136,7 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
     if (kGy) {
 #pragma unroll
         for (int q = 0; q < NG; ++q) {
-            const int e = min((int)threadIdx.x + q * FFT_BLOCK, nel - 1);
+            const int e = min((int)threadIdx.x + q * BLOCK, nel - 1);
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
                 const size_t o = (size_t)(js + k) * npl + (size_t)z0 * nx + e;
@@ -144,10 +150,10 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
     // element) adds nothing to the sums and rewrites the last element's LDS
     // entries with the same values
     double mq = 0, muv = 0, mpv = 0, mqu = 0, mqv = 0, mqw = 0, mgy = 0;
-    Walk2 wr(threadIdx.x, FFT_BLOCK, nx);   // (row, x)
+    Walk2 wr(threadIdx.x, BLOCK, nx);   // (row, x)
 #pragma unroll
     for (int q = 0; q < NI; ++q) {
-        const bool ok = (int)threadIdx.x + q * FFT_BLOCK < nel;
+        const bool ok = (int)threadIdx.x + q * BLOCK < nel;
         const double a = (double)in[q][0] - U, b = (double)in[q][1] - V;
         const double c = (double)in[q][2] - W, dd = (double)in[q][3] - P;
         const double qq = a * a + b * b + c * c;
@@ -185,16 +191,18 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
     const double ws = wave_sum8(parts);
     {
         const int lane = threadIdx.x & 63, g = lane >> 3;
-        if ((lane & 7) == 0 && g < NMOMP) shm[g * (FFT_BLOCK / 64) + (threadIdx.x >> 6)] = ws;
+        if ((lane & 7) == 0 && g < NMOMP) shm[g * (BLOCK / 64) + (threadIdx.x >> 6)] = ws;
     }
     __syncthreads();
-    lds_fft_ip<T, FFT_CAP, FFT_BLOCK>(lds, 5 * zb, bs, t.px, tw, -1);
+    lds_fft_ip<T, CAP, BLOCK>(lds, 5 * zb, bs, t.px, tw, -1);
     // split the two real transforms: Fa = (Z(k) + conj Z(-k))/2, Fb = (Z(k) - conj Z(-k))/(2i)
-    cx<T> *dst = inter + ((size_t)j * d.nzb + zblk) * NFIELD * nkx * zb;
+    // row group g of zg rows holds this block's rows at r0 .. r0 + zb - 1
+    const int zg = d.zg, g = z0 / zg, r0 = z0 - g * zg;
+    cx<T> *dst = inter + ((size_t)j * d.nzg + g) * NFIELD * nkx * zg + r0;
     // e = (pr nkx + k) zb + row; zb divides the block size, so row is fixed
     const int lzb = __builtin_ctz(zb), row = threadIdx.x & (zb - 1);
-    Walk2 wk(threadIdx.x >> lzb, FFT_BLOCK >> lzb, nkx);   // (pr, k)
-    for (int e = threadIdx.x; e < 5 * nkx * zb; e += FFT_BLOCK) {
+    Walk2 wk(threadIdx.x >> lzb, BLOCK >> lzb, nkx);   // (pr, k)
+    for (int e = threadIdx.x; e < 5 * nkx * zb; e += BLOCK) {
         const int pr = wk.hi, k = wk.lo;
         wk.next();
         const cx<T> *R = lds + (pr * zb + row) * bs;
@@ -202,14 +210,26 @@ __global__ GKE_FFT_BOUNDS void k_fluct_xfft(const TI *__restrict__ u,
         const cx<T> Zc = cconj(R[fft_pad(k == 0 ? 0 : nx - k)]);
         const cx<T> Fa = cx<T>{T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y + Zc.y)};
         const cx<T> Fb = cx<T>{T(0.5) * (Z.y - Zc.y), T(-0.5) * (Z.x - Zc.x)};
-        dst[((2 * pr) * nkx + k) * zb + row] = Fa;
-        dst[((2 * pr + 1) * nkx + k) * zb + row] = Fb;
+        dst[((2 * pr) * nkx + k) * zg + row] = Fa;
+        dst[((2 * pr + 1) * nkx + k) * zg + row] = Fb;
     }
     if ((int)threadIdx.x < NMOMP) {   // shm was written before the first barrier
         double r = 0.0;
-        for (int i = 0; i < FFT_BLOCK / 64; ++i) r += shm[threadIdx.x * (FFT_BLOCK / 64) + i];
+        for (int i = 0; i < BLOCK / 64; ++i) r += shm[threadIdx.x * (BLOCK / 64) + i];
         momp[((size_t)j * NMOMP + threadIdx.x) * d.nzb + zblk] += r;
     }
+}
+
+template <typename TI, typename T, int BLOCK>
+static void launch_fx_shape(hipStream_t st, const Dims &d, const Tables &t, const void *u,
+                            const void *v, const void *w, const void *p, const double *prof,
+                            void *inter, double *momp)
+{
+    const size_t lds = sizeof(cx<T>) * (5 * (size_t)d.zb * fft_stride(d.nx) + d.nx);
+    set_lds_limit(k_fluct_xfft<TI, T, BLOCK>);
+    hipLaunchKernelGGL((k_fluct_xfft<TI, T, BLOCK>), dim3(d.nzb * d.ny), dim3(BLOCK), lds, st,
+                       (const TI *)u, (const TI *)v, (const TI *)w, (const TI *)p, prof, d, t,
+                       (cx<T> *)inter, momp);
 }
 
 template <typename TI, typename T>
@@ -217,11 +237,10 @@ static void launch_fx(hipStream_t st, const Dims &d, const Tables &t, const void
                       const void *v, const void *w, const void *p, const double *prof,
                       void *inter, double *momp)
 {
-    const size_t lds = sizeof(cx<T>) * (5 * (size_t)d.zb * fft_stride(d.nx) + d.nx);
-    set_lds_limit(k_fluct_xfft<TI, T>);
-    hipLaunchKernelGGL((k_fluct_xfft<TI, T>), dim3(d.nzb, d.ny), dim3(FFT_BLOCK), lds, st,
-                       (const TI *)u, (const TI *)v, (const TI *)w, (const TI *)p, prof, d, t,
-                       (cx<T> *)inter, momp);
+    if (d.xblk == SMALL_BLOCK)
+        launch_fx_shape<TI, T, SMALL_BLOCK>(st, d, t, u, v, w, p, prof, inter, momp);
+    else
+        launch_fx_shape<TI, T, FFT_BLOCK>(st, d, t, u, v, w, p, prof, inter, momp);
 }
 
 hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int f32,
@@ -258,12 +277,12 @@ __global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, 
     const int j0 = jblk * jb;
     const int nb = min(jb, ny - j0);
     const int bs = fft_stride(nz);
-    const int zb = d.zb, lzb = __builtin_ctz(zb), zm = zb - 1;
+    const int zg = d.zg, lzg = __builtin_ctz(zg), zm = zg - 1;
     cx<T> *tw = lds + jb * bs;
-    // inter[((((j0 + b) nzb + zblk) NFIELD + f) nkx + kx) zb + row], z = zblk zb + row
+    // inter[((((j0 + b) nzg + g) NFIELD + f) nkx + kx) zg + row], z = g zg + row
     // offsets within a block stay below 2^31 (jb planes of inter)
-    const int szb = NFIELD * nkx * zb, sb = d.nzb * szb;
-    const cx<T> *ib = inter + (size_t)j0 * sb + ((size_t)f * nkx + kx) * zb;
+    const int szg = NFIELD * nkx * zg, sb = d.nzg * szg;
+    const cx<T> *ib = inter + (size_t)j0 * sb + ((size_t)f * nkx + kx) * zg;
     const int cnt = nb * nz;
     {
         // nb * nz <= FFT_CAP: every load of this thread is in flight at once.
@@ -278,7 +297,7 @@ __global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, 
         for (int q = 0; q < MAXE; ++q) {
             const bool ok = w.hi < nb;
             const int b = ok ? w.hi : nb - 1, z = ok ? w.lo : 0;
-            x[q] = ib[b * sb + (z >> lzb) * szb + (z & zm)];
+            x[q] = ib[b * sb + (z >> lzg) * szg + (z & zm)];
             w.next();
         }
         TwiddleCopy<T, FFT_BLOCK> twc;   // in flight with the gathers
