@@ -91,6 +91,7 @@ struct Dims {
     int pstr;         // pair stride of the accumulators: npair rounded up to 8 (128-byte rows)
     int xblk;         // threads of an x-pass block (SMALL_BLOCK or FFT_BLOCK)
     int kxblk;        // threads of a kx-finalize block (SMALL_BLOCK or FFT_BLOCK)
+    int zpblk;        // threads of a z-pass block (SMALL_BLOCK or FFT_BLOCK)
     int zb, nzb;      // z rows per block in the x pass, number of blocks
     int zg, nzg;      // z rows per group of the x-transformed layout (a multiple of zb)
     int jb, njb;      // planes per block in the z pass, number of blocks

@@ -270,6 +270,29 @@ void build_slabs(gke_plan_t p)
     }
 }
 
+// Precision-dependent shapes of the z pass: the row groups of the
+// x-transformed layout it reads, its block shape (the smaller one when the
+// transforms are FP32, on the split path, and it still holds eight planes,
+// measured faster there; the 512-thread one for FP64) and the planes per
+// block (spread evenly over the blocks).
+void set_zpass_shape(gke::Dims &d)
+{
+    // rows of one run of the x-transformed layout: 64-byte runs for the z pass
+    // (4 rows of FP64 or 8 of FP32 complex) even when an x-pass block holds fewer
+    const int zg_min = d.prec == gke::PREC_BF16X3 ? 8 : 4;
+    d.zg = d.zb;
+    while (d.zg < zg_min && d.nz % (2 * d.zg) == 0) d.zg *= 2;
+    d.nzg = d.nz / d.zg;
+    const size_t cap = std::min<size_t>(gke::LDS_BUDGET / 16 - std::max(d.nx, d.nz), gke::FFT_CAP);
+    const size_t cap_small = std::min<size_t>(cap, gke::SMALL_CAP);
+    const size_t sz = gke::fft_stride(d.nz);
+    d.zpblk = d.prec == gke::PREC_BF16X3 && cap_small / sz >= 8 ? gke::SMALL_BLOCK : gke::FFT_BLOCK;
+    const size_t capz = d.zpblk == gke::SMALL_BLOCK ? cap_small : cap;
+    const int jmax = (int)std::min<size_t>(64, capz / sz);
+    d.njb = (d.ny + jmax - 1) / jmax;
+    d.jb = (d.ny + d.njb - 1) / d.njb;
+}
+
 // Workspace layout; with base != nullptr also assigns the pointers.
 size_t layout(gke_plan_t p, char *base)
 {
@@ -436,17 +459,7 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
     d.zb = 16;
     while (d.zb > 1 && (Nz % d.zb || (size_t)5 * d.zb * sx > capx)) d.zb >>= 1;
     d.nzb = Nz / d.zb;
-    // rows of one run of the x-transformed layout: at least 4 (64-byte runs of
-    // FP64 complex for the z pass) even when an x-pass block holds fewer
-    d.zg = d.zb;
-    while (d.zg < 4 && Nz % (2 * d.zg) == 0) d.zg *= 2;
-    d.nzg = Nz / d.zg;
-    // z pass: planes per block, spread evenly over the blocks
-    {
-        const int jmax = (int)std::min<size_t>(64, cap / sz);
-        d.njb = (Ny + jmax - 1) / jmax;
-        d.jb = (Ny + d.njb - 1) / d.njb;
-    }
+    set_zpass_shape(d);
     // finalize: pairs per kz block, complex transforms (2 pairs each) per kx block
     // (kz pass: multiples of 8 pairs where possible, 128-byte runs of acc and mid)
     d.pbz = (int)std::min<size_t>(48, cap / sz);
@@ -575,6 +588,7 @@ gke_status gke_set_option(gke_plan_t p, int key, int64_t value)
 constexpr size_t kAutoChunkBytes = (size_t)48 << 30;
 gke_status prepare_mode(gke_plan_t p)
 {
+    set_zpass_shape(p->d);
     if (p->chunk == 0) {
         const size_t esz = p->d.prec == gke::PREC_BF16X3 ? 8 : 16;
         const size_t per = esz * (size_t)p->d.nk * gke::NFIELD * p->d.ny;

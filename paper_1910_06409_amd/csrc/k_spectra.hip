@@ -263,11 +263,12 @@ hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int
 // XCD i mod 8) take a contiguous range of items, so the items of neighbouring
 // kx, which read the two halves of the same cache lines of inter, meet in one
 // L2 a few items apart.
-template <typename T, typename S>
-__global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, Dims d,
+template <typename T, typename S, int BLOCK>
+__global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_zfft_pack_blk(const cx<T> *__restrict__ inter, Dims d,
                                                          Tables t, int slot,
                                                          S *__restrict__ spec)
 {
+    constexpr int CAP = cap_of<BLOCK>();
     extern __shared__ unsigned char lds_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
     const int nx = d.nx, ny = d.ny, nz = d.nz, nkx = d.nkx, jb = d.jb;
@@ -285,14 +286,14 @@ __global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, 
     const cx<T> *ib = inter + (size_t)j0 * sb + ((size_t)f * nkx + kx) * zg;
     const int cnt = nb * nz;
     {
-        // nb * nz <= FFT_CAP: every load of this thread is in flight at once.
+        // nb * nz <= CAP: every load of this thread is in flight at once.
         // Loads and LDS stores are unconditional, so that no branch holds a
         // load and its wait: a slot past the end takes the last plane's first
         // element and stores it where that element goes (the same value as
         // its own thread stores).  Element e = b nz + z walked without divisions.
-        constexpr int MAXE = (FFT_CAP + FFT_BLOCK - 1) / FFT_BLOCK;
+        constexpr int MAXE = (CAP + BLOCK - 1) / BLOCK;
         cx<T> x[MAXE];
-        Walk2 w(threadIdx.x, FFT_BLOCK, nz);   // (b, z)
+        Walk2 w(threadIdx.x, BLOCK, nz);   // (b, z)
 #pragma unroll
         for (int q = 0; q < MAXE; ++q) {
             const bool ok = w.hi < nb;
@@ -300,10 +301,10 @@ __global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, 
             x[q] = ib[b * sb + (z >> lzg) * szg + (z & zm)];
             w.next();
         }
-        TwiddleCopy<T, FFT_BLOCK> twc;   // in flight with the gathers
+        TwiddleCopy<T, BLOCK> twc;   // in flight with the gathers
         twc.load(tw_of<T>(t, 1), nz);
         twc.store(tw, tw_of<T>(t, 1), nz);
-        w = Walk2(threadIdx.x, FFT_BLOCK, nz);
+        w = Walk2(threadIdx.x, BLOCK, nz);
 #pragma unroll
         for (int q = 0; q < MAXE; ++q) {
             const bool ok = w.hi < nb;
@@ -312,13 +313,13 @@ __global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, 
         }
     }
     __syncthreads();
-    lds_fft_ip<T, FFT_CAP, FFT_BLOCK>(lds, nb, bs, t.pz, tw, -1);
+    lds_fft_ip<T, CAP, BLOCK>(lds, nb, bs, t.pz, tw, -1);
     const double scale = 1.0 / ((double)nx * (double)nz);
     // spec[(((kx nz + kz) NFIELD + f) chunk + slot) ny + j0 + b]; nz * skz < 2^31
     const int skz = NFIELD * d.chunk * ny;
     S *sp = spec + (size_t)kx * nz * skz + ((size_t)f * d.chunk + slot) * ny + j0;
-    Walk2 ws(threadIdx.x, FFT_BLOCK, nb);   // (kz, b)
-    for (int e = threadIdx.x; e < cnt; e += FFT_BLOCK) {
+    Walk2 ws(threadIdx.x, BLOCK, nb);   // (kz, b)
+    for (int e = threadIdx.x; e < cnt; e += BLOCK) {
         const cx<T> Y = lds[ws.lo * bs + fft_pad(ws.hi)];
         const cx<double> X = cx<double>{(double)Y.x * scale, (double)Y.y * scale};
         store_spec<double>(sp, ws.hi * skz + ws.lo, X);
@@ -326,23 +327,27 @@ __global__ GKE_FFT_BOUNDS void k_zfft_pack_blk(const cx<T> *__restrict__ inter, 
     }
 }
 
+template <typename T, typename S, int BLOCK>
+static void launch_zp(hipStream_t st, const Dims &d, const Tables &t, const void *inter, int slot,
+                      void *spec)
+{
+    const int nitems = d.njb * d.nkx * NFIELD;
+    const size_t lds = sizeof(cx<T>) * ((size_t)d.jb * fft_stride(d.nz) + d.nz);
+    set_lds_limit(k_zfft_pack_blk<T, S, BLOCK>);
+    hipLaunchKernelGGL((k_zfft_pack_blk<T, S, BLOCK>), dim3(nitems), dim3(BLOCK), lds, st,
+                       (const cx<T> *)inter, d, t, slot, (S *)spec);
+}
+
 hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t, const void *inter,
                             int slot, void *spec)
 {
-    // two blocks per compute unit (a persistent form with a register prefetch
-    // of the next item measured slower on both paths)
-    const int nitems = d.njb * d.nkx * NFIELD;
-    if (d.prec == PREC_BF16X3) {
-        const size_t lds = sizeof(cx<float>) * ((size_t)d.jb * fft_stride(d.nz) + d.nz);
-        set_lds_limit(k_zfft_pack_blk<float, bf16x4>);
-        hipLaunchKernelGGL((k_zfft_pack_blk<float, bf16x4>), dim3(nitems), dim3(FFT_BLOCK), lds,
-                           st, (const cx<float> *)inter, d, t, slot, (bf16x4 *)spec);
-    } else {
-        const size_t lds = sizeof(cx<double>) * ((size_t)d.jb * fft_stride(d.nz) + d.nz);
-        set_lds_limit(k_zfft_pack_blk<double, cx<double>>);
-        hipLaunchKernelGGL((k_zfft_pack_blk<double, cx<double>>), dim3(nitems), dim3(FFT_BLOCK),
-                           lds, st, (const cx<double> *)inter, d, t, slot, (cx<double> *)spec);
-    }
+    // (a persistent form with a register prefetch of the next item measured
+    // slower on both paths)
+    const bool sp = d.prec == PREC_BF16X3, small = d.zpblk == SMALL_BLOCK;
+    if (sp && small) launch_zp<float, bf16x4, SMALL_BLOCK>(st, d, t, inter, slot, spec);
+    else if (sp) launch_zp<float, bf16x4, FFT_BLOCK>(st, d, t, inter, slot, spec);
+    else if (small) launch_zp<double, cx<double>, SMALL_BLOCK>(st, d, t, inter, slot, spec);
+    else launch_zp<double, cx<double>, FFT_BLOCK>(st, d, t, inter, slot, spec);
     return hipGetLastError();
 }
 
