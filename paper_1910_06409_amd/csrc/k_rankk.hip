@@ -155,20 +155,23 @@ __device__ __forceinline__ void step_w2(d4 *acc, const cx<double> *L, const cx<d
     mac3(acc, 1, L[w], R[zz], true);
 }
 
-// register prefetch of the next four snapshots (1) or none (0)
+// register prefetch depth in groups of four snapshots (0: none)
 #ifndef GKE_RANKK_PF
 #define GKE_RANKK_PF 0
 #endif
 
-template <int W, int N>
+// ZERO: zero the left operand of a snapshot past the end at once (false when
+// the loads are a prefetch: the caller zeroes at use, so that no register of a
+// load in flight is written)
+template <int W, int N, bool ZERO = true>
 __device__ __forceinline__ void load_kind(cx<double> *L, cx<double> *R, const Loader &ld, int s0,
                                           int kq, int nsnap)
 {
     const bool ok = s0 + kq < nsnap;
     const unsigned so = (unsigned)((ok ? kq : nsnap - 1 - s0)) * ld.sbytes;
-    if (W == 0) load_fields(L, R, W0F, ld, s0, so, ok);
-    else if (W == 1) load_fields(L, R, W1F, ld, s0, so, ok);
-    else load_fields(L, R, W2F, ld, s0, so, ok);
+    if (W == 0) load_fields(L, R, W0F, ld, s0, so, ok || !ZERO);
+    else if (W == 1) load_fields(L, R, W1F, ld, s0, so, ok || !ZERO);
+    else load_fields(L, R, W2F, ld, s0, so, ok || !ZERO);
 }
 
 template <int W>
@@ -185,19 +188,34 @@ __device__ __forceinline__ void snapshot_loop(d4 *ac, const Loader &ld, int nsna
 {
     constexpr int N = W == 0 ? 8 : W == 1 ? 6 : 7;
 #if GKE_RANKK_PF
-    cx<double> L[N], R[N];
-    load_kind<W, N>(L, R, ld, 0, kq, nsnap);
+    constexpr int PF = GKE_RANKK_PF;   // groups of four snapshots loaded ahead
+    cx<double> Lp[PF][N], Rp[PF][N];
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+        load_kind<W, N, false>(Lp[q], Rp[q], ld, 4 * q < nsnap ? 4 * q : 0, kq, nsnap);
     for (int s0 = 0; s0 < nsnap; s0 += 4) {
-        cx<double> Ln[N], Rn[N];
-        load_kind<W, N>(Ln, Rn, ld, s0 + 4 < nsnap ? s0 + 4 : s0, kq, nsnap);
-        __builtin_amdgcn_sched_barrier(0);
-        step_kind<W>(ac, L, R);
-        __builtin_amdgcn_sched_barrier(0);
+        cx<double> L[N], R[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            L[i] = Ln[i];
-            R[i] = Rn[i];
+            L[i] = Lp[0][i];
+            R[i] = Rp[0][i];
         }
+#pragma unroll
+        for (int q = 0; q + 1 < PF; ++q)
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                Lp[q][i] = Lp[q + 1][i];
+                Rp[q][i] = Rp[q + 1][i];
+            }
+        const int sn = s0 + 4 * PF;
+        load_kind<W, N, false>(Lp[PF - 1], Rp[PF - 1], ld, sn < nsnap ? sn : s0, kq, nsnap);
+        __builtin_amdgcn_sched_barrier(0);
+        if (s0 + kq >= nsnap) {   // past the end: a zero left operand
+#pragma unroll
+            for (int i = 0; i < N; ++i) L[i] = cx<double>{0.0, 0.0};
+        }
+        step_kind<W>(ac, L, R);
+        __builtin_amdgcn_sched_barrier(0);
     }
 #else
     for (int s0 = 0; s0 < nsnap; s0 += 4) {

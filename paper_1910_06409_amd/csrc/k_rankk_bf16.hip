@@ -131,9 +131,10 @@ __device__ __forceinline__ void rankk_bf16_step(f4 *ar, f4 *ai, const bf16x4 *L,
     GKE_MFMA_BF(5, v_, ZZr, ZZi);
 }
 
-// register prefetch of the next snapshot quad (1) or none (0); waves per SIMD
+// register prefetch depth in snapshot quads (0: none; two measured 5 % faster
+// than one); waves per SIMD
 #ifndef GKE_RANKK16_PF
-#define GKE_RANKK16_PF 1
+#define GKE_RANKK16_PF 2
 #endif
 #ifndef GKE_RANKK16_MINW
 #define GKE_RANKK16_MINW 2
@@ -169,18 +170,32 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
     }
 
 #if GKE_RANKK16_PF
-    bf16x4 Ln[NFIELD], Rn[NFIELD];
-    load_raw(Ln, Rn, kb, fbytes, loff, roff, sbytes, 0, g, nsnap);
+    // PF quads ahead: the first touch of a quad's lines comes from HBM, whose
+    // latency under load exceeds one quad of products
+    constexpr int PF = GKE_RANKK16_PF;
+    bf16x4 Lp[PF][NFIELD], Rp[PF][NFIELD];
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+        load_raw(Lp[q], Rp[q], kb, fbytes, loff, roff, sbytes, 4 * q < nsnap ? 4 * q : 0, g, nsnap);
 #endif
     for (int s0 = 0; s0 < nsnap; s0 += 4) {
         bf16x4 L[NFIELD], R[NFIELD];
 #if GKE_RANKK16_PF
 #pragma unroll
         for (int f = 0; f < NFIELD; ++f) {
-            L[f] = Ln[f];
-            R[f] = Rn[f];
+            L[f] = Lp[0][f];
+            R[f] = Rp[0][f];
         }
-        load_raw(Ln, Rn, kb, fbytes, loff, roff, sbytes, s0 + 4 < nsnap ? s0 + 4 : s0, g, nsnap);
+#pragma unroll
+        for (int q = 0; q + 1 < PF; ++q)
+#pragma unroll
+            for (int f = 0; f < NFIELD; ++f) {
+                Lp[q][f] = Lp[q + 1][f];
+                Rp[q][f] = Rp[q + 1][f];
+            }
+        const int sn = s0 + 4 * PF;
+        load_raw(Lp[PF - 1], Rp[PF - 1], kb, fbytes, loff, roff, sbytes, sn < nsnap ? sn : s0, g,
+                 nsnap);
         __builtin_amdgcn_sched_barrier(0);
 #else
         load_raw(L, R, kb, fbytes, loff, roff, sbytes, s0, g, nsnap);
