@@ -107,6 +107,22 @@ def test_radix_3_5_ragged_planes():
     compare(g, ref, pairs, w.nx, "24x21x20")
 
 
+@pytest.mark.parametrize("ny,S,chunk", [
+    (9, 2, 0),    # no full 16-plane tile: every pair goes to the remainder kernel
+    (16, 3, 2),   # exactly one tile, no remainder plane; a last chunk of one snapshot
+    (47, 1, 0),   # two tiles and the longest ragged tail (15 planes); one snapshot
+])
+def test_plane_tiling_edge_cases(ny, S, chunk):
+    w = synth.workload("tiny", ny=ny, S=S)
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 100 + ny)
+    say(f"case tiling Ny={ny} S={S} chunk={chunk}")
+    g, _ = run_gpu(snap, w, y, chunk=chunk)
+    pairs = oracle.all_pairs(w.ny)
+    ref = oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs)
+    compare(g, ref, pairs, w.nx, f"Ny={ny}")
+
+
 def test_fp32_inputs():
     w = synth.workload("tiny", dtype="f32")
     y = synth.y_grid(w)
@@ -256,6 +272,19 @@ def test_bf16x3_ragged_multi_chunk_f32_inputs():
     pairs = oracle.all_pairs(w.ny)
     ref = oracle.pair_terms(snap.astype(np.float64), y, w.lx, w.lz, w.nu, pairs)
     check_bf16(g, ref, pairs, w.nx, "bf16x3 24x21x20")
+
+
+def test_bf16x3_remainder_only_grid():
+    # Ny = 9: no full plane tile, every pair in the remainder kernel (packed
+    # across wavenumbers on the split path); 3 snapshots, one partial quad
+    w = synth.workload("tiny", ny=9, S=3)
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 91)
+    say("case bf16x3 Ny=9 S=3")
+    g, _ = run_gpu(snap, w, y, precision="bf16x3")
+    pairs = oracle.all_pairs(w.ny)
+    ref = oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs)
+    check_bf16(g, ref, pairs, w.nx, "bf16x3 Ny=9")
 
 
 @pytest.mark.timeout(900)
