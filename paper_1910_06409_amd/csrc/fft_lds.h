@@ -2,11 +2,12 @@
 //
 // Used for the in-plane transforms of the method (Section "Products instead of
 // correlations": correlations in x and z through the Parseval identity).
-// A batch of `batch` transforms of length n lives in LDS with element
-// (b, i) at buf[b * bs + i]; every pass reads one buffer and writes the
-// other (ping-pong), so the result ends in natural order in the buffer
-// returned by lds_fft.  Twiddles come from a table tw[m] = exp(-2 pi i m/n),
-// m < n, built on the host in FP64; the inverse direction conjugates them.
+// A batch of `batch` transforms of length n lives in one LDS buffer with
+// element (b, i) at buf[b * bs + fft_pad(i)]; every pass reads the inputs of all
+// its butterflies into registers, then, after a barrier, writes the outputs in
+// place, so the result ends in natural order in the same buffer.  Twiddles
+// come from a table tw[m] = exp(-2 pi i m/n), m < n, built on the host in FP64;
+// the inverse direction conjugates them.
 //   sign = -1: X[k] = sum_j x[j] exp(-2 pi i jk/n)      (forward)
 //   sign = +1: x[j] = sum_k X[k] exp(+2 pi i jk/n)      (inverse, unscaled)
 #pragma once
@@ -19,8 +20,6 @@ struct cx {
     T x, y;
 };
 
-template <typename T>
-__device__ __forceinline__ cx<T> cmk(T a, T b) { return cx<T>{a, b}; }
 template <typename T>
 __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return cx<T>{a.x + b.x, a.y + b.y}; }
 template <typename T>
@@ -183,69 +182,11 @@ struct Dft<8, T> {
     }
 };
 
-// One Stockham pass of radix R.  p = product of the radices already applied.
-template <int R, typename T>
-__device__ __forceinline__ void stockham_pass(const cx<T> *src, cx<T> *dst, int n, int p,
-                                              int batch, int bs, const cx<T> *tw, int sign)
-{
-    const int m = n / R;
-    const int total = batch * m;
-    const int twstep = n / (p * R);
-    for (int it = threadIdx.x; it < total; it += blockDim.x) {
-        const int b = it / m;
-        const int i = it - b * m;
-        const int k = i % p;
-        const cx<T> *s = src + b * bs;
-        cx<T> v[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) v[j] = s[i + j * m];
-        if (p > 1) {
-#pragma unroll
-            for (int j = 1; j < R; ++j) {
-                cx<T> w = tw[j * k * twstep];
-                if (sign > 0) w.y = -w.y;
-                v[j] = cmul(v[j], w);
-            }
-        }
-        Dft<R, T>::run(v, sign);
-        const int base = (i - k) * R + k;
-        cx<T> *d = dst + b * bs;
-#pragma unroll
-        for (int j = 0; j < R; ++j) d[base + j * p] = v[j];
-    }
-}
-
-// Run every pass; data starts in `a`, `b` is scratch of the same shape.
-// Returns the buffer that holds the result.  Ends with a barrier.
-template <typename T>
-__device__ cx<T> *lds_fft(cx<T> *a, cx<T> *b, int batch, int bs, const FftPlanDev &pl,
-                          const cx<T> *tw, int sign)
-{
-    cx<T> *src = a, *dst = b;
-    int p = 1;
-    for (int ps = 0; ps < pl.npass; ++ps) {
-        const int R = pl.radix[ps];
-        switch (R) {
-        case 2: stockham_pass<2, T>(src, dst, pl.n, p, batch, bs, tw, sign); break;
-        case 3: stockham_pass<3, T>(src, dst, pl.n, p, batch, bs, tw, sign); break;
-        case 4: stockham_pass<4, T>(src, dst, pl.n, p, batch, bs, tw, sign); break;
-        case 5: stockham_pass<5, T>(src, dst, pl.n, p, batch, bs, tw, sign); break;
-        default: stockham_pass<8, T>(src, dst, pl.n, p, batch, bs, tw, sign); break;
-        }
-        __syncthreads();
-        cx<T> *t = src;
-        src = dst;
-        dst = t;
-        p *= R;
-    }
-    return src;
-}
-
-// In-place variant for large batches (one LDS buffer): every pass first reads
-// the inputs of all its butterflies into registers, then, after a barrier,
-// writes the outputs.  CAP bounds batch * n and BLOCK the block size, so a
-// thread holds at most ceil(CAP / (R * BLOCK)) butterflies of radix R.
-// Element i of transform b lives at b * bs + fft_pad(i).
+// One in-place Stockham pass of radix R (p = product of the radices already
+// applied): every thread first reads the inputs of its butterflies into
+// registers, then, after a barrier, writes the outputs.  CAP bounds batch * n
+// and BLOCK the block size, so a thread holds at most ceil(CAP / (R * BLOCK))
+// butterflies of radix R.  Element i of transform b lives at b * bs + fft_pad(i).
 template <int R, typename T, int CAP, int BLOCK>
 __device__ __forceinline__ void stockham_pass_ip(cx<T> *buf, int n, int p, int batch, int bs,
                                                  const cx<T> *tw, int sign)
@@ -293,19 +234,12 @@ __device__ __forceinline__ void stockham_pass_ip(cx<T> *buf, int n, int p, int b
     __syncthreads();
 }
 
-// Copy a twiddle table of n entries into LDS (call before the first pass; the
-// passes' first barrier orders it).
-template <typename T>
-__device__ __forceinline__ void load_twiddles(cx<T> *dst, const cx<T> *src, int n)
-{
-    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
-}
-
-// The same copy in two steps, for a caller that issues it among its other
-// loads: load() reads two entries per thread, unconditionally (a thread past
-// the end reads the last entry), store() writes them to LDS (a thread past the
-// end writes the last entry onto itself); entries beyond 2 * BLOCK are copied
-// by a loop in store().  No branch holds a load and its wait.
+// Copy of a twiddle table of n entries into LDS, in two steps so that the
+// caller can issue it among its other loads: load() reads two entries per
+// thread, unconditionally (a thread past the end reads the last entry),
+// store() writes them to LDS (a thread past the end writes the last entry onto
+// itself); entries beyond 2 * BLOCK are copied by a loop in store().  No branch
+// holds a load and its wait.
 template <typename T, int BLOCK>
 struct TwiddleCopy {
     cx<T> v[2];
@@ -321,27 +255,6 @@ struct TwiddleCopy {
         for (int i = threadIdx.x + 2 * BLOCK; i < n; i += BLOCK) dst[i] = src[i];
     }
 };
-
-// Gather `count` elements, MAXE per thread at a time: the loads of a group are
-// all issued before any is consumed, so a thread keeps MAXE loads in flight.
-// get(e) loads element e, put(e, v) stores it.
-template <int MAXE, int BLOCK, typename V, typename G, typename P>
-__device__ __forceinline__ void gather_batched(int count, G &&get, P &&put)
-{
-    for (int base = 0; base < count; base += MAXE * BLOCK) {
-        V v[MAXE];
-#pragma unroll
-        for (int q = 0; q < MAXE; ++q) {
-            const int e = base + threadIdx.x + q * BLOCK;
-            if (e < count) v[q] = get(e);
-        }
-#pragma unroll
-        for (int q = 0; q < MAXE; ++q) {
-            const int e = base + threadIdx.x + q * BLOCK;
-            if (e < count) put(e, v[q]);
-        }
-    }
-}
 
 // Batched in-place transform: batch transforms of length pl.n, element i of
 // transform b at buf[b * bs + fft_pad(i)] (bs >= fft_stride(n),

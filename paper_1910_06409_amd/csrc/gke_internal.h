@@ -61,10 +61,6 @@ constexpr int NSPLIT = 32;
 #ifndef GKE_FFT_WAVES
 #define GKE_FFT_WAVES 4
 #endif
-// loads a thread keeps in flight in the gathers of the transform kernels
-#ifndef GKE_GATHER
-#define GKE_GATHER 4
-#endif
 constexpr int FFT_CAP = GKE_FFT_CAP;
 constexpr int MAX_NTX = 16;   // complex transforms (two pairs each) per kx-pass block
 constexpr int FFT_BLOCK = GKE_FFT_BLOCK;
