@@ -192,7 +192,12 @@ __device__ __forceinline__ void stockham_pass_ip(cx<T> *buf, int n, int p, int b
                                                  const cx<T> *tw, int sign)
 {
     constexpr int MAXIT = (CAP / R + BLOCK - 1) / BLOCK;
-    const int m = n / R;
+    // the pass is selected at run time from the plan's radices: an empty asm
+    // keeps the compiler from hoisting this radix's index set-up out of the
+    // pass loop, where it would be computed for every radix of the switch
+    int nn = n;
+    asm volatile("" : "+s"(nn));
+    const int m = nn / R;
     const int total = batch * m;
     const int twstep = n / (p * R);
     const float inv_m = 1.0f / (float)m, inv_p = 1.0f / (float)p;
