@@ -461,10 +461,14 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
     d.nzb = Nz / d.zb;
     set_zpass_shape(d);
     // finalize: pairs per kz block, complex transforms (2 pairs each) per kx block
-    // (kz pass: multiples of 8 pairs where possible, 128-byte runs of acc and mid)
-    d.pbz = (int)std::min<size_t>(48, cap / sz);
+    // (kz pass: multiples of 8 pairs where possible, 128-byte runs of acc and
+    // mid; 16 pairs let three blocks share a compute unit, measured faster
+    // than 24 at re200)
+    d.pbz = (int)std::min<size_t>(16, cap / sz);
     d.pbz &= d.pbz >= 8 ? ~7 : ~1;   // even: the R blocks split it in halves
-    d.ntx = (int)std::min<size_t>(gke::MAX_NTX, capkx / sx);
+    // (kx pass: at most 8 transforms, five blocks per compute unit at re200,
+    // measured faster than ten)
+    d.ntx = (int)std::min<size_t>(8, capkx / sx);
     // 32-bit element offsets within one wavenumber row of acc (kz pass)
     if (d.zb < 1 || d.jb < 1 || d.pbz < 2 || d.ntx < 1 || (size_t)Nz * d.pstr >= ((size_t)1 << 31)) {
         delete p;
