@@ -342,8 +342,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(w, synth.y_grid(w), args.seed, args.cpu_threads, s_sample=min(60, S),
-                           j1=w.ny // 2 - 5, nb=10)
+        cpu = cpu_baseline(w, synth.y_grid(w), args.seed, args.cpu_threads, s_sample=min(80, S),
+                           j1=w.ny // 2 - 6, nb=12)
         log(f"[bench] oracle sample took {cpu['seconds']:.1f} s")
 
     t_step = main_res["t_step"]
