@@ -338,10 +338,12 @@ hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
 
 // Step 3: d/dY1 and d/dY2 of <du^2> with the five-point weights;
 // T6 = -2 nu d/dry = -nu (d/dY2 - d/dY1), T11 = -(nu/2)(d/dY1 + d/dY2).
-// Blocks in the order (Y1, Y2, chunk of the plane), chunk fastest; the blocks
-// of one XCD (workgroup i runs on XCD i mod 8) take a contiguous range of that
-// order, so the Y2 neighbours of a block were read into the same L2 shortly
-// before.
+// Blocks in the order (tile of FD_TY rows Y1, Y2, row within the tile, chunk
+// of the plane), chunk fastest; the blocks of one XCD (workgroup i runs on XCD
+// i mod 8) take a contiguous range of that order.  A tile's blocks for one Y2
+// read the tile's rows and their stencil halo once into L2, and the next Y2
+// finds four of its five stencil columns there.
+constexpr int FD_TY = 4;
 __global__ __launch_bounds__(256) void k_fd_terms(const double *__restrict__ t1, Dims d,
                                                   Tables t, double *__restrict__ t6,
                                                   double *__restrict__ t11, int nchunk)
@@ -350,9 +352,11 @@ __global__ __launch_bounds__(256) void k_fd_terms(const double *__restrict__ t1,
     const size_t plane = (size_t)d.nz * d.nkx;
     const int nb = (int)gridDim.x, q8 = nb >> 3, r8 = nb & 7, xcd = blockIdx.x & 7;
     const int item = xcd * q8 + min(xcd, r8) + (int)(blockIdx.x >> 3);
-    const int chunk = item % nchunk, j2 = (item / nchunk) % ny, j1 = item / (nchunk * ny);
+    const int chunk = item % nchunk, r = item / nchunk;
+    const int yi = r % FD_TY, j2 = (r / FD_TY) % ny, tile = r / (FD_TY * ny);
+    const int j1 = tile * FD_TY + yi;
     const size_t i = (size_t)chunk * blockDim.x + threadIdx.x;
-    if (i >= plane) return;
+    if (j1 >= ny || i >= plane) return;
     const int a1 = t.j0[j1], a2 = t.j0[j2];
     double d1 = 0.0, d2 = 0.0;
 #pragma unroll
@@ -370,7 +374,7 @@ hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const
 {
     const size_t plane = (size_t)d.nz * d.nkx;
     const int nchunk = (int)((plane + 255) / 256);
-    const size_t nblk = (size_t)nchunk * d.ny * d.ny;
+    const size_t nblk = (size_t)nchunk * d.ny * ((d.ny + FD_TY - 1) / FD_TY) * FD_TY;
     if (nblk >= ((size_t)1 << 31)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fd_terms, dim3((unsigned)nblk), dim3(256), 0, st, t1, d, t, t6, t11,
                        nchunk);
