@@ -94,6 +94,8 @@ struct Dims {
     int pbz;          // pairs per block in the finalize kz pass
     int ntx;          // complex transforms (two pairs each) per block in the kx pass
     int chunk;        // snapshot slots in the spectra buffer
+    int nys;          // planes per snapshot row of the spectra: ny rounded up so that
+                      // every 16-plane tile of a row starts on a 128-byte line
     int prec;         // PREC_FP64 or PREC_BF16X3
     double lx, lz, nu;
 };

@@ -291,6 +291,8 @@ void set_zpass_shape(gke::Dims &d)
     const int jmax = (int)std::min<size_t>(64, capz / sz);
     d.njb = (d.ny + jmax - 1) / jmax;
     d.jb = (d.ny + d.njb - 1) / d.njb;
+    // spectra rows: 16 planes of 8-byte split values or 8 of FP64 complex per line
+    d.nys = d.prec == gke::PREC_BF16X3 ? (d.ny + 15) & ~15 : round8(d.ny);
 }
 
 // Workspace layout; with base != nullptr also assigns the pointers.
@@ -338,7 +340,7 @@ size_t layout(gke_plan_t p, char *base)
     // both split-BF16 buffers hold 8-byte elements (cx<float>, bf16x4)
     const size_t esz = d.prec == gke::PREC_BF16X3 ? 8 : sizeof(cx<double>);
     p->inter = take(esz * (size_t)d.ny * d.nzg * gke::NFIELD * d.nkx * d.zg);
-    p->spec = take(esz * (size_t)d.nk * gke::NFIELD * d.chunk * d.ny);
+    p->spec = take(esz * (size_t)d.nk * gke::NFIELD * d.chunk * d.nys);
     p->acc = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NSPEC * d.nk * round8(npair));
     p->mid = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NMAP * d.nkx * d.nz * round8(pbt));
     p->mstride = nrows * d.ny * (size_t)d.nz * d.nx;
@@ -595,11 +597,14 @@ gke_status prepare_mode(gke_plan_t p)
     set_zpass_shape(p->d);
     if (p->chunk == 0) {
         const size_t esz = p->d.prec == gke::PREC_BF16X3 ? 8 : 16;
-        const size_t per = esz * (size_t)p->d.nk * gke::NFIELD * p->d.ny;
+        const size_t per = esz * (size_t)p->d.nk * gke::NFIELD * p->d.nys;
         size_t c = kAutoChunkBytes / per;
         c = std::max<size_t>(8, std::min<size_t>(512, c)) & ~(size_t)1;
         p->d.chunk = (int)c;
     }
+    // 32-bit element offsets within the spectra of one kx (z pass, rank-k)
+    if ((size_t)p->d.nz * gke::NFIELD * p->d.chunk * p->d.nys >= ((size_t)1 << 31))
+        return fail(p, GKE_ERR_UNSUPPORTED, "chunk too large for this grid");
     if (p->domain == GKE_DOMAIN_FUNDAMENTAL_FULLR && !p->mirror)
         return fail(p, GKE_ERR_ARG, "the fundamental domain needs GKE_OPT_MIRROR = 1");
     p->general = p->mirror || p->domain != GKE_DOMAIN_ALLPAIRS_HALFRX || p->slab_rows > 0;

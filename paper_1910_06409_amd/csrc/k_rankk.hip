@@ -251,11 +251,11 @@ __global__ __launch_bounds__(192, GKE_RANKK_MINW) void k_rankk_f64(
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kq = lane >> 4;
-    const size_t fstride = (size_t)d.chunk * d.ny;  // complex elements per field
+    const size_t fstride = (size_t)d.chunk * d.nys;  // complex elements per field
     Loader ld;
     ld.kb = reinterpret_cast<const char *>(spec + (size_t)k * NFIELD * fstride);
     ld.fbytes = fstride * sizeof(cx<double>);
-    ld.sbytes = (unsigned)d.ny * sizeof(cx<double>);
+    ld.sbytes = (unsigned)d.nys * sizeof(cx<double>);
     ld.loff = (unsigned)t_rowplane[ta * 16 + row] * sizeof(cx<double>);
     ld.roff = (unsigned)(tb * 16 + row) * sizeof(cx<double>);
 

@@ -155,10 +155,10 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
 
     const int lane = threadIdx.x;
     const int row = lane & 15, g = lane >> 4;
-    const size_t fstride = (size_t)d.chunk * d.ny;
+    const size_t fstride = (size_t)d.chunk * d.nys;
     const char *kb = reinterpret_cast<const char *>(spec + (size_t)k * NFIELD * fstride);
     const size_t fbytes = fstride * sizeof(bf16x4);
-    const unsigned sbytes = (unsigned)d.ny * sizeof(bf16x4);
+    const unsigned sbytes = (unsigned)d.nys * sizeof(bf16x4);
     const unsigned loff = (unsigned)t_rowplane[ta * 16 + row] * sizeof(bf16x4);
     const unsigned roff = (unsigned)(tb * 16 + row) * sizeof(bf16x4);
 

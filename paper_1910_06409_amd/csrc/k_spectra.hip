@@ -316,8 +316,8 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_zfft_pack_blk(const cx
     lds_fft_ip<T, CAP, BLOCK>(lds, nb, bs, t.pz, tw, -1);
     const double scale = 1.0 / ((double)nx * (double)nz);
     // spec[(((kx nz + kz) NFIELD + f) chunk + slot) ny + j0 + b]; nz * skz < 2^31
-    const int skz = NFIELD * d.chunk * ny;
-    S *sp = spec + (size_t)kx * nz * skz + ((size_t)f * d.chunk + slot) * ny + j0;
+    const int skz = NFIELD * d.chunk * d.nys;
+    S *sp = spec + (size_t)kx * nz * skz + ((size_t)f * d.chunk + slot) * d.nys + j0;
     Walk2 ws(threadIdx.x, BLOCK, nb);   // (kz, b)
     for (int e = threadIdx.x; e < cnt; e += BLOCK) {
         const cx<T> Y = lds[ws.lo * bs + fft_pad(ws.hi)];

@@ -234,7 +234,7 @@ __global__ __launch_bounds__(256) void k_band(const S *__restrict__ spec, Dims d
                                               int accumulate, double *__restrict__ band)
 {
     const int k = blockIdx.x, ny = d.ny;
-    const size_t fstride = (size_t)d.chunk * ny;
+    const size_t fstride = (size_t)d.chunk * d.nys;
     const S *kb = spec + (size_t)k * NFIELD * fstride;
     for (int e = threadIdx.x; e < 5 * ny; e += blockDim.x) {
         const int a = e / ny, j = e - a * ny;
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(256) void k_band(const S *__restrict__ spec, Dims d
         if (j + a < ny) {
             for (int sl = 0; sl < nsnap; ++sl)
                 for (int f = F_U; f <= F_W; ++f) {
-                    const size_t o = f * fstride + (size_t)sl * ny + j;
+                    const size_t o = f * fstride + (size_t)sl * d.nys + j;
                     const cx<double> x = band_value(kb, o), y = band_value(kb, o + a);
                     s += x.x * y.x + x.y * y.y;
                 }

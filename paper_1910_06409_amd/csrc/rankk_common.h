@@ -90,7 +90,7 @@ __global__ __launch_bounds__(64, 2) void k_rankk_rem(const S *__restrict__ spec,
     }
     const int code = pairs[d.npair_tiles + i];
     const int j1 = pair_j1(code), j2 = pair_j2(code);
-    const int fstride = d.chunk * d.ny;   // offsets within one wavenumber stay below 2^31
+    const int fstride = d.chunk * d.nys;   // offsets within one wavenumber stay below 2^31
     const S *kb = spec + (size_t)k * NFIELD * fstride;
     double cr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ci[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     S An[NFIELD], Bn[NFIELD];
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(64, 2) void k_rankk_rem(const S *__restrict__ spec,
             A[f] = spec_value(An, f);
             B[f] = spec_value(Bn, f);
         }
-        const int sn = (s + 1 < nsnap ? s + 1 : s) * d.ny;
+        const int sn = (s + 1 < nsnap ? s + 1 : s) * d.nys;
 #pragma unroll
         for (int f = 0; f < NFIELD; ++f) {
             An[f] = kb[f * fstride + sn + j1];
