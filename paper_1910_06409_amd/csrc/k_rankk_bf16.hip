@@ -131,10 +131,27 @@ __device__ __forceinline__ void rankk_bf16_step(f4 *ar, f4 *ai, const bf16x4 *L,
     GKE_MFMA_BF(5, v_, ZZr, ZZi);
 }
 
-// register prefetch depth in snapshot quads (0: none; two measured 5 % faster
-// than one); waves per SIMD
-#ifndef GKE_RANKK16_PF
-#define GKE_RANKK16_PF 2
+// The products of one snapshot quad; ok = false (a snapshot past the end)
+// zeroes the left operand, which folds into the copies that build the MFMA
+// operands.
+__device__ __forceinline__ void quad_products(f4 *ar, f4 *ai, const bf16x4 *Lq, const bf16x4 *R,
+                                              bool ok)
+{
+    bf16x4 L[NFIELD];
+#pragma unroll
+    for (int f = 0; f < NFIELD; ++f) {
+        L[f].hi = ok ? Lq[f].hi : 0u;
+        L[f].lo = ok ? Lq[f].lo : 0u;
+    }
+    rankk_bf16_step(ar, ai, L, R);
+}
+
+// Register buffers of snapshot quads: quad q is read from buffer q mod NB,
+// which is refilled with quad q + NB right after its last use, so every load
+// has NB - 1 quads of products to arrive in.  (A rotating prefetch queue would
+// copy the newest buffer down each quad, and a copy waits for its loads.)
+#ifndef GKE_RANKK16_NB
+#define GKE_RANKK16_NB 3
 #endif
 #ifndef GKE_RANKK16_MINW
 #define GKE_RANKK16_MINW 2
@@ -169,48 +186,29 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
         ai[c] = f4{0.f, 0.f, 0.f, 0.f};
     }
 
-#if GKE_RANKK16_PF
-    // PF quads ahead: the first touch of a quad's lines comes from HBM, whose
-    // latency under load exceeds one quad of products
-    constexpr int PF = GKE_RANKK16_PF;
-    bf16x4 Lp[PF][NFIELD], Rp[PF][NFIELD];
+    constexpr int NB = GKE_RANKK16_NB;
+    const int nq = (nsnap + 3) >> 2;
+    bf16x4 Lb[NB][NFIELD], Rb[NB][NFIELD];
 #pragma unroll
-    for (int q = 0; q < PF; ++q)
-        load_raw(Lp[q], Rp[q], kb, fbytes, loff, roff, sbytes, 4 * q < nsnap ? 4 * q : 0, g, nsnap);
-#endif
-    for (int s0 = 0; s0 < nsnap; s0 += 4) {
-        bf16x4 L[NFIELD], R[NFIELD];
-#if GKE_RANKK16_PF
+    for (int i = 0; i < NB; ++i)
+        load_raw(Lb[i], Rb[i], kb, fbytes, loff, roff, sbytes, 4 * min(i, nq - 1), g, nsnap);
+    // full groups of NB quads, without branches (a branch around a quad would
+    // make the wait before it cover every load in flight)
+    int q0 = 0;
+    for (; q0 + NB <= nq; q0 += NB) {
 #pragma unroll
-        for (int f = 0; f < NFIELD; ++f) {
-            L[f] = Lp[0][f];
-            R[f] = Rp[0][f];
+        for (int i = 0; i < NB; ++i) {
+            quad_products(ar, ai, Lb[i], Rb[i], 4 * (q0 + i) + g < nsnap);
+            // the refill is issued after the last read of the buffer
+            __builtin_amdgcn_sched_barrier(0);
+            load_raw(Lb[i], Rb[i], kb, fbytes, loff, roff, sbytes, 4 * min(q0 + i + NB, nq - 1), g,
+                     nsnap);
         }
-#pragma unroll
-        for (int q = 0; q + 1 < PF; ++q)
-#pragma unroll
-            for (int f = 0; f < NFIELD; ++f) {
-                Lp[q][f] = Lp[q + 1][f];
-                Rp[q][f] = Rp[q + 1][f];
-            }
-        const int sn = s0 + 4 * PF;
-        load_raw(Lp[PF - 1], Rp[PF - 1], kb, fbytes, loff, roff, sbytes, sn < nsnap ? sn : s0, g,
-                 nsnap);
-        __builtin_amdgcn_sched_barrier(0);
-#else
-        load_raw(L, R, kb, fbytes, loff, roff, sbytes, s0, g, nsnap);
-#endif
-        if (s0 + 4 > nsnap) {
-            // a snapshot past the end contributes nothing: zero its left operand
-            const bool ok = s0 + g < nsnap;
-#pragma unroll
-            for (int f = 0; f < NFIELD; ++f) {
-                L[f].hi = ok ? L[f].hi : 0u;
-                L[f].lo = ok ? L[f].lo : 0u;
-            }
-        }
-        rankk_bf16_step(ar, ai, L, R);
     }
+    // the last nq - q0 < NB quads are in buffers 0, 1, ...
+#pragma unroll
+    for (int i = 0; i + 1 < NB; ++i)
+        if (q0 + i < nq) quad_products(ar, ai, Lb[i], Rb[i], 4 * (q0 + i) + g < nsnap);
 
     const size_t sp_stride = (size_t)d.nk * d.pstr;
 #pragma unroll

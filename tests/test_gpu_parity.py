@@ -274,6 +274,24 @@ def test_bf16x3_ragged_multi_chunk_f32_inputs():
     check_bf16(g, ref, pairs, w.nx, "bf16x3 24x21x20")
 
 
+@pytest.mark.parametrize("S,chunk", [
+    (27, 26),   # 7 quads in the first chunk (full groups of three, one quad with
+                # two snapshots after them), then a chunk of one snapshot
+    (24, 24),   # exactly two full groups of three quads
+])
+def test_bf16x3_snapshot_quad_groups(S, chunk):
+    # the split update reads snapshot quads from three register buffers in
+    # groups of three quads; Ny = 33: two plane tiles and a remainder plane
+    w = synth.workload("tiny", ny=33, S=S, M=6)
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 100 + S)
+    say(f"case bf16x3 quad groups Ny=33 S={S} chunk={chunk}")
+    g, _ = run_gpu(snap, w, y, precision="bf16x3", chunk=chunk)
+    pairs = oracle.all_pairs(w.ny)
+    ref = oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs)
+    check_bf16(g, ref, pairs, w.nx, f"bf16x3 S={S} chunk={chunk}")
+
+
 def test_bf16x3_remainder_only_grid():
     # Ny = 9: no full plane tile, every pair in the remainder kernel (packed
     # across wavenumbers on the split path); 3 snapshots, one partial quad
