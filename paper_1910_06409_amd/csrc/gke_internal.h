@@ -33,6 +33,10 @@ enum { S_R = 0, S_FX, S_FY, S_FZ, S_PHI, S_PP, S_UVS, S_UVA, NSPEC };
 
 // r-space maps produced by the inverse transforms in finalize
 enum { M_R = 0, M_DRX, M_DRZ, M_FX, M_FY, M_FZ, M_PHI, M_PP, M_UVS, M_UVA, NMAP };
+// planes of the finalize intermediate (kz-transformed spectra): every map but
+// M_DRX, which the kx pass forms from the M_R plane (i alpha is constant along kz)
+constexpr int NMID = NMAP - 1;
+__host__ __device__ inline int mid_plane(int m) { return m == M_DRX ? M_R : m > M_DRX ? m - 1 : m; }
 
 // terms kept as full-plane maps per slab in the general output modes:
 // T1-T5, T7-T10, T12, T13 (T6, T11 and T14 are formed from them at output)

@@ -342,7 +342,7 @@ size_t layout(gke_plan_t p, char *base)
     p->inter = take(esz * (size_t)d.ny * d.nzg * gke::NFIELD * d.nkx * d.zg);
     p->spec = take(esz * (size_t)d.nk * gke::NFIELD * d.chunk * d.nys);
     p->acc = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NSPEC * d.nk * round8(npair));
-    p->mid = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NMAP * d.nkx * d.nz * round8(pbt));
+    p->mid = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NMID * d.nkx * d.nz * round8(pbt));
     p->mstride = nrows * d.ny * (size_t)d.nz * d.nx;
     p->mf = (double *)take(sizeof(double) * gke::NSTORED * p->mstride);
     p->band = (double *)take(p->general ? sizeof(double) * (size_t)d.nk * 5 * d.ny : 0);

@@ -28,7 +28,7 @@ __host__ __device__ inline int mid_stride(int ptot) { return (ptot + 7) & ~7; }
 // Blocks z = 0, 1 take the two halves of a block of pb pairs of the R spectrum
 // and transform R^ and i beta R^ together (2 * pb/2 transforms); blocks z >= 2
 // take pb pairs of spectrum z - 1.  Every block reads its part of acc once.
-// mid layout: [NMAP][nkx][nz (rz)][mid_stride(ptot)] (the pairs of this batch,
+// mid layout: [NMID][nkx][nz (rz)][mid_stride(ptot)] (the pairs of this batch,
 // rows padded to whole 128-byte lines).
 __global__ GKE_FFT_BOUNDS void k_fin_kz(const cx<double> *__restrict__ acc, Dims d,
                                                       Tables t, int p0, int ptot,
@@ -47,7 +47,6 @@ __global__ GKE_FFT_BOUNDS void k_fin_kz(const cx<double> *__restrict__ acc, Dims
     const size_t mst = (size_t)mid_stride(ptot);
     const int bs = fft_stride(nz);
     const double two_pi = 6.283185307179586476925286766559;
-    const double alpha = (2 * kx == d.nx) ? 0.0 : two_pi * kx / d.lx;
     cx<double> *tw = lds + pb * bs;
     const cx<double> *ab = acc + ((size_t)sp * d.nk + (size_t)kx * nz) * pall + p0 + pl0;
     const int cnt = nz * np;
@@ -96,12 +95,10 @@ __global__ GKE_FFT_BOUNDS void k_fin_kz(const cx<double> *__restrict__ acc, Dims
         const cx<double> Y = lds[b * bs + fft_pad(rz)];
         const size_t o = ((size_t)kx * nz + rz) * mst + pl0 + b;
         if (isr) {
-            mid[(size_t)M_R * mplane + o] = Y;
-            // i alpha R^: alpha is constant along kz
-            mid[(size_t)M_DRX * mplane + o] = cx<double>{-alpha * Y.y, alpha * Y.x};
-            mid[(size_t)M_DRZ * mplane + o] = lds[(np + b) * bs + fft_pad(rz)];
+            mid[(size_t)mid_plane(M_R) * mplane + o] = Y;
+            mid[(size_t)mid_plane(M_DRZ) * mplane + o] = lds[(np + b) * bs + fft_pad(rz)];
         } else {
-            mid[(size_t)(M_FX + (sp - S_FX)) * mplane + o] = Y;   // FX .. UVA one to one
+            mid[(size_t)mid_plane(M_FX + (sp - S_FX)) * mplane + o] = Y;   // FX .. UVA one to one
         }
     }
 }
@@ -234,7 +231,7 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fin_kx(const cx<double
     cx<double> xa[MAXG], xb[MAXG];
     const size_t mst = (size_t)mid_stride(ptot);
     {
-        const cx<double> *mb = mid + ((size_t)m * nkx * nz + rz) * mst + pl0;
+        const cx<double> *mb = mid + ((size_t)mid_plane(m) * nkx * nz + rz) * mst + pl0;
         const size_t skx = (size_t)nz * mst;
         Walk2 w(threadIdx.x, BLOCK, nt);   // (kx, c)
 #pragma unroll
@@ -273,8 +270,13 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fin_kx(const cx<double
             const int kx = ok ? w.hi : nkx - 1, c = ok ? w.lo : nt - 1;
             w.next();
             const cx<double> zero = cx<double>{0.0, 0.0};
-            const cx<double> a = 2 * c < np ? xa[q] : zero;      // padding pairs read 0
-            const cx<double> b = 2 * c + 1 < np ? xb[q] : zero;
+            cx<double> a = 2 * c < np ? xa[q] : zero;      // padding pairs read 0
+            cx<double> b = 2 * c + 1 < np ? xb[q] : zero;
+            if (m == M_DRX) {   // i alpha R^, read from the R plane (0 at the Nyquist kx)
+                const double al = (2 * kx == nx) ? 0.0 : 6.283185307179586476925286766559 * kx / d.lx;
+                a = cx<double>{-al * a.y, al * a.x};
+                b = cx<double>{-al * b.y, al * b.x};
+            }
             cx<double> *Ac = A + c * bs;
             Ac[fft_pad(kx)] = cx<double>{a.x - b.y, a.y + b.x};  // a + i b
             const int kn = (kx == 0 || 2 * kx == nx) ? kx : nx - kx;
