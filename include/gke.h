@@ -63,7 +63,7 @@ enum {
     GKE_OPT_DTYPE = 1,        /* input storage: GKE_DTYPE_F64 (default) or GKE_DTYPE_F32 */
     GKE_OPT_PRECISION = 2,    /* rank-k arithmetic: GKE_PREC_FP64 (default) or GKE_PREC_BF16X3 */
     GKE_OPT_CHUNK = 3,        /* snapshots per cross-spectral batch, even, 2..4096 (default 64);
-                                 0: the most whose spectra fit 48 GiB, in [8, 512] */
+                                 0: the most whose spectra fit 96 GiB, in [8, 512] */
     GKE_OPT_PAIR_BATCH = 4,   /* plane pairs per finalize batch, 0 = all at once (default) */
     GKE_OPT_TIMING = 5,       /* 1: record HIP events around every kernel launch (any time) */
     GKE_OPT_MIRROR = 6,       /* 1: average every term with the reflected pair (below) */
