@@ -57,10 +57,11 @@ def kernel_work(w, chunk):
         # read the x-transformed fields, write the 10 spectra
         "zfft_pack": ("byte", 2 * 10.0 * ny * nkx * nz * c8),
         "plane_sums": ("byte", 4.0 * n_pts * b_in),
-        # read 8 term spectra of every unordered pair, write 10 kz-transformed maps
-        "fin_kz": ("byte", (8 + 10) * float(nk) * npair_u * c16),
-        # read 10 maps, write 12 FP64 term maps for both orientations
-        "fin_kx": ("byte", 10.0 * nk * npair_u * c16 + 12.0 * ny * ny * nkx * nz * 8),
+        # read 8 term spectra of every unordered pair, write 9 kz-transformed
+        # maps (i alpha R is formed from R in the kx pass)
+        "fin_kz": ("byte", (8 + 9) * float(nk) * npair_u * c16),
+        # read the 9 maps, write 12 FP64 term maps for both orientations
+        "fin_kx": ("byte", 9.0 * nk * npair_u * c16 + 12.0 * ny * ny * nkx * nz * 8),
         # read <du^2>, write two maps
         "fd_terms": ("byte", 3.0 * ny * ny * nkx * nz * 8),
     }
