@@ -111,6 +111,8 @@ def test_radix_3_5_ragged_planes():
     (9, 2, 0),    # no full 16-plane tile: every pair goes to the remainder kernel
     (16, 3, 2),   # exactly one tile, no remainder plane; a last chunk of one snapshot
     (47, 1, 0),   # two tiles and the longest ragged tail (15 planes); one snapshot
+    (33, 5, 2),   # one leftover plane: its pairs with the tiled planes are formed by
+                  # the blocks of the last column tile; three chunks, the last partial
 ])
 def test_plane_tiling_edge_cases(ny, S, chunk):
     w = synth.workload("tiny", ny=ny, S=S)
