@@ -54,8 +54,9 @@ def kernel_work(w, chunk):
         "rankk_rem": ("flop", 216.0 * chunk * nk * (npair_u - pairs_tiles)),
         # read the 4 input fields once, write the 10 x-transformed fields
         "fluct_xfft": ("byte", 4.0 * n_pts * b_in + 10.0 * ny * nkx * nz * c8),
-        # read the x-transformed fields, write the 10 spectra
-        "zfft_pack": ("byte", 2 * 10.0 * ny * nkx * nz * c8),
+        # read the x-transformed fields, write the 10 spectra (the split path
+        # transforms the four snapshots of a quad per launch)
+        "zfft_pack": ("byte", 2 * 10.0 * ny * nkx * nz * c8 * (4 if w.precision == "bf16x3" else 1)),
         "plane_sums": ("byte", 4.0 * n_pts * b_in),
         # read 8 term spectra of every unordered pair, write 9 kz-transformed
         # maps (i alpha R is formed from R in the kx pass)

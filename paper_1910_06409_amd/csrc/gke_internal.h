@@ -21,11 +21,19 @@ enum { PREC_FP64 = 0, PREC_BF16X3 = 1 };
 
 // one complex spectral value split for the three-term BF16 products, as BF16
 // bit patterns with hi = RN(x), lo = RN(x - hi) for x = re, im; the two high
-// parts share one dword and the two low parts the other (the operand layout
-// of the matrix-core update, k_rankk_bf16.hip)
+// parts share one dword and the two low parts the other
 struct bf16x4 {
     unsigned int hi;  // re_hi | im_hi << 16
     unsigned int lo;  // re_lo | im_lo << 16
+};
+// The split spectra hold the values of four consecutive snapshots of one
+// plane as one 32-byte record: the four hi dwords, then the four lo dwords
+// (snapshot 4 q + i at dword i), so that one 16-byte load is a whole operand
+// of the matrix-core update (k_rankk_bf16.hip).  Record (k, f, q, j) sits at
+// ((k NFIELD + f) nqs + q) nys + j.
+struct SplitRec {
+    unsigned int h[4];
+    unsigned int l[4];
 };
 
 // term spectra accumulated per unordered pair tile (see k_rankk.hip)
@@ -100,8 +108,45 @@ struct Dims {
     int chunk;        // snapshot slots in the spectra buffer
     int nys;          // planes per snapshot row of the spectra: ny rounded up so that
                       // every 16-plane tile of a row starts on a 128-byte line
+    int nqs;          // split path: snapshot quads per chunk, (chunk + 3) / 4
     int prec;         // PREC_FP64 or PREC_BF16X3
     double lx, lz, nu;
+};
+
+// Stored value of (field f, snapshot s, plane j) of one wavenumber (kb: its
+// first element), as loaded (raw_at) and as an FP64 complex (value_of).
+__device__ __forceinline__ const cx<double> *spec_base(const cx<double> *s, const Dims &d, int k)
+{
+    return s + (size_t)k * NFIELD * d.chunk * d.nys;
+}
+__device__ __forceinline__ const SplitRec *spec_base(const SplitRec *s, const Dims &d, int k)
+{
+    return s + (size_t)k * NFIELD * d.nqs * d.nys;
+}
+__device__ __forceinline__ cx<double> raw_at(const cx<double> *kb, const Dims &d, int f, int s,
+                                             int j)
+{
+    return kb[(f * d.chunk + s) * d.nys + j];   // below 2^31 within a wavenumber (host)
+}
+__device__ __forceinline__ bf16x4 raw_at(const SplitRec *kb, const Dims &d, int f, int s, int j)
+{
+    const unsigned int *r = kb[(f * d.nqs + (s >> 2)) * d.nys + j].h;
+    return bf16x4{r[s & 3], r[4 + (s & 3)]};
+}
+__device__ __forceinline__ cx<double> value_of(cx<double> v) { return v; }
+__device__ __forceinline__ cx<double> value_of(bf16x4 v)
+{
+    const double rh = __uint_as_float(v.hi << 16), rl = __uint_as_float(v.lo << 16);
+    const double ih = __uint_as_float(v.hi & 0xffff0000u), il = __uint_as_float(v.lo & 0xffff0000u);
+    return cx<double>{rh + rl, ih + il};
+}
+template <typename S>
+struct RawOf {
+    typedef cx<double> type;
+};
+template <>
+struct RawOf<SplitRec> {
+    typedef bf16x4 type;
 };
 
 // pair table entry: j1 | j2 << 12 | mirror << 24 (mirror: also write (j2, j1))
@@ -160,10 +205,14 @@ hipError_t launch_profiles(hipStream_t st, const Dims &d, const Tables &t, const
 hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int f32,
                              const void *u, const void *v, const void *w, const void *p,
                              const double *prof, void *inter, double *momp);
-// z transforms and packing into the spectra slot.  spec holds cx<double>
-// (FP64 path) or bf16x4 (split-BF16 path).
+// z transforms and packing into the spectra slot (FP64 path: cx<double>)
 hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t, const void *inter,
                             int slot, void *spec);
+// split path: z transforms of ng <= 4 snapshots (x-transformed rows in inter,
+// one buffer of inter_stride elements each) into the records of quad q
+// (missing snapshots of a partial quad written as zero)
+hipError_t launch_zfft_rec(hipStream_t st, const Dims &d, const Tables &t, const void *inter,
+                           size_t inter_stride, int q, int ng, SplitRec *spec);
 // cross-spectral rank-k update over the snapshots of one chunk, pairs of full
 // plane tiles (FP64 MFMA)
 hipError_t launch_rankk_f64(hipStream_t st, const Dims &d, const Tables &t,
@@ -171,14 +220,14 @@ hipError_t launch_rankk_f64(hipStream_t st, const Dims &d, const Tables &t,
                             cx<double> *acc);
 // the same with split-BF16 three-term MFMA products and FP32 accumulation
 hipError_t launch_rankk_bf16x3(hipStream_t st, const Dims &d, const Tables &t,
-                               const bf16x4 *spec, int nsnap, int accumulate,
+                               const SplitRec *spec, int nsnap, int accumulate,
                                cx<double> *acc);
 // the pairs that involve the last Ny mod 16 planes (FP64 vector arithmetic)
 hipError_t launch_rankk_rem_f64(hipStream_t st, const Dims &d, const Tables &t,
                                 const cx<double> *spec, int nsnap, int accumulate,
                                 cx<double> *acc);
 hipError_t launch_rankk_rem_bf16x3(hipStream_t st, const Dims &d, const Tables &t,
-                                   const bf16x4 *spec, int nsnap, int accumulate,
+                                   const SplitRec *spec, int nsnap, int accumulate,
                                    cx<double> *acc);
 // finalize: inverse transform along kz of the term spectra of the pairs
 // [p0, p1) of the compact pair index, scaled by 1/count

@@ -61,7 +61,7 @@ struct gke_plan_s {
     size_t mstride = 0;            // doubles per term map in mf
     double *sums1 = nullptr, *prof = nullptr, *momp = nullptr, *r0 = nullptr, *gxz = nullptr;
     void *inter = nullptr;  // cx<double> (FP64) or cx<float> (split-BF16)
-    void *spec = nullptr;   // cx<double> (FP64) or gke::bf16x4 (split-BF16)
+    void *spec = nullptr;   // cx<double> (FP64) or gke::SplitRec records (split-BF16)
     cx<double> *acc = nullptr, *mid = nullptr;
     gke::Tables tab{};
 
@@ -286,13 +286,25 @@ void set_zpass_shape(gke::Dims &d)
     const size_t cap = std::min<size_t>(gke::LDS_BUDGET / 16 - std::max(d.nx, d.nz), gke::FFT_CAP);
     const size_t cap_small = std::min<size_t>(cap, gke::SMALL_CAP);
     const size_t sz = gke::fft_stride(d.nz);
-    d.zpblk = d.prec == gke::PREC_BF16X3 && cap_small / sz >= 8 ? gke::SMALL_BLOCK : gke::FFT_BLOCK;
+    // split path: the record z pass transforms the four snapshots of a quad
+    // together (512 threads); FP64: one snapshot, the smaller block when its
+    // cap still holds eight planes
+    const bool split = d.prec == gke::PREC_BF16X3;
+    d.zpblk = !split && cap_small / sz >= 8 ? gke::SMALL_BLOCK : gke::FFT_BLOCK;
     const size_t capz = d.zpblk == gke::SMALL_BLOCK ? cap_small : cap;
-    const int jmax = (int)std::min<size_t>(64, capz / sz);
+    const int jmax = std::max(1, (int)std::min<size_t>(64, capz / (split ? 4 * sz : sz)));
     d.njb = (d.ny + jmax - 1) / jmax;
     d.jb = (d.ny + d.njb - 1) / d.njb;
+    d.nqs = (d.chunk + 3) / 4;
     // spectra rows: 16 planes of 8-byte split values or 8 of FP64 complex per line
     d.nys = d.prec == gke::PREC_BF16X3 ? (d.ny + 15) & ~15 : round8(d.ny);
+}
+
+// bytes of one buffer of x-transformed rows
+size_t inter_bytes(const gke::Dims &d)
+{
+    const size_t esz = d.prec == gke::PREC_BF16X3 ? sizeof(cx<float>) : sizeof(cx<double>);
+    return esz * (size_t)d.ny * d.nzg * gke::NFIELD * d.nkx * d.zg;
 }
 
 // Workspace layout; with base != nullptr also assigns the pointers.
@@ -337,10 +349,12 @@ size_t layout(gke_plan_t p, char *base)
     p->momp = (double *)take(sizeof(double) * d.ny * gke::NMOMP * d.nzb);
     p->r0 = (double *)take(sizeof(double) * d.ny * 5);
     p->gxz = (double *)take(sizeof(double) * d.ny);
-    // both split-BF16 buffers hold 8-byte elements (cx<float>, bf16x4)
-    const size_t esz = d.prec == gke::PREC_BF16X3 ? 8 : sizeof(cx<double>);
-    p->inter = take(esz * (size_t)d.ny * d.nzg * gke::NFIELD * d.nkx * d.zg);
-    p->spec = take(esz * (size_t)d.nk * gke::NFIELD * d.chunk * d.nys);
+    // split path: four x-transformed buffers of cx<float> (one per snapshot of
+    // a quad) and records of four snapshots; FP64: one buffer, cx<double>
+    const bool split = d.prec == gke::PREC_BF16X3;
+    p->inter = take(inter_bytes(d) * (split ? 4 : 1));
+    p->spec = take(split ? sizeof(gke::SplitRec) * (size_t)d.nk * gke::NFIELD * d.nqs * d.nys
+                         : sizeof(cx<double>) * (size_t)d.nk * gke::NFIELD * d.chunk * d.nys);
     p->acc = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NSPEC * d.nk * round8(npair));
     p->mid = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NMID * d.nkx * d.nz * round8(pbt));
     p->mstride = nrows * d.ny * (size_t)d.nz * d.nx;
@@ -371,13 +385,28 @@ gke_status select_slab(gke_plan_t p, int s)
     return GKE_OK;
 }
 
+// split path: z transforms of the snapshots of quad q (ng of them) into records
+gke_status zfft_quad(gke_plan_t p, int q, int ng)
+{
+    const size_t istride = inter_bytes(p->d) / sizeof(cx<float>);
+    GKE_HIP(p, timed(p, GKE_K_ZFFT_PACK, [&] {
+        return gke::launch_zfft_rec(p->stream, p->d, p->tab, p->inter, istride, q, ng,
+                                    (gke::SplitRec *)p->spec);
+    }));
+    return GKE_OK;
+}
+
 gke_status launch_flush(gke_plan_t p)
 {
     if (p->pending == 0) return GKE_OK;
     const int accumulate = p->chunks_done > 0 ? 1 : 0;
     const bool split = p->d.prec == gke::PREC_BF16X3;
+    if (split && (p->pending & 3)) {   // the last, partial quad
+        const gke_status s = zfft_quad(p, p->pending >> 2, p->pending & 3);
+        if (s != GKE_OK) return s;
+    }
     const auto *s64 = (const cx<double> *)p->spec;
-    const auto *s16 = (const gke::bf16x4 *)p->spec;
+    const auto *s16 = (const gke::SplitRec *)p->spec;
     if (p->d.ntp > 0) {
         GKE_HIP(p, timed(p, GKE_K_RANKK, [&] {
             return split ? gke::launch_rankk_bf16x3(p->stream, p->d, p->tab, s16, p->pending,
@@ -604,9 +633,14 @@ gke_status prepare_mode(gke_plan_t p)
         c = std::max<size_t>(8, std::min<size_t>(512, c)) & ~(size_t)1;
         p->d.chunk = (int)c;
     }
+    p->d.nqs = (p->d.chunk + 3) / 4;
     // 32-bit element offsets within the spectra of one kx (z pass, rank-k)
     if ((size_t)p->d.nz * gke::NFIELD * p->d.chunk * p->d.nys >= ((size_t)1 << 31))
         return fail(p, GKE_ERR_UNSUPPORTED, "chunk too large for this grid");
+    // the record z pass holds the four snapshots of a quad in one block
+    if (p->d.prec == gke::PREC_BF16X3 &&
+        (size_t)4 * gke::fft_stride(p->d.nz) > (size_t)gke::FFT_CAP)
+        return fail(p, GKE_ERR_UNSUPPORTED, "Nz too long for the split-path z pass");
     if (p->domain == GKE_DOMAIN_FUNDAMENTAL_FULLR && !p->mirror)
         return fail(p, GKE_ERR_ARG, "the fundamental domain needs GKE_OPT_MIRROR = 1");
     p->general = p->mirror || p->domain != GKE_DOMAIN_ALLPAIRS_HALFRX || p->slab_rows > 0;
@@ -712,15 +746,24 @@ gke_status gke_accumulate(gke_plan_t p, const void *u, const void *v, const void
         ++p->n1;
         return GKE_OK;
     }
+    const bool split = p->d.prec == gke::PREC_BF16X3;
+    // split path: snapshot i of a quad in x-transformed buffer i
+    void *xdst = split ? (void *)((char *)p->inter + (p->pending & 3) * inter_bytes(p->d))
+                       : p->inter;
     GKE_HIP(p, timed(p, GKE_K_FLUCT_XFFT, [&] {
         return gke::launch_fluct_xfft(p->stream, p->d, p->tab, f32, u, v, w, pr, p->prof,
-                                      p->inter, p->momp);
+                                      xdst, p->momp);
     }));
-    GKE_HIP(p, timed(p, GKE_K_ZFFT_PACK, [&] {
-        return gke::launch_zfft_pack(p->stream, p->d, p->tab, p->inter, p->pending, p->spec);
-    }));
+    if (!split)
+        GKE_HIP(p, timed(p, GKE_K_ZFFT_PACK, [&] {
+            return gke::launch_zfft_pack(p->stream, p->d, p->tab, p->inter, p->pending, p->spec);
+        }));
     ++p->pending;
     ++p->n2;
+    if (split && (p->pending & 3) == 0) {
+        const gke_status s = zfft_quad(p, (p->pending >> 2) - 1, 4);
+        if (s != GKE_OK) return s;
+    }
     if (p->pending == p->d.chunk) return launch_flush(p);
     return GKE_OK;
 }

@@ -1,24 +1,28 @@
 // k_rankk_bf16.hip -- the cross-spectral update of k_rankk.hip with split-BF16
-// three-term MFMA products and FP32 accumulation.
+// MFMA products and FP32 accumulation.
 //
 // Every spectral value x is stored as x ~ hi + lo with hi = RN_bf16(x) and
 // lo = RN_bf16(x - hi); a real product a b is taken as ah bh + ah bl + al bh
-// (the al bl term, below 2^-16 |a b|, is dropped).  The stored dwords are
-// h = (re_hi, im_hi) and l = (re_lo, im_lo) (bf16x4).  For conj(L) R of one
-// snapshot the six real terms of each output part form one group of eight K
-// entries (two zero), built from the dwords without arithmetic:
-//   A    = [Lh, Lh, Ll, 0]           = [Lrh, Lih, Lrh, Lih, Lrl, Lil, 0, 0]
-//   B_re = [Rh, Rl, Rh, 0]           = [Rrh, Rih, Rrl, Ril, Rrh, Rih, 0, 0]
-//   B_im = [s(Rh), s(Rl), s(Rh), 0]  = [Rih,-Rrh, Ril,-Rrl, Rih,-Rrh, 0, 0]
-// (s(x) swaps the two halves and negates the new upper one):
-//   A . B_re = Re conj(L) R,  A . B_im = Im conj(L) R  (three terms each).
+// (the al bl term, below 2^-16 |a b|, is dropped).  A stored dword holds one
+// (re, im) pair of BF16 values, h = (re_hi, im_hi) or l = (re_lo, im_lo), and
+// a 32-byte record holds one plane's h dwords of four consecutive snapshots,
+// then their l dwords (SplitRec).  For conj(L) R summed over snapshots, the dot
+// product of two h dwords is Re(conj(Lh) Rh) of one snapshot, and with the
+// right dword rotated, s(re, im) = (im, -re), it is Im(conj(Lh) Rh).
+//
 // v_mfma_f32_16x16x32_bf16 takes K = 32: lane l carries K entries 8(l/16)..+7,
-// so lane group g = l/16 carries snapshot s0 + g and one MFMA covers four
-// snapshots.  Rows (Y1) and columns (Y2) are planes, l%16 within the tile.
-// Output (checked on the device): lane l, register v -> (row 4(l/16) + v, col l%16).
+// i.e. four dwords.  Lane group g = l/16 takes quad q0 + g, so one MFMA sums
+// 16 snapshots with every K entry in use, and its operands are whole loaded
+// records: per product and part (Re, Im) three MFMAs, (Lh, Rh), (Lh, Rl),
+// (Ll, Rh), per 16 snapshots.  Rows (Y1) and columns (Y2) are planes, l%16
+// within the tile.  Output (checked on the device): lane l, register v ->
+// (row 4(l/16) + v, col l%16).
 // The nine accumulators are those of k_rankk.hip; q never enters as a field:
 // c5 = (v, q) + (q, v) = 0.2 sum_i [(v, Q_ii) + (Q_ii, v)], 31 products per
-// snapshot, which costs four MFMA pairs and saves forming q from split values.
+// snapshot, which costs four products more and saves forming q from split
+// values.  The products are grouped by their right field, whose rotated forms
+// are made once per group of 16 snapshots; the right fields are loaded two
+// groups ahead of their products.
 #include "rankk_common.h"
 
 namespace gke {
@@ -27,138 +31,105 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ bf8 op3(unsigned int d0, unsigned int d1, unsigned int d2)
-{
-    return __builtin_bit_cast(bf8, u4{d0, d1, d2, 0u});
-}
 // swap the BF16 halves, negate the new upper one: (a, b) -> (b, -a)
 __device__ __forceinline__ unsigned int swapneg(unsigned int x)
 {
     return ((x >> 16) | (x << 16)) ^ 0x80000000u;
 }
+__device__ __forceinline__ u4 swapneg4(u4 x)
+{
+    return u4{swapneg(x.x), swapneg(x.y), swapneg(x.z), swapneg(x.w)};
+}
 constexpr unsigned int NEG2 = 0x80008000u;   // negate both halves
+__device__ __forceinline__ u4 neg4(u4 x) { return x ^ u4{NEG2, NEG2, NEG2, NEG2}; }
+__device__ __forceinline__ bf8 as_bf8(u4 x) { return __builtin_bit_cast(bf8, x); }
 
-#define GKE_MFMA_BF(c, A, BRE, BIM)                                                \
-    do {                                                                           \
-        ar[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16((A), (BRE), ar[c], 0, 0, 0); \
-        ai[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16((A), (BIM), ai[c], 0, 0, 0); \
-    } while (0)
-
-// Loads of one snapshot quad (lane group g takes snapshot s0 + g): a
-// wave-uniform base (wavenumber, field, quad) plus a 32-bit lane offset.  A
-// snapshot past the end reloads the last valid one (zeroed at use).
-__device__ __forceinline__ void load_raw(bf16x4 *L, bf16x4 *R, const char *kb, size_t fbytes,
-                                         unsigned loff, unsigned roff, unsigned sbytes, int s0,
-                                         int g, int nsnap)
+__device__ __forceinline__ f4 mfma(u4 a, u4 b, f4 c)
 {
-    const int s = s0 + g < nsnap ? s0 + g : nsnap - 1;
-    const unsigned so = (unsigned)(s - s0) * sbytes;
-    const char *base = kb + (size_t)s0 * sbytes;
-#pragma unroll
-    for (int f = 0; f < NFIELD; ++f) {
-        const char *bf = base + f * fbytes;
-        const unsigned lo = loff + so, ro = roff + so;
-        L[f] = *reinterpret_cast<const bf16x4 *>(bf + lo);
-        R[f] = *reinterpret_cast<const bf16x4 *>(bf + ro);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), as_bf8(b), c, 0, 0, 0);
+}
+
+// One right field of 16 snapshots and its rotated forms (for the Im part).
+struct RightField {
+    u4 h, l, sh, sl;
+};
+__device__ __forceinline__ RightField right_field(u4 h, u4 l)
+{
+    return RightField{h, l, swapneg4(h), swapneg4(l)};
+}
+// conj(L) R into channel c: Re with (h, l), Im with the rotated forms
+__device__ __forceinline__ void prod(f4 *ar, f4 *ai, int c, u4 ah, u4 al, const RightField &r)
+{
+    ar[c] = mfma(ah, r.h, ar[c]);
+    ai[c] = mfma(ah, r.sh, ai[c]);
+    ar[c] = mfma(ah, r.l, ar[c]);
+    ai[c] = mfma(ah, r.sl, ai[c]);
+    ar[c] = mfma(al, r.h, ar[c]);
+    ai[c] = mfma(al, r.sh, ai[c]);
+}
+
+// The products of right field B over one group of 16 snapshots (31 in all
+// over the ten right fields); the products with a minus sign take the negated
+// left field.
+template <int B>
+__device__ __forceinline__ void group_products(f4 *ar, f4 *ai, const u4 *LH, const u4 *LL, u4 rh,
+                                               u4 rl)
+{
+    const RightField r = right_field(rh, rl);
+    if constexpr (B == F_U) {
+        prod(ar, ai, 0, LH[F_U], LL[F_U], r);
+        prod(ar, ai, 1, LH[F_QXX], LL[F_QXX], r);
+        prod(ar, ai, 2, LH[F_QXZ], LL[F_QXZ], r);
+        prod(ar, ai, 3, LH[F_QXY], LL[F_QXY], r);
+        prod(ar, ai, 8, LH[F_V], LL[F_V], r);
+    } else if constexpr (B == F_V) {
+        prod(ar, ai, 0, LH[F_V], LL[F_V], r);
+        prod(ar, ai, 1, LH[F_QXY], LL[F_QXY], r);
+        prod(ar, ai, 2, LH[F_QYZ], LL[F_QYZ], r);
+        prod(ar, ai, 3, LH[F_QYY], LL[F_QYY], r);
+        prod(ar, ai, 5, LH[F_QXX], LL[F_QXX], r);
+        prod(ar, ai, 5, LH[F_QYY], LL[F_QYY], r);
+        prod(ar, ai, 5, LH[F_QZZ], LL[F_QZZ], r);
+        prod(ar, ai, 6, LH[F_P], LL[F_P], r);
+        prod(ar, ai, 7, LH[F_U], LL[F_U], r);
+    } else if constexpr (B == F_W) {
+        prod(ar, ai, 0, LH[F_W], LL[F_W], r);
+        prod(ar, ai, 1, LH[F_QXZ], LL[F_QXZ], r);
+        prod(ar, ai, 2, LH[F_QZZ], LL[F_QZZ], r);
+        prod(ar, ai, 3, LH[F_QYZ], LL[F_QYZ], r);
+    } else if constexpr (B == F_P) {
+        prod(ar, ai, 6, LH[F_V], LL[F_V], r);
+    } else if constexpr (B == F_QXX) {
+        prod(ar, ai, 1, neg4(LH[F_U]), neg4(LL[F_U]), r);
+        prod(ar, ai, 5, LH[F_V], LL[F_V], r);
+    } else if constexpr (B == F_QYY) {
+        prod(ar, ai, 4, LH[F_V], LL[F_V], r);
+        prod(ar, ai, 5, LH[F_V], LL[F_V], r);
+    } else if constexpr (B == F_QZZ) {
+        prod(ar, ai, 2, neg4(LH[F_W]), neg4(LL[F_W]), r);
+        prod(ar, ai, 5, LH[F_V], LL[F_V], r);
+    } else if constexpr (B == F_QXY) {
+        prod(ar, ai, 1, neg4(LH[F_V]), neg4(LL[F_V]), r);
+        prod(ar, ai, 4, LH[F_U], LL[F_U], r);
+    } else if constexpr (B == F_QXZ) {
+        prod(ar, ai, 1, neg4(LH[F_W]), neg4(LL[F_W]), r);
+        prod(ar, ai, 2, neg4(LH[F_U]), neg4(LL[F_U]), r);
+    } else {   // F_QYZ
+        prod(ar, ai, 2, neg4(LH[F_V]), neg4(LL[F_V]), r);
+        prod(ar, ai, 4, LH[F_W], LL[F_W], r);
     }
 }
 
-// The split products of one snapshot quad into the nine accumulators.
-__device__ __forceinline__ void rankk_bf16_step(f4 *ar, f4 *ai, const bf16x4 *L,
-                                                const bf16x4 *R)
-{
-    // left operands (planes Y1) and the negated u, v, w
-    const bf8 u_ = op3(L[F_U].hi, L[F_U].hi, L[F_U].lo);
-    const bf8 v_ = op3(L[F_V].hi, L[F_V].hi, L[F_V].lo);
-    const bf8 w_ = op3(L[F_W].hi, L[F_W].hi, L[F_W].lo);
-    const bf8 p_ = op3(L[F_P].hi, L[F_P].hi, L[F_P].lo);
-    const bf8 xx = op3(L[F_QXX].hi, L[F_QXX].hi, L[F_QXX].lo);
-    const bf8 yy = op3(L[F_QYY].hi, L[F_QYY].hi, L[F_QYY].lo);
-    const bf8 zz = op3(L[F_QZZ].hi, L[F_QZZ].hi, L[F_QZZ].lo);
-    const bf8 xy = op3(L[F_QXY].hi, L[F_QXY].hi, L[F_QXY].lo);
-    const bf8 xz = op3(L[F_QXZ].hi, L[F_QXZ].hi, L[F_QXZ].lo);
-    const bf8 yz = op3(L[F_QYZ].hi, L[F_QYZ].hi, L[F_QYZ].lo);
-    const bf8 nu_ = op3(L[F_U].hi ^ NEG2, L[F_U].hi ^ NEG2, L[F_U].lo ^ NEG2);
-    const bf8 nv_ = op3(L[F_V].hi ^ NEG2, L[F_V].hi ^ NEG2, L[F_V].lo ^ NEG2);
-    const bf8 nw_ = op3(L[F_W].hi ^ NEG2, L[F_W].hi ^ NEG2, L[F_W].lo ^ NEG2);
-    // right operands (planes Y2): real-output and imaginary-output forms
-#define GKE_B(f, re, im)                                                     \
-    const bf8 re = op3(R[f].hi, R[f].lo, R[f].hi);                           \
-    const unsigned int im##h = swapneg(R[f].hi), im##l = swapneg(R[f].lo);   \
-    const bf8 im = op3(im##h, im##l, im##h)
-    GKE_B(F_U, Ur, Ui);
-    GKE_B(F_V, Vr, Vi);
-    GKE_B(F_W, Wr, Wi);
-    GKE_B(F_P, Pr, Pi);
-    GKE_B(F_QXX, XXr, XXi);
-    GKE_B(F_QYY, YYr, YYi);
-    GKE_B(F_QZZ, ZZr, ZZi);
-    GKE_B(F_QXY, XYr, XYi);
-    GKE_B(F_QXZ, XZr, XZi);
-    GKE_B(F_QYZ, YZr, YZi);
-#undef GKE_B
-    // 31 products, ordered so that successive ones feed different accumulators
-    GKE_MFMA_BF(0, u_, Ur, Ui);
-    GKE_MFMA_BF(1, xx, Ur, Ui);
-    GKE_MFMA_BF(2, xz, Ur, Ui);
-    GKE_MFMA_BF(3, xy, Ur, Ui);
-    GKE_MFMA_BF(8, v_, Ur, Ui);
-    GKE_MFMA_BF(5, v_, XXr, XXi);
-    GKE_MFMA_BF(4, u_, XYr, XYi);
-    GKE_MFMA_BF(1, nu_, XXr, XXi);
-    GKE_MFMA_BF(2, nu_, XZr, XZi);
-    GKE_MFMA_BF(0, v_, Vr, Vi);
-    GKE_MFMA_BF(5, xx, Vr, Vi);
-    GKE_MFMA_BF(1, xy, Vr, Vi);
-    GKE_MFMA_BF(2, yz, Vr, Vi);
-    GKE_MFMA_BF(3, yy, Vr, Vi);
-    GKE_MFMA_BF(6, p_, Vr, Vi);
-    GKE_MFMA_BF(7, u_, Vr, Vi);
-    GKE_MFMA_BF(5, yy, Vr, Vi);
-    GKE_MFMA_BF(4, v_, YYr, YYi);
-    GKE_MFMA_BF(1, nv_, XYr, XYi);
-    GKE_MFMA_BF(2, nv_, YZr, YZi);
-    GKE_MFMA_BF(6, v_, Pr, Pi);
-    GKE_MFMA_BF(5, v_, YYr, YYi);
-    GKE_MFMA_BF(0, w_, Wr, Wi);
-    GKE_MFMA_BF(1, xz, Wr, Wi);
-    GKE_MFMA_BF(2, zz, Wr, Wi);
-    GKE_MFMA_BF(3, yz, Wr, Wi);
-    GKE_MFMA_BF(5, zz, Vr, Vi);
-    GKE_MFMA_BF(4, w_, YZr, YZi);
-    GKE_MFMA_BF(1, nw_, XZr, XZi);
-    GKE_MFMA_BF(2, nw_, ZZr, ZZi);
-    GKE_MFMA_BF(5, v_, ZZr, ZZi);
-}
-
-// The products of one snapshot quad; ok = false (a snapshot past the end)
-// zeroes the left operand, which folds into the copies that build the MFMA
-// operands.
-__device__ __forceinline__ void quad_products(f4 *ar, f4 *ai, const bf16x4 *Lq, const bf16x4 *R,
-                                              bool ok)
-{
-    bf16x4 L[NFIELD];
-#pragma unroll
-    for (int f = 0; f < NFIELD; ++f) {
-        L[f].hi = ok ? Lq[f].hi : 0u;
-        L[f].lo = ok ? Lq[f].lo : 0u;
-    }
-    rankk_bf16_step(ar, ai, L, R);
-}
-
-// Register buffers of snapshot quads: quad q is read from buffer q mod NB,
-// which is refilled with quad q + NB right after its last use, so every load
-// has NB - 1 quads of products to arrive in.  (A rotating prefetch queue would
-// copy the newest buffer down each quad, and a copy waits for its loads.)
-#ifndef GKE_RANKK16_NB
-#define GKE_RANKK16_NB 3
-#endif
 #ifndef GKE_RANKK16_MINW
 #define GKE_RANKK16_MINW 2
 #endif
 
+// One wave per (wavenumber, tile pair); groups of 16 snapshots (four quads,
+// one per lane group).  A quad past the end reloads the last one and its left
+// operands are zeroed (the records of a partial last quad hold zeros in the
+// missing snapshots, written by the z pass).
 __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
-    const bf16x4 *__restrict__ spec, Dims d, const int *__restrict__ tile_a,
+    const SplitRec *__restrict__ spec, Dims d, const int *__restrict__ tile_a,
     const int *__restrict__ tile_b, const int *__restrict__ t_rowplane, int nsnap,
     int accumulate, int total, cx<double> *__restrict__ acc)
 {
@@ -172,12 +143,14 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
 
     const int lane = threadIdx.x;
     const int row = lane & 15, g = lane >> 4;
-    const size_t fstride = (size_t)d.chunk * d.nys;
-    const char *kb = reinterpret_cast<const char *>(spec + (size_t)k * NFIELD * fstride);
-    const size_t fbytes = fstride * sizeof(bf16x4);
-    const unsigned sbytes = (unsigned)d.nys * sizeof(bf16x4);
-    const unsigned loff = (unsigned)t_rowplane[ta * 16 + row] * sizeof(bf16x4);
-    const unsigned roff = (unsigned)(tb * 16 + row) * sizeof(bf16x4);
+    const int nq = (nsnap + 3) >> 2;
+    // records of this wavenumber: ((f nqs + q) nys + plane); the field and
+    // quad parts are wave-uniform, the plane and lane-group parts a lane offset
+    const char *kb = reinterpret_cast<const char *>(spec_base(spec, d, k));
+    const size_t fbytes = (size_t)d.nqs * d.nys * sizeof(SplitRec);
+    const unsigned qbytes = (unsigned)d.nys * sizeof(SplitRec);
+    const unsigned loff = (unsigned)t_rowplane[ta * 16 + row] * sizeof(SplitRec);
+    const unsigned roff = (unsigned)(tb * 16 + row) * sizeof(SplitRec);
 
     f4 ar[9], ai[9];
 #pragma unroll
@@ -186,29 +159,52 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
         ai[c] = f4{0.f, 0.f, 0.f, 0.f};
     }
 
-    constexpr int NB = GKE_RANKK16_NB;
-    const int nq = (nsnap + 3) >> 2;
-    bf16x4 Lb[NB][NFIELD], Rb[NB][NFIELD];
+    for (int q0 = 0; q0 < nq; q0 += 4) {
+        const bool ok = q0 + g < nq;
+        const unsigned so = (unsigned)(ok ? g : nq - 1 - q0) * qbytes;
+        const char *base = kb + (size_t)q0 * qbytes;
+        // the right fields go through three register pairs, each loaded two
+        // groups before its products, so that the left records (all ten
+        // fields) and three right fields are live at once
+        auto ldr = [&](int f, u4 &h, u4 &l) {
+            const u4 *rr = reinterpret_cast<const u4 *>(base + f * fbytes + roff + so);
+            h = rr[0];
+            l = rr[1];
+        };
+        u4 h0, l0, h1, l1, h2, l2;
+        ldr(F_U, h0, l0);
+        ldr(F_V, h1, l1);
+        u4 LH[NFIELD], LL[NFIELD];
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
-        load_raw(Lb[i], Rb[i], kb, fbytes, loff, roff, sbytes, 4 * min(i, nq - 1), g, nsnap);
-    // full groups of NB quads, without branches (a branch around a quad would
-    // make the wait before it cover every load in flight)
-    int q0 = 0;
-    for (; q0 + NB <= nq; q0 += NB) {
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            quad_products(ar, ai, Lb[i], Rb[i], 4 * (q0 + i) + g < nsnap);
-            // the refill is issued after the last read of the buffer
-            __builtin_amdgcn_sched_barrier(0);
-            load_raw(Lb[i], Rb[i], kb, fbytes, loff, roff, sbytes, 4 * min(q0 + i + NB, nq - 1), g,
-                     nsnap);
+        for (int f = 0; f < NFIELD; ++f) {
+            const u4 *lr = reinterpret_cast<const u4 *>(base + f * fbytes + loff + so);
+            LH[f] = lr[0];
+            LL[f] = lr[1];
         }
-    }
-    // the last nq - q0 < NB quads are in buffers 0, 1, ...
+        if (!ok) {
 #pragma unroll
-    for (int i = 0; i + 1 < NB; ++i)
-        if (q0 + i < nq) quad_products(ar, ai, Lb[i], Rb[i], 4 * (q0 + i) + g < nsnap);
+            for (int f = 0; f < NFIELD; ++f) {
+                LH[f] = u4{0u, 0u, 0u, 0u};
+                LL[f] = u4{0u, 0u, 0u, 0u};
+            }
+        }
+#define GKE_GROUP(NEXT, HN, LN, CUR, HC, LC)                 \
+        ldr(NEXT, HN, LN);                                   \
+        group_products<CUR>(ar, ai, LH, LL, HC, LC);         \
+        __builtin_amdgcn_sched_barrier(0)
+        GKE_GROUP(F_W, h2, l2, F_U, h0, l0);
+        GKE_GROUP(F_P, h0, l0, F_V, h1, l1);
+        GKE_GROUP(F_QXX, h1, l1, F_W, h2, l2);
+        GKE_GROUP(F_QYY, h2, l2, F_P, h0, l0);
+        GKE_GROUP(F_QZZ, h0, l0, F_QXX, h1, l1);
+        GKE_GROUP(F_QXY, h1, l1, F_QYY, h2, l2);
+        GKE_GROUP(F_QXZ, h2, l2, F_QZZ, h0, l0);
+        GKE_GROUP(F_QYZ, h0, l0, F_QXY, h1, l1);
+#undef GKE_GROUP
+        group_products<F_QXZ>(ar, ai, LH, LL, h2, l2);
+        group_products<F_QYZ>(ar, ai, LH, LL, h0, l0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
 
     const size_t sp_stride = (size_t)d.nk * d.pstr;
 #pragma unroll
@@ -227,7 +223,7 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
 }
 
 hipError_t launch_rankk_bf16x3(hipStream_t st, const Dims &d, const Tables &t,
-                               const bf16x4 *spec, int nsnap, int accumulate, cx<double> *acc)
+                               const SplitRec *spec, int nsnap, int accumulate, cx<double> *acc)
 {
     if (d.ntp > 0) {
         const long long total = (long long)d.nk * d.ntp;
@@ -240,7 +236,7 @@ hipError_t launch_rankk_bf16x3(hipStream_t st, const Dims &d, const Tables &t,
 }
 
 hipError_t launch_rankk_rem_bf16x3(hipStream_t st, const Dims &d, const Tables &t,
-                                   const bf16x4 *spec, int nsnap, int accumulate,
+                                   const SplitRec *spec, int nsnap, int accumulate,
                                    cx<double> *acc)
 {
     return launch_rankk_rem(st, d, t, spec, nsnap, accumulate, acc);

@@ -67,11 +67,12 @@ __device__ __forceinline__ double wave_sum8(const double (&v)[8])
 
 template <typename T>
 __device__ __forceinline__ void store_spec(cx<double> *spec, size_t i, cx<T> X) { spec[i] = cx<double>{X.x, X.y}; }
-template <typename T>
-__device__ __forceinline__ void store_spec(bf16x4 *spec, size_t i, cx<T> X)
+// the split dwords of one value: hi = (re_hi, im_hi), lo = (re_lo, im_lo)
+__device__ __forceinline__ void split_value(float re, float im, unsigned int &hi, unsigned int &lo)
 {
-    const unsigned int r = split_bf16((float)X.x), m = split_bf16((float)X.y);
-    spec[i] = bf16x4{(r & 0xffffu) | (m << 16), (r >> 16) | (m & 0xffff0000u)};
+    const unsigned int r = split_bf16(re), m = split_bf16(im);
+    hi = (r & 0xffffu) | (m << 16);
+    lo = (r >> 16) | (m & 0xffff0000u);
 }
 
 // One block = zb consecutive z rows of plane j.  One pass over the inputs:
@@ -343,11 +344,97 @@ hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t, cons
 {
     // (a persistent form with a register prefetch of the next item measured
     // slower on both paths)
-    const bool sp = d.prec == PREC_BF16X3, small = d.zpblk == SMALL_BLOCK;
-    if (sp && small) launch_zp<float, bf16x4, SMALL_BLOCK>(st, d, t, inter, slot, spec);
-    else if (sp) launch_zp<float, bf16x4, FFT_BLOCK>(st, d, t, inter, slot, spec);
-    else if (small) launch_zp<double, cx<double>, SMALL_BLOCK>(st, d, t, inter, slot, spec);
+    if (d.prec == PREC_BF16X3) return hipErrorInvalidValue;   // records: launch_zfft_rec
+    if (d.zpblk == SMALL_BLOCK) launch_zp<double, cx<double>, SMALL_BLOCK>(st, d, t, inter, slot, spec);
     else launch_zp<double, cx<double>, FFT_BLOCK>(st, d, t, inter, slot, spec);
+    return hipGetLastError();
+}
+
+// Split path: one block = jb planes of one field at one kx for the ng <= 4
+// snapshots of quad q, whose x-transformed rows sit in ng buffers of
+// `istride` elements: the z transforms of all of them in one batch (FP32),
+// then one 32-byte record per (kz, plane), the missing snapshots of a partial
+// quad as zeros.  Work items in the order of k_zfft_pack_blk.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_zfft_rec(const cx<float> *__restrict__ inter,
+                                                    size_t istride, Dims d, Tables t, int q,
+                                                    int ng, SplitRec *__restrict__ spec)
+{
+    constexpr int CAP = cap_of<BLOCK>();
+    extern __shared__ unsigned char lds_raw[];
+    cx<float> *lds = reinterpret_cast<cx<float> *>(lds_raw);
+    const int nx = d.nx, ny = d.ny, nz = d.nz, nkx = d.nkx, jb = d.jb;
+    const int nitem = (int)gridDim.x, q8 = nitem >> 3, r8 = nitem & 7, xcd = blockIdx.x & 7;
+    const int item = xcd * q8 + min(xcd, r8) + (int)(blockIdx.x >> 3);
+    const int jblk = item % d.njb, kx = (item / d.njb) % nkx, f = item / (d.njb * nkx);
+    const int j0 = jblk * jb;
+    const int nb = min(jb, ny - j0);
+    const int ngb = ng * nb;               // transforms of this block
+    const int bs = fft_stride(nz);
+    const int zg = d.zg, lzg = __builtin_ctz(zg), zm = zg - 1;
+    cx<float> *tw = lds + 4 * jb * bs;
+    const int szg = NFIELD * nkx * zg, sb = d.nzg * szg;
+    const cx<float> *ib = inter + (size_t)j0 * sb + ((size_t)f * nkx + kx) * zg;
+    {
+        // ngb * nz <= CAP: every load of this thread is in flight at once;
+        // unconditional loads and stores at clamped indices, as in
+        // k_zfft_pack_blk.  Element e = (g nb + b) nz + z.
+        constexpr int MAXE = (CAP + BLOCK - 1) / BLOCK;
+        cx<float> x[MAXE];
+        Walk2 w(threadIdx.x, BLOCK, nz);   // (g nb + b, z)
+#pragma unroll
+        for (int i = 0; i < MAXE; ++i) {
+            const bool ok = w.hi < ngb;
+            const int gb = ok ? w.hi : ngb - 1, z = ok ? w.lo : 0;
+            const int g = gb / nb, b = gb - g * nb;
+            x[i] = ib[g * istride + (size_t)b * sb + (z >> lzg) * szg + (z & zm)];
+            w.next();
+        }
+        TwiddleCopy<float, BLOCK> twc;   // in flight with the gathers
+        twc.load(tw_of<float>(t, 1), nz);
+        twc.store(tw, tw_of<float>(t, 1), nz);
+        w = Walk2(threadIdx.x, BLOCK, nz);
+#pragma unroll
+        for (int i = 0; i < MAXE; ++i) {
+            const bool ok = w.hi < ngb;
+            lds[(ok ? w.hi : ngb - 1) * bs + fft_pad(ok ? w.lo : 0)] = x[i];
+            w.next();
+        }
+    }
+    __syncthreads();
+    lds_fft_ip<float, CAP, BLOCK>(lds, ngb, bs, t.pz, tw, -1);
+    const double scale = 1.0 / ((double)nx * (double)nz);
+    // record (k = kx nz + kz, f, q, j0 + b): ((k NFIELD + f) nqs + q) nys + j0 + b
+    const size_t rkz = (size_t)NFIELD * d.nqs * d.nys;
+    SplitRec *sp = spec + (size_t)kx * nz * rkz + ((size_t)f * d.nqs + q) * d.nys + j0;
+    Walk2 ws(threadIdx.x, BLOCK, nb);   // (kz, b)
+    for (int e = threadIdx.x; e < nz * nb; e += BLOCK) {
+        const int kz = ws.hi, b = ws.lo;
+        ws.next();
+        unsigned int h[4] = {0u, 0u, 0u, 0u}, l[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            if (g < ng) {
+                const cx<float> Y = lds[(g * nb + b) * bs + fft_pad(kz)];
+                split_value((float)((double)Y.x * scale), (float)((double)Y.y * scale), h[g], l[g]);
+            }
+        }
+        SplitRec *r = sp + (size_t)kz * rkz + b;
+        *reinterpret_cast<uint4 *>(r->h) = make_uint4(h[0], h[1], h[2], h[3]);
+        *reinterpret_cast<uint4 *>(r->l) = make_uint4(l[0], l[1], l[2], l[3]);
+    }
+}
+
+hipError_t launch_zfft_rec(hipStream_t st, const Dims &d, const Tables &t, const void *inter,
+                           size_t inter_stride, int q, int ng, SplitRec *spec)
+{
+    if (d.prec != PREC_BF16X3 || ng < 1 || ng > 4 || q < 0 || q >= d.nqs)
+        return hipErrorInvalidValue;
+    const int nitems = d.njb * d.nkx * NFIELD;
+    const size_t lds = sizeof(cx<float>) * (4 * (size_t)d.jb * fft_stride(d.nz) + d.nz);
+    set_lds_limit(k_zfft_rec<FFT_BLOCK>);
+    hipLaunchKernelGGL(k_zfft_rec<FFT_BLOCK>, dim3(nitems), dim3(FFT_BLOCK), lds, st,
+                       (const cx<float> *)inter, inter_stride, d, t, q, ng, spec);
     return hipGetLastError();
 }
 

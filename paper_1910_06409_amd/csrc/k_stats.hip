@@ -220,30 +220,20 @@ hipError_t launch_profiles(hipStream_t st, const Dims &d, const Tables &t, const
 // the rows of one slab): for every wavenumber k, plane Y and offset a = 0..4,
 //   band[k][a][Y] (+)= sum over the chunk of sum_i Re conj(u_i^(k;Y)) u_i^(k;Y+a),
 // the same scale-energy products k_r0 reads from the full accumulators.
-__device__ __forceinline__ cx<double> band_value(const cx<double> *s, size_t i) { return s[i]; }
-__device__ __forceinline__ cx<double> band_value(const bf16x4 *s, size_t i)
-{
-    const bf16x4 v = s[i];
-    return cx<double>{(double)__uint_as_float(v.hi << 16) + (double)__uint_as_float(v.lo << 16),
-                      (double)__uint_as_float(v.hi & 0xffff0000u) +
-                          (double)__uint_as_float(v.lo & 0xffff0000u)};
-}
-
 template <typename S>
 __global__ __launch_bounds__(256) void k_band(const S *__restrict__ spec, Dims d, int nsnap,
                                               int accumulate, double *__restrict__ band)
 {
     const int k = blockIdx.x, ny = d.ny;
-    const size_t fstride = (size_t)d.chunk * d.nys;
-    const S *kb = spec + (size_t)k * NFIELD * fstride;
+    const S *kb = spec_base(spec, d, k);
     for (int e = threadIdx.x; e < 5 * ny; e += blockDim.x) {
         const int a = e / ny, j = e - a * ny;
         double s = 0.0;
         if (j + a < ny) {
             for (int sl = 0; sl < nsnap; ++sl)
                 for (int f = F_U; f <= F_W; ++f) {
-                    const size_t o = f * fstride + (size_t)sl * d.nys + j;
-                    const cx<double> x = band_value(kb, o), y = band_value(kb, o + a);
+                    const cx<double> x = value_of(raw_at(kb, d, f, sl, j));
+                    const cx<double> y = value_of(raw_at(kb, d, f, sl, j + a));
                     s += x.x * y.x + x.y * y.y;
                 }
         }
@@ -256,8 +246,8 @@ hipError_t launch_band(hipStream_t st, const Dims &d, const void *spec, int nsna
                        int accumulate, double *band)
 {
     if (d.prec == PREC_BF16X3)
-        hipLaunchKernelGGL(k_band<bf16x4>, dim3(d.nk), dim3(256), 0, st, (const bf16x4 *)spec, d,
-                           nsnap, accumulate, band);
+        hipLaunchKernelGGL(k_band<SplitRec>, dim3(d.nk), dim3(256), 0, st, (const SplitRec *)spec,
+                           d, nsnap, accumulate, band);
     else
         hipLaunchKernelGGL(k_band<cx<double>>, dim3(d.nk), dim3(256), 0, st,
                            (const cx<double> *)spec, d, nsnap, accumulate, band);

@@ -57,13 +57,36 @@ __device__ __forceinline__ void store_spectra(cx<double> *acc, size_t sp_stride,
 // Pairs that involve the last Ny mod 16 planes: one thread per (k, pair), FP64
 // vector arithmetic on the stored values (for split spectra: hi + lo).
 // pairs[i] = j1 | j2 << 12 for compact index P = npair_tiles + i.
-__device__ __forceinline__ cx<double> spec_value(const cx<double> *s, size_t i) { return s[i]; }
-__device__ __forceinline__ cx<double> spec_value(const bf16x4 *s, size_t i)
+
+// The 27 products conj(A) B of one pair and snapshot into the nine channels
+// (A: plane Y1, B: plane Y2, fields in the order of the spectra), formed in
+// type V and summed in FP64.
+template <typename V>
+__device__ __forceinline__ void rem_macs(double *cr, double *ci, const cx<V> *A, const cx<V> *B)
 {
-    const bf16x4 v = s[i];
-    const double rh = __uint_as_float(v.hi << 16), rl = __uint_as_float(v.lo << 16);
-    const double ih = __uint_as_float(v.hi & 0xffff0000u), il = __uint_as_float(v.lo & 0xffff0000u);
-    return cx<double>{rh + rl, ih + il};
+    const V fifth = V(0.2);
+    const cx<V> qa = cx<V>{fifth * (A[F_QXX].x + A[F_QYY].x + A[F_QZZ].x),
+                           fifth * (A[F_QXX].y + A[F_QYY].y + A[F_QZZ].y)};
+    const cx<V> qb = cx<V>{fifth * (B[F_QXX].x + B[F_QYY].x + B[F_QZZ].x),
+                           fifth * (B[F_QXX].y + B[F_QYY].y + B[F_QZZ].y)};
+    // conj(a) b accumulated into channel c with sign sg
+    auto mac = [&](int c, cx<V> a, cx<V> b, double sg) {
+        cr[c] += sg * (double)(a.x * b.x + a.y * b.y);
+        ci[c] += sg * (double)(a.x * b.y - a.y * b.x);
+    };
+    const cx<V> ua = A[F_U], va = A[F_V], wa = A[F_W], pa = A[F_P];
+    const cx<V> ub = B[F_U], vb = B[F_V], wb = B[F_W], pb = B[F_P];
+    mac(0, ua, ub, 1.0); mac(0, va, vb, 1.0); mac(0, wa, wb, 1.0);
+    mac(1, A[F_QXX], ub, 1.0); mac(1, A[F_QXY], vb, 1.0); mac(1, A[F_QXZ], wb, 1.0);
+    mac(1, ua, B[F_QXX], -1.0); mac(1, va, B[F_QXY], -1.0); mac(1, wa, B[F_QXZ], -1.0);
+    mac(2, A[F_QXZ], ub, 1.0); mac(2, A[F_QYZ], vb, 1.0); mac(2, A[F_QZZ], wb, 1.0);
+    mac(2, ua, B[F_QXZ], -1.0); mac(2, va, B[F_QYZ], -1.0); mac(2, wa, B[F_QZZ], -1.0);
+    mac(3, A[F_QXY], ub, 1.0); mac(3, A[F_QYY], vb, 1.0); mac(3, A[F_QYZ], wb, 1.0);
+    mac(4, ua, B[F_QXY], 1.0); mac(4, va, B[F_QYY], 1.0); mac(4, wa, B[F_QYZ], 1.0);
+    mac(5, va, qb, 1.0); mac(5, qa, vb, 1.0);
+    mac(6, pa, vb, 1.0); mac(6, va, pb, 1.0);
+    mac(7, ua, vb, 1.0);
+    mac(8, va, ub, 1.0);
 }
 
 // One thread per (k, pair).  FLAT: threads packed across wavenumbers with the
@@ -90,50 +113,67 @@ __global__ __launch_bounds__(64, 2) void k_rankk_rem(const S *__restrict__ spec,
     }
     const int code = pairs[d.npair_tiles + i];
     const int j1 = pair_j1(code), j2 = pair_j2(code);
-    const int fstride = d.chunk * d.nys;   // offsets within one wavenumber stay below 2^31
-    const S *kb = spec + (size_t)k * NFIELD * fstride;
+    const S *kb = spec_base(spec, d, k);
     double cr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ci[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    S An[NFIELD], Bn[NFIELD];
+    if constexpr (sizeof(S) == sizeof(SplitRec)) {
+        // one snapshot quad per step: 16-byte loads of both planes' records
+        // (the h and l halves of a wave's records cover whole lines), then the
+        // four snapshots with hi + lo as FP32 (exact: two 8-bit significands
+        // 2^-8 apart) and FP32 products (error 2^-24, far below the split
+        // form's 2^-16), summed in FP64
+        const int nq = (nsnap + 3) >> 2;
+        for (int q = 0; q < nq; ++q) {
+            typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+            u4v ah[NFIELD], al[NFIELD], bh[NFIELD], bl[NFIELD];
 #pragma unroll
-    for (int f = 0; f < NFIELD; ++f) {
-        An[f] = kb[f * fstride + j1];
-        Bn[f] = kb[f * fstride + j2];
-    }
-    for (int s = 0; s < nsnap; ++s) {
-        cx<double> A[NFIELD], B[NFIELD];
+            for (int f = 0; f < NFIELD; ++f) {
+                const int rq = (f * d.nqs + q) * d.nys;
+                const SplitRec *ra = kb + rq + j1, *rb = kb + rq + j2;
+                ah[f] = *reinterpret_cast<const u4v *>(ra->h);
+                al[f] = *reinterpret_cast<const u4v *>(ra->l);
+                bh[f] = *reinterpret_cast<const u4v *>(rb->h);
+                bl[f] = *reinterpret_cast<const u4v *>(rb->l);
+            }
+            auto val = [](unsigned int h, unsigned int l) {
+                return cx<float>{__uint_as_float(h << 16) + __uint_as_float(l << 16),
+                                 __uint_as_float(h & 0xffff0000u) + __uint_as_float(l & 0xffff0000u)};
+            };
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (4 * q + t < nsnap) {
+                    cx<float> A[NFIELD], B[NFIELD];
+#pragma unroll
+                    for (int f = 0; f < NFIELD; ++f) {
+                        A[f] = val(ah[f][t], al[f][t]);
+                        B[f] = val(bh[f][t], bl[f][t]);
+                    }
+                    rem_macs(cr, ci, A, B);
+                }
+            }
+        }
+    } else {
+        typedef typename RawOf<S>::type Raw;
+        Raw An[NFIELD], Bn[NFIELD];
 #pragma unroll
         for (int f = 0; f < NFIELD; ++f) {
-            A[f] = spec_value(An, f);
-            B[f] = spec_value(Bn, f);
+            An[f] = raw_at(kb, d, f, 0, j1);
+            Bn[f] = raw_at(kb, d, f, 0, j2);
         }
-        const int sn = (s + 1 < nsnap ? s + 1 : s) * d.nys;
+        for (int s = 0; s < nsnap; ++s) {
+            cx<double> A[NFIELD], B[NFIELD];
 #pragma unroll
-        for (int f = 0; f < NFIELD; ++f) {
-            An[f] = kb[f * fstride + sn + j1];
-            Bn[f] = kb[f * fstride + sn + j2];
+            for (int f = 0; f < NFIELD; ++f) {
+                A[f] = value_of(An[f]);
+                B[f] = value_of(Bn[f]);
+            }
+            const int sn = s + 1 < nsnap ? s + 1 : s;
+#pragma unroll
+            for (int f = 0; f < NFIELD; ++f) {
+                An[f] = raw_at(kb, d, f, sn, j1);
+                Bn[f] = raw_at(kb, d, f, sn, j2);
+            }
+            rem_macs(cr, ci, A, B);
         }
-        const cx<double> qa = cx<double>{0.2 * (A[F_QXX].x + A[F_QYY].x + A[F_QZZ].x),
-                                         0.2 * (A[F_QXX].y + A[F_QYY].y + A[F_QZZ].y)};
-        const cx<double> qb = cx<double>{0.2 * (B[F_QXX].x + B[F_QYY].x + B[F_QZZ].x),
-                                         0.2 * (B[F_QXX].y + B[F_QYY].y + B[F_QZZ].y)};
-        // conj(a) b accumulated into channel c with sign sg
-        auto mac = [&](int c, cx<double> a, cx<double> b, double sg) {
-            cr[c] += sg * (a.x * b.x + a.y * b.y);
-            ci[c] += sg * (a.x * b.y - a.y * b.x);
-        };
-        const cx<double> ua = A[F_U], va = A[F_V], wa = A[F_W], pa = A[F_P];
-        const cx<double> ub = B[F_U], vb = B[F_V], wb = B[F_W], pb = B[F_P];
-        mac(0, ua, ub, 1.0); mac(0, va, vb, 1.0); mac(0, wa, wb, 1.0);
-        mac(1, A[F_QXX], ub, 1.0); mac(1, A[F_QXY], vb, 1.0); mac(1, A[F_QXZ], wb, 1.0);
-        mac(1, ua, B[F_QXX], -1.0); mac(1, va, B[F_QXY], -1.0); mac(1, wa, B[F_QXZ], -1.0);
-        mac(2, A[F_QXZ], ub, 1.0); mac(2, A[F_QYZ], vb, 1.0); mac(2, A[F_QZZ], wb, 1.0);
-        mac(2, ua, B[F_QXZ], -1.0); mac(2, va, B[F_QYZ], -1.0); mac(2, wa, B[F_QZZ], -1.0);
-        mac(3, A[F_QXY], ub, 1.0); mac(3, A[F_QYY], vb, 1.0); mac(3, A[F_QYZ], wb, 1.0);
-        mac(4, ua, B[F_QXY], 1.0); mac(4, va, B[F_QYY], 1.0); mac(4, wa, B[F_QYZ], 1.0);
-        mac(5, va, qb, 1.0); mac(5, qa, vb, 1.0);
-        mac(6, pa, vb, 1.0); mac(6, va, pb, 1.0);
-        mac(7, ua, vb, 1.0);
-        mac(8, va, ub, 1.0);
     }
     store_spectra(acc, (size_t)d.nk * d.pstr, (size_t)k * d.pstr + d.npair_tiles + i, cr, ci,
                   accumulate);
@@ -145,7 +185,7 @@ hipError_t launch_rankk_rem(hipStream_t st, const Dims &d, const Tables &t, cons
 {
     const int nrem = d.npair - d.npair_tiles;
     if (nrem <= 0) return hipSuccess;
-    constexpr bool flat = sizeof(S) == sizeof(bf16x4);
+    constexpr bool flat = sizeof(S) == sizeof(SplitRec);
     if (flat) {
         const long long nthr = (long long)nrem * d.nk;
         if (nthr >= (1LL << 37)) return hipErrorInvalidValue;

@@ -33,7 +33,7 @@ CSRC = os.path.join(HERE, "csrc")
 KERNELS = {
     "plane_sums": ({"fp64": "k_plane_sums", "bf16x3": "k_plane_sums"}, ["k_stats.hip"]),
     "fluct_xfft": ({"fp64": "k_fluct_xfft", "bf16x3": "k_fluct_xfft"}, ["k_spectra.hip"]),
-    "zfft_pack": ({"fp64": "k_zfft_pack_blk", "bf16x3": "k_zfft_pack_blk"}, ["k_spectra.hip"]),
+    "zfft_pack": ({"fp64": "k_zfft_pack_blk", "bf16x3": "k_zfft_rec"}, ["k_spectra.hip"]),
     "rankk": ({"fp64": "k_rankk_f64", "bf16x3": "k_rankk_bf16x3"},
               ["k_rankk.hip", "k_rankk_bf16.hip", "rankk_common.h"]),
     "rankk_rem": ({"fp64": "k_rankk_rem", "bf16x3": "k_rankk_rem"},
