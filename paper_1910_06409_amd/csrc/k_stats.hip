@@ -230,12 +230,33 @@ __global__ __launch_bounds__(256) void k_band(const S *__restrict__ spec, Dims d
         const int a = e / ny, j = e - a * ny;
         double s = 0.0;
         if (j + a < ny) {
-            for (int sl = 0; sl < nsnap; ++sl)
-                for (int f = F_U; f <= F_W; ++f) {
-                    const cx<double> x = value_of(raw_at(kb, d, f, sl, j));
-                    const cx<double> y = value_of(raw_at(kb, d, f, sl, j + a));
-                    s += x.x * y.x + x.y * y.y;
-                }
+            if constexpr (sizeof(S) == sizeof(SplitRec)) {
+                // whole records (four snapshots) per 16-byte load pair
+                typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+                for (int q = 0; q < (nsnap + 3) >> 2; ++q)
+                    for (int f = F_U; f <= F_W; ++f) {
+                        const SplitRec *rx = kb + (f * d.nqs + q) * d.nys + j, *ry = rx + a;
+                        const u4v xh = *reinterpret_cast<const u4v *>(rx->h);
+                        const u4v xl = *reinterpret_cast<const u4v *>(rx->l);
+                        const u4v yh = *reinterpret_cast<const u4v *>(ry->h);
+                        const u4v yl = *reinterpret_cast<const u4v *>(ry->l);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            if (4 * q + t < nsnap) {
+                                const cx<double> x = value_of(bf16x4{xh[t], xl[t]});
+                                const cx<double> y = value_of(bf16x4{yh[t], yl[t]});
+                                s += x.x * y.x + x.y * y.y;
+                            }
+                        }
+                    }
+            } else {
+                for (int sl = 0; sl < nsnap; ++sl)
+                    for (int f = F_U; f <= F_W; ++f) {
+                        const cx<double> x = value_of(raw_at(kb, d, f, sl, j));
+                        const cx<double> y = value_of(raw_at(kb, d, f, sl, j + a));
+                        s += x.x * y.x + x.y * y.y;
+                    }
+            }
         }
         double *dst = band + (size_t)k * 5 * ny + e;
         *dst = accumulate ? *dst + s : s;
