@@ -296,7 +296,8 @@ void set_zpass_shape(gke::Dims &d)
     d.njb = (d.ny + jmax - 1) / jmax;
     d.jb = (d.ny + d.njb - 1) / d.njb;
     d.nqs = (d.chunk + 3) / 4;
-    // spectra rows: 16 planes of 8-byte split values or 8 of FP64 complex per line
+    // plane slots per snapshot row (FP64: 8 planes of 16 bytes per line) or per
+    // record row (split: 32-byte records, a 16-plane tile on four whole lines)
     d.nys = d.prec == gke::PREC_BF16X3 ? (d.ny + 15) & ~15 : round8(d.ny);
 }
 
