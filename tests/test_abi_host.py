@@ -141,3 +141,34 @@ def test_workspace_scales_with_grid():
         assert n < 200 * 2 ** 30
     finally:
         gke.gke_destroy(p)
+
+
+def test_split_records_and_long_nz():
+    """Split path: the spectra take 32-byte records of four snapshots (a chunk
+    rounded up to whole quads, plane slots rounded up to 16), and a z length
+    whose four-snapshot transform batch exceeds one block is refused."""
+    from paper_1910_06409_amd import synth
+    w = synth.workload("re200")
+    p = gke.gke_plan(w.nx, w.ny, w.nz, synth.y_grid(w), w.lx, w.lz, w.nu)
+    try:
+        gke.gke_set_option(p, gke.GKE_OPT_PRECISION, gke.GKE_PREC_BF16X3)
+        gke.gke_set_option(p, gke.GKE_OPT_CHUNK, 26)
+        n26 = gke.gke_workspace_size(p)
+        gke.gke_set_option(p, gke.GKE_OPT_CHUNK, 28)
+        n28 = gke.gke_workspace_size(p)
+        assert n26 == n28                      # 26 and 28 snapshots: seven quads
+        gke.gke_set_option(p, gke.GKE_OPT_CHUNK, 32)
+        n32 = gke.gke_workspace_size(p)
+        assert n32 - n28 == w.nk * 10 * 144 * 32   # one more quad of records
+    finally:
+        gke.gke_destroy(p)
+    y = np.linspace(-1, 1, 17)
+    p = gke.gke_plan(16, 17, 1000, y, 2 * np.pi, np.pi, 0.005)
+    try:
+        assert gke.gke_workspace_size(p) > 0   # FP64: one transform per block
+        gke.gke_set_option(p, gke.GKE_OPT_PRECISION, gke.GKE_PREC_BF16X3)
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_workspace_size(p)
+        assert e.value.status == gke.GKE_ERR_UNSUPPORTED
+    finally:
+        gke.gke_destroy(p)
