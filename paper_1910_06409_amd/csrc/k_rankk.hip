@@ -68,8 +68,10 @@ struct Loader {
     unsigned loff, roff, sbytes;
     __device__ __forceinline__ cx<double> get(int f, unsigned off, int s0, unsigned so) const
     {
-        return *reinterpret_cast<const cx<double> *>(kb + (size_t)s0 * sbytes + f * fbytes +
-                                                     off + so);
+        // the 32-bit lane offset is formed first, so that the load takes the
+        // uniform base from scalar registers
+        const char *base = kb + (size_t)s0 * sbytes + f * fbytes;
+        return *reinterpret_cast<const cx<double> *>(base + (off + so));
     }
 };
 
