@@ -7,7 +7,11 @@ Two summaries are kept as short text files next to the code they describe:
 * HBM traffic of one kernel from two counter runs (``--pmc FETCH_SIZE`` and
   ``--pmc WRITE_SIZE``, KiB per dispatch), each scaled by what the same
   counter reads for a plain device-to-device copy of known size issued in the
-  same process (``bench.py --calibrate-copy``).
+  same process (``bench.py --calibrate-copy``);
+* matrix-core use of a rank-k kernel from one run of shader-sequencer
+  counters: the cycles the MFMA pipes were busy, summed over the chip, over
+  (SIMDs x the kernel's GPU-active cycles per XCD), and the clock those
+  active cycles imply over the dispatch's own time stamps.
 
 A traffic summary records a hash of the kernel's sources and build flags;
 ``traffic_if_current`` returns its figure only while they are unchanged.
@@ -16,6 +20,8 @@ Command line (paths are the rocprofv3 CSV files):
   python -m paper_1910_06409_amd.profiling stats STATS_CSV --command "..." > out.txt
   python -m paper_1910_06409_amd.profiling traffic FETCH_CSV WRITE_CSV --family rankk \
       --precision fp64 --copy-bytes N --command-fetch "..." --command-write "..." > out.txt
+  python -m paper_1910_06409_amd.profiling mfma COUNTER_CSV AGENT_CSV --precision fp64 \
+      --workload "..." --command "..." > out.txt
 """
 from __future__ import annotations
 
@@ -143,6 +149,62 @@ def traffic_summary(fetch_csv: str, write_csv: str, family: str, precision: str,
     return "\n".join(lines) + "\n"
 
 
+MFMA_COUNTERS = ["SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ_WAVES", "SQ_WAVE_CYCLES",
+                 "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY",
+                 "SQ_ACTIVE_INST_VALU"]
+
+
+def gpu_agent(agent_csv: str) -> tuple[int, int]:
+    """(SIMDs, XCDs) of the profiled GPU."""
+    for r in read_csv(agent_csv):
+        if r["Agent_Type"] == "GPU":
+            return int(r["Simd_Count"]), int(r["Num_Xcc"])
+    raise ValueError("no GPU agent")
+
+
+def mfma_summary(counter_csv: str, agent_csv: str, precision: str, workload: str,
+                 command: str) -> str:
+    """Per-dispatch means of the shader-sequencer counters of the rank-k
+    kernel and the fraction of cycles its matrix pipes were busy."""
+    sym = symbol("rankk", precision)
+    simds, xcc = gpu_agent(agent_csv)
+    per = {}   # dispatch -> {counter: value}, plus its duration
+    for r in read_csv(counter_csv):
+        if sym + "(" not in r["Kernel_Name"] and not r["Kernel_Name"].endswith(sym):
+            continue
+        d = per.setdefault(r["Dispatch_Id"], {})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+        d["_ns"] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+    if not per:
+        raise ValueError(f"no dispatch of {sym}")
+    mean = {c: sum(d[c] for d in per.values()) / len(per)
+            for c in MFMA_COUNTERS + ["_ns"] if all(c in d for d in per.values())}
+    active = mean["GRBM_GUI_ACTIVE"] / xcc   # GPU-active cycles of one XCD
+    busy = mean["SQ_VALU_MFMA_BUSY_CYCLES"] / (simds * active)
+    lines = [
+        f"# matrix-core use of {sym} (rankk), {workload}, precision {precision}",
+        f"# command: {command}",
+        "family: rankk",
+        f"precision: {precision}",
+        f"kernel: {sym}",
+        f"source_hash: {source_hash('rankk')}",
+        f"dispatches: {len(per)}",
+        f"simds: {simds}",
+        f"xcds: {xcc}",
+    ]
+    lines += [f"{c}: {mean[c]:.0f}" for c in MFMA_COUNTERS if c in mean]
+    lines += [
+        f"dispatch_ns: {mean['_ns']:.0f}",
+        f"active_cycles_per_xcd: {active:.0f}",
+        f"clock_ghz: {active / mean['_ns']:.3f}",
+        f"mfma_busy_fraction: {busy:.4f}",
+    ]
+    if "SQ_WAVES" in mean:
+        lines.append(f"mfma_busy_cycles_per_wave: "
+                     f"{mean['SQ_VALU_MFMA_BUSY_CYCLES'] / mean['SQ_WAVES']:.0f}")
+    return "\n".join(lines) + "\n"
+
+
 def read_summary(path: str) -> dict:
     d = {}
     with open(path) as f:
@@ -182,8 +244,17 @@ def main(argv=None) -> int:
     t.add_argument("--workload", required=True)
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
+    m = sub.add_parser("mfma")
+    m.add_argument("counter_csv")
+    m.add_argument("agent_csv")
+    m.add_argument("--precision", default="fp64", choices=["fp64", "bf16x3"])
+    m.add_argument("--workload", required=True)
+    m.add_argument("--command", required=True)
     a = ap.parse_args(argv)
-    if a.what == "stats":
+    if a.what == "mfma":
+        sys.stdout.write(mfma_summary(a.counter_csv, a.agent_csv, a.precision, a.workload,
+                                      a.command))
+    elif a.what == "stats":
         sys.stdout.write(stats_summary(a.stats_csv, a.command))
     else:
         sys.stdout.write(traffic_summary(a.fetch_csv, a.write_csv, a.family, a.precision,
