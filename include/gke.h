@@ -162,13 +162,18 @@ gke_status gke_set_option(gke_plan_t plan, int key, int64_t value);
  * Errors: GKE_ERR_ARG (NULL, unknown key). */
 gke_status gke_get_option(gke_plan_t plan, int key, int64_t *value);
 
-/* Device workspace bytes the plan needs with its current options. */
+/* Device workspace bytes the plan needs with its current options (fixes the
+ * automatic chunk).  Errors: GKE_ERR_ARG (NULL; the fundamental domain without
+ * the mirror), GKE_ERR_UNSUPPORTED (the spectra of one kx wavenumber reach
+ * 2^31 elements, Nz * 10 * chunk * Ny rounded up; split-BF16 with Nz above
+ * 972, whose four-snapshot z transforms exceed one block's LDS). */
 gke_status gke_workspace_size(gke_plan_t plan, size_t *bytes);
 
 /* Hand the plan a caller-owned device buffer of at least gke_workspace_size
  * bytes (256-byte aligned).  The caller keeps ownership and must keep it
  * alive until gke_destroy.  Fixes the options.  Errors: GKE_ERR_OOM if too
- * small, GKE_ERR_ARG for NULL/misaligned, GKE_ERR_STATE if already set. */
+ * small, GKE_ERR_ARG for NULL/misaligned, GKE_ERR_STATE if already set, and
+ * those of gke_workspace_size. */
 gke_status gke_set_workspace(gke_plan_t plan, void *device_ptr, size_t bytes);
 
 /* HIP stream (hipStream_t) on which all work is enqueued; NULL = default. */
