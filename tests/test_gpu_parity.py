@@ -294,6 +294,22 @@ def test_bf16x3_snapshot_quad_groups(S, chunk):
     check_bf16(g, ref, pairs, w.nx, f"bf16x3 S={S} chunk={chunk}")
 
 
+@pytest.mark.timeout(600)
+def test_bf16x3_512_snapshots_one_batch():
+    # the split path's launch configuration at Re_tau = 200 (512 FP32
+    # snapshots in one FP32-accumulated rank-k batch of 128 quads, the chunk
+    # the automatic choice takes there) on a small grid, every pair: the FP32
+    # sums over the longest batch stay within the split-BF16 bar
+    w = synth.workload("tiny", nx=24, nz=20, ny=33, S=512, M=6, dtype="f32")
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 512)
+    say("case bf16x3 Ny=33 S=512 chunk=512 f32")
+    g, _ = run_gpu(snap, w, y, precision="bf16x3", chunk=512)
+    pairs = oracle.all_pairs(w.ny)
+    ref = oracle.pair_terms(snap.astype(np.float64), y, w.lx, w.lz, w.nu, pairs)
+    check_bf16(g, ref, pairs, w.nx, "bf16x3 S=512 chunk=512")
+
+
 def test_bf16x3_remainder_only_grid():
     # Ny = 9: no full plane tile, every pair in the remainder kernel (packed
     # across wavenumbers on the split path); 3 snapshots, one partial quad
