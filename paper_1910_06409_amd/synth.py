@@ -22,6 +22,12 @@ no-slip fluctuations:
 * A mean profile U(y) (laminar for the tiny case, a Reichardt wall law with
   U(0)=1 otherwise) is added to u.
 * One RNG stream per snapshot: SeedSequence([seed, s]).
+* Optional full-band content (noise > 0): seeded white noise of relative
+  amplitude `noise` added to u', v', w', p' at every grid point (stream
+  SeedSequence([seed, s, 1])).  It is neither divergence-free nor
+  band-limited: every (kx, kz) bin of every plane carries content, the
+  Nyquist bins included, so that no part of the spectrum is zero by
+  construction.
 """
 from __future__ import annotations
 
@@ -54,6 +60,7 @@ class Workload:
     spectrum_scale: float = 1.0   # k -> k/spectrum_scale in the amplitude law
     rms_u: float = 0.15           # target peak rms of the velocity fluctuation
     rms_p: float = 0.10           # target peak rms of the pressure fluctuation
+    noise: float = 0.0            # relative amplitude of added full-band white noise
 
     @property
     def nk(self) -> int:
@@ -227,6 +234,15 @@ def _scales(w: Workload, seed: int):
     return _SCALE_CACHE[key]
 
 
+def _noise(w: Workload, seed: int, s: int) -> np.ndarray:
+    """Seeded white noise [4][ny][nz][nx] scaled to noise * (rms_u, rms_p)."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), int(s), 1]))
+    n = rng.standard_normal((4, w.ny, w.nz, w.nx))
+    n[:3] *= w.noise * w.rms_u
+    n[3] *= w.noise * w.rms_p
+    return n
+
+
 def snapshot(w: Workload, seed: int, s: int) -> np.ndarray:
     """Full fields (u~, v~, w~, p~) of snapshot s, shape [4][ny][nz][nx].
 
@@ -237,6 +253,8 @@ def snapshot(w: Workload, seed: int, s: int) -> np.ndarray:
     r = _raw_snapshot(w, seed, s)
     r[:3] *= su
     r[3] *= sp
+    if w.noise:
+        r += _noise(w, seed, s)
     y = y_grid(w)
     r[0] += mean_profile(w, y)[:, None, None]
     if w.dtype == "f32":
@@ -279,6 +297,8 @@ class DeviceSnapshots:
         r = torch.fft.irfft2(spec, s=(w.nz, w.nx), norm="forward")
         r[:3] *= self.su
         r[3] *= self.sp
+        if w.noise:
+            r += torch.from_numpy(_noise(w, self.seed, s)).to(self.device)
         r[0] += self.mean
         dt = torch.float32 if w.dtype == "f32" else torch.float64
         if out is None:

@@ -110,6 +110,40 @@ def test_parseval_oracle_matches_direct_sums_tiny(tiny):
         assert nerr(a[:, t], b[:, t]) < 1e-12, f"T{t + 1}"
 
 
+@pytest.mark.parametrize("kw", [dict(nx=8, nz=6, ny=9), dict(nx=10, nz=10, ny=7, M=5)])
+def test_parseval_oracle_matches_direct_sums_full_band(kw):
+    """Full-band inputs (white noise in every bin, the Nyquist bins included):
+    the half-spectrum weights, the zero Nyquist multipliers of the spectral
+    r-derivatives and every correlation at high wavenumbers are compared with
+    the direct sums of the definitions."""
+    w = synth.workload("tiny", S=3, noise=1.0, **kw)
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 12)
+    X = np.fft.rfft2(snap[:, :, 1:-1], axes=(-2, -1))
+    assert np.abs(X[..., -1]).min() > 1e-6 and np.abs(X[..., w.nz // 2, :]).min() > 1e-6
+    pairs = oracle.all_pairs(w.ny)
+    a = oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs)
+    b = direct.terms(snap, y, w.lx, w.lz, w.nu, pairs)
+    for t in range(14):
+        assert nerr(a[:, t], b[:, t]) < 1e-12, f"T{t + 1}"
+    # the profiles, eps included (x, z derivatives spectral, zero at Nyquist)
+    prof = oracle.step1(snap, y, w.lx, w.lz, w.nu)
+    mean, _, S, eps, _ = direct.profiles(snap, y, w.lx, w.lz, w.nu)
+    assert nerr(prof[4], S) < 1e-12
+    assert nerr(prof[oracle.PROFILE_ROWS.index("eps")], eps) < 1e-12
+
+
+def test_parseval_oracle_matches_direct_sums_tiny_full_band():
+    w = synth.workload("tiny", S=2, noise=0.5)
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 31)
+    pairs = [(0, 0), (0, 16), (16, 0), (3, 5), (8, 8), (15, 1), (2, 3)]
+    a = oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs)
+    b = direct.terms(snap, y, w.lx, w.lz, w.nu, pairs)
+    for t in range(14):
+        assert nerr(a[:, t], b[:, t]) < 1e-12, f"T{t + 1}"
+
+
 # ---------------------------------------------------------------------------
 # closed forms for prescribed trigonometric fields
 # ---------------------------------------------------------------------------
@@ -178,6 +212,41 @@ def test_closed_form_single_harmonic():
             scale = max(np.abs(e).max(), np.abs(T1).max() * 1e-3)
             assert np.abs(o1[k, t - 1] - e).max() < 1e-12 * scale, (k, t)
             assert np.abs(o0[k, t - 1] - e).max() < 1e-12 * scale, (k, t)
+
+
+def test_closed_form_wall_normal_derivative_terms():
+    """T6 and T11 (Step 3) in closed form.  Velocity amplitudes of degree <= 2
+    in y make <du^2> a polynomial of degree <= 4 in Y1 and in Y2, on which the
+    five-point stencil is exact, so the two terms equal the analytic
+    derivatives: T6 = -nu (d/dY2 - d/dY1) <du^2>, T11 = -(nu/2)(d/dY1 + d/dY2) <du^2>
+    (Section "Step 3": d/dry = (d/dY2 - d/dY1)/2, d/dY = d/dY1 + d/dY2)."""
+    P = np.polynomial.Polynomial
+    nx, nz, lx, lz, nu = 12, 10, 3.0, 2.5, 0.03
+    y = -np.cos(np.pi * np.arange(13) / 12)
+    amp = [P([1.0, 0.5, -0.8]), P([0.3, -0.6, 0.4]), P([0.7, 0.2, 0.0]), P([0.5, 0.1, 0.3])]
+    ph = [0.4, -1.2, 2.1, 0.9]
+    snap = _trig_snapshots(nx, nz, lx, lz, y, amp, [1, 1, 1, 1], ph, lambda y: 1 - y ** 2)
+    pairs = [(0, 12), (12, 0), (1, 3), (6, 6), (2, 11), (11, 10), (5, 0)]
+    o1 = oracle.pair_terms(snap, y, lx, lz, nu, pairs)
+    o0 = direct.terms(snap, y, lx, lz, nu, pairs)
+    psi = _psi(nx, nz)
+    q = 0.5 * sum(a * a for a in amp[:3])     # <u'_i u'_i>
+    dq = q.deriv()
+    da = [a.deriv() for a in amp[:3]]
+    for k, (j1, j2) in enumerate(pairs):
+        y1, y2 = y[j1], y[j2]
+        T1 = q(y1) + q(y2) - sum(amp[i](y1) * amp[i](y2) for i in range(3)) * np.cos(psi)
+        d1 = dq(y1) - sum(da[i](y1) * amp[i](y2) for i in range(3)) * np.cos(psi)
+        d2 = dq(y2) - sum(amp[i](y1) * da[i](y2) for i in range(3)) * np.cos(psi)
+        T6 = -nu * (d2 - d1)
+        T11 = -0.5 * nu * (d1 + d2)
+        scale = nu * np.abs(T1).max()
+        for t, e in {1: T1, 6: T6, 11: T11}.items():
+            sc = np.abs(T1).max() if t == 1 else scale
+            assert np.abs(o1[k, t - 1] - e).max() < 1e-12 * sc, (k, t)
+            assert np.abs(o0[k, t - 1] - e).max() < 1e-12 * sc, (k, t)
+        if j1 != j2:   # non-trivial: both derivatives matter
+            assert np.abs(T6).max() > 1e-3 * scale and np.abs(T11).max() > 1e-3 * scale
 
 
 def test_closed_form_triple_terms():

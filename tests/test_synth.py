@@ -4,6 +4,7 @@ device-side builder with the host one."""
 import numpy as np
 import pytest
 
+from conftest import nyquist_content
 from paper_1910_06409_amd import synth
 
 
@@ -57,3 +58,28 @@ def test_device_builder_matches_host(name):
         assert b.dtype == a.dtype
         tol = 1e-13 if a.dtype == np.float64 else 1e-6
         assert np.abs(a.astype(np.float64) - b).max() <= tol * np.abs(a).max()
+
+
+
+def test_band_limited_default_has_no_nyquist_content(tiny):
+    w, _, snap = tiny
+    assert nyquist_content(snap[:, :3, 1:-1]) < 1e-28
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(nx=24, nz=20, ny=21, M=6)])
+def test_full_band_inputs_fill_every_bin(kw):
+    w = synth.workload("tiny", noise=0.5, S=2, **kw)
+    snap = synth.snapshots(w, 3)
+    # every field, every plane (walls included), both Nyquist lines carry energy
+    # of the order of a white spectrum's share (1/Nx and 1/Nz of the plane)
+    share = min(1.0 / w.nx, 1.0 / w.nz)
+    assert nyquist_content(snap) > 0.05 * share
+    # every single bin is non-zero
+    X = np.fft.rfft2(snap - snap.mean(axis=(-2, -1), keepdims=True), axes=(-2, -1))
+    X[..., 0, 0] = 1.0
+    assert np.abs(X).min() > 1e-9
+    # deterministic, and noise = 0 gives back the band-limited snapshot
+    assert np.array_equal(snap[1], synth.snapshot(w, 3, 1))
+    w0 = synth.workload("tiny", S=2, **kw)
+    assert not np.array_equal(snap[1], synth.snapshot(w0, 3, 1))
+    assert np.abs(snap[1] - synth.snapshot(w0, 3, 1)).max() < 10 * w.noise * w.rms_u
