@@ -176,6 +176,28 @@ gke_status gke_workspace_size(gke_plan_t plan, size_t *bytes);
  * those of gke_workspace_size. */
 gke_status gke_set_workspace(gke_plan_t plan, void *device_ptr, size_t bytes);
 
+/* Size of the library-owned workspace of gke_set_static_workspace. */
+#define GKE_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+ * gke_set_workspace, but the plan takes the library's own static device
+ * workspace of GKE_STATIC_WORKSPACE_BYTES instead of a caller buffer.  Set the
+ * stream (gke_set_stream) first: the tables are uploaded and the sums cleared
+ * on it.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine); inputs and outputs are still the caller's.
+ * Sharing: there is one static workspace per GPU, that of the device current
+ * at this call, held until the process ends; the plan must run on that
+ * device.  Every plan that takes it on one GPU uses the same memory, which
+ * keeps the last plan's contents: this call re-uploads the tables and clears
+ * what must start at zero, so plans used one after another are independent,
+ * but plans whose work overlaps on one GPU race (use one at a time).
+ * Errors: GKE_ERR_OOM (the plan, with its options, needs more than
+ * GKE_STATIC_WORKSPACE_BYTES: see gke_workspace_size), GKE_ERR_STATE (a
+ * workspace is already set), GKE_ERR_HIP (device or symbol lookup failed),
+ * and those of gke_workspace_size. */
+gke_status gke_set_static_workspace(gke_plan_t plan);
+
 /* HIP stream (hipStream_t) on which all work is enqueued; NULL = default. */
 gke_status gke_set_stream(gke_plan_t plan, void *hip_stream);
 

@@ -256,6 +256,8 @@ hipError_t launch_r0_band(hipStream_t st, const Dims &d, const double *band, dou
 // Step 3: T6 and T11 from T1 along Y1 and Y2
 hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const double *t1,
                            double *t6, double *t11);
+// zero `bytes` bytes at p (8-byte aligned, a multiple of 8) with a fill kernel
+hipError_t launch_zero(hipStream_t st, void *p, size_t bytes);
 // T14 = -2 (eps(Y1) + eps(Y2))
 hipError_t launch_t14(hipStream_t st, const Dims &d, const double *prof, double *t14);
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -677,18 +678,15 @@ gke_status gke_workspace_size(gke_plan_t p, size_t *bytes)
     return GKE_OK;
 }
 
-gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
+}  // extern "C"
+
+namespace {
+
+// Carve a device buffer of `bytes` (256-byte aligned, at least the layout's
+// size, options already fixed by prepare_mode) into the plan's workspace:
+// upload the tables and clear the sums, profiles and moment partials.
+gke_status attach_workspace(gke_plan_t p, void *dev, size_t bytes)
 {
-    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
-    if (p->ws) return fail(p, GKE_ERR_STATE, "workspace already set");
-    if (!dev || ((uintptr_t)dev & 255)) return fail(p, GKE_ERR_ARG, "workspace NULL or not 256-byte aligned");
-    {
-        gke_status s = prepare_mode(p);
-        if (s != GKE_OK) return s;
-    }
-    const size_t need = layout(p, nullptr);
-    if (bytes < need)
-        return fail(p, GKE_ERR_OOM, "workspace too small: need " + std::to_string(need) + " bytes");
     p->ws = (char *)dev;
     p->ws_bytes = bytes;
     layout(p, p->ws);
@@ -708,7 +706,7 @@ gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
     }
     GKE_HIP(p, hipMemcpyAsync(p->pidx, p->h_pidx.data(), sizeof(int) * d.ny * d.ny, hipMemcpyHostToDevice, st));
     // sums, profiles and moment partials start at zero
-    GKE_HIP(p, hipMemsetAsync(p->sums1, 0, (char *)p->inter - (char *)p->sums1, st));
+    GKE_HIP(p, gke::launch_zero(st, p->sums1, (char *)p->inter - (char *)p->sums1));
     GKE_HIP(p, hipStreamSynchronize(st));
     p->tab.twx = p->twx;
     p->tab.twz = p->twz;
@@ -724,6 +722,72 @@ gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
     p->tab.rowidx = p->rowidx;
     if (p->general) return select_slab(p, 0);
     return GKE_OK;
+}
+
+// The library-owned workspace of gke_set_static_workspace: one copy per GPU,
+// held until the process ends.  Host code never uses the array's name as an
+// address; it takes the per-device address from hipGetSymbolAddress.
+__device__ __align__(256) unsigned char scratch[GKE_STATIC_WORKSPACE_BYTES];
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;   // [device] address of `scratch` on that device
+
+// Address of `scratch` on the current device (looked up once per device).
+gke_status static_scratch(gke_plan_t p, void **out)
+{
+    int dev = -1;
+    GKE_HIP(p, hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0) return fail(p, GKE_ERR_HIP, "no current device");
+    if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *a = nullptr;
+        GKE_HIP(p, hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+        if (!a || ((uintptr_t)a & 255)) return fail(p, GKE_ERR_HIP, "static workspace address");
+        g_scratch_ptr[dev] = a;
+    }
+    *out = g_scratch_ptr[dev];
+    return GKE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gke_status gke_set_workspace(gke_plan_t p, void *dev, size_t bytes)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (p->ws) return fail(p, GKE_ERR_STATE, "workspace already set");
+    if (!dev || ((uintptr_t)dev & 255)) return fail(p, GKE_ERR_ARG, "workspace NULL or not 256-byte aligned");
+    {
+        gke_status s = prepare_mode(p);
+        if (s != GKE_OK) return s;
+    }
+    const size_t need = layout(p, nullptr);
+    if (bytes < need)
+        return fail(p, GKE_ERR_OOM, "workspace too small: need " + std::to_string(need) + " bytes");
+    return attach_workspace(p, dev, bytes);
+}
+
+gke_status gke_set_static_workspace(gke_plan_t p)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (p->ws) return fail(p, GKE_ERR_STATE, "workspace already set");
+    {
+        gke_status s = prepare_mode(p);
+        if (s != GKE_OK) return s;
+    }
+    const size_t need = layout(p, nullptr);
+    if (need > (size_t)GKE_STATIC_WORKSPACE_BYTES)
+        return fail(p, GKE_ERR_OOM, "the plan needs " + std::to_string(need) +
+                                        " workspace bytes; the static workspace holds " +
+                                        std::to_string((size_t)GKE_STATIC_WORKSPACE_BYTES));
+    void *dev = nullptr;
+    {
+        gke_status s = static_scratch(p, &dev);
+        if (s != GKE_OK) return s;
+    }
+    return attach_workspace(p, dev, (size_t)GKE_STATIC_WORKSPACE_BYTES);
 }
 
 gke_status gke_set_stream(gke_plan_t p, void *stream)
@@ -918,7 +982,7 @@ gke_status gke_begin_slab(gke_plan_t p, int slab)
     if (!p->second_scan) return fail(p, GKE_ERR_STATE, "the means are not known yet");
     // forget the second scan of the previous slab: moments restart, the
     // accumulators are overwritten by the first chunk
-    GKE_HIP(p, hipMemsetAsync(p->momp, 0, sizeof(double) * p->d.ny * gke::NMOMP * p->d.nzb, p->stream));
+    GKE_HIP(p, gke::launch_zero(p->stream, p->momp, sizeof(double) * p->d.ny * gke::NMOMP * p->d.nzb));
     p->n2 = 0;
     p->pending = 0;
     p->chunks_done = 0;
@@ -942,7 +1006,7 @@ gke_status gke_reset(gke_plan_t p)
     if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
     // sums, profiles and moment partials are contiguous in the workspace;
     // the cross-spectral accumulators are overwritten by the first chunk
-    GKE_HIP(p, hipMemsetAsync(p->sums1, 0, (char *)p->inter - (char *)p->sums1, p->stream));
+    GKE_HIP(p, gke::launch_zero(p->stream, p->sums1, (char *)p->inter - (char *)p->sums1));
     p->n1 = p->n2 = 0;
     p->pending = 0;
     p->chunks_done = 0;

@@ -2,6 +2,8 @@
 // mean shear; the one-point moments and the pseudo-dissipation used by the
 // assembly of the terms).  Every reduction has a fixed order, so results are
 // bit-reproducible run to run.
+#include <algorithm>
+
 #include "gke_internal.h"
 
 namespace gke {
@@ -312,6 +314,25 @@ hipError_t launch_r0_band(hipStream_t st, const Dims &d, const double *band, dou
                           double *r0, double *gxz)
 {
     hipLaunchKernelGGL(k_r0_band, dim3(d.ny, 5), dim3(256), 0, st, band, d, inv_count, r0, gxz);
+    return hipGetLastError();
+}
+
+// Zero n bytes at p (p 8-byte aligned, n a multiple of 8): a plain fill kernel,
+// so that clearing never records a memset node in a caller's captured graph.
+__global__ __launch_bounds__(256) void k_zero(unsigned long long *__restrict__ p, size_t n8)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+hipError_t launch_zero(hipStream_t st, void *p, size_t bytes)
+{
+    if (bytes == 0) return hipSuccess;
+    if (((uintptr_t)p & 7) || (bytes & 7)) return hipErrorInvalidValue;
+    const size_t n8 = bytes >> 3;
+    const unsigned nb = (unsigned)std::min<size_t>((n8 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero, dim3(nb), dim3(256), 0, st, (unsigned long long *)p, n8);
     return hipGetLastError();
 }
 

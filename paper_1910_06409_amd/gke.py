@@ -67,6 +67,7 @@ def lib() -> ctypes.CDLL:
         "gke_get_option": ([vp, i32, ctypes.POINTER(i64)], i32),
         "gke_workspace_size": ([vp, ctypes.POINTER(sz)], i32),
         "gke_set_workspace": ([vp, vp, sz], i32),
+        "gke_set_static_workspace": ([vp], i32),
         "gke_set_stream": ([vp, vp], i32),
         "gke_accumulate": ([vp, vp, vp, vp, vp], i32),
         "gke_begin_stats": ([vp], i32),
@@ -136,6 +137,13 @@ def gke_workspace_size(plan) -> int:
 
 def gke_set_workspace(plan, device_ptr: int, nbytes: int) -> None:
     _check(lib().gke_set_workspace(plan, device_ptr, nbytes), plan)
+
+
+def gke_set_static_workspace(plan) -> None:
+    _check(lib().gke_set_static_workspace(plan), plan)
+
+
+GKE_STATIC_WORKSPACE_BYTES = 64 << 20
 
 
 def gke_set_stream(plan, stream_ptr: int) -> None:

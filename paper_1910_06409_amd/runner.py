@@ -18,7 +18,7 @@ class GkeRun:
 
     def __init__(self, nx, ny, nz, y, lx, lz, nu, *, dtype="f64", precision="fp64",
                  chunk=64, pair_batch=0, mirror=0, domain=0, slab=0, device="cuda",
-                 stream=None):
+                 stream=None, static_workspace=False):
         self.nx, self.ny, self.nz = nx, ny, nz
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
@@ -38,11 +38,17 @@ class GkeRun:
         self.domain = int(domain)
         self.general = bool(mirror or domain or slab)
         gke.gke_set_stream(self.plan, self.stream.cuda_stream)
-        nbytes = gke.gke_workspace_size(self.plan)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        aligned = (base + 255) // 256 * 256
-        gke.gke_set_workspace(self.plan, aligned, nbytes)
+        if static_workspace:
+            # the library's own device workspace: nothing allocated here
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                gke.gke_set_static_workspace(self.plan)
+        else:
+            nbytes = gke.gke_workspace_size(self.plan)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            gke.gke_set_workspace(self.plan, aligned, nbytes)
         self.tdtype = torch.float32 if dtype == "f32" else torch.float64
 
     def accumulate(self, u, v, w, p):

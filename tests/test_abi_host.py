@@ -172,3 +172,26 @@ def test_split_records_and_long_nz():
         assert e.value.status == gke.GKE_ERR_UNSUPPORTED
     finally:
         gke.gke_destroy(p)
+
+
+def test_static_workspace_refuses_a_plan_larger_than_it():
+    """gke_set_static_workspace checks the plan's size before any device work."""
+    from paper_1910_06409_amd import synth
+    w = synth.workload("re200")
+    p = gke.gke_plan(w.nx, w.ny, w.nz, synth.y_grid(w), w.lx, w.lz, w.nu)
+    try:
+        assert gke.gke_workspace_size(p) > gke.GKE_STATIC_WORKSPACE_BYTES
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_set_static_workspace(p)
+        assert e.value.status == gke.GKE_ERR_OOM
+        assert str(gke.GKE_STATIC_WORKSPACE_BYTES) in str(e.value)
+    finally:
+        gke.gke_destroy(p)
+    # the tiny channel fits it (the size the GPU test runs)
+    w = synth.workload("tiny")
+    p = gke.gke_plan(w.nx, w.ny, w.nz, synth.y_grid(w), w.lx, w.lz, w.nu)
+    try:
+        gke.gke_set_option(p, gke.GKE_OPT_CHUNK, 2)
+        assert gke.gke_workspace_size(p) <= gke.GKE_STATIC_WORKSPACE_BYTES
+    finally:
+        gke.gke_destroy(p)
