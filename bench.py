@@ -68,27 +68,97 @@ def kernel_work(w, chunk):
     }
 
 
-def cpu_baseline(w, y, seed, threads, s_sample, j1, nb=8):
+def s8d_work(w, chunk):
+    """Algorithmic work per launch on the basis of the measurement contract:
+    124 real flops per (snapshot, wavenumber, ordered plane pair) for the
+    cross-spectral update (15.5 complex MACs of the needed correlation set;
+    three times that for the split-BF16 form), and for the HBM-bound stages
+    the inputs read once and the spectra written once per snapshot (4 N b +
+    10 Ny nk c bytes), and the accumulators read once plus the 14 output maps
+    written once per finalize."""
+    ny, nx, nz, nkx, nk = w.ny, w.nx, w.nz, w.nx // 2 + 1, w.nk
+    n16 = 16 * (ny // 16)
+    b_in = 8 if w.dtype == "f64" else 4
+    c = 8 if w.precision == "bf16x3" else 16
+    mult = 3 if w.precision == "bf16x3" else 1
+    npair_u = ny * (ny + 1) // 2
+    return {
+        "rankk": 124.0 * mult * chunk * nk * n16 * n16,
+        "rankk_rem": 124.0 * chunk * nk * (ny * ny - n16 * n16),
+        # per snapshot (the two transform kernels together)
+        "transforms": 4.0 * nx * ny * nz * b_in + 10.0 * ny * nk * c,
+        # per finalize: 8 accumulated term spectra of every unordered pair read
+        # once, 13 maps [Y1][Y2][rz][rx <= Nx/2] and T14 [Y1][Y2] written once
+        "finalize": 8.0 * nk * npair_u * 16 + 13.0 * ny * ny * nkx * nz * 8 + ny * ny * 8.0,
+    }
+
+
+def host_info():
+    """Host CPU facts recorded with the CPU baseline."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    mem = 0.0
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem = float(line.split()[1]) / 2**20
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity_cores": avail, "cpu_model": model,
+            "mem_gib": round(mem, 1), "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline(w, y, seed, threads, s_sample, j1, nb=8, s_single=2, nb_single=2):
     """The oracle on a bounded sample: S_sample snapshots, the nb x nb block of
-    ordered pairs with Y1, Y2 in [j1, j1 + nb)."""
+    ordered pairs with Y1, Y2 in [j1, j1 + nb), on `threads` threads; and a
+    smaller sample on one thread (the analogue of a serial run)."""
     import numpy as np
 
     from oracle import oracle
     from paper_1910_06409_amd import synth
 
-    used = oracle.set_threads(threads)
-    snap = np.stack([synth.snapshot(w, seed, s) for s in range(s_sample)])
+    pts_pair = (w.nx // 2 + 1) * w.nz
+    planes = list(range(max(0, j1 - 2), min(w.ny, j1 + nb + 2)))
+    snap = np.stack([synth.snapshot(w, seed, s)[:, planes] for s in range(s_sample)])
+    snap = snap.astype(np.float64)
     pairs = [(a, b) for a in range(j1, j1 + nb) for b in range(j1, j1 + nb)]
+    used = oracle.set_threads(threads)
     t0 = time.perf_counter()
-    oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs, nthreads=threads)
+    oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs, nthreads=threads, held=planes)
     dt = time.perf_counter() - t0
-    pts = len(pairs) * (w.nx // 2 + 1) * w.nz
-    return {"value": pts * s_sample / dt, "unit": UNIT, "cores": used, "kind": "oracle",
-            "seconds": dt,
-            "sample": f"{w.name}: first {s_sample} snapshots, the {nb}x{nb} block of ordered "
-                      f"pairs Y1, Y2 in [{j1}, {j1 + nb}) (plus the five-point neighbour pairs "
-                      f"the oracle needs), whole oracle path incl. Step 1 on the touched "
-                      f"planes; value = pairs*(Nx/2+1)*Nz*S_sample/seconds"}
+    p1 = pairs[:nb_single * nb_single]
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.pair_terms(np.ascontiguousarray(snap[:s_single]), y, w.lx, w.lz, w.nu,
+                      [(j1 + a, j1 + b) for a in range(nb_single) for b in range(nb_single)],
+                      nthreads=1, held=planes)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(used)
+    res = {"value": len(pairs) * pts_pair * s_sample / dt, "unit": UNIT, "cores": used,
+           "kind": "oracle", "seconds": dt,
+           "sample": f"{w.name}: first {s_sample} snapshots, the {nb}x{nb} block of ordered "
+                     f"pairs Y1, Y2 in [{j1}, {j1 + nb}) (plus the five-point neighbour pairs "
+                     f"the oracle needs), whole oracle path incl. Step 1 on the touched "
+                     f"planes; value = pairs*(Nx/2+1)*Nz*S_sample/seconds"}
+    res.update(host_info())
+    res["single_thread"] = {
+        "value": len(p1) * pts_pair * s_single / dt1, "seconds": dt1, "cores": 1,
+        "sample": f"first {s_single} snapshots, the {nb_single}x{nb_single} block of pairs "
+                  f"from [{j1}, {j1 + nb_single})"}
+    return res
 
 
 def main():
@@ -105,11 +175,12 @@ def main():
     ap.add_argument("--precision", default="", choices=["", "fp64", "bf16x3"],
                     help="override the rank-k arithmetic of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="oracle threads (0: every core this job may use)")
     ap.add_argument("--slab-rows", type=int, default=0,
                     help="config-5 path: mirror average, fundamental domain, Y1 slabs of this "
                          "many rows (one timed pass over all slabs)")
-    ap.add_argument("--also", default="re200_bf16",
+    ap.add_argument("--also", default="re200_bf16,re200_batched",
                     help="comma-separated workloads measured after the main one (speed-up per "
                          "snapshot reported under 'extra'); empty for none")
     ap.add_argument("--also-steps", type=int, default=2)
@@ -203,6 +274,7 @@ def main():
 
         t_step = elapsed / steps
         work = kernel_work(w, chunk_used)
+        s8 = s8d_work(w, chunk_used)
         kernels = {}
         for name, (ms, n) in tm.items():
             if n == 0:
@@ -214,19 +286,51 @@ def main():
                 if name in ("rankk", "rankk_rem"):
                     # the last launch of a step may hold fewer snapshots: use the mean
                     amount = amount * (S / chunk_used) / (n / steps)
-                if kind == "flop":
+                    k["achieved_tflops"] = (s8[name] * (S / chunk_used) / (n / steps)
+                                            / (avg * 1e-3) / 1e12)
+                    k["achieved_tflops_own_basis"] = amount / (avg * 1e-3) / 1e12
+                elif kind == "flop":
                     k["achieved_tflops"] = amount / (avg * 1e-3) / 1e12
                 else:
                     k["achieved_gbs"] = amount / (avg * 1e-3) / 1e9
             kernels[name] = k
+        # stage rates on the contract's algorithmic bytes
+        ms_of = lambda *names: sum(kernels[n]["ms_per_step"] for n in names if n in kernels)
+        stages = {}
+        t_tr = ms_of("fluct_xfft", "zfft_pack")
+        if t_tr:
+            gbs = s8["transforms"] * S / (t_tr * 1e-3) / 1e9
+            stages["transforms"] = {"ms_per_step": t_tr, "bytes_per_step": s8["transforms"] * S,
+                                    "achieved_gbs": gbs, "frac_hbm": gbs / PEAK["hbm"]}
+        t_fin = ms_of("fin_kz", "fin_kx", "fd_terms")
+        if t_fin:
+            gbs = s8["finalize"] / (t_fin * 1e-3) / 1e9
+            stages["finalize"] = {"ms_per_step": t_fin, "bytes_per_step": s8["finalize"],
+                                  "achieved_gbs": gbs, "frac_hbm": gbs / PEAK["hbm"]}
         dom = max(kernels, key=lambda n: kernels[n]["ms_per_step"])
         dk = kernels[dom]
+        extra_roof = {}
         if dom == "rankk_rem":
             # FP64 vector arithmetic: the fp64 vector peak of the chip
             ach, peak, unit, bound = dk["achieved_tflops"], PEAK["fp64_vector"], "TFLOP/s", "alu"
         elif "achieved_tflops" in dk:
             peak = PEAK["bf16_mfma" if w.precision == "bf16x3" else "fp64_mfma"]
             ach, unit, bound = dk["achieved_tflops"], "TFLOP/s", "mfma"
+            extra_roof = {
+                "basis": "124 flops per (snapshot, wavenumber, ordered plane pair)"
+                         + (" x 3 split products" if w.precision == "bf16x3" else ""),
+                "achieved_own_basis": dk.get("achieved_tflops_own_basis"),
+                "own_basis": "216 flops per (snapshot, wavenumber, unordered pair): the 27 "
+                             "complex products the kernel forms"
+                             + (", x 3 split products" if w.precision == "bf16x3" else ""),
+            }
+            # matrix-core busy fraction and clock from the committed counter run
+            mf = profiling.read_summary_if_current(
+                os.path.join(ROOT, "profiles", f"mfma_rankk_{w.name}_{w.precision}.txt"),
+                "rankk")
+            if mf:
+                extra_roof["mfma_busy_fraction"] = float(mf["mfma_busy_fraction"])
+                extra_roof["mfma_clock_ghz"] = float(mf["clock_ghz"])
         else:
             ach, peak, unit, bound = dk.get("achieved_gbs", 0.0), PEAK["hbm"], "GB/s", "hbm"
         # HBM bytes per launch of that kernel from the committed counter summary,
@@ -237,8 +341,9 @@ def main():
         roof = {"kernel": profiling.symbol(dom, w.precision) if dom in profiling.KERNELS else dom,
                 "bound": bound, "achieved": ach, "peak": peak, "unit": unit,
                 "frac": ach / peak, "traffic": traffic}
+        roof.update(extra_roof)
         return {"w": w, "S": S, "chunk": chunk_used, "t_step": t_step, "kernels": kernels,
-                "roofline": roof, "value": w.points_out * S / t_step}
+                "roofline": roof, "stages": stages, "value": w.points_out * S / t_step}
 
     def measure_slabs(w, slab_rows, chunk, pair_batch):
         """The config-5 path: mirror average, fundamental domain, Y1 slabs (one
@@ -335,17 +440,23 @@ def main():
             "snapshots": we.S, "chunk": er["chunk"], "dtype": we.dtype,
             "precision": we.precision, "steps": args.also_steps,
             "speedup_per_snapshot_vs_main": per_snap_main / per_snap,
-            "roofline": er["roofline"],
+            "roofline": er["roofline"], "stages": er["stages"],
             "kernels_ms_per_step": {k: v["ms_per_step"] for k, v in er["kernels"].items()},
         }
+        stated = profiling.stated_error(
+            os.path.join(ROOT, "profiles", f"error_{we.name}_{we.precision}.txt"))
+        if stated:
+            extra[name]["stated_error"] = stated
         log(f"[bench] {name}: {1e3 * er['t_step']:.1f} ms/step, "
             f"{per_snap_main / per_snap:.2f}x per snapshot vs {w.name}")
 
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(w, synth.y_grid(w), args.seed, args.cpu_threads, s_sample=min(80, S),
-                           j1=w.ny // 2 - 6, nb=12)
+        threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS") or 0) or \
+            host_info()["affinity_cores"]
+        cpu = cpu_baseline(w, synth.y_grid(w), args.seed, threads, s_sample=min(100, S),
+                           j1=w.ny // 2 - 8, nb=16)
         log(f"[bench] oracle sample took {cpu['seconds']:.1f} s")
 
     t_step = main_res["t_step"]
@@ -362,6 +473,7 @@ def main():
                    "points_out": w.points_out},
         "points_per_s": w.points_out / t_step,
         "roofline": main_res["roofline"],
+        "stages": main_res["stages"],
         "cpu_baseline": cpu,
         "kernels": main_res["kernels"],
         "extra": extra,

@@ -114,22 +114,49 @@ def _as_snap(snap: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(snap, dtype=np.float64)
 
 
+def _held(snap, y, held):
+    """Global plane index of each plane the snapshot array holds."""
+    if held is None:
+        if snap.shape[2] != y.size:
+            raise ValueError("the snapshots must hold every plane of y (or pass held=)")
+        return list(range(y.size))
+    held = [int(j) for j in held]
+    if len(held) != snap.shape[2] or sorted(set(held)) != held:
+        raise ValueError("held must list the snapshot planes in increasing order")
+    return held
+
+
+def stencil_closure(y: np.ndarray, planes) -> list:
+    """The planes plus the five-point stencil nodes of each of them: the
+    planes an ensemble must hold for the terms of pairs on `planes`."""
+    D = fd5_matrix(y)
+    out = set(int(j) for j in planes)
+    for j in list(out):
+        out.update(int(m) for m in np.nonzero(D[j])[0])
+    return sorted(out)
+
+
 def step1(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float,
-          planes=None, means=None) -> np.ndarray:
+          planes=None, means=None, held=None) -> np.ndarray:
     """Profiles [NPROF][ny]: U V W P S=dU/dy <q> <uv> <pv> Tx Ty Tz eps.
 
     planes: optional iterable of plane indices; the one-point moments are then
     computed on those planes only (the other rows of q..eps are left 0).
     means: optional [4][ny] means to use instead of the ensemble means.
+    held: optional increasing global indices of the planes `snap` holds (a
+    subset of the grid y); the profiles are then [NPROF][len(held)] in that
+    order, `planes` and `means` refer to the held planes, and S and eps are
+    valid on the planes whose five-point stencil is held.
     """
     snap = _as_snap(snap)
     ns, _, ny, nz, nx = snap.shape
+    held = _held(snap, np.asarray(y), held)
     if means is None:
         means = np.zeros((4, ny))
         lib().or_means(nx, ny, nz, ns, _dp(snap), _dp(means))
     else:
         means = np.ascontiguousarray(np.asarray(means, dtype=np.float64)[:4])
-    D = fd5_matrix(y)
+    D = np.ascontiguousarray(fd5_matrix(y)[np.ix_(held, held)])
     prof = np.zeros((NPROF, ny))
     mask = None
     if planes is not None:
@@ -157,16 +184,26 @@ def _raw_pairs(snap, prof, lx, lz, nu, pairs, nthreads):
 
 
 def pair_terms(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float,
-               pairs, prof: np.ndarray | None = None, nthreads: int | None = None):
+               pairs, prof: np.ndarray | None = None, nthreads: int | None = None,
+               held=None):
     """All 14 term maps for each ordered pair (Y1, Y2): array [npairs][14][nz][nx].
 
     T6 and T11 (Step 3) use T1 on the five-point stencil neighbours along Y1
     and Y2, which are computed as extra pairs.
+    held: optional increasing global indices of the planes `snap` holds; pairs
+    are global indices and the snapshots must hold stencil_closure of their
+    planes (prof, when given, is then in held order).  The arithmetic is the
+    same as with every plane held.
     """
     snap = _as_snap(snap)
-    ny = snap.shape[2]
+    y = np.asarray(y, dtype=np.float64)
+    held = _held(snap, y, held)
+    loc = {g: i for i, g in enumerate(held)}
     D = fd5_matrix(y)
     pairs = [tuple(int(v) for v in p) for p in np.asarray(pairs).reshape(-1, 2)]
+    missing = sorted(set(stencil_closure(y, {j for pr in pairs for j in pr})) - set(held))
+    if missing:
+        raise ValueError(f"the snapshots do not hold planes {missing}")
     need = list(dict.fromkeys(pairs))
     for (j1, j2) in pairs:
         for m in np.nonzero(D[j1])[0]:
@@ -175,10 +212,10 @@ def pair_terms(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float,
             need.append((j1, int(m)))
     need = list(dict.fromkeys(need))
     if prof is None:
-        planes = sorted({j for pr in need for j in pr})
-        prof = step1(snap, y, lx, lz, nu, planes=planes)
+        planes = sorted({loc[j] for pr in need for j in pr})
+        prof = step1(snap, y, lx, lz, nu, planes=planes, held=held)
     index = {p: i for i, p in enumerate(need)}
-    raw = _raw_pairs(snap, prof, lx, lz, nu, need, nthreads)
+    raw = _raw_pairs(snap, prof, lx, lz, nu, [(loc[a], loc[b]) for (a, b) in need], nthreads)
     out = np.empty((len(pairs),) + raw.shape[1:])
     for k, (j1, j2) in enumerate(pairs):
         o = raw[index[(j1, j2)]].copy()
@@ -187,7 +224,6 @@ def pair_terms(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float,
         o[5] = -nu * (d2 - d1)          # -2 nu * (d/dY2 - d/dY1)/2 <du^2>
         o[10] = -0.5 * nu * (d1 + d2)   # -(nu/2) (d/dY1 + d/dY2) <du^2>
         out[k] = o
-    del ny
     return out
 
 
@@ -202,16 +238,17 @@ SIGMA_Y = np.array([+1, +1, +1, +1, -1, -1, +1, +1, -1, -1, -1, +1, +1, +1], dty
 
 
 def mirror_terms(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float,
-                 pairs, prof: np.ndarray | None = None, nthreads: int | None = None):
+                 pairs, prof: np.ndarray | None = None, nthreads: int | None = None,
+                 held=None):
     """Terms of each ordered pair averaged with those of the reflected pair
     (Section "Step 2": the other half of the channel doubles the sample):
         Tbar(Y1, Y2) = (T(Y1, Y2) + SIGMA_Y * T(2h - Y1, 2h - Y2)) / 2,
     same (rx, rz).  The y grid must be symmetric about the centreline, so the
     reflected plane of index j is Ny - 1 - j.  Returns [npairs][14][nz][nx]."""
-    ny = _as_snap(snap).shape[2]
+    ny = np.asarray(y).size
     pairs = [tuple(int(v) for v in p) for p in np.asarray(pairs).reshape(-1, 2)]
     refl = [(ny - 1 - a, ny - 1 - b) for (a, b) in pairs]
-    t = pair_terms(snap, y, lx, lz, nu, pairs + refl, prof=prof, nthreads=nthreads)
+    t = pair_terms(snap, y, lx, lz, nu, pairs + refl, prof=prof, nthreads=nthreads, held=held)
     n = len(pairs)
     return 0.5 * (t[:n] + SIGMA_Y[None, :, None, None] * t[n:])
 

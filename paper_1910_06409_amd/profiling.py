@@ -216,6 +216,43 @@ def read_summary(path: str) -> dict:
     return d
 
 
+def read_summary_if_current(path: str, family: str) -> dict | None:
+    """A committed summary's fields, provided the kernel's sources still
+    hash to the value it records (else None)."""
+    if not os.path.exists(path):
+        return None
+    d = read_summary(path)
+    if d.get("source_hash") != source_hash(family):
+        return None
+    return d
+
+
+def stated_error(path: str) -> dict | None:
+    """Per-term norm-wise errors recorded for a workload (a committed text
+    file: `T1: 1.2e-07` lines, a `source:` line naming the test that measured
+    them and a `command:` comment)."""
+    if not os.path.exists(path):
+        return None
+    terms, out = {}, {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                if line.startswith("# command:"):
+                    out["command"] = line.split(":", 1)[1].strip()
+                continue
+            k, v = (x.strip() for x in line.split(":", 1))
+            if k.startswith("T") and k[1:].isdigit():
+                terms[k] = float(v)
+            else:
+                out[k] = v
+    if not terms:
+        return None
+    out["per_term"] = terms
+    out["max"] = max(terms.values())
+    return out
+
+
 def traffic_if_current(path: str, family: str, precision: str) -> float | None:
     """Bytes per launch from a traffic summary, or None when there is none or
     the kernel's sources changed since the counters were taken."""

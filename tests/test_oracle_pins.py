@@ -433,3 +433,29 @@ def test_mirror_average_on_reflection_closed_ensemble():
     mb = oracle.mirror_terms(base, y, w.lx, w.lz, w.nu, pairs)
     mr = oracle.mirror_terms(base, y, w.lx, w.lz, w.nu, [(ny - 1 - a, ny - 1 - b) for a, b in pairs])
     assert nerr(mb, oracle.SIGMA_Y[None, :, None, None] * mr) < 1e-12
+
+
+def test_plane_subset_gives_the_same_terms():
+    """The oracle on the stencil closure of a few pairs' planes (what the
+    large sampled-pair parity cases hold in memory) returns the terms of the
+    whole-grid run: the subset changes which planes are read, not the
+    arithmetic."""
+    w = synth.workload("tiny", ny=33, S=3, noise=0.3)
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 77)
+    pairs = [(0, 32), (5, 17), (16, 16), (31, 2)]
+    held = oracle.stencil_closure(y, {j for p in pairs for j in p})
+    assert len(held) < w.ny
+    full = oracle.pair_terms(snap, y, w.lx, w.lz, w.nu, pairs)
+    sub = oracle.pair_terms(np.ascontiguousarray(snap[:, :, held]), y, w.lx, w.lz, w.nu, pairs,
+                            held=held)
+    assert nerr(sub, full) < 1e-14
+    m_full = oracle.mirror_terms(snap, y, w.lx, w.lz, w.nu, pairs[:2])
+    hm = oracle.stencil_closure(y, {j for p in pairs[:2] for j in (p[0], p[1], w.ny - 1 - p[0],
+                                                                   w.ny - 1 - p[1])})
+    m_sub = oracle.mirror_terms(np.ascontiguousarray(snap[:, :, hm]), y, w.lx, w.lz, w.nu,
+                                pairs[:2], held=hm)
+    assert nerr(m_sub, m_full) < 1e-14
+    with pytest.raises(ValueError):
+        oracle.pair_terms(np.ascontiguousarray(snap[:, :, held[1:]]), y, w.lx, w.lz, w.nu,
+                          pairs, held=held[1:])
