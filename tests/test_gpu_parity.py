@@ -277,13 +277,14 @@ def test_bf16x3_ragged_multi_chunk_f32_inputs():
 
 
 @pytest.mark.parametrize("S,chunk", [
-    (27, 26),   # 7 quads in the first chunk (full groups of three, one quad with
-                # two snapshots after them), then a chunk of one snapshot
-    (24, 24),   # exactly two full groups of three quads
+    (27, 26),   # first chunk: one full group of 16 snapshots (four quads), then
+                # two full quads and a quad of two snapshots; then a chunk of one
+    (24, 24),   # one full group of 16 snapshots and a half group (two quads)
+    (32, 32),   # exactly two full groups, no partial group or quad
 ])
 def test_bf16x3_snapshot_quad_groups(S, chunk):
-    # the split update reads snapshot quads from three register buffers in
-    # groups of three quads; Ny = 33: two plane tiles and a remainder plane
+    # the split update sums 16 snapshots (four 32-byte records of four) per
+    # matrix-core product; Ny = 33: two plane tiles and a remainder plane
     w = synth.workload("tiny", ny=33, S=S, M=6)
     y = synth.y_grid(w)
     snap = synth.snapshots(w, 100 + S)
