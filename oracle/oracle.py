@@ -253,5 +253,57 @@ def mirror_terms(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: floa
     return 0.5 * (t[:n] + SIGMA_Y[None, :, None, None] * t[n:])
 
 
+def _spectral_dr(f: np.ndarray, length: float, axis: int) -> np.ndarray:
+    """Spectral derivative of a real periodic map along one separation axis
+    (numpy's FFT as a library step), zero multiplier at the Nyquist index."""
+    n = f.shape[axis]
+    k = np.fft.fftfreq(n, d=1.0 / n)
+    mult = 2.0 * np.pi * k / length
+    if n % 2 == 0:
+        mult[n // 2] = 0.0
+    shape = [1] * f.ndim
+    shape[axis] = n
+    F = np.fft.fft(f, axis=axis)
+    return np.real(np.fft.ifft(1j * mult.reshape(shape) * F, axis=axis))
+
+
+def residual(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float, pairs,
+             prof: np.ndarray | None = None, nthreads: int | None = None, held=None):
+    """Residual of the budget in conservative form (eq. GKE-conservative),
+        div_r Phi + d phi / dY - xi,
+    for each ordered pair (Y1, Y2): array [npairs][nz][nx] over the full
+    periodic (rz, rx) plane.  Phi_rx = T2 + T3 + T4, Phi_ry = T5 + T6,
+    Phi_rz = T7 + T8, phi = T9 + T10 + T11, xi = T12 + T13 + T14.  The r_x and
+    r_z derivatives are spectral (Section "GKE and turbulence physics": the
+    homogeneous derivatives are spectral, the wall-normal ones use the same
+    finite differences as elsewhere); with Y1, Y2 as the variables (Section
+    "Step 3"), d/dry = (d/dY2 - d/dY1)/2 and d/dY = d/dY1 + d/dY2, each
+    d/dYk the five-point stencil applied to the term maps of the neighbour
+    pairs along that index.  With held=, the snapshots must hold the stencil
+    closure of the stencil closure of the pairs' planes."""
+    y = np.asarray(y, dtype=np.float64)
+    D = fd5_matrix(y)
+    pairs = [tuple(int(v) for v in p) for p in np.asarray(pairs).reshape(-1, 2)]
+    ring = list(pairs)
+    for (j1, j2) in pairs:
+        ring += [(int(m), j2) for m in np.nonzero(D[j1])[0]]
+        ring += [(j1, int(m)) for m in np.nonzero(D[j2])[0]]
+    ring = list(dict.fromkeys(ring))
+    T = pair_terms(snap, y, lx, lz, nu, ring, prof=prof, nthreads=nthreads, held=held)
+    idx = {p: i for i, p in enumerate(ring)}
+    phi_ry = lambda p: T[idx[p], 4] + T[idx[p], 5]
+    phi_y = lambda p: T[idx[p], 8] + T[idx[p], 9] + T[idx[p], 10]
+    out = np.empty((len(pairs),) + T.shape[2:])
+    for k, (j1, j2) in enumerate(pairs):
+        t = T[idx[(j1, j2)]]
+        div_r = (_spectral_dr(t[1] + t[2] + t[3], lx, axis=1)
+                 + _spectral_dr(t[6] + t[7], lz, axis=0))
+        d1 = lambda f: sum(D[j1, m] * f((int(m), j2)) for m in np.nonzero(D[j1])[0])
+        d2 = lambda f: sum(D[j2, m] * f((j1, int(m))) for m in np.nonzero(D[j2])[0])
+        div_r = div_r + 0.5 * (d2(phi_ry) - d1(phi_ry))
+        out[k] = div_r + d1(phi_y) + d2(phi_y) - (t[11] + t[12] + t[13])
+    return out
+
+
 def all_pairs(ny: int):
     return [(a, b) for a in range(ny) for b in range(ny)]
