@@ -68,7 +68,9 @@ enum {
     GKE_OPT_TIMING = 5,       /* 1: record HIP events around every kernel launch (any time) */
     GKE_OPT_MIRROR = 6,       /* 1: average every term with the reflected pair (below) */
     GKE_OPT_DOMAIN = 7,       /* output domain, GKE_DOMAIN_* (default ALLPAIRS_HALFRX) */
-    GKE_OPT_SLAB = 8          /* output Y1 rows per slab, 0 = all rows in one slab (default) */
+    GKE_OPT_SLAB = 8,         /* output Y1 rows per slab, 0 = all rows in one slab (default) */
+    GKE_OPT_RESIDUAL = 9      /* 1: reserve what gke_finalize needs to write the budget
+                                 residual (gke_terms.residual; all-pairs mode only) */
 };
 enum { GKE_DTYPE_F64 = 0, GKE_DTYPE_F32 = 1 };
 enum { GKE_PREC_FP64 = 0, GKE_PREC_BF16X3 = 1 };
@@ -121,7 +123,8 @@ enum {
 };
 
 /* Output of gke_finalize.  Each non-NULL t[i] is a caller-owned FP64 device
- * array.  Default (no mirror, all-pairs domain, one slab): maps T1..T13 are
+ * array (dtype GKE_OUT_F64, the only type this build writes; other values
+ * are refused with GKE_ERR_UNSUPPORTED).  Default (no mirror, all-pairs domain, one slab): maps T1..T13 are
  * laid out [Y1 0..Ny)[Y2 0..Ny)[q 0..Nz)[p 0..Nx/2] (all ordered pairs, the
  * half plane rx >= 0; the half rx <= 0 of pair (Y1,Y2) is the half rx >= 0 of
  * pair (Y2,Y1) by the r-inversion symmetry of Section "Exploiting
@@ -129,11 +132,24 @@ enum {
  * With mirror, another domain or slabs: the maps of the current slab are laid
  * out [n 0..npairs)[q 0..Nz)[p 0..width) with the slab's output pairs in the
  * order of gke_slab_pairs, width = Nx/2 + 1 (ALLPAIRS_HALFRX) or Nx (FULLR
- * domains), and T14 is laid out [n].  on_device must be 1. */
+ * domains), and T14 is laid out [n].  With rx / rz undersampling the q and p
+ * extents are the kept rows and columns (gke_sample_indices).  on_device must be 1. */
+enum { GKE_OUT_F64 = 0, GKE_OUT_F32 = 1 };
+/* Budget residual (optional, gke_terms.residual; needs GKE_OPT_RESIDUAL = 1
+ * and the all-pairs mode): the left-hand side minus the right-hand side of
+ * the budget in conservative form (eq. GKE-conservative, the validation of
+ * Section "GKE and turbulence physics"),
+ *   Res = d(T2 + T3 + T4)/drx + d(T7 + T8)/drz + (d/dY2 - d/dY1)(T5 + T6)/2
+ *         + (d/dY1 + d/dY2)(T9 + T10 + T11) - (T12 + T13 + T14),
+ * with spectral rx, rz derivatives (zero multipliers at the Nyquist
+ * wavenumbers) and the five-point stencil along Y1 and Y2, laid out like the
+ * maps T1..T13.  It is assembled from the caller's maps, so T1, T5, T6, T9,
+ * T10, T11, T12 and T13 must be requested too (else GKE_ERR_ARG). */
 typedef struct {
     void *t[GKE_NTERMS];
     int on_device;
-    int reserved;
+    int dtype;          /* GKE_OUT_F64 (0) */
+    void *residual;     /* budget residual map, or NULL */
 } gke_terms;
 
 /* profile rows returned by gke_get_profiles, each of length Ny (FP64):
@@ -161,6 +177,28 @@ gke_status gke_set_option(gke_plan_t plan, int key, int64_t value);
  * gke_set_workspace, GKE_OPT_CHUNK reports the chunk chosen for 0.
  * Errors: GKE_ERR_ARG (NULL, unknown key). */
 gke_status gke_get_option(gke_plan_t plan, int key, int64_t *value);
+
+/* rx / rz undersampling (Section "Undersampling and parallelisation": the
+ * correlations are always computed on the full grid and the stored maps keep
+ * full resolution below a first threshold of the separation, one point in s1
+ * between the two thresholds and one in s2 above the second; it drops output
+ * points only, so every derivative -- the spectral rx, rz ones of T4, T8 and
+ * of the residual, the five-point Y ones -- is taken at full resolution).
+ * dir = 0: rx, dir = 1: rz.  In grid-index units, a separation of signed
+ * index k (k = n, or n - N for n past N/2) is kept iff |k| < t1, or
+ * t1 <= |k| < t2 and |k| is a multiple of s1, or |k| >= t2 and |k| is a
+ * multiple of s2.  Default (t1, t2, s1, s2) = (0, 0, 1, 1): every separation.
+ * The output maps then hold [..][nrz][nrx] over the kept rows and columns,
+ * in increasing index order (gke_sample_indices).  Before gke_set_workspace.
+ * Errors: GKE_ERR_ARG (dir, t1 < 0, t2 < t1, a step < 1), GKE_ERR_STATE. */
+gke_status gke_set_undersampling(gke_plan_t plan, int dir, int t1, int t2, int s1, int s2);
+
+/* Kept grid indices of the output maps along rx (dir 0: among 0..Nx/2 in the
+ * ALLPAIRS_HALFRX domain, 0..Nx-1 in the full-r domains) or rz (dir 1, among
+ * 0..Nz-1), increasing: *count receives their number and idx, when not NULL,
+ * the indices (host array of at least Nx or Nz ints).  Follows the options in
+ * effect.  Errors: GKE_ERR_ARG, and those of gke_workspace_size. */
+gke_status gke_sample_indices(gke_plan_t plan, int dir, int *count, int *idx);
 
 /* Device workspace bytes the plan needs with its current options (fixes the
  * automatic chunk).  Errors: GKE_ERR_ARG (NULL; the fundamental domain without
@@ -254,9 +292,10 @@ gke_status gke_reset(gke_plan_t plan);
 
 /* kernel families reported by gke_timings (GKE_K_RANKK: the matrix-core
  * update of full 16-plane tiles; GKE_K_RANKK_REM: the pairs that involve the
- * last Ny mod 16 planes) */
+ * last Ny mod 16 planes; GKE_K_RESID: the two residual passes, the kz
+ * transform of its spectral divergence and its five-point Y part) */
 enum { GKE_K_PLANE_SUMS = 0, GKE_K_FLUCT_XFFT, GKE_K_ZFFT_PACK, GKE_K_RANKK, GKE_K_FIN_KZ,
-       GKE_K_FIN_KX, GKE_K_FD, GKE_K_SMALL, GKE_K_RANKK_REM, GKE_NKERNELS };
+       GKE_K_FIN_KX, GKE_K_FD, GKE_K_SMALL, GKE_K_RANKK_REM, GKE_K_RESID, GKE_NKERNELS };
 
 /* With GKE_OPT_TIMING set, HIP events bracket every kernel launch on the
  * plan's stream.  Synchronises the stream, then writes per kernel family the

@@ -268,40 +268,82 @@ def _spectral_dr(f: np.ndarray, length: float, axis: int) -> np.ndarray:
 
 
 def residual(snap: np.ndarray, y: np.ndarray, lx: float, lz: float, nu: float, pairs,
-             prof: np.ndarray | None = None, nthreads: int | None = None, held=None):
+             prof: np.ndarray | None = None, nthreads: int | None = None, held=None,
+             parts: bool = False):
     """Residual of the budget in conservative form (eq. GKE-conservative),
         div_r Phi + d phi / dY - xi,
     for each ordered pair (Y1, Y2): array [npairs][nz][nx] over the full
-    periodic (rz, rx) plane.  Phi_rx = T2 + T3 + T4, Phi_ry = T5 + T6,
-    Phi_rz = T7 + T8, phi = T9 + T10 + T11, xi = T12 + T13 + T14.  The r_x and
-    r_z derivatives are spectral (Section "GKE and turbulence physics": the
-    homogeneous derivatives are spectral, the wall-normal ones use the same
-    finite differences as elsewhere); with Y1, Y2 as the variables (Section
-    "Step 3"), d/dry = (d/dY2 - d/dY1)/2 and d/dY = d/dY1 + d/dY2, each
-    d/dYk the five-point stencil applied to the term maps of the neighbour
-    pairs along that index.  With held=, the snapshots must hold the stencil
-    closure of the stencil closure of the pairs' planes."""
+    periodic (rz, rx) plane, from the oracle's own term maps (pair_terms) of
+    the pairs and of their five-point neighbour pairs, by residual_of_maps.
+    With held=, the snapshots must hold the stencil closure of the stencil
+    closure of the pairs' planes."""
     y = np.asarray(y, dtype=np.float64)
+    ring = neighbour_pairs(y, pairs)
+    T = pair_terms(snap, y, lx, lz, nu, ring, prof=prof, nthreads=nthreads, held=held)
+    idx = {p: i for i, p in enumerate(ring)}
+    return residual_of_maps(lambda p: T[idx[p]], y, lx, lz, pairs, parts=parts)
+
+
+def neighbour_pairs(y: np.ndarray, pairs) -> list:
+    """The pairs and their five-point neighbours along Y1 and along Y2."""
     D = fd5_matrix(y)
     pairs = [tuple(int(v) for v in p) for p in np.asarray(pairs).reshape(-1, 2)]
     ring = list(pairs)
     for (j1, j2) in pairs:
         ring += [(int(m), j2) for m in np.nonzero(D[j1])[0]]
         ring += [(j1, int(m)) for m in np.nonzero(D[j2])[0]]
-    ring = list(dict.fromkeys(ring))
-    T = pair_terms(snap, y, lx, lz, nu, ring, prof=prof, nthreads=nthreads, held=held)
-    idx = {p: i for i, p in enumerate(ring)}
-    phi_ry = lambda p: T[idx[p], 4] + T[idx[p], 5]
-    phi_y = lambda p: T[idx[p], 8] + T[idx[p], 9] + T[idx[p], 10]
-    out = np.empty((len(pairs),) + T.shape[2:])
+    return list(dict.fromkeys(ring))
+
+
+def residual_of_maps(maps, y: np.ndarray, lx: float, lz: float, pairs, parts: bool = False):
+    """The residual operator applied to given term maps: maps(pair) returns
+    the 14 full-plane maps [14][nz][nx] of an ordered pair and is called for
+    the pairs and their neighbour_pairs.  Phi_rx = T2 + T3 + T4,
+    Phi_ry = T5 + T6, Phi_rz = T7 + T8, phi = T9 + T10 + T11,
+    xi = T12 + T13 + T14.  The r_x and r_z derivatives are spectral (Section
+    "GKE and turbulence physics": the homogeneous derivatives are spectral,
+    the wall-normal ones use the same finite differences as elsewhere); with
+    Y1, Y2 as the variables (Section "Step 3"), d/dry = (d/dY2 - d/dY1)/2 and
+    d/dY = d/dY1 + d/dY2, each d/dYk the five-point stencil applied to the
+    maps of the neighbour pairs along that index.  parts=True also returns the
+    four parts [npairs][4][nz][nx]: the r_x + r_z divergence, the r_y
+    divergence, the Y derivative of phi, and xi (residual = the first three
+    minus xi)."""
+    y = np.asarray(y, dtype=np.float64)
+    D = fd5_matrix(y)
+    pairs = [tuple(int(v) for v in p) for p in np.asarray(pairs).reshape(-1, 2)]
+    phi_ry = lambda p: maps(p)[4] + maps(p)[5]
+    phi_y = lambda p: maps(p)[8] + maps(p)[9] + maps(p)[10]
+    first = maps(pairs[0])
+    out = np.empty((len(pairs),) + first.shape[1:])
+    part = np.empty((len(pairs), 4) + first.shape[1:])
     for k, (j1, j2) in enumerate(pairs):
-        t = T[idx[(j1, j2)]]
-        div_r = (_spectral_dr(t[1] + t[2] + t[3], lx, axis=1)
-                 + _spectral_dr(t[6] + t[7], lz, axis=0))
+        t = maps((j1, j2))
+        div_xz = (_spectral_dr(t[1] + t[2] + t[3], lx, axis=1)
+                  + _spectral_dr(t[6] + t[7], lz, axis=0))
         d1 = lambda f: sum(D[j1, m] * f((int(m), j2)) for m in np.nonzero(D[j1])[0])
         d2 = lambda f: sum(D[j2, m] * f((j1, int(m))) for m in np.nonzero(D[j2])[0])
-        div_r = div_r + 0.5 * (d2(phi_ry) - d1(phi_ry))
-        out[k] = div_r + d1(phi_y) + d2(phi_y) - (t[11] + t[12] + t[13])
+        div_y = 0.5 * (d2(phi_ry) - d1(phi_ry))
+        dphi = d1(phi_y) + d2(phi_y)
+        xi = t[11] + t[12] + t[13]
+        part[k] = (div_xz, div_y, dphi, xi)
+        out[k] = div_xz + div_y + dphi - xi
+    return (out, part) if parts else out
+
+
+def sample_indices(n: int, t1: int, t2: int, s1: int, s2: int, half: bool) -> list:
+    """Grid indices of the separations kept by the two-threshold undersampling
+    (Section "Undersampling and parallelisation": full resolution below the
+    first threshold, one point in s1 between the thresholds, one in s2 above
+    the second; readings: thresholds and steps in grid-index units, steps
+    counted from zero separation, applied to |separation|).  Indices 0..n/2
+    (half=True, the rx >= 0 half plane) or 0..n-1 (signed separation n - N for
+    indices past N/2), increasing."""
+    out = []
+    for i in range(n // 2 + 1 if half else n):
+        k = abs(i if i <= n // 2 else i - n)
+        if k < t1 or (k < t2 and k % s1 == 0) or (k >= t2 and k % s2 == 0):
+            out.append(i)
     return out
 
 

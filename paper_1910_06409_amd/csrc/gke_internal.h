@@ -39,10 +39,13 @@ struct SplitRec {
 // term spectra accumulated per unordered pair tile (see k_rankk.hip)
 enum { S_R = 0, S_FX, S_FY, S_FZ, S_PHI, S_PP, S_UVS, S_UVA, NSPEC };
 
-// r-space maps produced by the inverse transforms in finalize
-enum { M_R = 0, M_DRX, M_DRZ, M_FX, M_FY, M_FZ, M_PHI, M_PP, M_UVS, M_UVA, NMAP };
+// r-space maps produced by the inverse transforms in finalize; M_H, the
+// spectral divergence of the homogeneous scale fluxes (the r_x and r_z part
+// of the budget residual), only when the residual is requested
+enum { M_R = 0, M_DRX, M_DRZ, M_FX, M_FY, M_FZ, M_PHI, M_PP, M_UVS, M_UVA, NMAP, M_H = NMAP };
 // planes of the finalize intermediate (kz-transformed spectra): every map but
-// M_DRX, which the kx pass forms from the M_R plane (i alpha is constant along kz)
+// M_DRX, which the kx pass forms from the M_R plane (i alpha is constant along kz);
+// M_H takes plane NMID after them
 constexpr int NMID = NMAP - 1;
 __host__ __device__ inline int mid_plane(int m) { return m == M_DRX ? M_R : m > M_DRX ? m - 1 : m; }
 
@@ -110,6 +113,8 @@ struct Dims {
                       // every 16-plane tile of a row starts on a 128-byte line
     int nqs;          // split path: snapshot quads per chunk, (chunk + 3) / 4
     int prec;         // PREC_FP64 or PREC_BF16X3
+    int nqo, npo;     // rows (rz) and columns (rx) of an output map: the separations kept
+                      // by the rx/rz undersampling (Nz and Nx/2 + 1 or Nx without it)
     double lx, lz, nu;
 };
 
@@ -167,6 +172,9 @@ struct Tables {
     const int *rowidx;       // [ny] row of plane Y1 in the full-plane map buffer, or -1
     const int *pairs;        // [npair] pair table
     const int *pidx;         // [ny][ny] compact pair index of (Y1, Y2), either order
+    const int *rzk;          // [nqo] rz index of each output row (kept separations)
+    const int *rzinv;        // [nz] output row of rz index q, -1 if not kept
+    const int *rxk;          // [npo] rx index of each output column
     FftPlanDev px, pz;
 };
 
@@ -234,18 +242,30 @@ hipError_t launch_rankk_rem_bf16x3(hipStream_t st, const Dims &d, const Tables &
 hipError_t launch_fin_kz(hipStream_t st, const Dims &d, const Tables &t,
                          const cx<double> *acc, int p0, int p1, double inv_count,
                          cx<double> *mid);
+// residual: the spectral divergence of the homogeneous fluxes,
+//   H^ = i alpha FX^ + i beta FZ^ - 2 (U(Y2) - U(Y1)) i alpha R^ - 4 nu (alpha^2 + beta^2) R^,
+// of the pairs [p0, p1), scaled by 1/count, inverse-transformed along kz into
+// mid plane NMID (the kx pass then transforms it as map M_H)
+hipError_t launch_fin_kz_h(hipStream_t st, const Dims &d, const Tables &t,
+                           const cx<double> *acc, int p0, int p1, double inv_count,
+                           const double *prof, cx<double> *mid);
 // finalize: inverse real transform along kx, FP64 assembly.  full = 0: both
 // orientations into the all-pairs half-plane maps out[t][Y1][Y2][rz][rx <= Nx/2];
 // full = 1: orientation (Y1, Y2) of the pair code only, every rx, into
 // out[t][rowidx[Y1]][Y2][rz][rx < Nx]
 hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
                          const cx<double> *mid, int p0, int p1, const double *prof,
-                         double *const *out, int full);
+                         double *const *out, int full, double *resid);
+// residual, Y part: resid += (d/dY2 - d/dY1)(T5 + T6)/2 + (d/dY1 + d/dY2)(T9 + T10 + T11)
+// - (T12 + T13 + T14), five-point derivatives along Y1 and Y2 of the maps
+// out[t][Y1][Y2][rz][rx <= Nx/2]; resid holds the homogeneous part on entry
+hipError_t launch_resid(hipStream_t st, const Dims &d, const Tables &t, double *const *out,
+                        const double *prof, double *resid);
 // general output modes: mirror average, output domain, T6/T11/T14, from the
 // full-plane map buffer of the slab rows (see k_final.hip)
 hipError_t launch_slab_out(hipStream_t st, const Dims &d, const Tables &t, const double *mf,
                            size_t mstride, const int *opairs, int nopairs, const double *prof,
-                           int mirror, int width, double *const *out);
+                           int mirror, double *const *out);
 // band accumulators for eps in the general modes: band[a][Y][k] += sum over the
 // chunk of sum_i Re conj(u_i^(k; Y)) u_i^(k; Y + a), a = 0..4
 hipError_t launch_band(hipStream_t st, const Dims &d, const void *spec, int nsnap,

@@ -38,6 +38,9 @@ struct gke_plan_s {
     int chunk = 64;
     int pair_batch = 0;  // pairs per finalize batch (0 = all)
     int mirror = 0, domain = GKE_DOMAIN_ALLPAIRS_HALFRX, slab_rows = 0;
+    int residual = 0;              // mid holds one more plane for the budget residual
+    int us[2][4] = {{0, 0, 1, 1}, {0, 0, 1, 1}};   // rx, rz undersampling: t1 t2 s1 s2
+    std::vector<int> h_rzk, h_rzinv, h_rxk;        // kept separations (output rows, columns)
     bool general = false;          // mirror, a FULLR domain or slabs
     std::vector<SlabTables> slabs;
     int cur_slab = 0;
@@ -58,6 +61,7 @@ struct gke_plan_s {
     double *w5 = nullptr;
     int *j0 = nullptr, *ta = nullptr, *tb = nullptr, *pairs = nullptr, *pidx = nullptr;
     int *rowplane = nullptr, *rowidx = nullptr, *opairs = nullptr;
+    int *rzk = nullptr, *rzinv = nullptr, *rxk = nullptr;
     double *mf = nullptr, *band = nullptr;
     size_t mstride = 0;            // doubles per term map in mf
     double *sums1 = nullptr, *prof = nullptr, *momp = nullptr, *r0 = nullptr, *gxz = nullptr;
@@ -271,6 +275,39 @@ void build_slabs(gke_plan_t p)
     }
 }
 
+// Separations kept by the two-threshold undersampling (Section "Undersampling
+// and parallelisation": full resolution below the first threshold, every s1-th
+// point between the thresholds, every s2-th above the second), per direction:
+// a grid index n of signed separation k (k = n, or n - N past N/2) is kept iff
+// |k| < t1, or |k| < t2 and |k| is a multiple of s1, or |k| >= t2 and |k| is a
+// multiple of s2.  The set is symmetric in the sign of k.
+bool kept(int k, const int *u)
+{
+    const int m = k < 0 ? -k : k;
+    if (m < u[0]) return true;
+    return m < u[1] ? m % u[2] == 0 : m % u[3] == 0;
+}
+
+// Output rows (rz) and columns (rx: 0..Nx/2 in the half-plane domains, 0..Nx-1
+// in the full-r ones) of the plan's maps.
+void build_samples(gke_plan_t p)
+{
+    gke::Dims &d = p->d;
+    p->h_rzk.clear();
+    p->h_rzinv.assign(d.nz, -1);
+    for (int q = 0; q < d.nz; ++q)
+        if (kept(q <= d.nz / 2 ? q : q - d.nz, p->us[1])) {
+            p->h_rzinv[q] = (int)p->h_rzk.size();
+            p->h_rzk.push_back(q);
+        }
+    const int width = p->domain == GKE_DOMAIN_ALLPAIRS_HALFRX ? d.nkx : d.nx;
+    p->h_rxk.clear();
+    for (int c = 0; c < width; ++c)
+        if (kept(c <= d.nx / 2 ? c : c - d.nx, p->us[0])) p->h_rxk.push_back(c);
+    d.nqo = (int)p->h_rzk.size();
+    d.npo = (int)p->h_rxk.size();
+}
+
 // Precision-dependent shapes of the z pass: the row groups of the
 // x-transformed layout it reads, its block shape (the smaller one when the
 // transforms are FP32, on the split path, and it still holds eight planes,
@@ -346,6 +383,9 @@ size_t layout(gke_plan_t p, char *base)
     p->rowplane = (int *)take(sizeof(int) * nrowp);
     p->rowidx = (int *)take(sizeof(int) * d.ny);
     p->opairs = (int *)take(sizeof(int) * nopairs);
+    p->rzk = (int *)take(sizeof(int) * d.nz);
+    p->rzinv = (int *)take(sizeof(int) * d.nz);
+    p->rxk = (int *)take(sizeof(int) * d.nx);
     p->sums1 = (double *)take(sizeof(double) * 4 * d.ny * gke::NSPLIT);
     p->prof = (double *)take(sizeof(double) * gke::NPROF * d.ny);
     p->momp = (double *)take(sizeof(double) * d.ny * gke::NMOMP * d.nzb);
@@ -358,7 +398,8 @@ size_t layout(gke_plan_t p, char *base)
     p->spec = take(split ? sizeof(gke::SplitRec) * (size_t)d.nk * gke::NFIELD * d.nqs * d.nys
                          : sizeof(cx<double>) * (size_t)d.nk * gke::NFIELD * d.chunk * d.nys);
     p->acc = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NSPEC * d.nk * round8(npair));
-    p->mid = (cx<double> *)take(sizeof(cx<double>) * (size_t)gke::NMID * d.nkx * d.nz * round8(pbt));
+    const size_t nmid = gke::NMID + (p->residual && !p->general ? 1 : 0);
+    p->mid = (cx<double> *)take(sizeof(cx<double>) * nmid * d.nkx * d.nz * round8(pbt));
     p->mstride = nrows * d.ny * (size_t)d.nz * d.nx;
     p->mf = (double *)take(sizeof(double) * gke::NSTORED * p->mstride);
     p->band = (double *)take(p->general ? sizeof(double) * (size_t)d.nk * 5 * d.ny : 0);
@@ -613,6 +654,10 @@ gke_status gke_set_option(gke_plan_t p, int key, int64_t value)
         if (value < 0 || value > 4096) return fail(p, GKE_ERR_ARG, "slab rows must be in [0, 4096]");
         p->slab_rows = (int)value;
         return GKE_OK;
+    case GKE_OPT_RESIDUAL:
+        if (value != 0 && value != 1) return fail(p, GKE_ERR_ARG, "residual must be 0 or 1");
+        p->residual = (int)value;
+        return GKE_OK;
     default:
         return fail(p, GKE_ERR_ARG, "unknown option key");
     }
@@ -648,6 +693,7 @@ gke_status prepare_mode(gke_plan_t p)
     p->general = p->mirror || p->domain != GKE_DOMAIN_ALLPAIRS_HALFRX || p->slab_rows > 0;
     if (p->general) build_slabs(p);
     else p->slabs.clear();
+    build_samples(p);
     return GKE_OK;
 }
 
@@ -663,6 +709,7 @@ gke_status gke_get_option(gke_plan_t p, int key, int64_t *value)
     case GKE_OPT_MIRROR: *value = p->mirror; return GKE_OK;
     case GKE_OPT_DOMAIN: *value = p->domain; return GKE_OK;
     case GKE_OPT_SLAB: *value = p->slab_rows; return GKE_OK;
+    case GKE_OPT_RESIDUAL: *value = p->residual; return GKE_OK;
     default: return fail(p, GKE_ERR_ARG, "unknown option key");
     }
 }
@@ -705,6 +752,9 @@ gke_status attach_workspace(gke_plan_t p, void *dev, size_t bytes)
         GKE_HIP(p, hipMemcpyAsync(p->rowplane, p->h_rowplane.data(), sizeof(int) * p->h_rowplane.size(), hipMemcpyHostToDevice, st));
     }
     GKE_HIP(p, hipMemcpyAsync(p->pidx, p->h_pidx.data(), sizeof(int) * d.ny * d.ny, hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->rzk, p->h_rzk.data(), sizeof(int) * p->h_rzk.size(), hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->rzinv, p->h_rzinv.data(), sizeof(int) * d.nz, hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->rxk, p->h_rxk.data(), sizeof(int) * p->h_rxk.size(), hipMemcpyHostToDevice, st));
     // sums, profiles and moment partials start at zero
     GKE_HIP(p, gke::launch_zero(st, p->sums1, (char *)p->inter - (char *)p->sums1));
     GKE_HIP(p, hipStreamSynchronize(st));
@@ -720,6 +770,9 @@ gke_status attach_workspace(gke_plan_t p, void *dev, size_t bytes)
     p->tab.pidx = p->pidx;
     p->tab.rowplane = p->rowplane;
     p->tab.rowidx = p->rowidx;
+    p->tab.rzk = p->rzk;
+    p->tab.rzinv = p->rzinv;
+    p->tab.rxk = p->rxk;
     if (p->general) return select_slab(p, 0);
     return GKE_OK;
 }
@@ -788,6 +841,32 @@ gke_status gke_set_static_workspace(gke_plan_t p)
         if (s != GKE_OK) return s;
     }
     return attach_workspace(p, dev, (size_t)GKE_STATIC_WORKSPACE_BYTES);
+}
+
+gke_status gke_set_undersampling(gke_plan_t p, int dir, int t1, int t2, int s1, int s2)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (p->ws) return fail(p, GKE_ERR_STATE, "undersampling is fixed once the workspace is set");
+    if (dir != 0 && dir != 1) return fail(p, GKE_ERR_ARG, "dir must be 0 (rx) or 1 (rz)");
+    if (t1 < 0 || t2 < t1 || s1 < 1 || s2 < 1)
+        return fail(p, GKE_ERR_ARG, "need 0 <= t1 <= t2 and steps >= 1");
+    const int u[4] = {t1, t2, s1, s2};
+    for (int k = 0; k < 4; ++k) p->us[dir][k] = u[k];
+    return GKE_OK;
+}
+
+gke_status gke_sample_indices(gke_plan_t p, int dir, int *count, int *idx)
+{
+    if (!p || !count) return fail(p, GKE_ERR_ARG, "NULL argument");
+    if (dir != 0 && dir != 1) return fail(p, GKE_ERR_ARG, "dir must be 0 (rx) or 1 (rz)");
+    if (!p->ws) {   // the lists follow the options in effect
+        gke_status s = prepare_mode(p);
+        if (s != GKE_OK) return s;
+    }
+    const std::vector<int> &v = dir == 0 ? p->h_rxk : p->h_rzk;
+    *count = (int)v.size();
+    if (idx) std::copy(v.begin(), v.end(), idx);
+    return GKE_OK;
 }
 
 gke_status gke_set_stream(gke_plan_t p, void *stream)
@@ -875,8 +954,21 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
     if (!p->second_scan || p->n2 == 0) return fail(p, GKE_ERR_STATE, "no second-scan snapshot");
     if (!p->means_from_host && p->n1 != p->n2)
         return fail(p, GKE_ERR_STATE, "the two scans saw different snapshot counts");
+    if (out->dtype != GKE_OUT_F64)
+        return fail(p, GKE_ERR_UNSUPPORTED, "output dtype not supported");
     if (!p->general && (out->t[GKE_T_PHIY_V] || out->t[GKE_T_PHI_V]) && !out->t[GKE_T_DU2])
         return fail(p, GKE_ERR_ARG, "the Y-derivative terms need the <du^2> output buffer");
+    double *resid = (double *)out->residual;
+    if (resid) {
+        if (p->general)
+            return fail(p, GKE_ERR_UNSUPPORTED, "the residual is written in the all-pairs mode only");
+        if (!p->residual)
+            return fail(p, GKE_ERR_STATE, "the residual needs GKE_OPT_RESIDUAL = 1 before the workspace");
+        for (int k : {GKE_T_DU2, GKE_T_PHIY_T, GKE_T_PHIY_V, GKE_T_PHI_T, GKE_T_PHI_P, GKE_T_PHI_V,
+                      GKE_T_XI_P1, GKE_T_XI_P2})
+            if (!out->t[k])
+                return fail(p, GKE_ERR_ARG, "the residual needs the maps T1, T5, T6, T9-T13");
+    }
     gke_status s = launch_flush(p);
     if (s != GKE_OK) return s;
     const gke::Dims &d = p->d;
@@ -905,14 +997,13 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
                 return gke::launch_fin_kz(st, d, p->tab, p->acc, q0, q1, inv, p->mid);
             }));
             GKE_HIP(p, timed(p, GKE_K_FIN_KX, [&] {
-                return gke::launch_fin_kx(st, d, p->tab, p->mid, q0, q1, p->prof, mfp, 1);
+                return gke::launch_fin_kx(st, d, p->tab, p->mid, q0, q1, p->prof, mfp, 1, nullptr);
             }));
         }
         const SlabTables &t = p->slabs[p->cur_slab];
-        const int width = p->domain == GKE_DOMAIN_ALLPAIRS_HALFRX ? d.nkx : d.nx;
         GKE_HIP(p, timed(p, GKE_K_FD, [&] {
             return gke::launch_slab_out(st, d, p->tab, p->mf, p->mstride, p->opairs,
-                                        (int)t.opairs.size(), p->prof, p->mirror, width, outp);
+                                        (int)t.opairs.size(), p->prof, p->mirror, outp);
         }));
         GKE_HIP(p, hipStreamSynchronize(st));
         return GKE_OK;
@@ -922,14 +1013,22 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
         GKE_HIP(p, timed(p, GKE_K_FIN_KZ, [&] {
             return gke::launch_fin_kz(st, d, p->tab, p->acc, q0, q1, inv, p->mid);
         }));
+        if (resid)
+            GKE_HIP(p, timed(p, GKE_K_RESID, [&] {
+                return gke::launch_fin_kz_h(st, d, p->tab, p->acc, q0, q1, inv, p->prof, p->mid);
+            }));
         GKE_HIP(p, timed(p, GKE_K_FIN_KX, [&] {
-            return gke::launch_fin_kx(st, d, p->tab, p->mid, q0, q1, p->prof, outp, 0);
+            return gke::launch_fin_kx(st, d, p->tab, p->mid, q0, q1, p->prof, outp, 0, resid);
         }));
     }
     if (outp[GKE_T_PHIY_V] || outp[GKE_T_PHI_V])
         GKE_HIP(p, timed(p, GKE_K_FD, [&] {
             return gke::launch_fd_terms(st, d, p->tab, outp[GKE_T_DU2], outp[GKE_T_PHIY_V],
                                         outp[GKE_T_PHI_V]);
+        }));
+    if (resid)
+        GKE_HIP(p, timed(p, GKE_K_RESID, [&] {
+            return gke::launch_resid(st, d, p->tab, outp, p->prof, resid);
         }));
     if (outp[GKE_T_XI_D])
         GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {

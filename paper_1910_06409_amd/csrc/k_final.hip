@@ -116,15 +116,117 @@ hipError_t launch_fin_kz(hipStream_t st, const Dims &d, const Tables &t,
     return hipGetLastError();
 }
 
+// Residual of the budget, homogeneous part (eq. GKE-conservative: the r_x and
+// r_z divergence of the scale fluxes, spectral as in Section "GKE and
+// turbulence physics").  With Phi_rx = T2 + T3 + T4 and Phi_rz = T7 + T8, whose
+// r-dependent spectra are FX^ (T2), -2 dU R^ (T3 = dU <du^2>, <du^2> = const
+// - 2 R), 4 nu i alpha R^ (T4), FZ^ (T7) and 4 nu i beta R^ (T8):
+//   H^ = i alpha FX^ + i beta FZ^ - 2 dU i alpha R^ - 4 nu (alpha^2 + beta^2) R^,
+// dU = U(Y2) - U(Y1), zero multipliers at the Nyquist wavenumbers.  One block
+// per (pb pairs, kx): the three spectra are read one after the other into the
+// same per-thread elements, then the kz transform as in k_fin_kz, into mid
+// plane NMID.
+constexpr int MAX_PBZ = 16;
+__global__ GKE_FFT_BOUNDS void k_fin_kz_h(const cx<double> *__restrict__ acc, Dims d, Tables t,
+                                          int p0, int ptot, double inv_count,
+                                          const double *__restrict__ prof,
+                                          cx<double> *__restrict__ mid)
+{
+    extern __shared__ cx<double> lds[];
+    __shared__ double sdu[MAX_PBZ];
+    const int nz = d.nz, nkx = d.nkx, pb = d.pbz, ny = d.ny;   // pb <= MAX_PBZ (host)
+    const int kx = blockIdx.y;
+    const int pl0 = blockIdx.x * pb;
+    const int np = min(pb, ptot - pl0);
+    if (np <= 0) return;                                       // whole block
+    const size_t pall = (size_t)d.pstr;
+    const size_t mst = (size_t)mid_stride(ptot);
+    const int bs = fft_stride(nz);
+    const double two_pi = 6.283185307179586476925286766559;
+    cx<double> *tw = lds + pb * bs;
+    if ((int)threadIdx.x < np) {
+        const int code = t.pairs[p0 + pl0 + threadIdx.x];
+        sdu[threadIdx.x] = prof[P_U * ny + pair_j2(code)] - prof[P_U * ny + pair_j1(code)];
+    }
+    TwiddleCopy<double, FFT_BLOCK> twc;
+    twc.load(t.twz, nz);
+    twc.store(tw, t.twz, nz);
+    __syncthreads();
+    const double al = (2 * kx == d.nx) ? 0.0 : two_pi * kx / d.lx;
+    const double bscale = two_pi / d.lz;
+    const int ps = (int)pall;   // nz * pall < 2^31 (host)
+    constexpr int MAXE = (FFT_CAP + FFT_BLOCK - 1) / FFT_BLOCK;
+    cx<double> h[MAXE];
+    // elements past the end take (nz - 1, 0) and compute its value (stores repeat it)
+    const int sps[3] = {S_R, S_FX, S_FZ};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const cx<double> *ab = acc + ((size_t)sps[k] * d.nk + (size_t)kx * nz) * pall + p0 + pl0;
+        cx<double> x[MAXE];
+        Walk2 w(threadIdx.x, FFT_BLOCK, np);   // (kz, b)
+#pragma unroll
+        for (int q = 0; q < MAXE; ++q) {
+            const bool ok = w.hi < nz;
+            x[q] = ab[(ok ? w.hi : nz - 1) * ps + (ok ? w.lo : 0)];
+            w.next();
+        }
+        w = Walk2(threadIdx.x, FFT_BLOCK, np);
+#pragma unroll
+        for (int q = 0; q < MAXE; ++q) {
+            const bool ok = w.hi < nz;
+            const int kz = ok ? w.hi : nz - 1, b = ok ? w.lo : 0;
+            w.next();
+            const int kzs = (kz <= nz / 2) ? kz : kz - nz;
+            const double be = (2 * kz == nz) ? 0.0 : bscale * kzs;
+            const cx<double> X = cscale(x[q], inv_count);
+            if (k == 0) {        // -(2 dU i alpha + 4 nu (alpha^2 + beta^2)) R^
+                const double c = -4.0 * d.nu * (al * al + be * be), s = -2.0 * sdu[b] * al;
+                h[q] = cx<double>{c * X.x - s * X.y, c * X.y + s * X.x};
+            } else if (k == 1) { // + i alpha FX^
+                h[q] = cx<double>{h[q].x - al * X.y, h[q].y + al * X.x};
+            } else {             // + i beta FZ^
+                h[q] = cx<double>{h[q].x - be * X.y, h[q].y + be * X.x};
+                lds[b * bs + fft_pad(kz)] = h[q];
+            }
+        }
+    }
+    __syncthreads();
+    lds_fft_ip<double, FFT_CAP, FFT_BLOCK>(lds, np, bs, t.pz, tw, +1);
+    const size_t mplane = (size_t)nkx * nz * mst;
+    const int cnt = nz * np;
+    Walk2 ws(threadIdx.x, FFT_BLOCK, np);   // (rz, b)
+    for (int e = threadIdx.x; e < cnt; e += FFT_BLOCK) {
+        const int rz = ws.hi, b = ws.lo;
+        ws.next();
+        mid[(size_t)NMID * mplane + ((size_t)kx * nz + rz) * mst + pl0 + b] =
+            lds[b * bs + fft_pad(rz)];
+    }
+}
+
+hipError_t launch_fin_kz_h(hipStream_t st, const Dims &d, const Tables &t,
+                           const cx<double> *acc, int p0, int p1, double inv_count,
+                           const double *prof, cx<double> *mid)
+{
+    if (d.pbz > MAX_PBZ) return hipErrorInvalidValue;
+    const int ptot = p1 - p0;
+    const size_t lds = sizeof(cx<double>) * ((size_t)d.pbz * fft_stride(d.nz) + d.nz);
+    dim3 grid((ptot + d.pbz - 1) / d.pbz, d.nkx, 1);
+    set_lds_limit(k_fin_kz_h);
+    hipLaunchKernelGGL(k_fin_kz_h, grid, dim3(FFT_BLOCK), lds, st, acc, d, t, p0, ptot,
+                       inv_count, prof, mid);
+    return hipGetLastError();
+}
+
 struct OutPtrs {
     double *t[14];
+    double *res;   // residual map (its homogeneous part, map M_H), or NULL
 };
 
 // sign of each map under r-inversion: map(r; Y2, Y1) = sigma * map(-r; Y1, Y2)
 __device__ __forceinline__ double map_sigma(int m)
 {
     switch (m) {
-    case M_R: case M_PHI: case M_PP: case M_UVS: return 1.0;
+    case M_R: case M_PHI: case M_PP: case M_UVS: case M_H: return 1.0;
     default: return -1.0;
     }
 }
@@ -181,6 +283,9 @@ __device__ __forceinline__ void assemble_store(int m, double val, double a1, dou
     case M_UVS:
         if (out.t[11]) out.t[11][o] = -2.0 * (a1 + a2 - val) * 0.5 * (b1 + b2);
         break;
+    case M_H:
+        if (out.res) out.res[o] = val;
+        break;
     default:  // M_UVA
         if (out.t[12]) out.t[12][o] = -(a2 - a1 + val) * (b2 - b1);
         break;
@@ -197,9 +302,10 @@ struct PairInfo {
 // transform), then assembly for pair (Y1, Y2) and, when the pair table asks
 // for it, the mirrored pair (Y2, Y1) from r -> -r.
 //   Transform c packs pairs 2c and 2c + 1: A_c[n] = X_2c[n] + i X_2c+1[n] with
-//   X[n] for n > Nx/2 from Hermitian symmetry, X[Nx - kx] = conj X[kx]; the
-//   real and imaginary parts of its inverse are the two maps.  A thread loads
-//   both pairs of (kx, c) (adjacent in mid) and writes A_c[kx] and A_c[Nx - kx].
+//   X[n] for n > Nx/2 from Hermitian symmetry, X[Nx - kx] = conj X[kx], and
+//   the real parts of X[0] and X[Nx/2] (values of real maps); the real and
+//   imaginary parts of its inverse are the two maps.  A thread loads both
+//   pairs of (kx, c) (adjacent in mid) and writes A_c[kx] and A_c[Nx - kx].
 //   Output: a group of tpp consecutive threads per pair, consecutive threads
 //   on consecutive rx.
 template <int BLOCK>
@@ -212,7 +318,9 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fin_kx(const cx<double
     extern __shared__ cx<double> lds[];
     const int nx = d.nx, nz = d.nz, nkx = d.nkx, ny = d.ny, nt = d.ntx;
     const int npair = 2 * nt;
-    const int pblk = blockIdx.x, rz = blockIdx.y, m = blockIdx.z;
+    const int pblk = blockIdx.x, m = blockIdx.z;
+    // full-plane mode: every rz; all-pairs mode: the kept rz rows only
+    const int rz = full ? (int)blockIdx.y : t.rzk[blockIdx.y];
     const int pl0 = pblk * npair;
     const int np = min(npair, ptot - pl0);
     const int bs = fft_stride(nx);
@@ -278,10 +386,18 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fin_kx(const cx<double
                 b = cx<double>{-al * b.y, al * b.x};
             }
             cx<double> *Ac = A + c * bs;
-            Ac[fft_pad(kx)] = cx<double>{a.x - b.y, a.y + b.x};  // a + i b
-            const int kn = (kx == 0 || 2 * kx == nx) ? kx : nx - kx;
-            Ac[fft_pad(kn)] = kn == kx ? cx<double>{a.x - b.y, a.y + b.x}
-                                       : cx<double>{a.x + b.y, b.x - a.y};   // conj a + i conj b
+            const bool self = kx == 0 || 2 * kx == nx;   // its own Hermitian partner
+            if (self) {
+                // the kz-transformed values of a real map at kx = 0 and Nx/2 are
+                // real; keeping the real parts is the Hermitian average of the
+                // accumulated +kz and -kz bins (exact for exact spectra), so
+                // their rounding does not leak into the other pair of the
+                // packed transform
+                Ac[fft_pad(kx)] = cx<double>{a.x, b.x};
+            } else {
+                Ac[fft_pad(kx)] = cx<double>{a.x - b.y, a.y + b.x};          // a + i b
+                Ac[fft_pad(nx - kx)] = cx<double>{a.x + b.y, b.x - a.y};     // conj a + i conj b
+            }
         }
     }
     if ((int)threadIdx.x < np) pinfo[threadIdx.x] = pi;
@@ -301,31 +417,38 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fin_kx(const cx<double
         }
         return;
     }
+    // output maps [Y1][Y2][row of rz][column of rx] over the kept separations
+    // (every rz and rx <= Nx/2 without undersampling: identity tables); the
+    // kept set is symmetric in the sign of the separation, so -rz is kept too
     const double sig = map_sigma(m);
-    const size_t plane = (size_t)nz * nkx;
-    const size_t o0 = ((size_t)p.j1 * ny + p.j2) * plane + (size_t)rz * nkx;
+    const int npo = d.npo;
+    const bool sampled = npo != nkx;
+    const size_t plane = (size_t)d.nqo * npo;
+    const size_t o0 = ((size_t)p.j1 * ny + p.j2) * plane + (size_t)blockIdx.y * npo;
     const int rzm = (rz == 0) ? 0 : nz - rz;
-    const size_t om = ((size_t)p.j2 * ny + p.j1) * plane + (size_t)rzm * nkx;
-    for (int rx = lane; rx < nkx; rx += tpp) {
+    const size_t om = ((size_t)p.j2 * ny + p.j1) * plane + (size_t)t.rzinv[rzm] * npo;
+    for (int c = lane; c < npo; c += tpp) {
+        const int rx = sampled ? t.rxk[c] : c;
         const cx<double> zv = Ac[fft_pad(rx)];
-        assemble_store(m, (b & 1) ? zv.y : zv.x, p.a1, p.a2, p.b1, p.b2, d.nu, out, o0 + rx);
+        assemble_store(m, (b & 1) ? zv.y : zv.x, p.a1, p.a2, p.b1, p.b2, d.nu, out, o0 + c);
         if (p.mirror) {   // (Y2, Y1) at -r: the profile roles swap
             const cx<double> zm = Ac[fft_pad(rx == 0 ? 0 : nx - rx)];
             const double vm = sig * ((b & 1) ? zm.y : zm.x);
-            assemble_store(m, vm, p.a2, p.a1, p.b2, p.b1, d.nu, out, om + rx);
+            assemble_store(m, vm, p.a2, p.a1, p.b2, p.b1, d.nu, out, om + c);
         }
     }
 }
 
 hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
                          const cx<double> *mid, int p0, int p1, const double *prof,
-                         double *const *out, int full)
+                         double *const *out, int full, double *resid)
 {
     const int ptot = p1 - p0;
     const size_t lds = sizeof(cx<double>) * ((size_t)d.ntx * fft_stride(d.nx) + d.nx);
     OutPtrs op;
     for (int i = 0; i < 14; ++i) op.t[i] = out[i];
-    dim3 grid((ptot + 2 * d.ntx - 1) / (2 * d.ntx), d.nz, NMAP);
+    op.res = full ? nullptr : resid;
+    dim3 grid((ptot + 2 * d.ntx - 1) / (2 * d.ntx), full ? d.nz : d.nqo, NMAP + (op.res ? 1 : 0));
     if (d.kxblk == SMALL_BLOCK) {
         set_lds_limit(k_fin_kx<SMALL_BLOCK>);
         hipLaunchKernelGGL(k_fin_kx<SMALL_BLOCK>, grid, dim3(SMALL_BLOCK), lds, st, mid, d, t, p0,
@@ -351,7 +474,7 @@ __global__ __launch_bounds__(256) void k_fd_terms(const double *__restrict__ t1,
                                                   double *__restrict__ t11, int nchunk)
 {
     const int ny = d.ny;
-    const size_t plane = (size_t)d.nz * d.nkx;
+    const size_t plane = (size_t)d.nqo * d.npo;   // output map points per pair
     const int nb = (int)gridDim.x, q8 = nb >> 3, r8 = nb & 7, xcd = blockIdx.x & 7;
     const int item = xcd * q8 + min(xcd, r8) + (int)(blockIdx.x >> 3);
     const int chunk = item % nchunk, r = item / nchunk;
@@ -374,11 +497,67 @@ __global__ __launch_bounds__(256) void k_fd_terms(const double *__restrict__ t1,
 hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const double *t1,
                            double *t6, double *t11)
 {
-    const size_t plane = (size_t)d.nz * d.nkx;
+    const size_t plane = (size_t)d.nqo * d.npo;   // output map points per pair
     const int nchunk = (int)((plane + 255) / 256);
     const size_t nblk = (size_t)nchunk * d.ny * ((d.ny + FD_TY - 1) / FD_TY) * FD_TY;
     if (nblk >= ((size_t)1 << 31)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fd_terms, dim3((unsigned)nblk), dim3(256), 0, st, t1, d, t, t6, t11,
+                       nchunk);
+    return hipGetLastError();
+}
+
+// Residual, wall-normal part and sources (eq. GKE-conservative; Section
+// "Step 3": d/dry = (d/dY2 - d/dY1)/2, d/dY = d/dY1 + d/dY2 with the
+// five-point weights along each index):
+//   res += (D2 - D1)(T5 + T6)/2 + (D1 + D2)(T9 + T10 + T11) - (T12 + T13 + T14),
+// T14 = -2 (eps(Y1) + eps(Y2)).  Same block order as k_fd_terms (tiles of
+// FD_TY rows Y1 per Y2, chunks of the plane fastest, XCD-contiguous ranges).
+__global__ __launch_bounds__(256) void k_resid(OutPtrs out, const double *__restrict__ prof,
+                                               Dims d, Tables t, double *__restrict__ res,
+                                               int nchunk)
+{
+    const int ny = d.ny;
+    const size_t plane = (size_t)d.nqo * d.npo;   // output map points per pair
+    const int nb = (int)gridDim.x, q8 = nb >> 3, r8 = nb & 7, xcd = blockIdx.x & 7;
+    const int item = xcd * q8 + min(xcd, r8) + (int)(blockIdx.x >> 3);
+    const int chunk = item % nchunk, r = item / nchunk;
+    const int yi = r % FD_TY, j2 = (r / FD_TY) % ny, tile = r / (FD_TY * ny);
+    const int j1 = tile * FD_TY + yi;
+    const size_t i = (size_t)chunk * blockDim.x + threadIdx.x;
+    if (j1 >= ny || i >= plane) return;
+    const double *t5 = out.t[4], *t6 = out.t[5], *t9 = out.t[8], *t10 = out.t[9];
+    const double *t11 = out.t[10];
+    const int a1 = t.j0[j1], a2 = t.j0[j2];
+    double y1 = 0.0, y2 = 0.0, f1 = 0.0, f2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        const size_t o1 = ((size_t)(a1 + a) * ny + j2) * plane + i;
+        const size_t o2 = ((size_t)j1 * ny + a2 + a) * plane + i;
+        const double w1 = t.w5[j1 * 5 + a], w2 = t.w5[j2 * 5 + a];
+        y1 += w1 * (t5[o1] + t6[o1]);
+        y2 += w2 * (t5[o2] + t6[o2]);
+        f1 += w1 * (t9[o1] + t10[o1] + t11[o1]);
+        f2 += w2 * (t9[o2] + t10[o2] + t11[o2]);
+    }
+    const size_t o = ((size_t)j1 * ny + j2) * plane + i;
+    const double *eps = prof + P_EPS * ny;
+    const double xi = out.t[11][o] + out.t[12][o] - 2.0 * (eps[j1] + eps[j2]);
+    res[o] = res[o] + 0.5 * (y2 - y1) + f1 + f2 - xi;
+}
+
+hipError_t launch_resid(hipStream_t st, const Dims &d, const Tables &t, double *const *out,
+                        const double *prof, double *resid)
+{
+    const size_t plane = (size_t)d.nqo * d.npo;   // output map points per pair
+    const int nchunk = (int)((plane + 255) / 256);
+    const size_t nblk = (size_t)nchunk * d.ny * ((d.ny + FD_TY - 1) / FD_TY) * FD_TY;
+    if (nblk >= ((size_t)1 << 31)) return hipErrorInvalidValue;
+    OutPtrs op;
+    for (int k = 0; k < 14; ++k) op.t[k] = out[k];
+    op.res = resid;
+    for (int k : {4, 5, 8, 9, 10, 11, 12})
+        if (!op.t[k]) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_resid, dim3((unsigned)nblk), dim3(256), 0, st, op, prof, d, t, resid,
                        nchunk);
     return hipGetLastError();
 }
@@ -388,14 +567,16 @@ hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const
 // rows sit in the full-plane buffer mf[slot][row][Y2][rz][rx < Nx] for the
 // eleven terms that come from the transforms (slot k of term t: kslot below).
 // For every output pair (Y1, Y2) of the slab (opairs[q] = Y1 | Y2 << 16) and
-// every (rz, rx < width):
+// every kept separation (rz = rzk[row], rx = rxk[c] < the domain's width; all
+// of them without the rx/rz undersampling):
 //   mirror = 1: the average with the reflected pair,
 //     (T(Y1, Y2) + sigma_y T(2h - Y1, 2h - Y2)) / 2   (Section "Step 2": the
 //     other half of the channel doubles the sample; sigma_y = sign of the term
 //     under the reflection, Section "Exploiting symmetries");
 //   T6, T11 from the five-point Y1 and Y2 derivatives of the (averaged) <du^2>
 //   (Section "Step 3"), T14 from eps.
-// out[t][(q Nz + rz) width + rx]; T14 out[13][q].
+// out[t][(q nqo + row) npo + c]; T14 out[13][q].  The derivatives along Y
+// are pointwise in r, so the undersampling drops output points only.
 struct OutPtrs14 {
     double *t[14];
 };
@@ -404,13 +585,13 @@ __global__ __launch_bounds__(256) void k_slab_out(const double *__restrict__ mf,
                                                   Dims d, Tables t,
                                                   const int *__restrict__ opairs,
                                                   const double *__restrict__ prof, int mirror,
-                                                  int width, OutPtrs14 out)
+                                                  OutPtrs14 out)
 {
     // slot of each term in mf (-1: not a transformed map)
     constexpr int kslot[14] = {0, 1, 2, 3, 4, -1, 5, 6, 7, 8, -1, 9, 10, -1};
     constexpr double sig[14] = {1, 1, 1, 1, -1, -1, 1, 1, -1, -1, -1, 1, 1, 1};
     const int ny = d.ny, nz = d.nz, nx = d.nx;
-    const int q = blockIdx.x, rz = blockIdx.y;
+    const int q = blockIdx.x, row = blockIdx.y, rz = t.rzk[row];   // a kept rz row
     const int code = opairs[q];
     const int j1 = code & 0xffff, j2 = code >> 16;
     const size_t plane = (size_t)nz * nx;
@@ -424,9 +605,10 @@ __global__ __launch_bounds__(256) void k_slab_out(const double *__restrict__ mf,
     };
     const bool fd = out.t[5] || out.t[10];
     const int a1 = t.j0[j1], a2 = t.j0[j2];
-    for (int rx = threadIdx.x; rx < width; rx += blockDim.x) {
+    for (int c = threadIdx.x; c < d.npo; c += blockDim.x) {
+        const int rx = t.rxk[c];   // a kept rx column of the domain's width
         const size_t ofs = (size_t)rz * nx + rx;
-        const size_t o = ((size_t)q * nz + rz) * width + rx;
+        const size_t o = ((size_t)q * d.nqo + row) * d.npo + c;
 #pragma unroll
         for (int k = 0; k < 14; ++k)
             if (kslot[k] >= 0 && out.t[k]) out.t[k][o] = Tb(kslot[k], j1, j2, ofs, sig[k]);
@@ -441,7 +623,7 @@ __global__ __launch_bounds__(256) void k_slab_out(const double *__restrict__ mf,
             if (out.t[10]) out.t[10][o] = -0.5 * d.nu * (d1 + d2);
         }
     }
-    if (out.t[13] && rz == 0 && threadIdx.x == 0) {
+    if (out.t[13] && row == 0 && threadIdx.x == 0) {
         const double *eps = prof + P_EPS * ny;
         double v = -2.0 * (eps[j1] + eps[j2]);
         if (mirror) v = 0.5 * (v - 2.0 * (eps[ny - 1 - j1] + eps[ny - 1 - j2]));
@@ -451,13 +633,13 @@ __global__ __launch_bounds__(256) void k_slab_out(const double *__restrict__ mf,
 
 hipError_t launch_slab_out(hipStream_t st, const Dims &d, const Tables &t, const double *mf,
                            size_t mstride, const int *opairs, int nopairs, const double *prof,
-                           int mirror, int width, double *const *out)
+                           int mirror, double *const *out)
 {
     OutPtrs14 op;
     for (int i = 0; i < 14; ++i) op.t[i] = out[i];
     if (nopairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_slab_out, dim3(nopairs, d.nz), dim3(256), 0, st, mf, mstride, d, t,
-                       opairs, prof, mirror, width, op);
+    hipLaunchKernelGGL(k_slab_out, dim3(nopairs, d.nqo), dim3(256), 0, st, mf, mstride, d, t,
+                       opairs, prof, mirror, op);
     return hipGetLastError();
 }
 

@@ -17,7 +17,8 @@ LIB_PATH = os.environ.get("GKE_LIBRARY") or os.path.join(_HERE, "libgke.so")
 
 GKE_OK, GKE_ERR_ARG, GKE_ERR_STATE, GKE_ERR_OOM, GKE_ERR_HIP, GKE_ERR_UNSUPPORTED = range(6)
 GKE_OPT_DTYPE, GKE_OPT_PRECISION, GKE_OPT_CHUNK, GKE_OPT_PAIR_BATCH, GKE_OPT_TIMING = 1, 2, 3, 4, 5
-GKE_OPT_MIRROR, GKE_OPT_DOMAIN, GKE_OPT_SLAB = 6, 7, 8
+GKE_OPT_MIRROR, GKE_OPT_DOMAIN, GKE_OPT_SLAB, GKE_OPT_RESIDUAL = 6, 7, 8, 9
+GKE_OUT_F64, GKE_OUT_F32 = 0, 1
 GKE_DOMAIN_ALLPAIRS_HALFRX, GKE_DOMAIN_Y1LEY2_FULLR, GKE_DOMAIN_FUNDAMENTAL_FULLR = 0, 1, 2
 GKE_DTYPE_F64, GKE_DTYPE_F32 = 0, 1
 GKE_PREC_FP64, GKE_PREC_BF16X3 = 0, 1
@@ -27,7 +28,7 @@ TERM_NAMES = ["du2", "phix_t", "phix_m", "phix_v", "phiy_t", "phiy_v", "phiz_t",
               "phi_t", "phi_p", "phi_v", "xi_p1", "xi_p2", "xi_d"]
 PROFILE_NAMES = ["U", "V", "W", "P", "S", "q", "uv", "pv", "Tx", "Ty", "Tz", "eps"]
 KERNEL_NAMES = ["plane_sums", "fluct_xfft", "zfft_pack", "rankk", "fin_kz", "fin_kx", "fd_terms",
-                "small", "rankk_rem"]
+                "small", "rankk_rem", "resid"]
 GKE_NKERNELS = len(KERNEL_NAMES)
 
 
@@ -39,7 +40,7 @@ class GkeError(RuntimeError):
 
 class gke_terms(ctypes.Structure):
     _fields_ = [("t", ctypes.c_void_p * GKE_NTERMS), ("on_device", ctypes.c_int),
-                ("reserved", ctypes.c_int)]
+                ("dtype", ctypes.c_int), ("residual", ctypes.c_void_p)]
 
 
 _lib = None
@@ -68,6 +69,8 @@ def lib() -> ctypes.CDLL:
         "gke_workspace_size": ([vp, ctypes.POINTER(sz)], i32),
         "gke_set_workspace": ([vp, vp, sz], i32),
         "gke_set_static_workspace": ([vp], i32),
+        "gke_set_undersampling": ([vp, i32, i32, i32, i32, i32], i32),
+        "gke_sample_indices": ([vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "gke_set_stream": ([vp, vp], i32),
         "gke_accumulate": ([vp, vp, vp, vp, vp], i32),
         "gke_begin_stats": ([vp], i32),
@@ -146,6 +149,20 @@ def gke_set_static_workspace(plan) -> None:
 GKE_STATIC_WORKSPACE_BYTES = 64 << 20
 
 
+def gke_set_undersampling(plan, dir_: int, t1: int, t2: int, s1: int, s2: int) -> None:
+    _check(lib().gke_set_undersampling(plan, dir_, t1, t2, s1, s2), plan)
+
+
+def gke_sample_indices(plan, dir_: int) -> np.ndarray:
+    """Kept output indices along rx (dir 0) or rz (dir 1)."""
+    n = ctypes.c_int()
+    _check(lib().gke_sample_indices(plan, dir_, ctypes.byref(n), None), plan)
+    out = np.zeros(max(n.value, 1), dtype=np.int32)
+    _check(lib().gke_sample_indices(plan, dir_, ctypes.byref(n),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))), plan)
+    return out[:n.value]
+
+
 def gke_set_stream(plan, stream_ptr: int) -> None:
     _check(lib().gke_set_stream(plan, stream_ptr), plan)
 
@@ -163,12 +180,16 @@ def gke_set_means(plan, U, V, W, P) -> None:
     _check(lib().gke_set_means(plan, *[_dp(a) for a in arrs]), plan)
 
 
-def gke_finalize(plan, ptrs) -> None:
-    """ptrs: sequence of 14 device pointers (int) or None for terms to skip."""
+def gke_finalize(plan, ptrs, residual: int = 0, on_device: int = 1,
+                 dtype: int = GKE_OUT_F64) -> None:
+    """ptrs: sequence of 14 pointers (int) or None for terms to skip;
+    residual: pointer of the budget residual map, or 0."""
     t = gke_terms()
     for i in range(GKE_NTERMS):
         t.t[i] = ptrs[i] if ptrs[i] else None
-    t.on_device = 1
+    t.on_device = int(on_device)
+    t.dtype = int(dtype)
+    t.residual = residual if residual else None
     _check(lib().gke_finalize(plan, ctypes.byref(t)), plan)
 
 

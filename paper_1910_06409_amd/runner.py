@@ -18,7 +18,7 @@ class GkeRun:
 
     def __init__(self, nx, ny, nz, y, lx, lz, nu, *, dtype="f64", precision="fp64",
                  chunk=64, pair_batch=0, mirror=0, domain=0, slab=0, device="cuda",
-                 stream=None, static_workspace=False):
+                 stream=None, static_workspace=False, residual=False, undersample=None):
         self.nx, self.ny, self.nz = nx, ny, nz
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
@@ -35,6 +35,10 @@ class GkeRun:
         gke.gke_set_option(self.plan, gke.GKE_OPT_MIRROR, int(mirror))
         gke.gke_set_option(self.plan, gke.GKE_OPT_DOMAIN, int(domain))
         gke.gke_set_option(self.plan, gke.GKE_OPT_SLAB, int(slab))
+        gke.gke_set_option(self.plan, gke.GKE_OPT_RESIDUAL, 1 if residual else 0)
+        # undersampling: {0: (t1, t2, s1, s2) for rx, 1: (...) for rz}
+        for d_, u in (undersample or {}).items():
+            gke.gke_set_undersampling(self.plan, int(d_), *[int(v) for v in u])
         self.domain = int(domain)
         self.general = bool(mirror or domain or slab)
         gke.gke_set_stream(self.plan, self.stream.cuda_stream)
@@ -50,6 +54,8 @@ class GkeRun:
             aligned = (base + 255) // 256 * 256
             gke.gke_set_workspace(self.plan, aligned, nbytes)
         self.tdtype = torch.float32 if dtype == "f32" else torch.float64
+        self.rx_kept = gke.gke_sample_indices(self.plan, 0)
+        self.rz_kept = gke.gke_sample_indices(self.plan, 1)
 
     def accumulate(self, u, v, w, p):
         for t in (u, v, w, p):
@@ -72,12 +78,12 @@ class GkeRun:
     def alloc_terms(self, which=None, slab=0):
         """Output maps for gke_finalize (of `slab` in the general modes)."""
         which = range(gke.GKE_NTERMS) if which is None else which
+        nq, npx = len(self.rz_kept), len(self.rx_kept)
         if self.general:
             n = len(gke.gke_slab_pairs(self.plan, slab))
-            width = self.nx // 2 + 1 if self.domain == gke.GKE_DOMAIN_ALLPAIRS_HALFRX else self.nx
-            shape, s14 = (n, self.nz, width), (n,)
+            shape, s14 = (n, nq, npx), (n,)
         else:
-            shape, s14 = (self.ny, self.ny, self.nz, self.nx // 2 + 1), (self.ny, self.ny)
+            shape, s14 = (self.ny, self.ny, nq, npx), (self.ny, self.ny)
         out = [None] * gke.GKE_NTERMS
         for i in which:
             out[i] = torch.empty(s14 if i == 13 else shape, dtype=torch.float64,
@@ -97,10 +103,16 @@ class GkeRun:
     def begin_slab(self, slab: int):
         gke.gke_begin_slab(self.plan, slab)
 
-    def finalize(self, out=None):
+    def alloc_residual(self):
+        """A map for the budget residual, laid out like the all-pairs term maps."""
+        return torch.empty((self.ny, self.ny, len(self.rz_kept), len(self.rx_kept)),
+                           dtype=torch.float64, device=self.device)
+
+    def finalize(self, out=None, residual=None):
         if out is None:
             out = self.alloc_terms()
-        gke.gke_finalize(self.plan, [t.data_ptr() if t is not None else 0 for t in out])
+        gke.gke_finalize(self.plan, [t.data_ptr() if t is not None else 0 for t in out],
+                         residual=residual.data_ptr() if residual is not None else 0)
         return out
 
     def reset(self):
@@ -128,31 +140,34 @@ class GkeRun:
 
 
 def run_snapshots(snaps_dev, y, lx, lz, nu, *, dtype="f64", precision="fp64", chunk=64,
-                  pair_batch=0, which=None):
-    """Both scans over a device tensor [S][4][ny][nz][nx]; returns (maps, profiles)."""
+                  pair_batch=0, which=None, residual=False, undersample=None):
+    """Both scans over a device tensor [S][4][ny][nz][nx]; returns (maps,
+    profiles), or (maps, profiles, residual map) with residual=True."""
     S, _, ny, nz, nx = snaps_dev.shape
     r = GkeRun(nx, ny, nz, y, lx, lz, nu, dtype=dtype, precision=precision, chunk=chunk,
-               pair_batch=pair_batch, device=snaps_dev.device)
+               pair_batch=pair_batch, device=snaps_dev.device, residual=residual,
+               undersample=undersample)
     for s in range(S):
         r.accumulate_snapshot(snaps_dev[s])
     r.begin_stats()
     for s in range(S):
         r.accumulate_snapshot(snaps_dev[s])
-    out = r.finalize(r.alloc_terms(which))
+    res = r.alloc_residual() if residual else None
+    out = r.finalize(r.alloc_terms(which), residual=res)
     prof = r.profiles()
     r.close()
-    return out, prof
+    return (out, prof, res) if residual else (out, prof)
 
 
 def run_slabs(snaps_dev, y, lx, lz, nu, *, dtype="f64", precision="fp64", chunk=64,
-              pair_batch=0, mirror=0, domain=0, slab=0, which=None):
+              pair_batch=0, mirror=0, domain=0, slab=0, which=None, undersample=None):
     """Both scans, then one second scan and finalize per slab.  Returns
     ([(pairs [n][2], maps of the slab)], profiles); maps as gke_finalize lays
     them out for the general modes."""
     S, _, ny, nz, nx = snaps_dev.shape
     r = GkeRun(nx, ny, nz, y, lx, lz, nu, dtype=dtype, precision=precision, chunk=chunk,
                pair_batch=pair_batch, mirror=mirror, domain=domain, slab=slab,
-               device=snaps_dev.device)
+               device=snaps_dev.device, undersample=undersample)
     for s in range(S):
         r.accumulate_snapshot(snaps_dev[s])
     r.begin_stats()

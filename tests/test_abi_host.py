@@ -195,3 +195,44 @@ def test_static_workspace_refuses_a_plan_larger_than_it():
         assert gke.gke_workspace_size(p) <= gke.GKE_STATIC_WORKSPACE_BYTES
     finally:
         gke.gke_destroy(p)
+
+
+def test_undersampling_indices_match_the_oracle_rule():
+    """The kept rx / rz separations the library reports follow the two-threshold
+    rule of the oracle (full resolution below t1, every s1-th index below t2,
+    every s2-th beyond), for the half-plane and the full-r domains."""
+    from oracle import oracle
+    from paper_1910_06409_amd import synth
+    # a hand-written case: n = 32, thresholds 4 and 10, steps 2 and 4
+    assert oracle.sample_indices(32, 4, 10, 2, 4, True) == [0, 1, 2, 3, 4, 6, 8, 12, 16]
+    assert oracle.sample_indices(8, 0, 0, 1, 1, False) == list(range(8))
+    full = oracle.sample_indices(32, 4, 10, 2, 4, False)
+    assert full == [0, 1, 2, 3, 4, 6, 8, 12, 16, 20, 24, 26, 28, 29, 30, 31]
+    w = synth.workload("re1000")
+    y = synth.y_grid(w)
+    cases = [(0, (0, 0, 1, 1)), (0, (8, 20, 4, 8)), (1, (12, 30, 4, 8)), (1, (3, 3, 5, 5)),
+             (0, (5, 100, 3, 7))]
+    for domain in (gke.GKE_DOMAIN_ALLPAIRS_HALFRX, gke.GKE_DOMAIN_Y1LEY2_FULLR):
+        for d, u in cases:
+            p = gke.gke_plan(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu)
+            try:
+                gke.gke_set_option(p, gke.GKE_OPT_DOMAIN, domain)
+                gke.gke_set_undersampling(p, d, *u)
+                n = w.nx if d == 0 else w.nz
+                half = d == 0 and domain == gke.GKE_DOMAIN_ALLPAIRS_HALFRX
+                got = list(gke.gke_sample_indices(p, d))
+                assert got == oracle.sample_indices(n, *u, half), (domain, d, u)
+                # the other direction keeps everything
+                o = 1 - d
+                assert len(gke.gke_sample_indices(p, o)) == (
+                    (w.nx // 2 + 1 if domain == 0 else w.nx) if o == 0 else w.nz)
+            finally:
+                gke.gke_destroy(p)
+    p = gke.gke_plan(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu)
+    try:
+        for bad in [(2, 0, 0, 1, 1), (0, 5, 4, 1, 1), (0, 0, 0, 0, 1), (1, -1, 2, 1, 1)]:
+            with pytest.raises(gke.GkeError) as e:
+                gke.gke_set_undersampling(p, *bad)
+            assert e.value.status == gke.GKE_ERR_ARG
+    finally:
+        gke.gke_destroy(p)
