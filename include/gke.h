@@ -69,8 +69,11 @@ enum {
     GKE_OPT_MIRROR = 6,       /* 1: average every term with the reflected pair (below) */
     GKE_OPT_DOMAIN = 7,       /* output domain, GKE_DOMAIN_* (default ALLPAIRS_HALFRX) */
     GKE_OPT_SLAB = 8,         /* output Y1 rows per slab, 0 = all rows in one slab (default) */
-    GKE_OPT_RESIDUAL = 9      /* 1: reserve what gke_finalize needs to write the budget
+    GKE_OPT_RESIDUAL = 9,     /* 1: reserve what gke_finalize needs to write the budget
                                  residual (gke_terms.residual; all-pairs mode only) */
+    GKE_OPT_HOST_STAGING = 10 /* device staging buffers for host outputs (gke_terms.on_device
+                                 = 0): 0 (default, device outputs only), 1, or 2 (the copies
+                                 of one finalize overlap the next slab's scan) */
 };
 enum { GKE_DTYPE_F64 = 0, GKE_DTYPE_F32 = 1 };
 enum { GKE_PREC_FP64 = 0, GKE_PREC_BF16X3 = 1 };
@@ -122,9 +125,17 @@ enum {
     GKE_T_XI_P2, GKE_T_XI_D, GKE_NTERMS
 };
 
-/* Output of gke_finalize.  Each non-NULL t[i] is a caller-owned FP64 device
- * array (dtype GKE_OUT_F64, the only type this build writes; other values
- * are refused with GKE_ERR_UNSUPPORTED).  Default (no mirror, all-pairs domain, one slab): maps T1..T13 are
+/* Output of gke_finalize.  Each non-NULL t[i] is a caller-owned array of
+ * dtype GKE_OUT_F64 (default) or GKE_OUT_F32 (every value is assembled in
+ * FP64 and rounded once when stored; in the all-pairs mode T6 and T11 are
+ * then formed from the rounded <du^2> and the residual from the rounded
+ * maps), on the device (on_device = 1) or on the host (on_device = 0: needs
+ * GKE_OPT_HOST_STAGING; the maps are written to a device staging buffer and
+ * copied on a stream of the library's own, so that gke_finalize returns once
+ * the maps are computed while the copies run; pinned host memory lets them
+ * overlap the caller's next work; the host arrays are complete after
+ * gke_wait_outputs, the next gke_finalize into the same staging buffer, or
+ * gke_destroy).  Default (no mirror, all-pairs domain, one slab): maps T1..T13 are
  * laid out [Y1 0..Ny)[Y2 0..Ny)[q 0..Nz)[p 0..Nx/2] (all ordered pairs, the
  * half plane rx >= 0; the half rx <= 0 of pair (Y1,Y2) is the half rx >= 0 of
  * pair (Y2,Y1) by the r-inversion symmetry of Section "Exploiting
@@ -147,8 +158,8 @@ enum { GKE_OUT_F64 = 0, GKE_OUT_F32 = 1 };
  * T10, T11, T12 and T13 must be requested too (else GKE_ERR_ARG). */
 typedef struct {
     void *t[GKE_NTERMS];
-    int on_device;
-    int dtype;          /* GKE_OUT_F64 (0) */
+    int on_device;      /* 1: device arrays; 0: host arrays */
+    int dtype;          /* GKE_OUT_F64 (0) or GKE_OUT_F32 (1) */
     void *residual;     /* budget residual map, or NULL */
 } gke_terms;
 
@@ -259,11 +270,20 @@ gke_status gke_set_means(gke_plan_t plan, const double *U, const double *V, cons
                          const double *P);
 
 /* Average, inverse transforms, assembly and the five-point derivatives; write
- * the requested maps (see gke_terms).  Blocking.  Does not consume the plan:
+ * the requested maps (see gke_terms).  Blocking for device outputs; with host
+ * outputs it returns once the maps are in the staging buffer and their copies
+ * are enqueued (gke_wait_outputs).  Does not consume the plan:
  * more snapshots may be accumulated and finalize called again.  Errors:
  * GKE_ERR_STATE (no second-scan snapshot, or the two scans have different
- * snapshot counts), GKE_ERR_ARG, GKE_ERR_UNSUPPORTED (host outputs), GKE_ERR_HIP. */
+ * snapshot counts; host outputs without staging; the residual without
+ * GKE_OPT_RESIDUAL), GKE_ERR_ARG (dtype; a map the requested terms need is
+ * missing), GKE_ERR_UNSUPPORTED (the residual in the slab modes), GKE_ERR_HIP. */
 gke_status gke_finalize(gke_plan_t plan, const gke_terms *out);
+
+/* Wait until the host copies of every gke_finalize with host outputs have
+ * completed (returns at once when there are none).  Errors: GKE_ERR_ARG,
+ * GKE_ERR_HIP. */
+gke_status gke_wait_outputs(gke_plan_t plan);
 
 /* Number of slabs (after gke_set_workspace): 1 unless GKE_OPT_SLAB cuts the
  * output rows.  Errors: GKE_ERR_STATE (no workspace). */

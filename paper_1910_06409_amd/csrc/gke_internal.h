@@ -249,23 +249,25 @@ hipError_t launch_fin_kz(hipStream_t st, const Dims &d, const Tables &t,
 hipError_t launch_fin_kz_h(hipStream_t st, const Dims &d, const Tables &t,
                            const cx<double> *acc, int p0, int p1, double inv_count,
                            const double *prof, cx<double> *mid);
+// Output maps below are FP64, or FP32 with f32 = 1 (assembled in FP64, rounded
+// once when stored).
 // finalize: inverse real transform along kx, FP64 assembly.  full = 0: both
 // orientations into the all-pairs half-plane maps out[t][Y1][Y2][rz][rx <= Nx/2];
 // full = 1: orientation (Y1, Y2) of the pair code only, every rx, into
 // out[t][rowidx[Y1]][Y2][rz][rx < Nx]
 hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
                          const cx<double> *mid, int p0, int p1, const double *prof,
-                         double *const *out, int full, double *resid);
+                         void *const *out, int f32, int full, void *resid);
 // residual, Y part: resid += (d/dY2 - d/dY1)(T5 + T6)/2 + (d/dY1 + d/dY2)(T9 + T10 + T11)
 // - (T12 + T13 + T14), five-point derivatives along Y1 and Y2 of the maps
 // out[t][Y1][Y2][rz][rx <= Nx/2]; resid holds the homogeneous part on entry
-hipError_t launch_resid(hipStream_t st, const Dims &d, const Tables &t, double *const *out,
-                        const double *prof, double *resid);
+hipError_t launch_resid(hipStream_t st, const Dims &d, const Tables &t, void *const *out,
+                        int f32, const double *prof, void *resid);
 // general output modes: mirror average, output domain, T6/T11/T14, from the
 // full-plane map buffer of the slab rows (see k_final.hip)
 hipError_t launch_slab_out(hipStream_t st, const Dims &d, const Tables &t, const double *mf,
                            size_t mstride, const int *opairs, int nopairs, const double *prof,
-                           int mirror, double *const *out);
+                           int mirror, void *const *out, int f32);
 // band accumulators for eps in the general modes: band[a][Y][k] += sum over the
 // chunk of sum_i Re conj(u_i^(k; Y)) u_i^(k; Y + a), a = 0..4
 hipError_t launch_band(hipStream_t st, const Dims &d, const void *spec, int nsnap,
@@ -274,11 +276,11 @@ hipError_t launch_band(hipStream_t st, const Dims &d, const void *spec, int nsna
 hipError_t launch_r0_band(hipStream_t st, const Dims &d, const double *band, double inv_count,
                           double *r0, double *gxz);
 // Step 3: T6 and T11 from T1 along Y1 and Y2
-hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const double *t1,
-                           double *t6, double *t11);
+hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const void *t1,
+                           void *t6, void *t11, int f32);
 // zero `bytes` bytes at p (8-byte aligned, a multiple of 8) with a fill kernel
 hipError_t launch_zero(hipStream_t st, void *p, size_t bytes);
 // T14 = -2 (eps(Y1) + eps(Y2))
-hipError_t launch_t14(hipStream_t st, const Dims &d, const double *prof, double *t14);
+hipError_t launch_t14(hipStream_t st, const Dims &d, const double *prof, void *t14, int f32);
 
 }  // namespace gke

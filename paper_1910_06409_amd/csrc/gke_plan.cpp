@@ -41,6 +41,15 @@ struct gke_plan_s {
     int residual = 0;              // mid holds one more plane for the budget residual
     int us[2][4] = {{0, 0, 1, 1}, {0, 0, 1, 1}};   // rx, rz undersampling: t1 t2 s1 s2
     std::vector<int> h_rzk, h_rzinv, h_rxk;        // kept separations (output rows, columns)
+    // host outputs: device staging buffers of the maps, copied to the caller's
+    // host arrays on a stream of the library's own
+    int host_stage = 0;            // staging buffers (GKE_OPT_HOST_STAGING: 0, 1 or 2)
+    char *stage = nullptr;         // host_stage buffers of stage_bytes
+    size_t stage_bytes = 0, stage_slot = 0;   // a buffer holds 15 slots (14 maps, residual)
+    int stage_next = 0;
+    bool stage_used[2] = {false, false};
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_copied[2] = {nullptr, nullptr};
     bool general = false;          // mirror, a FULLR domain or slabs
     std::vector<SlabTables> slabs;
     int cur_slab = 0;
@@ -403,6 +412,12 @@ size_t layout(gke_plan_t p, char *base)
     p->mstride = nrows * d.ny * (size_t)d.nz * d.nx;
     p->mf = (double *)take(sizeof(double) * gke::NSTORED * p->mstride);
     p->band = (double *)take(p->general ? sizeof(double) * (size_t)d.nk * 5 * d.ny : 0);
+    // staging for host outputs: 15 slots per buffer, each one FP64 map of the
+    // largest output (all pairs, or the largest slab) over the kept separations
+    const size_t npo_pairs = p->general ? nopairs : (size_t)d.ny * d.ny;
+    p->stage_slot = align256(sizeof(double) * npo_pairs * (size_t)d.nqo * d.npo);
+    p->stage_bytes = 15 * p->stage_slot;
+    p->stage = (char *)take(p->host_stage * p->stage_bytes);
     return off;
 }
 
@@ -658,6 +673,10 @@ gke_status gke_set_option(gke_plan_t p, int key, int64_t value)
         if (value != 0 && value != 1) return fail(p, GKE_ERR_ARG, "residual must be 0 or 1");
         p->residual = (int)value;
         return GKE_OK;
+    case GKE_OPT_HOST_STAGING:
+        if (value < 0 || value > 2) return fail(p, GKE_ERR_ARG, "host staging must be 0, 1 or 2");
+        p->host_stage = (int)value;
+        return GKE_OK;
     default:
         return fail(p, GKE_ERR_ARG, "unknown option key");
     }
@@ -710,6 +729,7 @@ gke_status gke_get_option(gke_plan_t p, int key, int64_t *value)
     case GKE_OPT_DOMAIN: *value = p->domain; return GKE_OK;
     case GKE_OPT_SLAB: *value = p->slab_rows; return GKE_OK;
     case GKE_OPT_RESIDUAL: *value = p->residual; return GKE_OK;
+    case GKE_OPT_HOST_STAGING: *value = p->host_stage; return GKE_OK;
     default: return fail(p, GKE_ERR_ARG, "unknown option key");
     }
 }
@@ -755,6 +775,13 @@ gke_status attach_workspace(gke_plan_t p, void *dev, size_t bytes)
     GKE_HIP(p, hipMemcpyAsync(p->rzk, p->h_rzk.data(), sizeof(int) * p->h_rzk.size(), hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->rzinv, p->h_rzinv.data(), sizeof(int) * d.nz, hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->rxk, p->h_rxk.data(), sizeof(int) * p->h_rxk.size(), hipMemcpyHostToDevice, st));
+    if (p->host_stage > 0 && !p->copy_stream) {
+        GKE_HIP(p, hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking));
+        for (int b = 0; b < 2; ++b) {
+            GKE_HIP(p, hipEventCreateWithFlags(&p->ev_ready[b], hipEventDisableTiming));
+            GKE_HIP(p, hipEventCreateWithFlags(&p->ev_copied[b], hipEventDisableTiming));
+        }
+    }
     // sums, profiles and moment partials start at zero
     GKE_HIP(p, gke::launch_zero(st, p->sums1, (char *)p->inter - (char *)p->sums1));
     GKE_HIP(p, hipStreamSynchronize(st));
@@ -830,6 +857,9 @@ gke_status gke_set_static_workspace(gke_plan_t p)
         gke_status s = prepare_mode(p);
         if (s != GKE_OK) return s;
     }
+    if (p->host_stage > 0)
+        return fail(p, GKE_ERR_UNSUPPORTED, "host staging (a copy stream of its own) needs a "
+                                            "caller workspace");
     const size_t need = layout(p, nullptr);
     if (need > (size_t)GKE_STATIC_WORKSPACE_BYTES)
         return fail(p, GKE_ERR_OOM, "the plan needs " + std::to_string(need) +
@@ -949,17 +979,18 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
 {
     if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
     if (!out) return fail(p, GKE_ERR_ARG, "out is NULL");
-    if (!out->on_device) return fail(p, GKE_ERR_UNSUPPORTED, "host outputs are not supported");
     if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
     if (!p->second_scan || p->n2 == 0) return fail(p, GKE_ERR_STATE, "no second-scan snapshot");
     if (!p->means_from_host && p->n1 != p->n2)
         return fail(p, GKE_ERR_STATE, "the two scans saw different snapshot counts");
-    if (out->dtype != GKE_OUT_F64)
-        return fail(p, GKE_ERR_UNSUPPORTED, "output dtype not supported");
+    if (out->dtype != GKE_OUT_F64 && out->dtype != GKE_OUT_F32)
+        return fail(p, GKE_ERR_ARG, "output dtype must be GKE_OUT_F64 or GKE_OUT_F32");
+    const bool host = out->on_device == 0;
+    if (host && p->host_stage == 0)
+        return fail(p, GKE_ERR_STATE, "host outputs need GKE_OPT_HOST_STAGING before the workspace");
     if (!p->general && (out->t[GKE_T_PHIY_V] || out->t[GKE_T_PHI_V]) && !out->t[GKE_T_DU2])
         return fail(p, GKE_ERR_ARG, "the Y-derivative terms need the <du^2> output buffer");
-    double *resid = (double *)out->residual;
-    if (resid) {
+    if (out->residual) {
         if (p->general)
             return fail(p, GKE_ERR_UNSUPPORTED, "the residual is written in the all-pairs mode only");
         if (!p->residual)
@@ -973,6 +1004,29 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
     if (s != GKE_OK) return s;
     const gke::Dims &d = p->d;
     hipStream_t st = p->stream;
+    const int f32 = out->dtype == GKE_OUT_F32 ? 1 : 0;
+    const size_t esz = f32 ? sizeof(float) : sizeof(double);
+    // maps of this call: the pairs of the slab (general modes) or all pairs
+    const size_t npairs = p->general ? p->slabs[p->cur_slab].opairs.size() : (size_t)d.ny * d.ny;
+    const size_t map_bytes = esz * npairs * (size_t)d.nqo * d.npo, t14_bytes = esz * npairs;
+    // device destinations: the caller's maps, or a staging buffer whose
+    // previous copies to the host have finished
+    void *dst[15];
+    int b = 0;
+    if (host) {
+        b = p->stage_next;
+        p->stage_next = (b + 1) % p->host_stage;
+        if (p->stage_used[b]) GKE_HIP(p, hipStreamWaitEvent(st, p->ev_copied[b], 0));
+        char *base = p->stage + b * p->stage_bytes;
+        for (int i = 0; i < 15; ++i) {
+            const void *want = i < 14 ? out->t[i] : out->residual;
+            dst[i] = want ? base + i * p->stage_slot : nullptr;
+        }
+    } else {
+        for (int i = 0; i < 14; ++i) dst[i] = out->t[i];
+        dst[14] = out->residual;
+    }
+    void *resid = dst[14];
     const double inv = 1.0 / (double)p->n2;
     GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {
         return p->general ? gke::launch_r0_band(st, d, p->band, inv, p->r0, p->gxz)
@@ -982,14 +1036,12 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
         return gke::launch_profiles(st, d, p->tab, p->momp, p->r0, p->gxz, (double)p->n2,
                                     p->prof);
     }));
-    double *outp[14];
-    for (int i = 0; i < 14; ++i) outp[i] = (double *)out->t[i];
     const int pbt = (p->pair_batch > 0 && p->pair_batch < d.npair) ? p->pair_batch : d.npair;
     if (p->general) {
         // every transformed term of the slab's rows into the full-plane buffer,
-        // then mirror average, domain, T6 / T11 / T14 into the caller's maps
+        // then mirror average, domain, T6 / T11 / T14 into the maps
         static const int kslot[14] = {0, 1, 2, 3, 4, -1, 5, 6, 7, 8, -1, 9, 10, -1};
-        double *mfp[14];
+        void *mfp[14];
         for (int i = 0; i < 14; ++i) mfp[i] = kslot[i] >= 0 ? p->mf + kslot[i] * p->mstride : nullptr;
         for (int q0 = 0; q0 < d.npair; q0 += pbt) {
             const int q1 = std::min(d.npair, q0 + pbt);
@@ -997,44 +1049,66 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
                 return gke::launch_fin_kz(st, d, p->tab, p->acc, q0, q1, inv, p->mid);
             }));
             GKE_HIP(p, timed(p, GKE_K_FIN_KX, [&] {
-                return gke::launch_fin_kx(st, d, p->tab, p->mid, q0, q1, p->prof, mfp, 1, nullptr);
+                return gke::launch_fin_kx(st, d, p->tab, p->mid, q0, q1, p->prof, mfp, 0, 1,
+                                          nullptr);
             }));
         }
-        const SlabTables &t = p->slabs[p->cur_slab];
         GKE_HIP(p, timed(p, GKE_K_FD, [&] {
-            return gke::launch_slab_out(st, d, p->tab, p->mf, p->mstride, p->opairs,
-                                        (int)t.opairs.size(), p->prof, p->mirror, outp);
+            return gke::launch_slab_out(st, d, p->tab, p->mf, p->mstride, p->opairs, (int)npairs,
+                                        p->prof, p->mirror, dst, f32);
         }));
-        GKE_HIP(p, hipStreamSynchronize(st));
-        return GKE_OK;
-    }
-    for (int q0 = 0; q0 < d.npair; q0 += pbt) {
-        const int q1 = std::min(d.npair, q0 + pbt);
-        GKE_HIP(p, timed(p, GKE_K_FIN_KZ, [&] {
-            return gke::launch_fin_kz(st, d, p->tab, p->acc, q0, q1, inv, p->mid);
-        }));
+    } else {
+        for (int q0 = 0; q0 < d.npair; q0 += pbt) {
+            const int q1 = std::min(d.npair, q0 + pbt);
+            GKE_HIP(p, timed(p, GKE_K_FIN_KZ, [&] {
+                return gke::launch_fin_kz(st, d, p->tab, p->acc, q0, q1, inv, p->mid);
+            }));
+            if (resid)
+                GKE_HIP(p, timed(p, GKE_K_RESID, [&] {
+                    return gke::launch_fin_kz_h(st, d, p->tab, p->acc, q0, q1, inv, p->prof,
+                                                p->mid);
+                }));
+            GKE_HIP(p, timed(p, GKE_K_FIN_KX, [&] {
+                return gke::launch_fin_kx(st, d, p->tab, p->mid, q0, q1, p->prof, dst, f32, 0,
+                                          resid);
+            }));
+        }
+        if (dst[GKE_T_PHIY_V] || dst[GKE_T_PHI_V])
+            GKE_HIP(p, timed(p, GKE_K_FD, [&] {
+                return gke::launch_fd_terms(st, d, p->tab, dst[GKE_T_DU2], dst[GKE_T_PHIY_V],
+                                            dst[GKE_T_PHI_V], f32);
+            }));
         if (resid)
             GKE_HIP(p, timed(p, GKE_K_RESID, [&] {
-                return gke::launch_fin_kz_h(st, d, p->tab, p->acc, q0, q1, inv, p->prof, p->mid);
+                return gke::launch_resid(st, d, p->tab, dst, f32, p->prof, resid);
             }));
-        GKE_HIP(p, timed(p, GKE_K_FIN_KX, [&] {
-            return gke::launch_fin_kx(st, d, p->tab, p->mid, q0, q1, p->prof, outp, 0, resid);
-        }));
+        if (dst[GKE_T_XI_D])
+            GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {
+                return gke::launch_t14(st, d, p->prof, dst[GKE_T_XI_D], f32);
+            }));
     }
-    if (outp[GKE_T_PHIY_V] || outp[GKE_T_PHI_V])
-        GKE_HIP(p, timed(p, GKE_K_FD, [&] {
-            return gke::launch_fd_terms(st, d, p->tab, outp[GKE_T_DU2], outp[GKE_T_PHIY_V],
-                                        outp[GKE_T_PHI_V]);
-        }));
-    if (resid)
-        GKE_HIP(p, timed(p, GKE_K_RESID, [&] {
-            return gke::launch_resid(st, d, p->tab, outp, p->prof, resid);
-        }));
-    if (outp[GKE_T_XI_D])
-        GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {
-            return gke::launch_t14(st, d, p->prof, outp[GKE_T_XI_D]);
-        }));
+    if (host) {
+        // the copies run on the library's stream once the maps are written;
+        // the next finalize into this buffer waits for them
+        GKE_HIP(p, hipEventRecord(p->ev_ready[b], st));
+        GKE_HIP(p, hipStreamWaitEvent(p->copy_stream, p->ev_ready[b], 0));
+        for (int i = 0; i < 15; ++i) {
+            void *h = i < 14 ? out->t[i] : out->residual;
+            if (!h) continue;
+            GKE_HIP(p, hipMemcpyAsync(h, dst[i], i == GKE_T_XI_D ? t14_bytes : map_bytes,
+                                      hipMemcpyDeviceToHost, p->copy_stream));
+        }
+        GKE_HIP(p, hipEventRecord(p->ev_copied[b], p->copy_stream));
+        p->stage_used[b] = true;
+    }
     GKE_HIP(p, hipStreamSynchronize(st));
+    return GKE_OK;
+}
+
+gke_status gke_wait_outputs(gke_plan_t p)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (p->copy_stream) GKE_HIP(p, hipStreamSynchronize(p->copy_stream));
     return GKE_OK;
 }
 
@@ -1135,6 +1209,14 @@ void gke_destroy(gke_plan_t p)
 {
     if (!p) return;
     if (p->ws) (void)hipStreamSynchronize(p->stream);
+    if (p->copy_stream) {
+        (void)hipStreamSynchronize(p->copy_stream);
+        for (int b = 0; b < 2; ++b) {
+            (void)hipEventDestroy(p->ev_ready[b]);
+            (void)hipEventDestroy(p->ev_copied[b]);
+        }
+        (void)hipStreamDestroy(p->copy_stream);
+    }
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     delete p;
 }

@@ -217,9 +217,22 @@ hipError_t launch_fin_kz_h(hipStream_t st, const Dims &d, const Tables &t,
     return hipGetLastError();
 }
 
+// Output maps are FP64 or FP32 (f32 = 1: every value, assembled in FP64, is
+// rounded once when stored); the flag is uniform over a launch.
+__device__ __forceinline__ void put(void *p, size_t o, double v, int f32)
+{
+    if (f32) static_cast<float *>(p)[o] = (float)v;
+    else static_cast<double *>(p)[o] = v;
+}
+__device__ __forceinline__ double get(const void *p, size_t o, int f32)
+{
+    return f32 ? (double)static_cast<const float *>(p)[o] : static_cast<const double *>(p)[o];
+}
+
 struct OutPtrs {
-    double *t[14];
-    double *res;   // residual map (its homogeneous part, map M_H), or NULL
+    void *t[14];
+    void *res;     // residual map (its homogeneous part, map M_H), or NULL
+    int f32;       // maps stored as FP32
 };
 
 // sign of each map under r-inversion: map(r; Y2, Y1) = sigma * map(-r; Y1, Y2)
@@ -252,42 +265,43 @@ __device__ __forceinline__ void assemble_store(int m, double val, double a1, dou
                                                double b1, double b2, double nu,
                                                const OutPtrs &out, size_t o)
 {
+    const int f = out.f32;
     switch (m) {
     case M_R: {
         const double t1 = a1 + a2 - 2.0 * val;                // <du^2>
-        if (out.t[0]) out.t[0][o] = t1;
-        if (out.t[2]) out.t[2][o] = (b2 - b1) * t1;            // <du^2 dU>
+        if (out.t[0]) put(out.t[0], o, t1, f);
+        if (out.t[2]) put(out.t[2], o, (b2 - b1) * t1, f);     // <du^2 dU>
         break;
     }
     case M_DRX:
-        if (out.t[3]) out.t[3][o] = 4.0 * nu * val;
+        if (out.t[3]) put(out.t[3], o, 4.0 * nu * val, f);
         break;
     case M_DRZ:
-        if (out.t[7]) out.t[7][o] = 4.0 * nu * val;
+        if (out.t[7]) put(out.t[7], o, 4.0 * nu * val, f);
         break;
     case M_FX:
-        if (out.t[1]) out.t[1][o] = a2 - a1 + val;
+        if (out.t[1]) put(out.t[1], o, a2 - a1 + val, f);
         break;
     case M_FY:
-        if (out.t[4]) out.t[4][o] = a2 - a1 + val;
+        if (out.t[4]) put(out.t[4], o, a2 - a1 + val, f);
         break;
     case M_FZ:
-        if (out.t[6]) out.t[6][o] = a2 - a1 + val;
+        if (out.t[6]) put(out.t[6], o, a2 - a1 + val, f);
         break;
     case M_PHI:
-        if (out.t[8]) out.t[8][o] = 0.5 * (a1 + a2 + val);
+        if (out.t[8]) put(out.t[8], o, 0.5 * (a1 + a2 + val), f);
         break;
     case M_PP:
-        if (out.t[9]) out.t[9][o] = 2.0 * (a1 + a2 - val);
+        if (out.t[9]) put(out.t[9], o, 2.0 * (a1 + a2 - val), f);
         break;
     case M_UVS:
-        if (out.t[11]) out.t[11][o] = -2.0 * (a1 + a2 - val) * 0.5 * (b1 + b2);
+        if (out.t[11]) put(out.t[11], o, -2.0 * (a1 + a2 - val) * 0.5 * (b1 + b2), f);
         break;
     case M_H:
-        if (out.res) out.res[o] = val;
+        if (out.res) put(out.res, o, val, f);
         break;
     default:  // M_UVA
-        if (out.t[12]) out.t[12][o] = -(a2 - a1 + val) * (b2 - b1);
+        if (out.t[12]) put(out.t[12], o, -(a2 - a1 + val) * (b2 - b1), f);
         break;
     }
 }
@@ -441,13 +455,14 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fin_kx(const cx<double
 
 hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
                          const cx<double> *mid, int p0, int p1, const double *prof,
-                         double *const *out, int full, double *resid)
+                         void *const *out, int f32, int full, void *resid)
 {
     const int ptot = p1 - p0;
     const size_t lds = sizeof(cx<double>) * ((size_t)d.ntx * fft_stride(d.nx) + d.nx);
     OutPtrs op;
     for (int i = 0; i < 14; ++i) op.t[i] = out[i];
     op.res = full ? nullptr : resid;
+    op.f32 = f32;
     dim3 grid((ptot + 2 * d.ntx - 1) / (2 * d.ntx), full ? d.nz : d.nqo, NMAP + (op.res ? 1 : 0));
     if (d.kxblk == SMALL_BLOCK) {
         set_lds_limit(k_fin_kx<SMALL_BLOCK>);
@@ -469,9 +484,9 @@ hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
 // read the tile's rows and their stencil halo once into L2, and the next Y2
 // finds four of its five stencil columns there.
 constexpr int FD_TY = 4;
-__global__ __launch_bounds__(256) void k_fd_terms(const double *__restrict__ t1, Dims d,
-                                                  Tables t, double *__restrict__ t6,
-                                                  double *__restrict__ t11, int nchunk)
+__global__ __launch_bounds__(256) void k_fd_terms(const void *__restrict__ t1, Dims d,
+                                                  Tables t, void *__restrict__ t6,
+                                                  void *__restrict__ t11, int f32, int nchunk)
 {
     const int ny = d.ny;
     const size_t plane = (size_t)d.nqo * d.npo;   // output map points per pair
@@ -486,23 +501,23 @@ __global__ __launch_bounds__(256) void k_fd_terms(const double *__restrict__ t1,
     double d1 = 0.0, d2 = 0.0;
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
-        d1 += t.w5[j1 * 5 + a] * t1[((size_t)(a1 + a) * ny + j2) * plane + i];
-        d2 += t.w5[j2 * 5 + a] * t1[((size_t)j1 * ny + a2 + a) * plane + i];
+        d1 += t.w5[j1 * 5 + a] * get(t1, ((size_t)(a1 + a) * ny + j2) * plane + i, f32);
+        d2 += t.w5[j2 * 5 + a] * get(t1, ((size_t)j1 * ny + a2 + a) * plane + i, f32);
     }
     const size_t o = ((size_t)j1 * ny + j2) * plane + i;
-    if (t6) t6[o] = -d.nu * (d2 - d1);
-    if (t11) t11[o] = -0.5 * d.nu * (d1 + d2);
+    if (t6) put(t6, o, -d.nu * (d2 - d1), f32);
+    if (t11) put(t11, o, -0.5 * d.nu * (d1 + d2), f32);
 }
 
-hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const double *t1,
-                           double *t6, double *t11)
+hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const void *t1,
+                           void *t6, void *t11, int f32)
 {
     const size_t plane = (size_t)d.nqo * d.npo;   // output map points per pair
     const int nchunk = (int)((plane + 255) / 256);
     const size_t nblk = (size_t)nchunk * d.ny * ((d.ny + FD_TY - 1) / FD_TY) * FD_TY;
     if (nblk >= ((size_t)1 << 31)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fd_terms, dim3((unsigned)nblk), dim3(256), 0, st, t1, d, t, t6, t11,
-                       nchunk);
+                       f32, nchunk);
     return hipGetLastError();
 }
 
@@ -513,8 +528,7 @@ hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const
 // T14 = -2 (eps(Y1) + eps(Y2)).  Same block order as k_fd_terms (tiles of
 // FD_TY rows Y1 per Y2, chunks of the plane fastest, XCD-contiguous ranges).
 __global__ __launch_bounds__(256) void k_resid(OutPtrs out, const double *__restrict__ prof,
-                                               Dims d, Tables t, double *__restrict__ res,
-                                               int nchunk)
+                                               Dims d, Tables t, int nchunk)
 {
     const int ny = d.ny;
     const size_t plane = (size_t)d.nqo * d.npo;   // output map points per pair
@@ -525,28 +539,32 @@ __global__ __launch_bounds__(256) void k_resid(OutPtrs out, const double *__rest
     const int j1 = tile * FD_TY + yi;
     const size_t i = (size_t)chunk * blockDim.x + threadIdx.x;
     if (j1 >= ny || i >= plane) return;
-    const double *t5 = out.t[4], *t6 = out.t[5], *t9 = out.t[8], *t10 = out.t[9];
-    const double *t11 = out.t[10];
+    const int f = out.f32;
     const int a1 = t.j0[j1], a2 = t.j0[j2];
+    // flux maps of one point: Phi_ry = T5 + T6, phi = T9 + T10 + T11
+    auto phi_ry = [&](size_t q) { return get(out.t[4], q, f) + get(out.t[5], q, f); };
+    auto phi_y = [&](size_t q) {
+        return get(out.t[8], q, f) + get(out.t[9], q, f) + get(out.t[10], q, f);
+    };
     double y1 = 0.0, y2 = 0.0, f1 = 0.0, f2 = 0.0;
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
         const size_t o1 = ((size_t)(a1 + a) * ny + j2) * plane + i;
         const size_t o2 = ((size_t)j1 * ny + a2 + a) * plane + i;
         const double w1 = t.w5[j1 * 5 + a], w2 = t.w5[j2 * 5 + a];
-        y1 += w1 * (t5[o1] + t6[o1]);
-        y2 += w2 * (t5[o2] + t6[o2]);
-        f1 += w1 * (t9[o1] + t10[o1] + t11[o1]);
-        f2 += w2 * (t9[o2] + t10[o2] + t11[o2]);
+        y1 += w1 * phi_ry(o1);
+        y2 += w2 * phi_ry(o2);
+        f1 += w1 * phi_y(o1);
+        f2 += w2 * phi_y(o2);
     }
     const size_t o = ((size_t)j1 * ny + j2) * plane + i;
     const double *eps = prof + P_EPS * ny;
-    const double xi = out.t[11][o] + out.t[12][o] - 2.0 * (eps[j1] + eps[j2]);
-    res[o] = res[o] + 0.5 * (y2 - y1) + f1 + f2 - xi;
+    const double xi = get(out.t[11], o, f) + get(out.t[12], o, f) - 2.0 * (eps[j1] + eps[j2]);
+    put(out.res, o, get(out.res, o, f) + 0.5 * (y2 - y1) + f1 + f2 - xi, f);
 }
 
-hipError_t launch_resid(hipStream_t st, const Dims &d, const Tables &t, double *const *out,
-                        const double *prof, double *resid)
+hipError_t launch_resid(hipStream_t st, const Dims &d, const Tables &t, void *const *out,
+                        int f32, const double *prof, void *resid)
 {
     const size_t plane = (size_t)d.nqo * d.npo;   // output map points per pair
     const int nchunk = (int)((plane + 255) / 256);
@@ -555,10 +573,10 @@ hipError_t launch_resid(hipStream_t st, const Dims &d, const Tables &t, double *
     OutPtrs op;
     for (int k = 0; k < 14; ++k) op.t[k] = out[k];
     op.res = resid;
+    op.f32 = f32;
     for (int k : {4, 5, 8, 9, 10, 11, 12})
         if (!op.t[k]) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_resid, dim3((unsigned)nblk), dim3(256), 0, st, op, prof, d, t, resid,
-                       nchunk);
+    hipLaunchKernelGGL(k_resid, dim3((unsigned)nblk), dim3(256), 0, st, op, prof, d, t, nchunk);
     return hipGetLastError();
 }
 
@@ -578,7 +596,8 @@ hipError_t launch_resid(hipStream_t st, const Dims &d, const Tables &t, double *
 // out[t][(q nqo + row) npo + c]; T14 out[13][q].  The derivatives along Y
 // are pointwise in r, so the undersampling drops output points only.
 struct OutPtrs14 {
-    double *t[14];
+    void *t[14];
+    int f32;
 };
 
 __global__ __launch_bounds__(256) void k_slab_out(const double *__restrict__ mf, size_t mstride,
@@ -611,7 +630,7 @@ __global__ __launch_bounds__(256) void k_slab_out(const double *__restrict__ mf,
         const size_t o = ((size_t)q * d.nqo + row) * d.npo + c;
 #pragma unroll
         for (int k = 0; k < 14; ++k)
-            if (kslot[k] >= 0 && out.t[k]) out.t[k][o] = Tb(kslot[k], j1, j2, ofs, sig[k]);
+            if (kslot[k] >= 0 && out.t[k]) put(out.t[k], o, Tb(kslot[k], j1, j2, ofs, sig[k]), out.f32);
         if (fd) {
             double d1 = 0.0, d2 = 0.0;
 #pragma unroll
@@ -619,24 +638,25 @@ __global__ __launch_bounds__(256) void k_slab_out(const double *__restrict__ mf,
                 d1 += t.w5[j1 * 5 + a] * Tb(0, a1 + a, j2, ofs, 1.0);
                 d2 += t.w5[j2 * 5 + a] * Tb(0, j1, a2 + a, ofs, 1.0);
             }
-            if (out.t[5]) out.t[5][o] = -d.nu * (d2 - d1);
-            if (out.t[10]) out.t[10][o] = -0.5 * d.nu * (d1 + d2);
+            if (out.t[5]) put(out.t[5], o, -d.nu * (d2 - d1), out.f32);
+            if (out.t[10]) put(out.t[10], o, -0.5 * d.nu * (d1 + d2), out.f32);
         }
     }
     if (out.t[13] && row == 0 && threadIdx.x == 0) {
         const double *eps = prof + P_EPS * ny;
         double v = -2.0 * (eps[j1] + eps[j2]);
         if (mirror) v = 0.5 * (v - 2.0 * (eps[ny - 1 - j1] + eps[ny - 1 - j2]));
-        out.t[13][q] = v;
+        put(out.t[13], q, v, out.f32);
     }
 }
 
 hipError_t launch_slab_out(hipStream_t st, const Dims &d, const Tables &t, const double *mf,
                            size_t mstride, const int *opairs, int nopairs, const double *prof,
-                           int mirror, double *const *out)
+                           int mirror, void *const *out, int f32)
 {
     OutPtrs14 op;
     for (int i = 0; i < 14; ++i) op.t[i] = out[i];
+    op.f32 = f32;
     if (nopairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_slab_out, dim3(nopairs, d.nqo), dim3(256), 0, st, mf, mstride, d, t,
                        opairs, prof, mirror, op);

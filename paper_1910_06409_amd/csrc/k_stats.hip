@@ -336,19 +336,21 @@ hipError_t launch_zero(hipStream_t st, void *p, size_t bytes)
     return hipGetLastError();
 }
 
-__global__ void k_t14(int ny, const double *__restrict__ prof, double *__restrict__ t14)
+__global__ void k_t14(int ny, const double *__restrict__ prof, void *__restrict__ t14, int f32)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ny * ny) return;
     const int j1 = i / ny, j2 = i - j1 * ny;
     // -4 <eps*>, eps* the average of the two points
-    t14[i] = -2.0 * (prof[P_EPS * ny + j1] + prof[P_EPS * ny + j2]);
+    const double v = -2.0 * (prof[P_EPS * ny + j1] + prof[P_EPS * ny + j2]);
+    if (f32) static_cast<float *>(t14)[i] = (float)v;
+    else static_cast<double *>(t14)[i] = v;
 }
 
-hipError_t launch_t14(hipStream_t st, const Dims &d, const double *prof, double *t14)
+hipError_t launch_t14(hipStream_t st, const Dims &d, const double *prof, void *t14, int f32)
 {
     const int n = d.ny * d.ny;
-    hipLaunchKernelGGL(k_t14, dim3((n + 255) / 256), dim3(256), 0, st, d.ny, prof, t14);
+    hipLaunchKernelGGL(k_t14, dim3((n + 255) / 256), dim3(256), 0, st, d.ny, prof, t14, f32);
     return hipGetLastError();
 }
 

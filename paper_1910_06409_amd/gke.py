@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("GKE_LIBRARY") or os.path.join(_HERE, "libgke.so")
 GKE_OK, GKE_ERR_ARG, GKE_ERR_STATE, GKE_ERR_OOM, GKE_ERR_HIP, GKE_ERR_UNSUPPORTED = range(6)
 GKE_OPT_DTYPE, GKE_OPT_PRECISION, GKE_OPT_CHUNK, GKE_OPT_PAIR_BATCH, GKE_OPT_TIMING = 1, 2, 3, 4, 5
 GKE_OPT_MIRROR, GKE_OPT_DOMAIN, GKE_OPT_SLAB, GKE_OPT_RESIDUAL = 6, 7, 8, 9
+GKE_OPT_HOST_STAGING = 10
 GKE_OUT_F64, GKE_OUT_F32 = 0, 1
 GKE_DOMAIN_ALLPAIRS_HALFRX, GKE_DOMAIN_Y1LEY2_FULLR, GKE_DOMAIN_FUNDAMENTAL_FULLR = 0, 1, 2
 GKE_DTYPE_F64, GKE_DTYPE_F32 = 0, 1
@@ -76,6 +77,7 @@ def lib() -> ctypes.CDLL:
         "gke_begin_stats": ([vp], i32),
         "gke_set_means": ([vp, dp, dp, dp, dp], i32),
         "gke_finalize": ([vp, ctypes.POINTER(gke_terms)], i32),
+        "gke_wait_outputs": ([vp], i32),
         "gke_get_profiles": ([vp, dp], i32),
         "gke_slab_count": ([vp, ctypes.POINTER(i32)], i32),
         "gke_slab_pairs": ([vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
@@ -191,6 +193,10 @@ def gke_finalize(plan, ptrs, residual: int = 0, on_device: int = 1,
     t.dtype = int(dtype)
     t.residual = residual if residual else None
     _check(lib().gke_finalize(plan, ctypes.byref(t)), plan)
+
+
+def gke_wait_outputs(plan) -> None:
+    _check(lib().gke_wait_outputs(plan), plan)
 
 
 def gke_get_profiles(plan, ny: int) -> np.ndarray:

@@ -18,7 +18,8 @@ class GkeRun:
 
     def __init__(self, nx, ny, nz, y, lx, lz, nu, *, dtype="f64", precision="fp64",
                  chunk=64, pair_batch=0, mirror=0, domain=0, slab=0, device="cuda",
-                 stream=None, static_workspace=False, residual=False, undersample=None):
+                 stream=None, static_workspace=False, residual=False, undersample=None,
+                 host_staging=0):
         self.nx, self.ny, self.nz = nx, ny, nz
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
@@ -36,6 +37,7 @@ class GkeRun:
         gke.gke_set_option(self.plan, gke.GKE_OPT_DOMAIN, int(domain))
         gke.gke_set_option(self.plan, gke.GKE_OPT_SLAB, int(slab))
         gke.gke_set_option(self.plan, gke.GKE_OPT_RESIDUAL, 1 if residual else 0)
+        gke.gke_set_option(self.plan, gke.GKE_OPT_HOST_STAGING, int(host_staging))
         # undersampling: {0: (t1, t2, s1, s2) for rx, 1: (...) for rz}
         for d_, u in (undersample or {}).items():
             gke.gke_set_undersampling(self.plan, int(d_), *[int(v) for v in u])
@@ -75,9 +77,11 @@ class GkeRun:
     def set_means(self, U, V, W, P):
         gke.gke_set_means(self.plan, U, V, W, P)
 
-    def alloc_terms(self, which=None, slab=0):
-        """Output maps for gke_finalize (of `slab` in the general modes)."""
+    def alloc_terms(self, which=None, slab=0, dtype=torch.float64, host=False):
+        """Output maps for gke_finalize (of `slab` in the general modes); host=True:
+        pinned host arrays (for a plan with host staging)."""
         which = range(gke.GKE_NTERMS) if which is None else which
+        kw = dict(dtype=dtype, pin_memory=True) if host else dict(dtype=dtype, device=self.device)
         nq, npx = len(self.rz_kept), len(self.rx_kept)
         if self.general:
             n = len(gke.gke_slab_pairs(self.plan, slab))
@@ -86,8 +90,7 @@ class GkeRun:
             shape, s14 = (self.ny, self.ny, nq, npx), (self.ny, self.ny)
         out = [None] * gke.GKE_NTERMS
         for i in which:
-            out[i] = torch.empty(s14 if i == 13 else shape, dtype=torch.float64,
-                                 device=self.device)
+            out[i] = torch.empty(s14 if i == 13 else shape, **kw)
         return out
 
     def chunk(self) -> int:
@@ -109,11 +112,24 @@ class GkeRun:
                            dtype=torch.float64, device=self.device)
 
     def finalize(self, out=None, residual=None):
+        """Write the maps into `out` (device or pinned host tensors, all FP64 or
+        all FP32); host maps are complete after wait_outputs()."""
         if out is None:
             out = self.alloc_terms()
+        ts = [t for t in out if t is not None]
+        host = not ts[0].is_cuda
+        f32 = ts[0].dtype == torch.float32
+        for t in ts + ([residual] if residual is not None else []):
+            if t.is_cuda == host or (t.dtype == torch.float32) != f32 or not t.is_contiguous():
+                raise ValueError("output maps must share one placement and one dtype")
         gke.gke_finalize(self.plan, [t.data_ptr() if t is not None else 0 for t in out],
-                         residual=residual.data_ptr() if residual is not None else 0)
+                         residual=residual.data_ptr() if residual is not None else 0,
+                         on_device=0 if host else 1,
+                         dtype=gke.GKE_OUT_F32 if f32 else gke.GKE_OUT_F64)
         return out
+
+    def wait_outputs(self):
+        gke.gke_wait_outputs(self.plan)
 
     def reset(self):
         gke.gke_reset(self.plan)
@@ -160,14 +176,16 @@ def run_snapshots(snaps_dev, y, lx, lz, nu, *, dtype="f64", precision="fp64", ch
 
 
 def run_slabs(snaps_dev, y, lx, lz, nu, *, dtype="f64", precision="fp64", chunk=64,
-              pair_batch=0, mirror=0, domain=0, slab=0, which=None, undersample=None):
+              pair_batch=0, mirror=0, domain=0, slab=0, which=None, undersample=None,
+              out_dtype=None, host=False):
     """Both scans, then one second scan and finalize per slab.  Returns
     ([(pairs [n][2], maps of the slab)], profiles); maps as gke_finalize lays
-    them out for the general modes."""
+    them out for the general modes, of torch dtype out_dtype (FP64 default),
+    on the device or (host=True) in pinned host memory streamed per slab."""
     S, _, ny, nz, nx = snaps_dev.shape
     r = GkeRun(nx, ny, nz, y, lx, lz, nu, dtype=dtype, precision=precision, chunk=chunk,
                pair_batch=pair_batch, mirror=mirror, domain=domain, slab=slab,
-               device=snaps_dev.device, undersample=undersample)
+               device=snaps_dev.device, undersample=undersample, host_staging=2 if host else 0)
     for s in range(S):
         r.accumulate_snapshot(snaps_dev[s])
     r.begin_stats()
@@ -177,8 +195,10 @@ def run_slabs(snaps_dev, y, lx, lz, nu, *, dtype="f64", precision="fp64", chunk=
             r.begin_slab(sl)
         for s in range(S):
             r.accumulate_snapshot(snaps_dev[s])
-        out = r.finalize(r.alloc_terms(which, slab=sl))
+        out = r.finalize(r.alloc_terms(which, slab=sl, dtype=out_dtype or torch.float64,
+                                       host=host))
         res.append((r.slab_pairs(sl), out))
+    r.wait_outputs()
     prof = r.profiles()
     r.close()
     return res, prof
