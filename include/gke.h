@@ -71,9 +71,10 @@ enum {
     GKE_OPT_SLAB = 8,         /* output Y1 rows per slab, 0 = all rows in one slab (default) */
     GKE_OPT_RESIDUAL = 9,     /* 1: reserve what gke_finalize needs to write the budget
                                  residual (gke_terms.residual; all-pairs mode only) */
-    GKE_OPT_HOST_STAGING = 10 /* device staging buffers for host outputs (gke_terms.on_device
+    GKE_OPT_HOST_STAGING = 10,/* device staging buffers for host outputs (gke_terms.on_device
                                  = 0): 0 (default, device outputs only), 1, or 2 (the copies
                                  of one finalize overlap the next slab's scan) */
+    GKE_OPT_STEP1 = 11        /* 1: reserve the buffers of gke_reconstruct */
 };
 enum { GKE_DTYPE_F64 = 0, GKE_DTYPE_F32 = 1 };
 enum { GKE_PREC_FP64 = 0, GKE_PREC_BF16X3 = 1 };
@@ -259,6 +260,37 @@ gke_status gke_set_stream(gke_plan_t plan, void *hip_stream);
 gke_status gke_accumulate(gke_plan_t plan, const void *u, const void *v, const void *w,
                           const void *p);
 
+/* Step 1 upstream of the statistics (Section "Step 1": a database holding the
+ * wall-normal velocity and vorticity as Fourier coefficients; the full
+ * velocity is computed and the pressure obtained from its Poisson equation).
+ * In: vhat, ohat, device complex FP64 (re, im interleaved) coefficients of v
+ * and omega_y = du/dz - dw/dx, layout [Ny][Nz][Nx/2 + 1], f(x, z) =
+ * sum_k f^ e^{i(alpha x + beta z)} over the half spectrum (the forward
+ * transform divided by Nx Nz); mean_u, mean_w, device FP64 [Ny], the (0, 0)
+ * coefficients of u and w.  Out: device FP64 u, v, w, p [Ny][Nz][Nx] (the
+ * layout gke_accumulate reads with GKE_DTYPE_F64).  alpha = 2 pi kx/Lx and
+ * beta = 2 pi kz/Lz are 0 at the Nyquist wavenumbers.
+ *   velocity, k^2 = alpha^2 + beta^2 > 0 (continuity and the definition of
+ *     omega_y):  u^ = i (alpha D v^ - beta omega^)/k^2,
+ *                w^ = i (beta D v^ + alpha omega^)/k^2;
+ *   pressure: lap p = -d_i d_j (u_i u_j) with the total velocity (products on
+ *     the grid), per wavenumber (D2 - k^2) p^ = alpha^2 uu^ + 2 alpha beta uw^
+ *     + beta^2 ww^ - 2 i alpha D uv^ - 2 i beta D vw^ - D2 vv^ at the interior
+ *     nodes, D p^ = nu D2 v^ at the two walls (wall-normal momentum with no
+ *     slip), solved per wavenumber by banded elimination with partial
+ *     pivoting; the (0, 0) coefficient p^ = -vv^ (the mean pressure does not
+ *     enter the terms) and 0 in the other bins with k^2 = 0;
+ *   D: the five-point first derivative used everywhere; D2: the five-point
+ *     second-derivative weights on the same node windows.
+ * Needs GKE_OPT_STEP1 = 1 before the workspace (about 19 Ny Nk complex FP64
+ * values more).  Asynchronous on the plan's stream; reads nothing else of the
+ * plan's state, so it may be called before or between gke_accumulate calls.
+ * Errors: GKE_ERR_ARG (NULL), GKE_ERR_STATE (no workspace, option not set),
+ * GKE_ERR_HIP. */
+gke_status gke_reconstruct(gke_plan_t plan, const void *vhat, const void *ohat,
+                           const double *mean_u, const double *mean_w, double *u, double *v,
+                           double *w, double *p);
+
 /* Close the first scan: means U V W P from the snapshots accumulated so far
  * and S = dU/dy.  Errors: GKE_ERR_STATE if no snapshot was accumulated or
  * the second scan already started. */
@@ -313,9 +345,11 @@ gke_status gke_reset(gke_plan_t plan);
 /* kernel families reported by gke_timings (GKE_K_RANKK: the matrix-core
  * update of full 16-plane tiles; GKE_K_RANKK_REM: the pairs that involve the
  * last Ny mod 16 planes; GKE_K_RESID: the two residual passes, the kz
- * transform of its spectral divergence and its five-point Y part) */
+ * transform of its spectral divergence and its five-point Y part;
+ * GKE_K_STEP1: one gke_reconstruct, all its launches) */
 enum { GKE_K_PLANE_SUMS = 0, GKE_K_FLUCT_XFFT, GKE_K_ZFFT_PACK, GKE_K_RANKK, GKE_K_FIN_KZ,
-       GKE_K_FIN_KX, GKE_K_FD, GKE_K_SMALL, GKE_K_RANKK_REM, GKE_K_RESID, GKE_NKERNELS };
+       GKE_K_FIN_KX, GKE_K_FD, GKE_K_SMALL, GKE_K_RANKK_REM, GKE_K_RESID, GKE_K_STEP1,
+       GKE_NKERNELS };
 
 /* With GKE_OPT_TIMING set, HIP events bracket every kernel launch on the
  * plan's stream.  Synchronises the stream, then writes per kernel family the

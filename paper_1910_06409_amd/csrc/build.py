@@ -11,7 +11,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libgke.so")
 SOURCES = ["gke_plan.cpp", "k_stats.hip", "k_spectra.hip", "k_rankk.hip", "k_rankk_bf16.hip",
-           "k_final.hip"]
+           "k_final.hip", "k_step1.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

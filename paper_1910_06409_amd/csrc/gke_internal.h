@@ -165,6 +165,7 @@ struct Tables {
     const cx<float> *twx32;  // the same rounded to FP32
     const cx<float> *twz32;
     const double *w5;        // [ny][5] five-point weights
+    const double *w2;        // [ny][5] five-point second-derivative weights (same windows)
     const int *j0;           // [ny] first stencil node
     const int *tile_a;       // [ntp] tile-pair row tiles (index into rowplane / 16)
     const int *tile_b;       // [ntp] tile-pair column tiles (planes 16 b .. 16 b + 15)
@@ -278,6 +279,14 @@ hipError_t launch_r0_band(hipStream_t st, const Dims &d, const double *band, dou
 // Step 3: T6 and T11 from T1 along Y1 and Y2
 hipError_t launch_fd_terms(hipStream_t st, const Dims &d, const Tables &t, const void *t1,
                            void *t6, void *t11, int f32);
+// Step 1 upstream (k_step1.hip): from v^ and omega_y^ ([Ny][Nz][Nkx] complex)
+// and the plane-mean u, w ([Ny]) the physical u, v, w and p ([Ny][Nz][Nx]);
+// vel [3], prod [6], ph: spectral buffers of [Ny][Nz][Nkx]; su [Ny][9][nk],
+// sb [Ny][nk]: the pivot rows of the pressure elimination
+hipError_t launch_step1(hipStream_t st, const Dims &d, const Tables &t, const cx<double> *vh,
+                        const cx<double> *oh, const double *mean_u, const double *mean_w,
+                        cx<double> *vel, cx<double> *prod, cx<double> *ph, double *su,
+                        cx<double> *sb, double *u, double *v, double *w, double *p);
 // zero `bytes` bytes at p (8-byte aligned, a multiple of 8) with a fill kernel
 hipError_t launch_zero(hipStream_t st, void *p, size_t bytes);
 // T14 = -2 (eps(Y1) + eps(Y2))

@@ -39,6 +39,7 @@ struct gke_plan_s {
     int pair_batch = 0;  // pairs per finalize batch (0 = all)
     int mirror = 0, domain = GKE_DOMAIN_ALLPAIRS_HALFRX, slab_rows = 0;
     int residual = 0;              // mid holds one more plane for the budget residual
+    int step1 = 0;                 // buffers of the Step-1 reconstruction (gke_reconstruct)
     int us[2][4] = {{0, 0, 1, 1}, {0, 0, 1, 1}};   // rx, rz undersampling: t1 t2 s1 s2
     std::vector<int> h_rzk, h_rzinv, h_rxk;        // kept separations (output rows, columns)
     // host outputs: device staging buffers of the maps, copied to the caller's
@@ -61,13 +62,15 @@ struct gke_plan_s {
     // host copies of the tables (kept alive for the async uploads)
     std::vector<cx<double>> h_twx, h_twz;
     std::vector<cx<float>> h_twx32, h_twz32;
-    std::vector<double> h_w5;
+    std::vector<double> h_w5, h_w2;
     std::vector<int> h_j0, h_ta, h_tb, h_pairs, h_pidx;
 
     // carved device pointers
     cx<double> *twx = nullptr, *twz = nullptr;
     cx<float> *twx32 = nullptr, *twz32 = nullptr;
-    double *w5 = nullptr;
+    double *w5 = nullptr, *w2 = nullptr;
+    cx<double> *s1vel = nullptr, *s1prod = nullptr, *s1ph = nullptr, *s1b = nullptr;
+    double *s1u = nullptr;
     int *j0 = nullptr, *ta = nullptr, *tb = nullptr, *pairs = nullptr, *pidx = nullptr;
     int *rowplane = nullptr, *rowidx = nullptr, *opairs = nullptr;
     int *rzk = nullptr, *rzinv = nullptr, *rxk = nullptr;
@@ -170,6 +173,35 @@ void fornberg_d1(double x0, const double *x, int n, double *w)
         a = b;
     }
     for (int i = 0; i < n; ++i) w[i] = c1[i];
+}
+
+// Second-derivative weights at x0 on the nodes x[0..n) by the same recurrence
+// carried to derivative order 2.
+void fornberg_d2(double x0, const double *x, int n, double *w)
+{
+    std::vector<double> c(3 * (size_t)n, 0.0);   // c[i * 3 + order]
+    double c1 = 1.0, c4 = x[0] - x0;
+    c[0] = 1.0;
+    for (int i = 1; i < n; ++i) {
+        const int mn = std::min(i, 2);
+        double c2 = 1.0;
+        const double c5 = c4;
+        c4 = x[i] - x0;
+        for (int j = 0; j < i; ++j) {
+            const double c3 = x[i] - x[j];
+            c2 *= c3;
+            if (j == i - 1) {
+                for (int k = mn; k >= 1; --k)
+                    c[i * 3 + k] = c1 * (k * c[(i - 1) * 3 + k - 1] - c5 * c[(i - 1) * 3 + k]) / c2;
+                c[i * 3] = -c1 * c5 * c[(i - 1) * 3] / c2;
+            }
+            for (int k = mn; k >= 1; --k)
+                c[j * 3 + k] = (c4 * c[j * 3 + k] - k * c[j * 3 + k - 1]) / c3;
+            c[j * 3] = c4 * c[j * 3] / c3;
+        }
+        c1 = c2;
+    }
+    for (int i = 0; i < n; ++i) w[i] = c[i * 3 + 2];
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -384,6 +416,7 @@ size_t layout(gke_plan_t p, char *base)
     p->twx32 = (cx<float> *)take(sizeof(cx<float>) * d.nx);
     p->twz32 = (cx<float> *)take(sizeof(cx<float>) * d.nz);
     p->w5 = (double *)take(sizeof(double) * 5 * d.ny);
+    p->w2 = (double *)take(sizeof(double) * 5 * d.ny);
     p->j0 = (int *)take(sizeof(int) * d.ny);
     p->ta = (int *)take(sizeof(int) * ntp);
     p->tb = (int *)take(sizeof(int) * ntp);
@@ -418,6 +451,14 @@ size_t layout(gke_plan_t p, char *base)
     p->stage_slot = align256(sizeof(double) * npo_pairs * (size_t)d.nqo * d.npo);
     p->stage_bytes = 15 * p->stage_slot;
     p->stage = (char *)take(p->host_stage * p->stage_bytes);
+    // Step 1: velocity (3) and product (6) spectra, the pressure spectrum and
+    // the pivot rows of its elimination
+    const size_t cf = p->step1 ? (size_t)d.ny * d.nk : 0;
+    p->s1vel = (cx<double> *)take(sizeof(cx<double>) * 3 * cf);
+    p->s1prod = (cx<double> *)take(sizeof(cx<double>) * 6 * cf);
+    p->s1ph = (cx<double> *)take(sizeof(cx<double>) * cf);
+    p->s1b = (cx<double> *)take(sizeof(cx<double>) * cf);
+    p->s1u = (double *)take(sizeof(double) * 9 * cf);
     return off;
 }
 
@@ -576,6 +617,9 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
         p->h_j0[j] = s;
         fornberg_d1(y[j], y + s, 5, &p->h_w5[5 * (size_t)j]);
     }
+    p->h_w2.assign(5 * (size_t)Ny, 0.0);
+    for (int j = 0; j < Ny; ++j)
+        fornberg_d2(y[j], y + p->h_j0[j], 5, &p->h_w2[5 * (size_t)j]);
     // pair table: tile pairs (a <= b) element by element, then the pairs of
     // the remainder planes j2 >= 16 ntile with j1 <= j2
     for (int a = 0; a < d.ntile; ++a)
@@ -677,6 +721,10 @@ gke_status gke_set_option(gke_plan_t p, int key, int64_t value)
         if (value < 0 || value > 2) return fail(p, GKE_ERR_ARG, "host staging must be 0, 1 or 2");
         p->host_stage = (int)value;
         return GKE_OK;
+    case GKE_OPT_STEP1:
+        if (value != 0 && value != 1) return fail(p, GKE_ERR_ARG, "step1 must be 0 or 1");
+        p->step1 = (int)value;
+        return GKE_OK;
     default:
         return fail(p, GKE_ERR_ARG, "unknown option key");
     }
@@ -730,6 +778,7 @@ gke_status gke_get_option(gke_plan_t p, int key, int64_t *value)
     case GKE_OPT_SLAB: *value = p->slab_rows; return GKE_OK;
     case GKE_OPT_RESIDUAL: *value = p->residual; return GKE_OK;
     case GKE_OPT_HOST_STAGING: *value = p->host_stage; return GKE_OK;
+    case GKE_OPT_STEP1: *value = p->step1; return GKE_OK;
     default: return fail(p, GKE_ERR_ARG, "unknown option key");
     }
 }
@@ -764,6 +813,7 @@ gke_status attach_workspace(gke_plan_t p, void *dev, size_t bytes)
     GKE_HIP(p, hipMemcpyAsync(p->twx32, p->h_twx32.data(), sizeof(cx<float>) * d.nx, hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->twz32, p->h_twz32.data(), sizeof(cx<float>) * d.nz, hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->w5, p->h_w5.data(), sizeof(double) * 5 * d.ny, hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipMemcpyAsync(p->w2, p->h_w2.data(), sizeof(double) * 5 * d.ny, hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipMemcpyAsync(p->j0, p->h_j0.data(), sizeof(int) * d.ny, hipMemcpyHostToDevice, st));
     if (!p->general) {  // all-pairs tables (a slab uploads its own)
         GKE_HIP(p, hipMemcpyAsync(p->ta, p->h_ta.data(), sizeof(int) * p->h_ta.size(), hipMemcpyHostToDevice, st));
@@ -790,6 +840,7 @@ gke_status attach_workspace(gke_plan_t p, void *dev, size_t bytes)
     p->tab.twx32 = p->twx32;
     p->tab.twz32 = p->twz32;
     p->tab.w5 = p->w5;
+    p->tab.w2 = p->w2;
     p->tab.j0 = p->j0;
     p->tab.tile_a = p->ta;
     p->tab.tile_b = p->tb;
@@ -939,6 +990,24 @@ gke_status gke_accumulate(gke_plan_t p, const void *u, const void *v, const void
         if (s != GKE_OK) return s;
     }
     if (p->pending == p->d.chunk) return launch_flush(p);
+    return GKE_OK;
+}
+
+gke_status gke_reconstruct(gke_plan_t p, const void *vhat, const void *ohat,
+                           const double *mean_u, const double *mean_w, double *u, double *v,
+                           double *w, double *pr)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (!vhat || !ohat || !mean_u || !mean_w || !u || !v || !w || !pr)
+        return fail(p, GKE_ERR_ARG, "pointer is NULL");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    if (!p->step1) return fail(p, GKE_ERR_STATE, "gke_reconstruct needs GKE_OPT_STEP1 = 1 "
+                                                 "before the workspace");
+    GKE_HIP(p, timed(p, GKE_K_STEP1, [&] {
+        return gke::launch_step1(p->stream, p->d, p->tab, (const cx<double> *)vhat,
+                                 (const cx<double> *)ohat, mean_u, mean_w, p->s1vel, p->s1prod,
+                                 p->s1ph, p->s1u, p->s1b, u, v, w, pr);
+    }));
     return GKE_OK;
 }
 

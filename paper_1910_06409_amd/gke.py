@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("GKE_LIBRARY") or os.path.join(_HERE, "libgke.so")
 GKE_OK, GKE_ERR_ARG, GKE_ERR_STATE, GKE_ERR_OOM, GKE_ERR_HIP, GKE_ERR_UNSUPPORTED = range(6)
 GKE_OPT_DTYPE, GKE_OPT_PRECISION, GKE_OPT_CHUNK, GKE_OPT_PAIR_BATCH, GKE_OPT_TIMING = 1, 2, 3, 4, 5
 GKE_OPT_MIRROR, GKE_OPT_DOMAIN, GKE_OPT_SLAB, GKE_OPT_RESIDUAL = 6, 7, 8, 9
-GKE_OPT_HOST_STAGING = 10
+GKE_OPT_HOST_STAGING, GKE_OPT_STEP1 = 10, 11
 GKE_OUT_F64, GKE_OUT_F32 = 0, 1
 GKE_DOMAIN_ALLPAIRS_HALFRX, GKE_DOMAIN_Y1LEY2_FULLR, GKE_DOMAIN_FUNDAMENTAL_FULLR = 0, 1, 2
 GKE_DTYPE_F64, GKE_DTYPE_F32 = 0, 1
@@ -29,7 +29,7 @@ TERM_NAMES = ["du2", "phix_t", "phix_m", "phix_v", "phiy_t", "phiy_v", "phiz_t",
               "phi_t", "phi_p", "phi_v", "xi_p1", "xi_p2", "xi_d"]
 PROFILE_NAMES = ["U", "V", "W", "P", "S", "q", "uv", "pv", "Tx", "Ty", "Tz", "eps"]
 KERNEL_NAMES = ["plane_sums", "fluct_xfft", "zfft_pack", "rankk", "fin_kz", "fin_kx", "fd_terms",
-                "small", "rankk_rem", "resid"]
+                "small", "rankk_rem", "resid", "step1"]
 GKE_NKERNELS = len(KERNEL_NAMES)
 
 
@@ -78,6 +78,7 @@ def lib() -> ctypes.CDLL:
         "gke_set_means": ([vp, dp, dp, dp, dp], i32),
         "gke_finalize": ([vp, ctypes.POINTER(gke_terms)], i32),
         "gke_wait_outputs": ([vp], i32),
+        "gke_reconstruct": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
         "gke_get_profiles": ([vp, dp], i32),
         "gke_slab_count": ([vp, ctypes.POINTER(i32)], i32),
         "gke_slab_pairs": ([vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
@@ -171,6 +172,12 @@ def gke_set_stream(plan, stream_ptr: int) -> None:
 
 def gke_accumulate(plan, u: int, v: int, w: int, p: int) -> None:
     _check(lib().gke_accumulate(plan, u, v, w, p), plan)
+
+
+def gke_reconstruct(plan, vhat: int, ohat: int, mean_u: int, mean_w: int, u: int, v: int,
+                    w: int, p: int) -> None:
+    """Device pointers (int): see include/gke.h."""
+    _check(lib().gke_reconstruct(plan, vhat, ohat, mean_u, mean_w, u, v, w, p), plan)
 
 
 def gke_begin_stats(plan) -> None:
