@@ -184,6 +184,9 @@ def main():
                     help="comma-separated workloads measured after the main one (speed-up per "
                          "snapshot reported under 'extra'); empty for none")
     ap.add_argument("--also-steps", type=int, default=2)
+    ap.add_argument("--tuned", default="auto", choices=["auto", "off"],
+                    help="auto: use the autotuner's cached chunk and block shapes for the "
+                         "workload's shape when present (paper_1910_06409_amd/tuned.json)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device-to-device copy of MIB MiB three times "
                          "(the known-size reference for HBM traffic counters)")
@@ -198,7 +201,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1910_06409_amd import profiling, runner, synth
+    from paper_1910_06409_amd import profiling, runner, synth, tune
 
     def load_workload(name, snapshots=0, precision=""):
         w = synth.workload(name)
@@ -214,8 +217,16 @@ def main():
         """Time `steps` whole-path steps of workload w; returns a result dict."""
         S = w.S
         # one batch for the whole ensemble when it is small, else the library's
-        # automatic chunk (largest batch whose spectra fit its memory budget)
+        # automatic chunk (largest batch whose spectra fit its memory budget);
+        # the autotuner's cached choice for this shape when there is one
         chunk = chunk_arg if chunk_arg else (S + (S & 1) if S <= 128 else 0)
+        tuned = tune.load(w) if args.tuned == "auto" and S == synth.workload(w.name).S else None
+        shapes = {}
+        if tuned:
+            if not chunk_arg:
+                chunk = int(tuned["chunk"])
+            shapes = {k: int(tuned[k]) for k in tune.SHAPE_KEYS if k in tuned}
+            log(f"[bench] autotuned for {tune.key_of(w)}: chunk {chunk}, {shapes}")
         y = synth.y_grid(w)
         tdt = torch.float64 if w.dtype == "f64" else torch.float32
         log(f"[bench] generating {S} snapshots of {w.name} ({w.nx}x{w.ny}x{w.nz}, {w.dtype})")
@@ -230,7 +241,7 @@ def main():
         del gen
         r = runner.GkeRun(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu, dtype=w.dtype,
                           precision=w.precision, chunk=chunk, pair_batch=args.pair_batch,
-                          device=dev)
+                          device=dev, shapes=shapes)
         chunk_used = r.chunk()
         outs = r.alloc_terms()
         log(f"[bench] workspace {r.workspace.numel() / 2**30:.1f} GiB, outputs "
@@ -343,7 +354,8 @@ def main():
                 "frac": ach / peak, "traffic": traffic}
         roof.update(extra_roof)
         return {"w": w, "S": S, "chunk": chunk_used, "t_step": t_step, "kernels": kernels,
-                "roofline": roof, "stages": stages, "value": w.points_out * S / t_step}
+                "roofline": roof, "stages": stages, "value": w.points_out * S / t_step,
+                "tuned": ({"chunk": chunk_used, **shapes} if tuned else None)}
 
     def measure_slabs(w, slab_rows, chunk, pair_batch):
         """The config-5 path: mirror average, fundamental domain, Y1 slabs (one
@@ -440,7 +452,7 @@ def main():
             "snapshots": we.S, "chunk": er["chunk"], "dtype": we.dtype,
             "precision": we.precision, "steps": args.also_steps,
             "speedup_per_snapshot_vs_main": per_snap_main / per_snap,
-            "roofline": er["roofline"], "stages": er["stages"],
+            "roofline": er["roofline"], "stages": er["stages"], "tuned": er["tuned"],
             "kernels_ms_per_step": {k: v["ms_per_step"] for k, v in er["kernels"].items()},
         }
         stated = profiling.stated_error(
@@ -470,7 +482,7 @@ def main():
                                f"{w.dtype} snapshots, all (Y1,Y2) pairs, rx>=0 half plane, "
                                f"14 term maps", "grid": [w.nx, w.ny, w.nz], "snapshots": S,
                    "precision": w.precision, "chunk": main_res["chunk"],
-                   "points_out": w.points_out},
+                   "points_out": w.points_out, "tuned": main_res["tuned"]},
         "points_per_s": w.points_out / t_step,
         "roofline": main_res["roofline"],
         "stages": main_res["stages"],

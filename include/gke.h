@@ -74,7 +74,12 @@ enum {
     GKE_OPT_HOST_STAGING = 10,/* device staging buffers for host outputs (gke_terms.on_device
                                  = 0): 0 (default, device outputs only), 1, or 2 (the copies
                                  of one finalize overlap the next slab's scan) */
-    GKE_OPT_STEP1 = 11        /* 1: reserve the buffers of gke_reconstruct */
+    GKE_OPT_STEP1 = 11,       /* 1: reserve the buffers of gke_reconstruct */
+    /* block shapes for an autotuner (0: the built-in rule; gke_get_option
+       reports the shape in effect once the workspace is sized): */
+    GKE_OPT_TUNE_ZPLANES = 12,/* at most this many planes per z-transform block (1..64) */
+    GKE_OPT_TUNE_KZPAIRS = 13,/* pairs per kz-finalize block (even, within its LDS) */
+    GKE_OPT_TUNE_KXTRANS = 14 /* packed transforms per kx-finalize block (within its LDS) */
 };
 enum { GKE_DTYPE_F64 = 0, GKE_DTYPE_F32 = 1 };
 enum { GKE_PREC_FP64 = 0, GKE_PREC_BF16X3 = 1 };

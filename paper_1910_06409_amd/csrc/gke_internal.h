@@ -113,6 +113,7 @@ struct Dims {
                       // every 16-plane tile of a row starts on a 128-byte line
     int nqs;          // split path: snapshot quads per chunk, (chunk + 3) / 4
     int prec;         // PREC_FP64 or PREC_BF16X3
+    int zplanes;      // an autotuned bound on the planes of a z-pass block (0: none)
     int nqo, npo;     // rows (rz) and columns (rx) of an output map: the separations kept
                       // by the rx/rz undersampling (Nz and Nx/2 + 1 or Nx without it)
     double lx, lz, nu;

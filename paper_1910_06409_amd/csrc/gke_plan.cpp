@@ -40,6 +40,9 @@ struct gke_plan_s {
     int mirror = 0, domain = GKE_DOMAIN_ALLPAIRS_HALFRX, slab_rows = 0;
     int residual = 0;              // mid holds one more plane for the budget residual
     int step1 = 0;                 // buffers of the Step-1 reconstruction (gke_reconstruct)
+    // block shapes chosen by an autotuner (0: the built-in rule) and their limits
+    int tune_zplanes = 0, tune_kzpairs = 0, tune_kxtrans = 0;
+    int max_zplanes = 1, max_kzpairs = 2, max_kxtrans = 1;
     int us[2][4] = {{0, 0, 1, 1}, {0, 0, 1, 1}};   // rx, rz undersampling: t1 t2 s1 s2
     std::vector<int> h_rzk, h_rzinv, h_rxk;        // kept separations (output rows, columns)
     // host outputs: device staging buffers of the maps, copied to the caller's
@@ -371,7 +374,8 @@ void set_zpass_shape(gke::Dims &d)
     const bool split = d.prec == gke::PREC_BF16X3;
     d.zpblk = !split && cap_small / sz >= 8 ? gke::SMALL_BLOCK : gke::FFT_BLOCK;
     const size_t capz = d.zpblk == gke::SMALL_BLOCK ? cap_small : cap;
-    const int jmax = std::max(1, (int)std::min<size_t>(64, capz / (split ? 4 * sz : sz)));
+    int jmax = std::max(1, (int)std::min<size_t>(64, capz / (split ? 4 * sz : sz)));
+    if (d.zplanes > 0) jmax = std::min(jmax, d.zplanes);   // an autotuned bound
     d.njb = (d.ny + jmax - 1) / jmax;
     d.jb = (d.ny + d.njb - 1) / d.njb;
     d.nqs = (d.chunk + 3) / 4;
@@ -599,6 +603,10 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
     // (kx pass: at most 8 transforms, five blocks per compute unit at re200,
     // measured faster than ten)
     d.ntx = (int)std::min<size_t>(8, capkx / sx);
+    // limits of the autotuned shapes: the LDS caps above
+    p->max_kzpairs = (int)std::min<size_t>(16, cap / sz) & ~1;
+    p->max_kxtrans = (int)std::min<size_t>(gke::MAX_NTX, capkx / sx);
+    p->max_zplanes = 64;
     // 32-bit element offsets within one wavenumber row of acc (kz pass)
     if (d.zb < 1 || d.jb < 1 || d.pbz < 2 || d.ntx < 1 || (size_t)Nz * d.pstr >= ((size_t)1 << 31)) {
         delete p;
@@ -725,6 +733,23 @@ gke_status gke_set_option(gke_plan_t p, int key, int64_t value)
         if (value != 0 && value != 1) return fail(p, GKE_ERR_ARG, "step1 must be 0 or 1");
         p->step1 = (int)value;
         return GKE_OK;
+    case GKE_OPT_TUNE_ZPLANES:
+        if (value < 0 || value > p->max_zplanes)
+            return fail(p, GKE_ERR_ARG, "z-pass planes per block out of range");
+        p->tune_zplanes = (int)value;
+        return GKE_OK;
+    case GKE_OPT_TUNE_KZPAIRS:
+        if (value < 0 || value > p->max_kzpairs || (value & 1))
+            return fail(p, GKE_ERR_ARG, "kz-finalize pairs per block must be even and within the "
+                                        "block's LDS (" + std::to_string(p->max_kzpairs) + ")");
+        p->tune_kzpairs = (int)value;
+        return GKE_OK;
+    case GKE_OPT_TUNE_KXTRANS:
+        if (value < 0 || value > p->max_kxtrans)
+            return fail(p, GKE_ERR_ARG, "kx-finalize transforms per block out of range (max " +
+                                            std::to_string(p->max_kxtrans) + ")");
+        p->tune_kxtrans = (int)value;
+        return GKE_OK;
     default:
         return fail(p, GKE_ERR_ARG, "unknown option key");
     }
@@ -739,6 +764,10 @@ gke_status gke_set_option(gke_plan_t p, int key, int64_t value)
 constexpr size_t kAutoChunkBytes = (size_t)96 << 30;
 gke_status prepare_mode(gke_plan_t p)
 {
+    // autotuned block shapes (0 keeps the built-in rule)
+    p->d.zplanes = p->tune_zplanes;
+    if (p->tune_kzpairs > 0) p->d.pbz = p->tune_kzpairs;
+    if (p->tune_kxtrans > 0) p->d.ntx = p->tune_kxtrans;
     set_zpass_shape(p->d);
     if (p->chunk == 0) {
         const size_t esz = p->d.prec == gke::PREC_BF16X3 ? 8 : 16;
@@ -779,6 +808,9 @@ gke_status gke_get_option(gke_plan_t p, int key, int64_t *value)
     case GKE_OPT_RESIDUAL: *value = p->residual; return GKE_OK;
     case GKE_OPT_HOST_STAGING: *value = p->host_stage; return GKE_OK;
     case GKE_OPT_STEP1: *value = p->step1; return GKE_OK;
+    case GKE_OPT_TUNE_ZPLANES: *value = p->d.jb; return GKE_OK;
+    case GKE_OPT_TUNE_KZPAIRS: *value = p->d.pbz; return GKE_OK;
+    case GKE_OPT_TUNE_KXTRANS: *value = p->d.ntx; return GKE_OK;
     default: return fail(p, GKE_ERR_ARG, "unknown option key");
     }
 }

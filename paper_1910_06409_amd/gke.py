@@ -19,6 +19,7 @@ GKE_OK, GKE_ERR_ARG, GKE_ERR_STATE, GKE_ERR_OOM, GKE_ERR_HIP, GKE_ERR_UNSUPPORTE
 GKE_OPT_DTYPE, GKE_OPT_PRECISION, GKE_OPT_CHUNK, GKE_OPT_PAIR_BATCH, GKE_OPT_TIMING = 1, 2, 3, 4, 5
 GKE_OPT_MIRROR, GKE_OPT_DOMAIN, GKE_OPT_SLAB, GKE_OPT_RESIDUAL = 6, 7, 8, 9
 GKE_OPT_HOST_STAGING, GKE_OPT_STEP1 = 10, 11
+GKE_OPT_TUNE_ZPLANES, GKE_OPT_TUNE_KZPAIRS, GKE_OPT_TUNE_KXTRANS = 12, 13, 14
 GKE_OUT_F64, GKE_OUT_F32 = 0, 1
 GKE_DOMAIN_ALLPAIRS_HALFRX, GKE_DOMAIN_Y1LEY2_FULLR, GKE_DOMAIN_FUNDAMENTAL_FULLR = 0, 1, 2
 GKE_DTYPE_F64, GKE_DTYPE_F32 = 0, 1

@@ -19,7 +19,7 @@ class GkeRun:
     def __init__(self, nx, ny, nz, y, lx, lz, nu, *, dtype="f64", precision="fp64",
                  chunk=64, pair_batch=0, mirror=0, domain=0, slab=0, device="cuda",
                  stream=None, static_workspace=False, residual=False, undersample=None,
-                 host_staging=0, step1=False):
+                 host_staging=0, step1=False, shapes=None):
         self.nx, self.ny, self.nz = nx, ny, nz
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
@@ -39,6 +39,11 @@ class GkeRun:
         gke.gke_set_option(self.plan, gke.GKE_OPT_RESIDUAL, 1 if residual else 0)
         gke.gke_set_option(self.plan, gke.GKE_OPT_HOST_STAGING, int(host_staging))
         gke.gke_set_option(self.plan, gke.GKE_OPT_STEP1, 1 if step1 else 0)
+        # block shapes from the autotuner: {"zplanes": n, "kzpairs": n, "kxtrans": n}
+        keys = {"zplanes": gke.GKE_OPT_TUNE_ZPLANES, "kzpairs": gke.GKE_OPT_TUNE_KZPAIRS,
+                "kxtrans": gke.GKE_OPT_TUNE_KXTRANS}
+        for k, v in (shapes or {}).items():
+            gke.gke_set_option(self.plan, keys[k], int(v))
         # undersampling: {0: (t1, t2, s1, s2) for rx, 1: (...) for rz}
         for d_, u in (undersample or {}).items():
             gke.gke_set_undersampling(self.plan, int(d_), *[int(v) for v in u])

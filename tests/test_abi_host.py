@@ -236,3 +236,17 @@ def test_undersampling_indices_match_the_oracle_rule():
             assert e.value.status == gke.GKE_ERR_ARG
     finally:
         gke.gke_destroy(p)
+
+
+def test_tuned_cache_round_trip(tmp_path):
+    """The autotuner's cache: one entry per (grid, precision, dtype) key."""
+    from paper_1910_06409_amd import synth, tune
+    path = str(tmp_path / "tuned.json")
+    a, b = synth.workload("re200"), synth.workload("re200_bf16")
+    assert tune.key_of(a) == "192x129x160/fp64/f64"
+    assert tune.load(a, path) is None
+    tune.save(a, {"chunk": 100, "zplanes": 12}, path)
+    tune.save(b, {"chunk": 512, "kxtrans": 8}, path)
+    assert tune.load(a, path)["zplanes"] == 12
+    assert tune.load(b, path)["chunk"] == 512
+    assert tune.load(synth.workload("tiny"), path) is None
