@@ -184,6 +184,12 @@ def main():
                     help="comma-separated workloads measured after the main one (speed-up per "
                          "snapshot reported under 'extra'); empty for none")
     ap.add_argument("--also-steps", type=int, default=2)
+    ap.add_argument("--graph", default="off", choices=["on", "off"],
+                    help="on: the timed steps feed each scan's snapshots as one captured HIP "
+                         "graph (gke_accumulate_batch) and the per-kernel times come from "
+                         "extra event-timed steps; off: one gke_accumulate per snapshot with "
+                         "HIP events over the timed region, and a few graph steps after it "
+                         "(graph_ms_per_step)")
     ap.add_argument("--tuned", default="auto", choices=["auto", "off"],
                     help="auto: use the autotuner's cached chunk and block shapes for the "
                          "workload's shape when present (paper_1910_06409_amd/tuned.json)")
@@ -256,34 +262,60 @@ def main():
             log(f"[bench] calibration copy of {nb} bytes done")
             del src, dst
 
-        def step():
+        def step(graph):
             r.reset()
-            for s in range(S):
-                r.accumulate_snapshot(snaps[s])
-            r.begin_stats()
-            for s in range(S):
-                r.accumulate_snapshot(snaps[s])
+            if graph:
+                r.accumulate_batch(snaps)
+                r.begin_stats()
+                r.accumulate_batch(snaps)
+            else:
+                for s in range(S):
+                    r.accumulate_snapshot(snaps[s])
+                r.begin_stats()
+                for s in range(S):
+                    r.accumulate_snapshot(snaps[s])
             r.finalize(outs)
 
+        graph = args.graph == "on"
         for i in range(warmup):
-            step()
+            step(graph)
             log(f"[bench] warmup step {i + 1}/{warmup} done")
-        r.set_timing(True)
+        # graph off: HIP events around every launch over the timed region;
+        # graph on: the timed steps run the captured graphs without events and
+        # the per-kernel device times come from extra event-timed steps
+        r.set_timing(not graph)
         r.timings(reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(steps):
-            step()
+            step(graph)
             log(f"[bench] timed step {i + 1}/{steps} done")
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        ksteps = steps
+        if graph:
+            r.set_timing(True)
+            ksteps = max(1, min(steps, 3))
+            for i in range(ksteps):
+                step(False)
         tm = r.timings(reset=True)
         r.set_timing(False)
+        graph_ms = None
+        if not graph:   # the same steps as captured graphs, for comparison
+            gsteps = max(1, min(steps, 3))
+            step(True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for i in range(gsteps):
+                step(True)
+            torch.cuda.synchronize()
+            graph_ms = 1e3 * (time.perf_counter() - t1) / gsteps
         r.close()
         del outs, snaps, r
         torch.cuda.empty_cache()
 
         t_step = elapsed / steps
+        steps_k = ksteps   # the per-kernel figures below are per event-timed step
         work = kernel_work(w, chunk_used)
         s8 = s8d_work(w, chunk_used)
         kernels = {}
@@ -291,13 +323,13 @@ def main():
             if n == 0:
                 continue
             avg = ms / n
-            k = {"ms_per_step": ms / steps, "launches_per_step": n / steps, "avg_launch_ms": avg}
+            k = {"ms_per_step": ms / steps_k, "launches_per_step": n / steps_k, "avg_launch_ms": avg}
             if name in work:
                 kind, amount = work[name]
                 if name in ("rankk", "rankk_rem"):
                     # the last launch of a step may hold fewer snapshots: use the mean
-                    amount = amount * (S / chunk_used) / (n / steps)
-                    k["achieved_tflops"] = (s8[name] * (S / chunk_used) / (n / steps)
+                    amount = amount * (S / chunk_used) / (n / steps_k)
+                    k["achieved_tflops"] = (s8[name] * (S / chunk_used) / (n / steps_k)
                                             / (avg * 1e-3) / 1e12)
                     k["achieved_tflops_own_basis"] = amount / (avg * 1e-3) / 1e12
                 elif kind == "flop":
@@ -355,7 +387,8 @@ def main():
         roof.update(extra_roof)
         return {"w": w, "S": S, "chunk": chunk_used, "t_step": t_step, "kernels": kernels,
                 "roofline": roof, "stages": stages, "value": w.points_out * S / t_step,
-                "tuned": ({"chunk": chunk_used, **shapes} if tuned else None)}
+                "tuned": ({"chunk": chunk_used, **shapes} if tuned else None),
+                "graph_ms_per_step": graph_ms}
 
     def measure_slabs(w, slab_rows, chunk, pair_batch):
         """The config-5 path: mirror average, fundamental domain, Y1 slabs (one
@@ -453,6 +486,7 @@ def main():
             "precision": we.precision, "steps": args.also_steps,
             "speedup_per_snapshot_vs_main": per_snap_main / per_snap,
             "roofline": er["roofline"], "stages": er["stages"], "tuned": er["tuned"],
+            "graph_ms_per_step": er["graph_ms_per_step"],
             "kernels_ms_per_step": {k: v["ms_per_step"] for k, v in er["kernels"].items()},
         }
         stated = profiling.stated_error(
@@ -484,6 +518,8 @@ def main():
                    "precision": w.precision, "chunk": main_res["chunk"],
                    "points_out": w.points_out, "tuned": main_res["tuned"]},
         "points_per_s": w.points_out / t_step,
+        "graph": {"timed_steps_as_graphs": args.graph == "on",
+                  "graph_ms_per_step": main_res["graph_ms_per_step"]},
         "roofline": main_res["roofline"],
         "stages": main_res["stages"],
         "cpu_baseline": cpu,

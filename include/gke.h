@@ -296,6 +296,18 @@ gke_status gke_reconstruct(gke_plan_t plan, const void *vhat, const void *ohat,
                            const double *mean_u, const double *mean_w, double *u, double *v,
                            double *w, double *p);
 
+/* The same as n calls of gke_accumulate with u[i], v[i], w[i], p[i] (host
+ * arrays of n device pointers), launched as one HIP graph: the launches are
+ * captured once (on a stream of the library's own) and the executable graph
+ * is replayed on the plan's stream as long as the pointers, n and the scan
+ * state at the call (which scan, the position in the current chunk) match; a
+ * different batch re-captures and updates the graph in place (up to four are
+ * kept per plan).  With GKE_OPT_TIMING the launches are made one by one.
+ * Errors: those of gke_accumulate, GKE_ERR_HIP for capture or launch. */
+gke_status gke_accumulate_batch(gke_plan_t plan, int n, const void *const *u,
+                                const void *const *v, const void *const *w,
+                                const void *const *p);
+
 /* Close the first scan: means U V W P from the snapshots accumulated so far
  * and S = dU/dy.  Errors: GKE_ERR_STATE if no snapshot was accumulated or
  * the second scan already started. */

@@ -93,6 +93,19 @@ struct gke_plan_s {
     bool means_from_host = false;
     std::string err;
 
+    // graphs of gke_accumulate_batch: the launches of n snapshots captured once
+    // and replayed while the pointers and the starting scan state match
+    struct BatchGraph {
+        hipGraphExec_t exec = nullptr;
+        std::vector<const void *> ptrs;
+        int n = 0, pending0 = 0, pending1 = 0;
+        bool second = false, acc0 = false;
+        long long dchunks = 0, used = 0;
+    };
+    std::vector<BatchGraph> graphs;    // at most kMaxGraphs
+    long long graph_clock = 0;
+    hipStream_t capture_stream = nullptr;
+
     // optional HIP-event timing of every launch
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;   // created once, reused
@@ -1025,6 +1038,110 @@ gke_status gke_accumulate(gke_plan_t p, const void *u, const void *v, const void
     return GKE_OK;
 }
 
+gke_status gke_accumulate_batch(gke_plan_t p, int n, const void *const *u,
+                                const void *const *v, const void *const *w,
+                                const void *const *pr)
+{
+    constexpr size_t kMaxGraphs = 4;
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    if (n <= 0 || !u || !v || !w || !pr) return fail(p, GKE_ERR_ARG, "bad batch");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    for (int i = 0; i < n; ++i)
+        if (!u[i] || !v[i] || !w[i] || !pr[i]) return fail(p, GKE_ERR_ARG, "field pointer is NULL");
+    if (p->timing) {   // per-launch events: run the launches one by one
+        for (int i = 0; i < n; ++i) {
+            const gke_status s = gke_accumulate(p, u[i], v[i], w[i], pr[i]);
+            if (s != GKE_OK) return s;
+        }
+        return GKE_OK;
+    }
+    std::vector<const void *> ptrs;
+    ptrs.reserve(4 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        ptrs.push_back(u[i]);
+        ptrs.push_back(v[i]);
+        ptrs.push_back(w[i]);
+        ptrs.push_back(pr[i]);
+    }
+    const bool acc0 = p->chunks_done > 0;
+    gke_plan_s::BatchGraph *g = nullptr;
+    for (auto &e : p->graphs)
+        if (e.exec && e.n == n && e.second == p->second_scan && e.pending0 == p->pending &&
+            e.acc0 == acc0 && e.ptrs == ptrs) {
+            g = &e;
+            break;
+        }
+    if (g) {   // replay: advance the host state as the captured calls did
+        if (g->second) {
+            p->n2 += n;
+            p->pending = g->pending1;
+            p->chunks_done += g->dchunks;
+        } else {
+            p->n1 += n;
+        }
+    } else {
+        // capture the launches of the n calls on a stream of the library's own
+        // (the plan's stream may be the legacy default stream, which cannot be
+        // captured), then launch the graph on the plan's stream
+        if (!p->capture_stream)
+            GKE_HIP(p, hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+        const int pending0 = p->pending;
+        const long long chunks0 = p->chunks_done;
+        const bool second = p->second_scan;
+        hipStream_t user = p->stream;
+        p->stream = p->capture_stream;
+        GKE_HIP(p, hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+        gke_status st = GKE_OK;
+        for (int i = 0; i < n && st == GKE_OK; ++i) st = gke_accumulate(p, u[i], v[i], w[i], pr[i]);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(p->capture_stream, &graph);
+        p->stream = user;
+        if (st != GKE_OK || ec != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            if (st != GKE_OK) return st;
+            return fail(p, GKE_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+        }
+        // a new entry, or the least recently used one updated in place
+        if (p->graphs.size() < kMaxGraphs) {
+            p->graphs.emplace_back();
+            g = &p->graphs.back();
+        } else {
+            g = &p->graphs[0];
+            for (auto &e : p->graphs)
+                if (e.used < g->used) g = &e;
+        }
+        bool updated = false;
+        if (g->exec) {
+            hipGraphNode_t bad = nullptr;
+            hipGraphExecUpdateResult res;
+            updated = hipGraphExecUpdate(g->exec, graph, &bad, &res) == hipSuccess &&
+                      res == hipGraphExecUpdateSuccess;
+            if (!updated) {
+                (void)hipGetLastError();
+                (void)hipGraphExecDestroy(g->exec);
+                g->exec = nullptr;
+            }
+        }
+        hipError_t ei = hipSuccess;
+        if (!updated) ei = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            g->exec = nullptr;
+            return fail(p, GKE_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        }
+        g->ptrs = ptrs;
+        g->n = n;
+        g->second = second;
+        g->pending0 = pending0;
+        g->acc0 = chunks0 > 0;
+        g->pending1 = p->pending;
+        g->dchunks = p->chunks_done - chunks0;
+    }
+    g->used = ++p->graph_clock;
+    GKE_HIP(p, hipGraphLaunch(g->exec, p->stream));
+    return GKE_OK;
+}
+
 gke_status gke_reconstruct(gke_plan_t p, const void *vhat, const void *ohat,
                            const double *mean_u, const double *mean_w, double *u, double *v,
                            double *w, double *pr)
@@ -1310,6 +1427,9 @@ void gke_destroy(gke_plan_t p)
 {
     if (!p) return;
     if (p->ws) (void)hipStreamSynchronize(p->stream);
+    for (auto &e : p->graphs)
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     if (p->copy_stream) {
         (void)hipStreamSynchronize(p->copy_stream);
         for (int b = 0; b < 2; ++b) {

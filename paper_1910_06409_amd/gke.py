@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
         "gke_sample_indices": ([vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "gke_set_stream": ([vp, vp], i32),
         "gke_accumulate": ([vp, vp, vp, vp, vp], i32),
+        "gke_accumulate_batch": ([vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  ctypes.POINTER(vp), ctypes.POINTER(vp)], i32),
         "gke_begin_stats": ([vp], i32),
         "gke_set_means": ([vp, dp, dp, dp, dp], i32),
         "gke_finalize": ([vp, ctypes.POINTER(gke_terms)], i32),
@@ -179,6 +181,13 @@ def gke_reconstruct(plan, vhat: int, ohat: int, mean_u: int, mean_w: int, u: int
                     w: int, p: int) -> None:
     """Device pointers (int): see include/gke.h."""
     _check(lib().gke_reconstruct(plan, vhat, ohat, mean_u, mean_w, u, v, w, p), plan)
+
+
+def gke_accumulate_batch(plan, u, v, w, p) -> None:
+    """u, v, w, p: sequences of n device pointers (int)."""
+    n = len(u)
+    arr = [(ctypes.c_void_p * n)(*[int(x) for x in a]) for a in (u, v, w, p)]
+    _check(lib().gke_accumulate_batch(plan, n, *arr), plan)
 
 
 def gke_begin_stats(plan) -> None:

@@ -77,6 +77,15 @@ class GkeRun:
         """snap: device tensor [4][ny][nz][nx]."""
         self.accumulate(snap[0], snap[1], snap[2], snap[3])
 
+    def accumulate_batch(self, snaps):
+        """snaps: device tensor [n][4][ny][nz][nx], accumulated as one graph."""
+        if snaps.dtype != self.tdtype or not snaps.is_contiguous() or snaps.device != self.device:
+            raise ValueError("snapshots must be a contiguous device tensor of the plan dtype")
+        if tuple(snaps.shape[1:]) != (4, self.ny, self.nz, self.nx):
+            raise ValueError("snapshots must be [n][4][ny][nz][nx]")
+        ptr = [[snaps[i, f].data_ptr() for i in range(snaps.shape[0])] for f in range(4)]
+        gke.gke_accumulate_batch(self.plan, *ptr)
+
     def begin_stats(self):
         gke.gke_begin_stats(self.plan)
 

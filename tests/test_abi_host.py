@@ -250,3 +250,17 @@ def test_tuned_cache_round_trip(tmp_path):
     assert tune.load(a, path)["zplanes"] == 12
     assert tune.load(b, path)["chunk"] == 512
     assert tune.load(synth.workload("tiny"), path) is None
+
+
+def test_accumulate_batch_argument_checks():
+    y = np.linspace(-1, 1, 17)
+    p = gke.gke_plan(16, 17, 16, y, 2 * np.pi, np.pi, 0.005)
+    try:
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_accumulate_batch(p, [1], [1], [1], [1])
+        assert e.value.status == gke.GKE_ERR_STATE     # no workspace yet
+        with pytest.raises(gke.GkeError) as e:
+            gke.gke_accumulate_batch(p, [], [], [], [])
+        assert e.value.status == gke.GKE_ERR_ARG
+    finally:
+        gke.gke_destroy(p)
