@@ -180,6 +180,8 @@ def main():
     ap.add_argument("--slab-rows", type=int, default=0,
                     help="config-5 path: mirror average, fundamental domain, Y1 slabs of this "
                          "many rows (one timed pass over all slabs)")
+    ap.add_argument("--host-out", action="store_true",
+                    help="config-5 path: stream every slab's maps to pinned host memory")
     ap.add_argument("--also", default="re200_bf16,re200_batched",
                     help="comma-separated workloads measured after the main one (speed-up per "
                          "snapshot reported under 'extra'); empty for none")
@@ -392,66 +394,94 @@ def main():
 
     def measure_slabs(w, slab_rows, chunk, pair_batch):
         """The config-5 path: mirror average, fundamental domain, Y1 slabs (one
-        second scan per slab).  One timed pass over every slab; device time
-        only (the caller would stream each slab's maps to the host)."""
+        second scan per slab), every slab's maps streamed to pinned host
+        memory (double-buffered device staging, copies on the library's own
+        stream).  When the ensemble does not fit in HBM beside the workspace,
+        every scan regenerates the snapshots on the device (the paper's
+        wall-normal slices each read the whole database); the generation is
+        timed apart from the library's device time."""
         S = w.S
         y = synth.y_grid(w)
         tdt = torch.float64 if w.dtype == "f64" else torch.float32
-        log(f"[bench] generating {S} snapshots of {w.name} ({w.nx}x{w.ny}x{w.nz}, {w.dtype})")
-        snaps = torch.empty((S, 4, w.ny, w.nz, w.nx), dtype=tdt, device=dev)
-        gen = synth.DeviceSnapshots(w, args.seed, dev)
-        for s in range(S):
-            gen(s, out=snaps[s])
-        torch.cuda.synchronize()
-        del gen
         from paper_1910_06409_amd import gke
         r = runner.GkeRun(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu, dtype=w.dtype,
                           precision=w.precision, chunk=chunk, pair_batch=pair_batch,
                           mirror=1, domain=gke.GKE_DOMAIN_FUNDAMENTAL_FULLR, slab=slab_rows,
-                          device=dev)
+                          device=dev, host_staging=2 if args.host_out else 0)
         nslab = r.slab_count()
         npairs = [len(r.slab_pairs(sl)) for sl in range(nslab)]
-        outs = r.alloc_terms(slab=int(np.argmax(npairs)))
-        log(f"[bench] workspace {r.workspace.numel() / 2**30:.1f} GiB, {nslab} slabs, "
-            f"slab outputs {sum(o.numel() for o in outs) * 8 / 2**30:.1f} GiB, chunk {r.chunk()}")
+        big = int(np.argmax(npairs))
+        snap_bytes = 4 * w.ny * w.nz * w.nx * (4 if w.dtype == "f32" else 8)
+        free = torch.cuda.mem_get_info(dev)[0]
+        out_dev = 0 if args.host_out else 14 * npairs[big] * w.nz * w.nx * 8
+        resident = S * snap_bytes + out_dev < free - (8 << 30)
+        log(f"[bench] workspace {r.workspace.numel() / 2**30:.1f} GiB, {nslab} slabs, chunk "
+            f"{r.chunk()}, {S} snapshots {'resident' if resident else 'regenerated per scan'}")
+        if resident:
+            snaps = torch.empty((S, 4, w.ny, w.nz, w.nx), dtype=tdt, device=dev)
+            g0 = synth.DeviceSnapshots(w, args.seed, dev)
+            for s in range(S):
+                g0(s, out=snaps[s])
+            del g0
+            gen = None
+        else:
+            snaps = torch.empty((2, 4, w.ny, w.nz, w.nx), dtype=tdt, device=dev)
+            gen = synth.FastDeviceSnapshots(w, args.seed, dev)
+        if args.host_out:   # two sets of pinned host maps, one per staging buffer
+            outs = [r.alloc_terms(slab=big, host=True) for _ in range(2)]
+        else:
+            outs = [r.alloc_terms(slab=big)]
+        per_pair_bytes = sum(o.numel() for o in outs[0] if o is not None) * 8 // npairs[big]
+        log(f"[bench] slab outputs {per_pair_bytes * npairs[big] / 2**30:.1f} GiB "
+            f"{'(pinned host, x2)' if args.host_out else '(device)'}")
+        gen_ev = []
+
+        def snapshot(s):
+            if gen is None:
+                return snaps[s]
+            buf = snaps[s & 1]
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            gen(s, out=buf)
+            e1.record()
+            gen_ev.append((e0, e1))
+            return buf
 
         def views(sl):
             n = npairs[sl]
-            return [o[:n] if o is not None else None for o in outs]
+            return [o[:n] if o is not None else None for o in outs[sl % len(outs)]]
 
+        torch.cuda.synchronize()
         r.set_timing(True)
         r.timings(reset=True)
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(S):
-            r.accumulate_snapshot(snaps[s])
+            r.accumulate_snapshot(snapshot(s))
         r.begin_stats()
         for sl in range(nslab):
             if sl > 0:
                 r.begin_slab(sl)
             for s in range(S):
-                r.accumulate_snapshot(snaps[s])
+                r.accumulate_snapshot(snapshot(s))
             r.finalize(views(sl))
-            if (sl + 1) % 8 == 0 or sl + 1 == nslab:
-                log(f"[bench] slab {sl + 1}/{nslab} done ({time.perf_counter() - t0:.1f} s)")
+            log(f"[bench] slab {sl + 1}/{nslab} done ({time.perf_counter() - t0:.1f} s)")
+        t_fin = time.perf_counter()
+        r.wait_outputs()
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        tail = time.perf_counter() - t_fin
         tm = r.timings(reset=True)
-        # device-to-host rate of one slab's maps into pinned memory
-        n0 = npairs[0]
-        host = torch.empty(n0 * w.nz * w.nx, dtype=torch.float64, pin_memory=True)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for o in outs[:13]:
-            host.copy_(o[:n0].reshape(-1))
-        torch.cuda.synchronize()
-        d2h = 13 * host.numel() * 8 / (time.perf_counter() - t1)
+        gen_s = sum(a.elapsed_time(b) for a, b in gen_ev) / 1e3
         r.close()
-        del outs, snaps, r
+        del outs, snaps, r, gen
         torch.cuda.empty_cache()
         p_out = sum(npairs) * w.nz * w.nx
+        lib_s = sum(v[0] for v in tm.values()) / 1e3
         return {"w": w, "S": S, "t": elapsed, "nslab": nslab, "p_out": p_out,
-                "value": p_out * S / elapsed, "d2h_gbs": d2h / 1e9,
+                "value": p_out * S / elapsed, "resident": resident,
+                "generation_s": gen_s, "library_device_s": lib_s,
+                "copy_tail_s": tail, "host_maps_bytes": (sum(npairs) * per_pair_bytes
+                                                         if args.host_out else 0),
                 "kernels_ms": {k: v[0] for k, v in tm.items() if v[1]}}
 
     w = load_workload(args.workload, args.snapshots, args.precision)
@@ -465,8 +495,13 @@ def main():
             "config": {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} channel grid, {sr['S']} "
                                    f"{w.dtype} snapshots, mirror average, fundamental domain "
                                    f"(full r), {sr['nslab']} Y1 slabs of {args.slab_rows} rows, "
-                                   f"14 term maps", "points_out": sr["p_out"]},
-            "d2h_gbs_pinned": sr["d2h_gbs"],
+                                   f"14 term maps"
+                                   + (" streamed to pinned host memory per slab"
+                                      if args.host_out else ""),
+                       "points_out": sr["p_out"],
+                       "snapshots_resident": sr["resident"]},
+            "library_device_s": sr["library_device_s"], "generation_s": sr["generation_s"],
+            "copy_tail_s": sr["copy_tail_s"], "host_maps_bytes": sr["host_maps_bytes"],
             "kernels_ms": sr["kernels_ms"],
         }
         print(json.dumps(res), flush=True)

@@ -307,6 +307,65 @@ class DeviceSnapshots:
         return out
 
 
+class FastDeviceSnapshots(DeviceSnapshots):
+    """Snapshots with the same amplitude law, envelope, scaling and mean as
+    DeviceSnapshots, but with the random coefficients drawn on the device
+    (a torch generator seeded per snapshot), for ensembles too large to keep
+    resident or to draw on the host: statistically the same fields, not the
+    same values as `snapshot`.  Built in the snapshot's own precision, with the
+    scales and the mean profile applied to the coefficients, so one inverse
+    transform writes the snapshot."""
+
+    def __init__(self, w: Workload, seed: int, device):
+        if w.noise:
+            raise ValueError("FastDeviceSnapshots draws no white-noise component")
+        super().__init__(w, seed, device)
+        torch = self.torch
+        self.rdt = torch.float32 if w.dtype == "f32" else torch.float64
+        self.cdt = torch.complex64 if w.dtype == "f32" else torch.complex128
+        for k in ("T", "dT", "f", "fp", "a", "b"):
+            setattr(self, k, getattr(self, k).to(self.cdt))
+        _, _, band, amp = _wavenumbers(w)
+        iz, ix = np.nonzero(band)
+        self.amp = torch.as_tensor(amp[iz, ix]).to(device=device, dtype=self.rdt)
+        self.nb = iz.size
+        self.scale = torch.tensor([self.su, self.su, self.su, self.sp], device=device,
+                                  dtype=self.rdt)[:, None, None]
+        nkx = w.nx // 2 + 1
+        # band entries are rewritten every call, the rest stay zero
+        self.spec = torch.zeros((4, w.ny, w.nz * nkx), dtype=self.cdt, device=device)
+        self.mean_in_band = bool(((iz == 0) & (ix == 0)).any())
+        self.mean_c = self.mean[:, 0, 0].to(self.cdt)
+        if not self.mean_in_band:
+            self.spec[0, :, 0] = self.mean_c
+
+    def coefficients(self, s: int):
+        torch, w = self.torch, self.w
+        g = torch.Generator(device=self.device)
+        g.manual_seed(int(self.seed) * 1000003 + int(s))
+        # unit-variance real and imaginary parts, as the host draw
+        re = torch.randn((4, w.M, self.nb), generator=g, device=self.device, dtype=self.rdt)
+        im = torch.randn((4, w.M, self.nb), generator=g, device=self.device, dtype=self.rdt)
+        c = torch.complex(re, im) * self.amp[None, None, :]
+        return c.permute(1, 0, 2).reshape(w.M, 4 * self.nb)
+
+    def __call__(self, s: int, out=None):
+        torch, w = self.torch, self.w
+        co = _assemble(torch, w, self.coefficients(s), self.T, self.dT, self.f, self.fp,
+                       self.a, self.b)
+        self.spec[:, :, self.flat] = co * self.scale
+        if self.mean_in_band:
+            self.spec[0, :, 0] += self.mean_c
+        nkx = w.nx // 2 + 1
+        spec = self.spec.view(4, w.ny, w.nz, nkx)
+        if out is None:
+            return torch.fft.irfft2(spec, s=(w.nz, w.nx), norm="forward")
+        if out.dtype != self.rdt or not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor of the snapshot dtype")
+        torch.fft.irfft2(spec, s=(w.nz, w.nx), norm="forward", out=out)
+        return out
+
+
 def snapshots(w: Workload, seed: int, S: int | None = None) -> np.ndarray:
     """Stack of S snapshots, shape [S][4][ny][nz][nx]."""
     S = w.S if S is None else S

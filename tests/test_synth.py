@@ -83,3 +83,32 @@ def test_full_band_inputs_fill_every_bin(kw):
     w0 = synth.workload("tiny", S=2, **kw)
     assert not np.array_equal(snap[1], synth.snapshot(w0, 3, 1))
     assert np.abs(snap[1] - synth.snapshot(w0, 3, 1)).max() < 10 * w.noise * w.rms_u
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_device_drawn_generator_statistics(dtype):
+    """The device-drawn generator (for ensembles regenerated per scan) has the
+    host generator's plane-mean profile and, over an ensemble, its fluctuation
+    rms per plane; it is seeded, and writes in the snapshot's dtype."""
+    import torch
+    w = synth.workload("tiny", dtype=dtype)
+    cpu = torch.device("cpu")
+    g = synth.FastDeviceSnapshots(w, 7, cpu)
+    d = synth.DeviceSnapshots(w, 7, cpu)
+
+    def rms(x):
+        x = x.double()
+        return torch.sqrt(((x - x.mean(dim=(-2, -1), keepdim=True)) ** 2).mean(dim=(-2, -1))).numpy()
+
+    S = 12
+    rf = np.mean([rms(g(s)) for s in range(S)], axis=0)[:, 1:-1]
+    rd = np.mean([rms(d(s)) for s in range(S)], axis=0)[:, 1:-1]
+    assert np.all(np.abs(rf.mean(axis=1) / rd.mean(axis=1) - 1) < 0.15)
+    a, b = g(0), d(0)
+    assert a.dtype == (torch.float32 if dtype == "f32" else torch.float64)
+    tol = 1e-6 if dtype == "f32" else 1e-14
+    assert float((a[0].double().mean(dim=(-2, -1)) - b[0].double().mean(dim=(-2, -1))).abs().max()) < tol
+    out = torch.empty_like(a)
+    g(0, out=out)
+    assert torch.equal(out, a)
+    assert not torch.equal(g(1), a)
