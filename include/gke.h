@@ -268,7 +268,7 @@ gke_status gke_accumulate(gke_plan_t plan, const void *u, const void *v, const v
 /* Step 1 upstream of the statistics (Section "Step 1": a database holding the
  * wall-normal velocity and vorticity as Fourier coefficients; the full
  * velocity is computed and the pressure obtained from its Poisson equation).
- * In: vhat, ohat, device complex FP64 (re, im interleaved) coefficients of v
+ * In: vhat, ohat, device complex FP64 (re, im interleaved, 16-byte aligned) coefficients of v
  * and omega_y = du/dz - dw/dx, layout [Ny][Nz][Nx/2 + 1], f(x, z) =
  * sum_k f^ e^{i(alpha x + beta z)} over the half spectrum (the forward
  * transform divided by Nx Nz); mean_u, mean_w, device FP64 [Ny], the (0, 0)
@@ -290,8 +290,8 @@ gke_status gke_accumulate(gke_plan_t plan, const void *u, const void *v, const v
  * Needs GKE_OPT_STEP1 = 1 before the workspace (about 19 Ny Nk complex FP64
  * values more).  Asynchronous on the plan's stream; reads nothing else of the
  * plan's state, so it may be called before or between gke_accumulate calls.
- * Errors: GKE_ERR_ARG (NULL), GKE_ERR_STATE (no workspace, option not set),
- * GKE_ERR_HIP. */
+ * Errors: GKE_ERR_ARG (NULL, vhat or ohat not 16-byte aligned), GKE_ERR_STATE
+ * (no workspace, option not set), GKE_ERR_HIP. */
 gke_status gke_reconstruct(gke_plan_t plan, const void *vhat, const void *ohat,
                            const double *mean_u, const double *mean_w, double *u, double *v,
                            double *w, double *p);

@@ -6,8 +6,12 @@
 // element (b, i) at buf[b * bs + fft_pad(i)]; every pass reads the inputs of all
 // its butterflies into registers, then, after a barrier, writes the outputs in
 // place, so the result ends in natural order in the same buffer.  Twiddles
-// come from a table tw[m] = exp(-2 pi i m/n), m < n, built on the host in FP64;
-// the inverse direction conjugates them.
+// come from a table built on the host in FP64, one block per pass after the
+// first (the first multiplies by none), laid out [j - 1][k]: entry
+// (j - 1) p + k = exp(-2 pi i j k / (p R)) for the pass of radix R after
+// radices of product p, so that the lanes of a wave, which take consecutive k,
+// read consecutive entries; n - R_first entries in all.  The inverse direction
+// conjugates them.
 //   sign = -1: X[k] = sum_j x[j] exp(-2 pi i jk/n)      (forward)
 //   sign = +1: x[j] = sum_k X[k] exp(+2 pi i jk/n)      (inverse, unscaled)
 #pragma once
@@ -15,8 +19,10 @@
 
 namespace gke {
 
+// aligned to its size, so that an LDS or global access of one value is a
+// single 16-byte (FP64) or 8-byte (FP32) access, not two halves
 template <typename T>
-struct cx {
+struct alignas(2 * sizeof(T)) cx {
     T x, y;
 };
 
@@ -43,7 +49,8 @@ __device__ __forceinline__ cx<T> cmul_si(cx<T> a, int sign)
 struct FftPlanDev {
     int n;
     int npass;
-    int radix[16];
+    int radix[16];   // powers of two first (the host's radix_plan)
+    int swz;         // 1: the first pass's outputs sit at swz8(i) (see below)
 };
 
 // LDS layout of a batch of transforms of length n: element i of transform b
@@ -55,6 +62,17 @@ __host__ __device__ __forceinline__ int fft_stride(int n)
     const int s = n + (n >> 5) + 1;
     return s | 1;
 }
+
+// LDS banks (measured on gfx950): a 16-byte access takes 8 lanes per cycle on
+// a write and 16 on a read, and is free of conflicts when those lanes fall
+// on distinct 16-byte slots modulo 8 (writes) or 16 (reads); 8-byte accesses
+// take 16 and 32 lanes.  The first pass of radix R writes R consecutive
+// outputs per lane, i.e. a lane stride of R, an R-way conflict for R = 2, 4,
+// 8 on 16-byte elements.  Its outputs therefore sit at swz8(i): the low three
+// index bits XORed with the next three, a permutation within every aligned
+// run of 8 elements, which puts the stride-R writes of 8 lanes on 8 distinct
+// slots and keeps a read of 16 consecutive elements (aligned to 8) on 16.
+__host__ __device__ __forceinline__ int swz8(int i) { return i ^ ((i >> 3) & 7); }
 
 // a / d and a % d for 0 <= a < 2^24 through a float reciprocal, corrected
 __device__ __forceinline__ int div_small(int a, int d, float inv_d)
@@ -186,10 +204,12 @@ struct Dft<8, T> {
 // applied): every thread first reads the inputs of its butterflies into
 // registers, then, after a barrier, writes the outputs.  CAP bounds batch * n
 // and BLOCK the block size, so a thread holds at most ceil(CAP / (R * BLOCK))
-// butterflies of radix R.  Element i of transform b lives at b * bs + fft_pad(i).
+// butterflies of radix R.  Element i of transform b lives at b * bs +
+// fft_pad(i), or at b * bs + fft_pad(swz8(i)) where sin (inputs) or sout
+// (outputs) is set.  tw: this pass's twiddle block (p > 1).
 template <int R, typename T, int CAP, int BLOCK>
 __device__ __forceinline__ void stockham_pass_ip(cx<T> *buf, int n, int p, int batch, int bs,
-                                                 const cx<T> *tw, int sign)
+                                                 const cx<T> *tw, int sign, bool sin, bool sout)
 {
     constexpr int MAXIT = (CAP / R + BLOCK - 1) / BLOCK;
     // the pass is selected at run time from the plan's radices: an empty asm
@@ -199,7 +219,6 @@ __device__ __forceinline__ void stockham_pass_ip(cx<T> *buf, int n, int p, int b
     asm volatile("" : "+s"(nn));
     const int m = nn / R;
     const int total = batch * m;
-    const int twstep = n / (p * R);
     const float inv_m = 1.0f / (float)m, inv_p = 1.0f / (float)p;
     cx<T> v[MAXIT][R];
     int out0[MAXIT];
@@ -213,11 +232,14 @@ __device__ __forceinline__ void stockham_pass_ip(cx<T> *buf, int n, int p, int b
             const int k = i - p * div_small(i, p, inv_p);
             const cx<T> *s = buf + b * bs;
 #pragma unroll
-            for (int j = 0; j < R; ++j) v[q][j] = s[fft_pad(i + j * m)];
+            for (int j = 0; j < R; ++j) {
+                const int e = i + j * m;
+                v[q][j] = s[fft_pad(sin ? swz8(e) : e)];
+            }
             if (p > 1) {
 #pragma unroll
                 for (int j = 1; j < R; ++j) {
-                    cx<T> w = tw[j * k * twstep];
+                    cx<T> w = tw[(j - 1) * p + k];
                     if (sign > 0) w.y = -w.y;
                     v[q][j] = cmul(v[q][j], w);
                 }
@@ -233,7 +255,10 @@ __device__ __forceinline__ void stockham_pass_ip(cx<T> *buf, int n, int p, int b
             const int o = out0[q] & 0xffff;
             cx<T> *d = buf + (out0[q] >> 16) * bs;
 #pragma unroll
-            for (int j = 0; j < R; ++j) d[fft_pad(o + j * p)] = v[q][j];
+            for (int j = 0; j < R; ++j) {
+                const int e = o + j * p;
+                d[fft_pad(sout ? swz8(e) : e)] = v[q][j];
+            }
         }
     }
     __syncthreads();
@@ -268,16 +293,19 @@ template <typename T, int CAP, int BLOCK>
 __device__ void lds_fft_ip(cx<T> *buf, int batch, int bs, const FftPlanDev &pl,
                            const cx<T> *tw, int sign)
 {
-    int p = 1;
+    int p = 1, toff = 0;
     for (int ps = 0; ps < pl.npass; ++ps) {
         const int R = pl.radix[ps];
+        const cx<T> *twp = tw + toff;
+        const bool sin = ps == 1 && pl.swz, sout = ps == 0 && pl.swz;
         switch (R) {
-        case 2: stockham_pass_ip<2, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, tw, sign); break;
-        case 3: stockham_pass_ip<3, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, tw, sign); break;
-        case 4: stockham_pass_ip<4, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, tw, sign); break;
-        case 5: stockham_pass_ip<5, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, tw, sign); break;
-        default: stockham_pass_ip<8, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, tw, sign); break;
+        case 2: stockham_pass_ip<2, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, twp, sign, sin, sout); break;
+        case 3: stockham_pass_ip<3, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, twp, sign, sin, sout); break;
+        case 4: stockham_pass_ip<4, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, twp, sign, sin, sout); break;
+        case 5: stockham_pass_ip<5, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, twp, sign, sin, sout); break;
+        default: stockham_pass_ip<8, T, CAP, BLOCK>(buf, pl.n, p, batch, bs, twp, sign, sin, sout); break;
         }
+        if (p > 1) toff += p * (R - 1);
         p *= R;
     }
 }

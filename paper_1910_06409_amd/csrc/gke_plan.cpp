@@ -139,28 +139,47 @@ bool factors_235(int n)
     return n == 1;
 }
 
+// Radices of an LDS transform: the powers of two first (8s, then 4s, then a
+// 2), then 5s and 3s.  After a first pass of 8 (or 4, 2) the later passes have
+// p >= 8 (or, for n = 4 or 2 times an odd number, odd radices), so their lanes
+// write runs of consecutive outputs; the first pass's stride-R writes go
+// through the swizzle (swz, when n is a multiple of 8).
 gke::FftPlanDev radix_plan(int n)
 {
     gke::FftPlanDev pl{};
     pl.n = n;
     int m = n, k = 0;
-    while (m % 5 == 0) { pl.radix[k++] = 5; m /= 5; }
-    while (m % 3 == 0) { pl.radix[k++] = 3; m /= 3; }
     int e2 = 0;
     while (m % 2 == 0) { ++e2; m /= 2; }
     while (e2 >= 3 && e2 != 4) { pl.radix[k++] = 8; e2 -= 3; }
     while (e2 >= 2) { pl.radix[k++] = 4; e2 -= 2; }
     if (e2 == 1) pl.radix[k++] = 2;
+    while (m % 5 == 0) { pl.radix[k++] = 5; m /= 5; }
+    while (m % 3 == 0) { pl.radix[k++] = 3; m /= 3; }
     pl.npass = k;
+    pl.swz = k > 1 && n % 8 == 0 && pl.radix[0] % 2 == 0 ? 1 : 0;
     return pl;
 }
 
-std::vector<cx<double>> twiddles(int n)
+// The twiddle table of a plan: for every pass after the first (radix R after
+// radices of product p), the block [j - 1][k], j = 1..R-1, k = 0..p-1, of
+// exp(-2 pi i j k / (p R)); n - R_first entries, zero-filled to n.
+std::vector<cx<double>> twiddles(const gke::FftPlanDev &pl)
 {
-    std::vector<cx<double>> t(n);
-    for (int m = 0; m < n; ++m) {
-        const double a = 2.0 * M_PI * (double)m / (double)n;
-        t[m] = cx<double>{std::cos(a), -std::sin(a)};
+    std::vector<cx<double>> t(pl.n, cx<double>{0.0, 0.0});
+    size_t off = 0;
+    int p = 1;
+    for (int ps = 0; ps < pl.npass; ++ps) {
+        const int R = pl.radix[ps];
+        if (p > 1) {
+            for (int j = 1; j < R; ++j)
+                for (int k = 0; k < p; ++k) {
+                    const double a = 2.0 * M_PI * (double)(j * k) / (double)(p * R);
+                    t[off + (size_t)(j - 1) * p + k] = cx<double>{std::cos(a), -std::sin(a)};
+                }
+            off += (size_t)p * (R - 1);
+        }
+        p *= R;
     }
     return t;
 }
@@ -627,8 +646,8 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
     }
     d.chunk = p->chunk;
 
-    p->h_twx = twiddles(Nx);
-    p->h_twz = twiddles(Nz);
+    p->h_twx = twiddles(radix_plan(Nx));
+    p->h_twz = twiddles(radix_plan(Nz));
     for (const auto &c : p->h_twx) p->h_twx32.push_back(cx<float>{(float)c.x, (float)c.y});
     for (const auto &c : p->h_twz) p->h_twz32.push_back(cx<float>{(float)c.x, (float)c.y});
     p->h_w5.assign(5 * (size_t)Ny, 0.0);
@@ -1149,6 +1168,8 @@ gke_status gke_reconstruct(gke_plan_t p, const void *vhat, const void *ohat,
     if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
     if (!vhat || !ohat || !mean_u || !mean_w || !u || !v || !w || !pr)
         return fail(p, GKE_ERR_ARG, "pointer is NULL");
+    if (((uintptr_t)vhat | (uintptr_t)ohat) % 16)
+        return fail(p, GKE_ERR_ARG, "vhat and ohat must be 16-byte aligned");
     if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
     if (!p->step1) return fail(p, GKE_ERR_STATE, "gke_reconstruct needs GKE_OPT_STEP1 = 1 "
                                                  "before the workspace");

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fluct_xfft(const TI *_
                                                           double *__restrict__ momp)
 {
     constexpr int CAP = cap_of<BLOCK>();
-    extern __shared__ unsigned char lds_raw[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
     __shared__ double shm[NMOMP * (BLOCK / 64)];
     const int nx = d.nx, ny = d.ny, nz = d.nz, nkx = d.nkx, zb = d.zb;
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_zfft_pack_blk(const cx
                                                          S *__restrict__ spec)
 {
     constexpr int CAP = cap_of<BLOCK>();
-    extern __shared__ unsigned char lds_raw[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
     const int nx = d.nx, ny = d.ny, nz = d.nz, nkx = d.nkx, jb = d.jb;
     const int nitem = (int)gridDim.x, q8 = nitem >> 3, r8 = nitem & 7, xcd = blockIdx.x & 7;
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_zfft_rec(const cx<floa
                                                     int ng, SplitRec *__restrict__ spec)
 {
     constexpr int CAP = cap_of<BLOCK>();
-    extern __shared__ unsigned char lds_raw[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     cx<float> *lds = reinterpret_cast<cx<float> *>(lds_raw);
     const int nx = d.nx, ny = d.ny, nz = d.nz, nkx = d.nkx, jb = d.jb;
     const int nitem = (int)gridDim.x, q8 = nitem >> 3, r8 = nitem & 7, xcd = blockIdx.x & 7;
