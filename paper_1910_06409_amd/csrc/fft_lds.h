@@ -310,4 +310,121 @@ __device__ void lds_fft_ip(cx<T> *buf, int batch, int bs, const FftPlanDev &pl,
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same transform with the length a compile-time constant N: the plan
+// (radix_order below, the host's rule), the pass extents and the butterfly
+// index arithmetic fold into constants (divisions by the pass extents become
+// multiplications), and the direction is a constant too.  Used for the
+// lengths of the workloads the library is tuned for; any other length takes
+// lds_fft_ip.
+
+// the radix plan of length n, as the host's radix_plan: 8s, 4s, a 2, 5s, 3s
+constexpr int cplan_npass(int n)
+{
+    int k = 0, m = n, e2 = 0;
+    while (m % 2 == 0) { ++e2; m /= 2; }
+    while (e2 >= 3 && e2 != 4) { ++k; e2 -= 3; }
+    while (e2 >= 2) { ++k; e2 -= 2; }
+    if (e2 == 1) ++k;
+    while (m % 5 == 0) { ++k; m /= 5; }
+    while (m % 3 == 0) { ++k; m /= 3; }
+    return k;
+}
+constexpr int cplan_radix(int n, int ps)
+{
+    int r[16] = {}, k = 0, m = n, e2 = 0;
+    while (m % 2 == 0) { ++e2; m /= 2; }
+    while (e2 >= 3 && e2 != 4) { r[k++] = 8; e2 -= 3; }
+    while (e2 >= 2) { r[k++] = 4; e2 -= 2; }
+    if (e2 == 1) r[k++] = 2;
+    while (m % 5 == 0) { r[k++] = 5; m /= 5; }
+    while (m % 3 == 0) { r[k++] = 3; m /= 3; }
+    return r[ps];
+}
+constexpr bool cplan_swz(int n)
+{
+    return cplan_npass(n) > 1 && n % 8 == 0 && cplan_radix(n, 0) % 2 == 0;
+}
+
+template <int R, typename T, int N, int P, int CAP, int BLOCK, int SIGN, bool SIN, bool SOUT>
+__device__ __forceinline__ void stockham_pass_n(cx<T> *buf, int batch, int bs, const cx<T> *tw)
+{
+    constexpr int M = N / R;
+    constexpr int MAXIT = (CAP / R + BLOCK - 1) / BLOCK;
+    const int total = batch * M;
+    cx<T> v[MAXIT][R];
+    int ob[MAXIT];   // (transform << 16) | first output, or -1
+#pragma unroll
+    for (int q = 0; q < MAXIT; ++q) {
+        const int it = threadIdx.x + q * BLOCK;
+        ob[q] = -1;
+        if (it < total) {
+            const int b = it / M;
+            const int i = it - b * M;
+            const int k = i % P;
+            const cx<T> *s = buf + b * bs;
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int e = i + j * M;
+                v[q][j] = s[fft_pad(SIN ? swz8(e) : e)];
+            }
+            if (P > 1) {
+#pragma unroll
+                for (int j = 1; j < R; ++j) {
+                    cx<T> w = tw[(j - 1) * P + k];
+                    if (SIGN > 0) w.y = -w.y;
+                    v[q][j] = cmul(v[q][j], w);
+                }
+            }
+            Dft<R, T>::run(v[q], SIGN);
+            ob[q] = (b << 16) | ((i - k) * R + k);   // transform, first output
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXIT; ++q) {
+        if (ob[q] >= 0) {
+            const int o = ob[q] & 0xffff;
+            cx<T> *d = buf + (ob[q] >> 16) * bs;
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int e = o + j * P;
+                d[fft_pad(SOUT ? swz8(e) : e)] = v[q][j];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int N, int CAP, int BLOCK, int SIGN, int PS, int P, int TOFF>
+__device__ __forceinline__ void lds_fft_n_from(cx<T> *buf, int batch, int bs, const cx<T> *tw)
+{
+    if constexpr (PS < cplan_npass(N)) {
+        constexpr int R = cplan_radix(N, PS);
+        constexpr bool SW = cplan_swz(N);
+        stockham_pass_n<R, T, N, P, CAP, BLOCK, SIGN, PS == 1 && SW, PS == 0 && SW>(buf, batch, bs,
+                                                                                   tw + TOFF);
+        lds_fft_n_from<T, N, CAP, BLOCK, SIGN, PS + 1, P * R, (P > 1 ? TOFF + P * (R - 1) : TOFF)>(
+            buf, batch, bs, tw);
+    }
+}
+
+// Batched in-place transform of length N (a constant), otherwise as
+// lds_fft_ip with the plan of N.  Ends with a barrier.
+template <typename T, int N, int CAP, int BLOCK, int SIGN>
+__device__ __forceinline__ void lds_fft_n(cx<T> *buf, int batch, int bs, const cx<T> *tw)
+{
+    static_assert(N > 1 && N < 65536 && cplan_npass(N) <= 16, "transform length");
+    lds_fft_n_from<T, N, CAP, BLOCK, SIGN, 0, 1, 0>(buf, batch, bs, tw);
+}
+
+// lds_fft_n when NF > 0, else lds_fft_ip with the run-time plan
+template <typename T, int NF, int CAP, int BLOCK, int SIGN>
+__device__ __forceinline__ void lds_fft(cx<T> *buf, int batch, int bs, const FftPlanDev &pl,
+                                        const cx<T> *tw)
+{
+    if constexpr (NF > 0) lds_fft_n<T, NF, CAP, BLOCK, SIGN>(buf, batch, bs, tw);
+    else lds_fft_ip<T, CAP, BLOCK>(buf, batch, bs, pl, tw, SIGN);
+}
+
 }  // namespace gke

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 #include "fft_lds.h"
 
@@ -90,6 +91,22 @@ constexpr size_t LDS_BUDGET = 156 * 1024;
 constexpr int SMALL_BLOCK = 256, SMALL_CAP = 2048;
 template <int BLOCK>
 constexpr int cap_of() { return BLOCK == SMALL_BLOCK ? SMALL_CAP : FFT_CAP; }
+
+// Transform lengths whose plans are compiled in (the x and z lengths of the
+// channel grids the library is tuned for, 192 x 160 and 512 x 384): f is
+// called with std::integral_constant<int, n> for those, with
+// std::integral_constant<int, 0> (the run-time plan) for any other n.
+template <typename F>
+inline void with_fft_len(int n, F &&f)
+{
+    switch (n) {
+    case 160: f(std::integral_constant<int, 160>{}); break;
+    case 192: f(std::integral_constant<int, 192>{}); break;
+    case 384: f(std::integral_constant<int, 384>{}); break;
+    case 512: f(std::integral_constant<int, 512>{}); break;
+    default: f(std::integral_constant<int, 0>{}); break;
+    }
+}
 
 struct Dims {
     int nx, ny, nz;

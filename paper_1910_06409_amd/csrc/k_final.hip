@@ -30,13 +30,15 @@ __host__ __device__ inline int mid_stride(int ptot) { return (ptot + 7) & ~7; }
 // take pb pairs of spectrum z - 1.  Every block reads its part of acc once.
 // mid layout: [NMID][nkx][nz (rz)][mid_stride(ptot)] (the pairs of this batch,
 // rows padded to whole 128-byte lines).
+template <int NF>
 __global__ GKE_FFT_BOUNDS void k_fin_kz(const cx<double> *__restrict__ acc, Dims d,
                                                       Tables t, int p0, int ptot,
                                                       double inv_count,
                                                       cx<double> *__restrict__ mid)
 {
     extern __shared__ cx<double> lds[];
-    const int nz = d.nz, nkx = d.nkx, pb = d.pbz;   // pb even (host)
+    // NF > 0: the z length as a constant (its plan compiled in)
+    const int nz = NF > 0 ? NF : d.nz, nkx = d.nkx, pb = d.pbz;   // pb even (host)
     const int kx = blockIdx.y;
     const bool isr = blockIdx.z < 2;
     const int sp = isr ? (int)S_R : (int)blockIdx.z - 1;
@@ -86,7 +88,7 @@ __global__ GKE_FFT_BOUNDS void k_fin_kz(const cx<double> *__restrict__ acc, Dims
         }
     }
     __syncthreads();
-    lds_fft_ip<double, FFT_CAP, FFT_BLOCK>(lds, isr ? 2 * np : np, bs, t.pz, tw, +1);
+    lds_fft<double, NF, FFT_CAP, FFT_BLOCK, +1>(lds, isr ? 2 * np : np, bs, t.pz, tw);
     const size_t mplane = (size_t)nkx * nz * mst;
     Walk2 ws(threadIdx.x, FFT_BLOCK, np);   // (rz, b)
     for (int e = threadIdx.x; e < cnt; e += FFT_BLOCK) {
@@ -110,9 +112,12 @@ hipError_t launch_fin_kz(hipStream_t st, const Dims &d, const Tables &t,
     const int ptot = p1 - p0;
     const size_t lds = sizeof(cx<double>) * ((size_t)d.pbz * fft_stride(d.nz) + d.nz);
     dim3 grid((ptot + d.pbz - 1) / d.pbz, d.nkx, NSPEC + 1);
-    set_lds_limit(k_fin_kz);
-    hipLaunchKernelGGL(k_fin_kz, grid, dim3(FFT_BLOCK), lds, st, acc, d, t, p0, ptot, inv_count,
-                       mid);
+    with_fft_len(d.nz, [&](auto len) {
+        constexpr int NF = decltype(len)::value;
+        set_lds_limit(k_fin_kz<NF>);
+        hipLaunchKernelGGL(k_fin_kz<NF>, grid, dim3(FFT_BLOCK), lds, st, acc, d, t, p0, ptot,
+                           inv_count, mid);
+    });
     return hipGetLastError();
 }
 
@@ -127,6 +132,7 @@ hipError_t launch_fin_kz(hipStream_t st, const Dims &d, const Tables &t,
 // same per-thread elements, then the kz transform as in k_fin_kz, into mid
 // plane NMID.
 constexpr int MAX_PBZ = 16;
+template <int NF>
 __global__ GKE_FFT_BOUNDS void k_fin_kz_h(const cx<double> *__restrict__ acc, Dims d, Tables t,
                                           int p0, int ptot, double inv_count,
                                           const double *__restrict__ prof,
@@ -134,7 +140,7 @@ __global__ GKE_FFT_BOUNDS void k_fin_kz_h(const cx<double> *__restrict__ acc, Di
 {
     extern __shared__ cx<double> lds[];
     __shared__ double sdu[MAX_PBZ];
-    const int nz = d.nz, nkx = d.nkx, pb = d.pbz, ny = d.ny;   // pb <= MAX_PBZ (host)
+    const int nz = NF > 0 ? NF : d.nz, nkx = d.nkx, pb = d.pbz, ny = d.ny;   // pb <= MAX_PBZ (host)
     const int kx = blockIdx.y;
     const int pl0 = blockIdx.x * pb;
     const int np = min(pb, ptot - pl0);
@@ -191,7 +197,7 @@ __global__ GKE_FFT_BOUNDS void k_fin_kz_h(const cx<double> *__restrict__ acc, Di
         }
     }
     __syncthreads();
-    lds_fft_ip<double, FFT_CAP, FFT_BLOCK>(lds, np, bs, t.pz, tw, +1);
+    lds_fft<double, NF, FFT_CAP, FFT_BLOCK, +1>(lds, np, bs, t.pz, tw);
     const size_t mplane = (size_t)nkx * nz * mst;
     const int cnt = nz * np;
     Walk2 ws(threadIdx.x, FFT_BLOCK, np);   // (rz, b)
@@ -211,9 +217,12 @@ hipError_t launch_fin_kz_h(hipStream_t st, const Dims &d, const Tables &t,
     const int ptot = p1 - p0;
     const size_t lds = sizeof(cx<double>) * ((size_t)d.pbz * fft_stride(d.nz) + d.nz);
     dim3 grid((ptot + d.pbz - 1) / d.pbz, d.nkx, 1);
-    set_lds_limit(k_fin_kz_h);
-    hipLaunchKernelGGL(k_fin_kz_h, grid, dim3(FFT_BLOCK), lds, st, acc, d, t, p0, ptot,
-                       inv_count, prof, mid);
+    with_fft_len(d.nz, [&](auto len) {
+        constexpr int NF = decltype(len)::value;
+        set_lds_limit(k_fin_kz_h<NF>);
+        hipLaunchKernelGGL(k_fin_kz_h<NF>, grid, dim3(FFT_BLOCK), lds, st, acc, d, t, p0, ptot,
+                           inv_count, prof, mid);
+    });
     return hipGetLastError();
 }
 
@@ -322,7 +331,7 @@ struct PairInfo {
 //   pairs of (kx, c) (adjacent in mid) and writes A_c[kx] and A_c[Nx - kx].
 //   Output: a group of tpp consecutive threads per pair, consecutive threads
 //   on consecutive rx.
-template <int BLOCK>
+template <int BLOCK, int NF>
 __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fin_kx(const cx<double> *__restrict__ mid, Dims d,
                                                       Tables t, int p0, int ptot,
                                                       const double *__restrict__ prof,
@@ -330,7 +339,8 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fin_kx(const cx<double
 {
     constexpr int CAP = cap_of<BLOCK>();
     extern __shared__ cx<double> lds[];
-    const int nx = d.nx, nz = d.nz, nkx = d.nkx, ny = d.ny, nt = d.ntx;
+    // NF > 0: the x length as a constant (its plan compiled in)
+    const int nx = NF > 0 ? NF : d.nx, nz = d.nz, nkx = nx / 2 + 1, ny = d.ny, nt = d.ntx;
     const int npair = 2 * nt;
     const int pblk = blockIdx.x, m = blockIdx.z;
     // full-plane mode: every rz; all-pairs mode: the kept rz rows only
@@ -416,7 +426,7 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fin_kx(const cx<double
     }
     if ((int)threadIdx.x < np) pinfo[threadIdx.x] = pi;
     __syncthreads();
-    lds_fft_ip<double, CAP, BLOCK>(A, nt, bs, t.px, tw, +1);
+    lds_fft<double, NF, CAP, BLOCK, +1>(A, nt, bs, t.px, tw);
     const int tpp = BLOCK / npair;            // threads per pair
     const int b = threadIdx.x / tpp, lane = threadIdx.x - b * tpp;
     if (b >= np) return;
@@ -464,15 +474,18 @@ hipError_t launch_fin_kx(hipStream_t st, const Dims &d, const Tables &t,
     op.res = full ? nullptr : resid;
     op.f32 = f32;
     dim3 grid((ptot + 2 * d.ntx - 1) / (2 * d.ntx), full ? d.nz : d.nqo, NMAP + (op.res ? 1 : 0));
-    if (d.kxblk == SMALL_BLOCK) {
-        set_lds_limit(k_fin_kx<SMALL_BLOCK>);
-        hipLaunchKernelGGL(k_fin_kx<SMALL_BLOCK>, grid, dim3(SMALL_BLOCK), lds, st, mid, d, t, p0,
-                           ptot, prof, op, full);
-    } else {
-        set_lds_limit(k_fin_kx<FFT_BLOCK>);
-        hipLaunchKernelGGL(k_fin_kx<FFT_BLOCK>, grid, dim3(FFT_BLOCK), lds, st, mid, d, t, p0,
-                           ptot, prof, op, full);
-    }
+    with_fft_len(d.nx, [&](auto len) {
+        constexpr int NF = decltype(len)::value;
+        if (d.kxblk == SMALL_BLOCK) {
+            set_lds_limit(k_fin_kx<SMALL_BLOCK, NF>);
+            hipLaunchKernelGGL((k_fin_kx<SMALL_BLOCK, NF>), grid, dim3(SMALL_BLOCK), lds, st, mid,
+                               d, t, p0, ptot, prof, op, full);
+        } else {
+            set_lds_limit(k_fin_kx<FFT_BLOCK, NF>);
+            hipLaunchKernelGGL((k_fin_kx<FFT_BLOCK, NF>), grid, dim3(FFT_BLOCK), lds, st, mid, d,
+                               t, p0, ptot, prof, op, full);
+        }
+    });
     return hipGetLastError();
 }
 

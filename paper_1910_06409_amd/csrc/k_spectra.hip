@@ -83,7 +83,7 @@ __device__ __forceinline__ void split_value(float re, float im, unsigned int &hi
 //   inter[j][g][f][kx][row]: x-transformed rows (unnormalised) in groups of zg
 //   rows (z = g zg + row); a block writes its zb rows of one group
 //   momp[j][k][zblk]: FP64 partial sums of q uv pv qu qv qw and (dy u')^2
-template <typename TI, typename T, int BLOCK>
+template <typename TI, typename T, int BLOCK, int NF>
 __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fluct_xfft(const TI *__restrict__ u,
                                                           const TI *__restrict__ v,
                                                           const TI *__restrict__ w,
@@ -97,7 +97,8 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fluct_xfft(const TI *_
     extern __shared__ __align__(16) unsigned char lds_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
     __shared__ double shm[NMOMP * (BLOCK / 64)];
-    const int nx = d.nx, ny = d.ny, nz = d.nz, nkx = d.nkx, zb = d.zb;
+    // NF > 0: the x length as a constant (its plan compiled in)
+    const int nx = NF > 0 ? NF : d.nx, ny = d.ny, nz = d.nz, nkx = nx / 2 + 1, zb = d.zb;
     // blocks in the order (j, zblk), zblk fastest; the blocks of one XCD
     // (workgroup i runs on XCD i mod 8) take a contiguous range of it, so the
     // blocks that share a row group of inter write it through one L2
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fluct_xfft(const TI *_
         if ((lane & 7) == 0 && g < NMOMP) shm[g * (BLOCK / 64) + (threadIdx.x >> 6)] = ws;
     }
     __syncthreads();
-    lds_fft_ip<T, CAP, BLOCK>(lds, 5 * zb, bs, t.px, tw, -1);
+    lds_fft<T, NF, CAP, BLOCK, -1>(lds, 5 * zb, bs, t.px, tw);
     // split the two real transforms: Fa = (Z(k) + conj Z(-k))/2, Fb = (Z(k) - conj Z(-k))/(2i)
     // row group g of zg rows holds this block's rows at r0 .. r0 + zb - 1
     const int zg = d.zg, g = z0 / zg, r0 = z0 - g * zg;
@@ -227,10 +228,13 @@ static void launch_fx_shape(hipStream_t st, const Dims &d, const Tables &t, cons
                             void *inter, double *momp)
 {
     const size_t lds = sizeof(cx<T>) * (5 * (size_t)d.zb * fft_stride(d.nx) + d.nx);
-    set_lds_limit(k_fluct_xfft<TI, T, BLOCK>);
-    hipLaunchKernelGGL((k_fluct_xfft<TI, T, BLOCK>), dim3(d.nzb * d.ny), dim3(BLOCK), lds, st,
-                       (const TI *)u, (const TI *)v, (const TI *)w, (const TI *)p, prof, d, t,
-                       (cx<T> *)inter, momp);
+    with_fft_len(d.nx, [&](auto len) {
+        constexpr int NF = decltype(len)::value;
+        set_lds_limit(k_fluct_xfft<TI, T, BLOCK, NF>);
+        hipLaunchKernelGGL((k_fluct_xfft<TI, T, BLOCK, NF>), dim3(d.nzb * d.ny), dim3(BLOCK), lds,
+                           st, (const TI *)u, (const TI *)v, (const TI *)w, (const TI *)p, prof, d,
+                           t, (cx<T> *)inter, momp);
+    });
 }
 
 template <typename TI, typename T>
@@ -264,7 +268,7 @@ hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int
 // XCD i mod 8) take a contiguous range of items, so the items of neighbouring
 // kx, which read the two halves of the same cache lines of inter, meet in one
 // L2 a few items apart.
-template <typename T, typename S, int BLOCK>
+template <typename T, typename S, int BLOCK, int NF>
 __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_zfft_pack_blk(const cx<T> *__restrict__ inter, Dims d,
                                                          Tables t, int slot,
                                                          S *__restrict__ spec)
@@ -272,7 +276,8 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_zfft_pack_blk(const cx
     constexpr int CAP = cap_of<BLOCK>();
     extern __shared__ __align__(16) unsigned char lds_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(lds_raw);
-    const int nx = d.nx, ny = d.ny, nz = d.nz, nkx = d.nkx, jb = d.jb;
+    // NF > 0: the z length as a constant (its plan compiled in)
+    const int nx = d.nx, ny = d.ny, nz = NF > 0 ? NF : d.nz, nkx = d.nkx, jb = d.jb;
     const int nitem = (int)gridDim.x, q8 = nitem >> 3, r8 = nitem & 7, xcd = blockIdx.x & 7;
     const int item = xcd * q8 + min(xcd, r8) + (int)(blockIdx.x >> 3);
     const int jblk = item % d.njb, kx = (item / d.njb) % nkx, f = item / (d.njb * nkx);
@@ -314,7 +319,7 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_zfft_pack_blk(const cx
         }
     }
     __syncthreads();
-    lds_fft_ip<T, CAP, BLOCK>(lds, nb, bs, t.pz, tw, -1);
+    lds_fft<T, NF, CAP, BLOCK, -1>(lds, nb, bs, t.pz, tw);
     const double scale = 1.0 / ((double)nx * (double)nz);
     // spec[(((kx nz + kz) NFIELD + f) chunk + slot) ny + j0 + b]; nz * skz < 2^31
     const int skz = NFIELD * d.chunk * d.nys;
@@ -334,9 +339,12 @@ static void launch_zp(hipStream_t st, const Dims &d, const Tables &t, const void
 {
     const int nitems = d.njb * d.nkx * NFIELD;
     const size_t lds = sizeof(cx<T>) * ((size_t)d.jb * fft_stride(d.nz) + d.nz);
-    set_lds_limit(k_zfft_pack_blk<T, S, BLOCK>);
-    hipLaunchKernelGGL((k_zfft_pack_blk<T, S, BLOCK>), dim3(nitems), dim3(BLOCK), lds, st,
-                       (const cx<T> *)inter, d, t, slot, (S *)spec);
+    with_fft_len(d.nz, [&](auto len) {
+        constexpr int NF = decltype(len)::value;
+        set_lds_limit(k_zfft_pack_blk<T, S, BLOCK, NF>);
+        hipLaunchKernelGGL((k_zfft_pack_blk<T, S, BLOCK, NF>), dim3(nitems), dim3(BLOCK), lds, st,
+                           (const cx<T> *)inter, d, t, slot, (S *)spec);
+    });
 }
 
 hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t, const void *inter,
@@ -355,7 +363,7 @@ hipError_t launch_zfft_pack(hipStream_t st, const Dims &d, const Tables &t, cons
 // `istride` elements: the z transforms of all of them in one batch (FP32),
 // then one 32-byte record per (kz, plane), the missing snapshots of a partial
 // quad as zeros.  Work items in the order of k_zfft_pack_blk.
-template <int BLOCK>
+template <int BLOCK, int NF>
 __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_zfft_rec(const cx<float> *__restrict__ inter,
                                                     size_t istride, Dims d, Tables t, int q,
                                                     int ng, SplitRec *__restrict__ spec)
@@ -363,7 +371,7 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_zfft_rec(const cx<floa
     constexpr int CAP = cap_of<BLOCK>();
     extern __shared__ __align__(16) unsigned char lds_raw[];
     cx<float> *lds = reinterpret_cast<cx<float> *>(lds_raw);
-    const int nx = d.nx, ny = d.ny, nz = d.nz, nkx = d.nkx, jb = d.jb;
+    const int nx = d.nx, ny = d.ny, nz = NF > 0 ? NF : d.nz, nkx = d.nkx, jb = d.jb;
     const int nitem = (int)gridDim.x, q8 = nitem >> 3, r8 = nitem & 7, xcd = blockIdx.x & 7;
     const int item = xcd * q8 + min(xcd, r8) + (int)(blockIdx.x >> 3);
     const int jblk = item % d.njb, kx = (item / d.njb) % nkx, f = item / (d.njb * nkx);
@@ -402,7 +410,7 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_zfft_rec(const cx<floa
         }
     }
     __syncthreads();
-    lds_fft_ip<float, CAP, BLOCK>(lds, ngb, bs, t.pz, tw, -1);
+    lds_fft<float, NF, CAP, BLOCK, -1>(lds, ngb, bs, t.pz, tw);
     const double scale = 1.0 / ((double)nx * (double)nz);
     // record (k = kx nz + kz, f, q, j0 + b): ((k NFIELD + f) nqs + q) nys + j0 + b
     const size_t rkz = (size_t)NFIELD * d.nqs * d.nys;
@@ -432,9 +440,12 @@ hipError_t launch_zfft_rec(hipStream_t st, const Dims &d, const Tables &t, const
         return hipErrorInvalidValue;
     const int nitems = d.njb * d.nkx * NFIELD;
     const size_t lds = sizeof(cx<float>) * (4 * (size_t)d.jb * fft_stride(d.nz) + d.nz);
-    set_lds_limit(k_zfft_rec<FFT_BLOCK>);
-    hipLaunchKernelGGL(k_zfft_rec<FFT_BLOCK>, dim3(nitems), dim3(FFT_BLOCK), lds, st,
-                       (const cx<float> *)inter, inter_stride, d, t, q, ng, spec);
+    with_fft_len(d.nz, [&](auto len) {
+        constexpr int NF = decltype(len)::value;
+        set_lds_limit(k_zfft_rec<FFT_BLOCK, NF>);
+        hipLaunchKernelGGL((k_zfft_rec<FFT_BLOCK, NF>), dim3(nitems), dim3(FFT_BLOCK), lds, st,
+                           (const cx<float> *)inter, inter_stride, d, t, q, ng, spec);
+    });
     return hipGetLastError();
 }
 
