@@ -4,7 +4,8 @@
   the automatic chunk: one FP32-accumulated rank-k batch), per-term error
   against the 1e-5 bar, printed term by term;
 * the batched FP64 path (same grid, 512 FP32 snapshots, FP64 rank-k in the
-  library's automatic chunks), against the 1e-10 bar.
+  library's automatic chunks), against the 1e-10 bar;
+* the Re_tau=1000 transform lengths (512 x 384) on a few planes, both paths.
 
 The snapshots are built on the device by the seeded generator; the planes the
 oracle needs (the sampled pairs' planes and their five-point stencils) are
@@ -93,3 +94,21 @@ def test_re200_batched_fp64_config():
         " ".join(f"T{t + 1}={e:.2e}" for t, e in enumerate(errs)))
     for t, e in enumerate(errs):
         assert e <= TOL_FP64, f"T{t + 1}: {e:.3e}"
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision,dtype,tol", [("fp64", "f64", TOL_FP64),
+                                                 ("bf16x3", "f32", TOL_BF16)])
+def test_re1000_transform_lengths(precision, dtype, tol):
+    """The x and z lengths of the Re_tau=1000 grid (512 and 384, whose plans
+    are compiled into the transform and finalize kernels) on a few planes and
+    snapshots, with full-band inputs so that every bin carries data."""
+    w = synth.workload("re1000", ny=13, S=6, noise=0.5, dtype=dtype, precision=precision)
+    say(f"case re1000 lengths: {w.nx}x{w.ny}x{w.nz}, {w.S} {dtype} snapshots, {precision}")
+    pairs = [(1, 11), (6, 6), (12, 0)]
+    g, ref = run_sampled(w, 77, pairs, chunk=6)
+    errs = term_errors(g, ref, w.nx)
+    say("re1000 lengths per-term norm-wise error: " +
+        " ".join(f"T{t + 1}={e:.2e}" for t, e in enumerate(errs)))
+    for t, e in enumerate(errs):
+        assert e <= tol, f"T{t + 1}: {e:.3e}"
