@@ -329,6 +329,22 @@ gke_status gke_set_means(gke_plan_t plan, const double *U, const double *V, cons
  * missing), GKE_ERR_UNSUPPORTED (the residual in the slab modes), GKE_ERR_HIP. */
 gke_status gke_finalize(gke_plan_t plan, const gke_terms *out);
 
+/* Notification per slab (Section "Undersampling and parallelisation": the
+ * wall-normal slices are computed one after another, each slice's results
+ * written out as it completes).  fn(slab, user) is called once per
+ * gke_finalize, on a HIP runtime thread, once that finalize's maps are
+ * complete where the caller reads them: for host outputs after the copies to
+ * the host arrays (so a caller may consume or reuse a slab's host arrays
+ * there, while the next slab scans), for device outputs after the kernels.
+ * slab is the slab being finalized (0 in the all-pairs mode).  fn must return
+ * promptly and must not call HIP or any gke_ function (the stream it runs on
+ * waits for it); fn = NULL removes the notification.  Allowed at any time;
+ * the plan keeps fn and user, the caller owns what user points to.
+ * Errors: GKE_ERR_ARG (NULL plan); a failure to enqueue the call is reported
+ * by gke_finalize (GKE_ERR_HIP). */
+typedef void (*gke_slab_fn)(int slab, void *user);
+gke_status gke_set_slab_callback(gke_plan_t plan, gke_slab_fn fn, void *user);
+
 /* Wait until the host copies of every gke_finalize with host outputs have
  * completed (returns at once when there are none).  Errors: GKE_ERR_ARG,
  * GKE_ERR_HIP. */

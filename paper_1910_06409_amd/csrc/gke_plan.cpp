@@ -54,6 +54,9 @@ struct gke_plan_s {
     bool stage_used[2] = {false, false};
     hipStream_t copy_stream = nullptr;
     hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_copied[2] = {nullptr, nullptr};
+    // notification once a finalize's maps are complete where the caller reads them
+    gke_slab_fn slab_fn = nullptr;
+    void *slab_user = nullptr;
     bool general = false;          // mirror, a FULLR domain or slabs
     std::vector<SlabTables> slabs;
     int cur_slab = 0;
@@ -528,6 +531,31 @@ gke_status zfft_quad(gke_plan_t p, int q, int ng)
         return gke::launch_zfft_rec(p->stream, p->d, p->tab, p->inter, istride, q, ng,
                                     (gke::SplitRec *)p->spec);
     }));
+    return GKE_OK;
+}
+
+// The slab notification: a host function enqueued on the stream where the
+// finalize's outputs complete; it runs on a HIP runtime thread and frees its note.
+struct SlabNote {
+    gke_slab_fn fn;
+    void *user;
+    int slab;
+};
+void run_slab_note(void *data)
+{
+    SlabNote *n = static_cast<SlabNote *>(data);
+    n->fn(n->slab, n->user);
+    delete n;
+}
+gke_status notify_slab(gke_plan_t p, hipStream_t st)
+{
+    SlabNote *n = new (std::nothrow) SlabNote{p->slab_fn, p->slab_user, p->general ? p->cur_slab : 0};
+    if (!n) return fail(p, GKE_ERR_OOM, "no host memory for the slab notification");
+    const hipError_t e = hipLaunchHostFunc(st, run_slab_note, n);
+    if (e != hipSuccess) {
+        delete n;
+        return fail(p, GKE_ERR_HIP, std::string("hipLaunchHostFunc: ") + hipGetErrorString(e));
+    }
     return GKE_OK;
 }
 
@@ -1340,7 +1368,21 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
         GKE_HIP(p, hipEventRecord(p->ev_copied[b], p->copy_stream));
         p->stage_used[b] = true;
     }
+    if (p->slab_fn) {   // after the copies (host) or the kernels (device outputs)
+        {
+            gke_status s = notify_slab(p, host ? p->copy_stream : st);
+            if (s != GKE_OK) return s;
+        }
+    }
     GKE_HIP(p, hipStreamSynchronize(st));
+    return GKE_OK;
+}
+
+gke_status gke_set_slab_callback(gke_plan_t p, gke_slab_fn fn, void *user)
+{
+    if (!p) return fail(nullptr, GKE_ERR_ARG, "plan is NULL");
+    p->slab_fn = fn;
+    p->slab_user = fn ? user : nullptr;
     return GKE_OK;
 }
 

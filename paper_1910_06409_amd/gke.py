@@ -48,6 +48,10 @@ class gke_terms(ctypes.Structure):
 _lib = None
 
 
+# gke_slab_fn: void (*)(int slab, void *user)
+SLAB_FN = ctypes.CFUNCTYPE(None, ctypes.c_int, ctypes.c_void_p)
+
+
 def lib() -> ctypes.CDLL:
     """Load libgke.so (after torch, so that both share one HIP runtime)."""
     global _lib
@@ -81,6 +85,7 @@ def lib() -> ctypes.CDLL:
         "gke_set_means": ([vp, dp, dp, dp, dp], i32),
         "gke_finalize": ([vp, ctypes.POINTER(gke_terms)], i32),
         "gke_wait_outputs": ([vp], i32),
+        "gke_set_slab_callback": ([vp, SLAB_FN, vp], i32),
         "gke_reconstruct": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
         "gke_get_profiles": ([vp, dp], i32),
         "gke_slab_count": ([vp, ctypes.POINTER(i32)], i32),
@@ -214,6 +219,15 @@ def gke_finalize(plan, ptrs, residual: int = 0, on_device: int = 1,
 
 def gke_wait_outputs(plan) -> None:
     _check(lib().gke_wait_outputs(plan), plan)
+
+
+def gke_set_slab_callback(plan, fn):
+    """Call fn(slab) once per gke_finalize when its maps are complete (on a HIP
+    runtime thread; fn must not call HIP or the library); fn=None removes it.
+    Returns the ctypes callback, which the caller keeps alive while it is set."""
+    cb = SLAB_FN(lambda slab, _user: fn(int(slab))) if fn is not None else SLAB_FN()
+    _check(lib().gke_set_slab_callback(plan, cb, None), plan)
+    return cb
 
 
 def gke_get_profiles(plan, ny: int) -> np.ndarray:

@@ -146,6 +146,10 @@ class GkeRun:
     def wait_outputs(self):
         gke.gke_wait_outputs(self.plan)
 
+    def on_slab(self, fn):
+        """fn(slab) once per finalize when its maps are complete (None: off)."""
+        self._slab_cb = gke.gke_set_slab_callback(self.plan, fn)
+
     def reset(self):
         gke.gke_reset(self.plan)
 

@@ -115,3 +115,63 @@ def test_all_pairs_fp32_and_host_outputs():
         rr = ref[:, t, :, :nkx]
         assert np.abs(g - rr).max() <= TOL_FP64 * np.abs(rr).max(), t
     say("  host == device, FP32 within the rounding bounds, FP64 == oracle")
+
+
+@pytest.mark.parametrize("host", [True, False])
+def test_slab_callback_sees_complete_maps(host):
+    """gke_set_slab_callback: one call per finalize, in slab order, and the
+    maps the callback reads (host arrays, or device maps for device outputs)
+    are already the final ones.  The host case reuses two sets of host arrays
+    in turn, as a streaming caller does, so a late copy would show."""
+    torch = _torch()
+    from paper_1910_06409_amd import runner
+    w = synth.workload("tiny", S=3, dtype="f32", noise=0.5)
+    y = synth.y_grid(w)
+    dev = torch.from_numpy(synth.snapshots(w, 73)).cuda()
+    ref = [[m.astype(np.float64) for m in maps] for _, maps in _slab_run(dev, w, y,
+                                                                          torch.float64, False)]
+    say(f"case slab callback, host outputs={host}")
+    r = runner.GkeRun(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu, dtype="f32", chunk=2, mirror=1,
+                      domain=gke.GKE_DOMAIN_FUNDAMENTAL_FULLR, slab=3, device=dev.device,
+                      host_staging=2 if host else 0)
+    nslab = r.slab_count()
+    npairs = [len(r.slab_pairs(sl)) for sl in range(nslab)]
+    big = int(np.argmax(npairs))
+    sets = [r.alloc_terms(slab=big, host=host) for _ in range(2 if host else 1)]
+    seen = []
+    cur = {}
+
+    def note(slab):
+        # runs on a HIP runtime thread once the slab's maps are complete
+        n = npairs[slab]
+        maps = sets[slab % len(sets)]
+        if host:
+            seen.append((slab, [maps[t][:n].numpy().copy() for t in range(14)]))
+        else:
+            seen.append((slab, None))
+        cur["last"] = slab
+
+    r.on_slab(note)
+    for s in range(w.S):
+        r.accumulate_snapshot(dev[s])
+    r.begin_stats()
+    dev_maps = []
+    for sl in range(nslab):
+        if sl > 0:
+            r.begin_slab(sl)
+        for s in range(w.S):
+            r.accumulate_snapshot(dev[s])
+        outs = sets[sl % len(sets)]
+        r.finalize([o[:npairs[sl]] for o in outs])
+        if not host:   # finalize returns after the device maps are written
+            assert cur.get("last") == sl
+            dev_maps.append([outs[t][:npairs[sl]].cpu().numpy().astype(np.float64)
+                             for t in range(14)])
+    r.wait_outputs()
+    r.on_slab(None)
+    r.close()
+    assert [s for s, _ in seen] == list(range(nslab))
+    got = [m for _, m in seen] if host else dev_maps
+    for sl in range(nslab):
+        for t in range(14):
+            assert np.array_equal(got[sl][t].astype(np.float64), ref[sl][t]), (sl, t)
