@@ -211,25 +211,62 @@ __device__ __forceinline__ const cx<float> *tw_of<float>(const Tables &t, int wh
     return which ? t.twz32 : t.twx32;
 }
 
-// pass 1: plane sums of u~ v~ w~ p~ added into sums[4][ny][NSPLIT]
-hipError_t launch_plane_sums(hipStream_t st, const Dims &d, int f32, const void *u,
-                             const void *v, const void *w, const void *p, double *sums);
-// means = sums / count, S = D U (profile rows U V W P S)
+// Sums each of eight values over the 64 lanes of a wave in a fixed order: on
+// return, every lane of the group of eight lanes g = lane / 8 holds the sum of
+// v[g].  Each step halves the values a lane keeps and sends the other half to
+// its partner (lanes 32, 16, 8 apart), then the last three steps finish the
+// sum within the group: 10 exchanges instead of 8 x 6.
+__device__ __forceinline__ double wave_sum8(const double (&v)[8])
+{
+    const int lane = threadIdx.x & 63;
+    double a[4], b[2];
+    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double keep = h5 ? v[4 + i] : v[i], send = h5 ? v[i] : v[4 + i];
+        a[i] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double keep = h4 ? a[2 + i] : a[i], send = h4 ? a[i] : a[2 + i];
+        b[i] = keep + __shfl_xor(send, 16, 64);
+    }
+    double c = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8, 64);
+    c += __shfl_xor(c, 4, 64);
+    c += __shfl_xor(c, 2, 64);
+    c += __shfl_xor(c, 1, 64);
+    return c;
+}
+
+// pass 1: plane sums of u~ v~ w~ p~ added into sums[f][ny][NSPLIT], f < 4;
+// with gy, also the plane sums of (D u~)^2 + (D v~)^2 + (D w~)^2 (D: the
+// five-point wall-normal weights) into sums[4][ny][NSPLIT]
+hipError_t launch_plane_sums(hipStream_t st, const Dims &d, const Tables &t, int f32, int gy,
+                             const void *u, const void *v, const void *w, const void *p,
+                             double *sums);
+// means = sums / count, S = D U (profile rows U V W P S); with gy1 != NULL
+// also gy1[j] = <(D u')^2 + (D v')^2 + (D w')^2> = <(D u~)^2 + ...> - (D U)^2
+// - (D V)^2 - (D W)^2 (D commutes with the average)
 hipError_t launch_means(hipStream_t st, const Dims &d, const Tables &t, const double *sums,
-                        double count, double *prof);
+                        double count, double *prof, double *gy1);
 // S = D U only (means already in prof)
 hipError_t launch_shear(hipStream_t st, const Dims &d, const Tables &t, double *prof);
 // plane averages of u'_i(Y1) u'_i(Y2) for |Y1 - Y2| <= 4 (r0[Y1][Y2 - Y1]) and
 // of |grad_xz u'|^2 (gxz[Y]) from the scale-energy spectrum accumulators
 hipError_t launch_r0(hipStream_t st, const Dims &d, const Tables &t, const cx<double> *acc,
                      double inv_count, double *r0, double *gxz);
-// reduce moment partials into the remaining profile rows; eps from r0, gxz
+// reduce moment partials into the remaining profile rows; eps from gxz and
+// the wall-normal part: gy_mode 0 from r0 (Parseval, FP64 spectra), 1 from
+// gy1 (first scan), 2 from the moment partials (the x pass's stencil)
 hipError_t launch_profiles(hipStream_t st, const Dims &d, const Tables &t, const double *momp,
-                           const double *r0, const double *gxz, double count, double *prof);
+                           const double *r0, const double *gxz, const double *gy1, int gy_mode,
+                           double count, double *prof);
 
-// pass 2, per snapshot: fluctuations, products, x transforms, moments.
+// pass 2, per snapshot: fluctuations, products, x transforms, moments;
+// with gy (split path only) also the plane sums of (D u')^2 + (D v')^2 +
+// (D w')^2 from the five-plane stencil of the fluctuations.
 // inter holds cx<double> (FP64 path) or cx<float> (split-BF16 path).
-hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int f32,
+hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int f32, int gy,
                              const void *u, const void *v, const void *w, const void *p,
                              const double *prof, void *inter, double *momp);
 // z transforms and packing into the spectra slot (FP64 path: cx<double>)

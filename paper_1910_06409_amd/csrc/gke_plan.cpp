@@ -83,6 +83,7 @@ struct gke_plan_s {
     double *mf = nullptr, *band = nullptr;
     size_t mstride = 0;            // doubles per term map in mf
     double *sums1 = nullptr, *prof = nullptr, *momp = nullptr, *r0 = nullptr, *gxz = nullptr;
+    double *gy1 = nullptr;   // split path: <|D u'|^2> per plane from the first scan
     void *inter = nullptr;  // cx<double> (FP64) or cx<float> (split-BF16)
     void *spec = nullptr;   // cx<double> (FP64) or gke::SplitRec records (split-BF16)
     cx<double> *acc = nullptr, *mid = nullptr;
@@ -467,11 +468,12 @@ size_t layout(gke_plan_t p, char *base)
     p->rzk = (int *)take(sizeof(int) * d.nz);
     p->rzinv = (int *)take(sizeof(int) * d.nz);
     p->rxk = (int *)take(sizeof(int) * d.nx);
-    p->sums1 = (double *)take(sizeof(double) * 4 * d.ny * gke::NSPLIT);
+    p->sums1 = (double *)take(sizeof(double) * 5 * d.ny * gke::NSPLIT);
     p->prof = (double *)take(sizeof(double) * gke::NPROF * d.ny);
     p->momp = (double *)take(sizeof(double) * d.ny * gke::NMOMP * d.nzb);
     p->r0 = (double *)take(sizeof(double) * d.ny * 5);
     p->gxz = (double *)take(sizeof(double) * d.ny);
+    p->gy1 = (double *)take(sizeof(double) * d.ny);
     // split path: four x-transformed buffers of cx<float> (one per snapshot of
     // a quad) and records of four snapshots; FP64: one buffer, cx<double>
     const bool split = d.prec == gke::PREC_BF16X3;
@@ -1058,7 +1060,10 @@ gke_status gke_accumulate(gke_plan_t p, const void *u, const void *v, const void
     const int f32 = p->dtype == GKE_DTYPE_F32;
     if (!p->second_scan) {
         GKE_HIP(p, timed(p, GKE_K_PLANE_SUMS, [&] {
-            return gke::launch_plane_sums(p->stream, p->d, f32, u, v, w, pr, p->sums1);
+            // split path: also the wall-normal gradient energy (first scan)
+            return gke::launch_plane_sums(p->stream, p->d, p->tab, f32,
+                                          p->d.prec == gke::PREC_BF16X3 ? 1 : 0, u, v, w, pr,
+                                          p->sums1);
         }));
         ++p->n1;
         return GKE_OK;
@@ -1067,8 +1072,11 @@ gke_status gke_accumulate(gke_plan_t p, const void *u, const void *v, const void
     // split path: snapshot i of a quad in x-transformed buffer i
     void *xdst = split ? (void *)((char *)p->inter + (p->pending & 3) * inter_bytes(p->d))
                        : p->inter;
+    // the gradient energy by the x pass's stencil only when the first scan
+    // did not sum it (means given by the caller)
+    const int gy = split && p->means_from_host ? 1 : 0;
     GKE_HIP(p, timed(p, GKE_K_FLUCT_XFFT, [&] {
-        return gke::launch_fluct_xfft(p->stream, p->d, p->tab, f32, u, v, w, pr, p->prof,
+        return gke::launch_fluct_xfft(p->stream, p->d, p->tab, f32, gy, u, v, w, pr, p->prof,
                                       xdst, p->momp);
     }));
     if (!split)
@@ -1216,7 +1224,8 @@ gke_status gke_begin_stats(gke_plan_t p)
     if (p->second_scan) return fail(p, GKE_ERR_STATE, "second scan already started");
     if (p->n1 == 0) return fail(p, GKE_ERR_STATE, "no first-scan snapshot");
     GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {
-        return gke::launch_means(p->stream, p->d, p->tab, p->sums1, (double)p->n1, p->prof);
+        return gke::launch_means(p->stream, p->d, p->tab, p->sums1, (double)p->n1, p->prof,
+                                 p->d.prec == gke::PREC_BF16X3 ? p->gy1 : nullptr);
     }));
     GKE_HIP(p, hipStreamSynchronize(p->stream));
     p->second_scan = true;
@@ -1300,8 +1309,9 @@ gke_status gke_finalize(gke_plan_t p, const gke_terms *out)
                           : gke::launch_r0(st, d, p->tab, p->acc, inv, p->r0, p->gxz);
     }));
     GKE_HIP(p, timed(p, GKE_K_SMALL, [&] {
-        return gke::launch_profiles(st, d, p->tab, p->momp, p->r0, p->gxz, (double)p->n2,
-                                    p->prof);
+        const int gy_mode = d.prec != gke::PREC_BF16X3 ? 0 : p->means_from_host ? 2 : 1;
+        return gke::launch_profiles(st, d, p->tab, p->momp, p->r0, p->gxz, p->gy1, gy_mode,
+                                    (double)p->n2, p->prof);
     }));
     const int pbt = (p->pair_batch > 0 && p->pair_batch < d.npair) ? p->pair_batch : d.npair;
     if (p->general) {

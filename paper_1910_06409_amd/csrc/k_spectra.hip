@@ -38,33 +38,6 @@ __device__ __forceinline__ unsigned int split_bf16(float x)
     return h | (l << 16);
 }
 
-// Sums each of eight values over the 64 lanes of a wave in a fixed order: on
-// return, every lane of the group of eight lanes g = lane / 8 holds the sum of
-// v[g].  Each step halves the values a lane keeps and sends the other half to
-// its partner (lanes 32, 16, 8 apart), then the last three steps finish the
-// sum within the group: 10 exchanges instead of 8 x 6.
-__device__ __forceinline__ double wave_sum8(const double (&v)[8])
-{
-    const int lane = threadIdx.x & 63;
-    double a[4], b[2];
-    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const double keep = h5 ? v[4 + i] : v[i], send = h5 ? v[i] : v[4 + i];
-        a[i] = keep + __shfl_xor(send, 32, 64);
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const double keep = h4 ? a[2 + i] : a[i], send = h4 ? a[i] : a[2 + i];
-        b[i] = keep + __shfl_xor(send, 16, 64);
-    }
-    double c = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8, 64);
-    c += __shfl_xor(c, 4, 64);
-    c += __shfl_xor(c, 2, 64);
-    c += __shfl_xor(c, 1, 64);
-    return c;
-}
-
 template <typename T>
 __device__ __forceinline__ void store_spec(cx<double> *spec, size_t i, cx<T> X) { spec[i] = cx<double>{X.x, X.y}; }
 // the split dwords of one value: hi = (re_hi, im_hi), lo = (re_lo, im_lo)
@@ -83,7 +56,7 @@ __device__ __forceinline__ void split_value(float re, float im, unsigned int &hi
 //   inter[j][g][f][kx][row]: x-transformed rows (unnormalised) in groups of zg
 //   rows (z = g zg + row); a block writes its zb rows of one group
 //   momp[j][k][zblk]: FP64 partial sums of q uv pv qu qv qw and (dy u')^2
-template <typename TI, typename T, int BLOCK, int NF>
+template <typename TI, typename T, int BLOCK, int NF, bool GY>
 __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fluct_xfft(const TI *__restrict__ u,
                                                           const TI *__restrict__ v,
                                                           const TI *__restrict__ w,
@@ -112,7 +85,9 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fluct_xfft(const TI *_
     const double U = prof[P_U * ny + j], V = prof[P_V * ny + j];
     const double W = prof[P_W * ny + j], P = prof[P_P * ny + j];
     const int nel = zb * nx;
-    constexpr bool kGy = sizeof(T) == sizeof(float);   // split-BF16 path
+    // the wall-normal gradient energy from the five-plane stencil: the split
+    // path when the first scan did not sum it (means given by the caller)
+    constexpr bool kGy = GY;
     // zb nx and nx stay below CAP / 5 (host check): NI elements per thread
     constexpr int NI = (CAP / 5 + BLOCK - 1) / BLOCK;
     constexpr int NG = kGy ? NI : 1;
@@ -222,7 +197,7 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fluct_xfft(const TI *_
     }
 }
 
-template <typename TI, typename T, int BLOCK>
+template <typename TI, typename T, int BLOCK, bool GY>
 static void launch_fx_shape(hipStream_t st, const Dims &d, const Tables &t, const void *u,
                             const void *v, const void *w, const void *p, const double *prof,
                             void *inter, double *momp)
@@ -230,33 +205,41 @@ static void launch_fx_shape(hipStream_t st, const Dims &d, const Tables &t, cons
     const size_t lds = sizeof(cx<T>) * (5 * (size_t)d.zb * fft_stride(d.nx) + d.nx);
     with_fft_len(d.nx, [&](auto len) {
         constexpr int NF = decltype(len)::value;
-        set_lds_limit(k_fluct_xfft<TI, T, BLOCK, NF>);
-        hipLaunchKernelGGL((k_fluct_xfft<TI, T, BLOCK, NF>), dim3(d.nzb * d.ny), dim3(BLOCK), lds,
-                           st, (const TI *)u, (const TI *)v, (const TI *)w, (const TI *)p, prof, d,
-                           t, (cx<T> *)inter, momp);
+        set_lds_limit(k_fluct_xfft<TI, T, BLOCK, NF, GY>);
+        hipLaunchKernelGGL((k_fluct_xfft<TI, T, BLOCK, NF, GY>), dim3(d.nzb * d.ny), dim3(BLOCK),
+                           lds, st, (const TI *)u, (const TI *)v, (const TI *)w, (const TI *)p,
+                           prof, d, t, (cx<T> *)inter, momp);
     });
 }
 
-template <typename TI, typename T>
+template <typename TI, typename T, bool GY>
 static void launch_fx(hipStream_t st, const Dims &d, const Tables &t, const void *u,
                       const void *v, const void *w, const void *p, const double *prof,
                       void *inter, double *momp)
 {
     if (d.xblk == SMALL_BLOCK)
-        launch_fx_shape<TI, T, SMALL_BLOCK>(st, d, t, u, v, w, p, prof, inter, momp);
+        launch_fx_shape<TI, T, SMALL_BLOCK, GY>(st, d, t, u, v, w, p, prof, inter, momp);
     else
-        launch_fx_shape<TI, T, FFT_BLOCK>(st, d, t, u, v, w, p, prof, inter, momp);
+        launch_fx_shape<TI, T, FFT_BLOCK, GY>(st, d, t, u, v, w, p, prof, inter, momp);
 }
 
-hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int f32,
+hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int f32, int gy,
                              const void *u, const void *v, const void *w, const void *p,
                              const double *prof, void *inter, double *momp)
 {
     const bool sp = d.prec == PREC_BF16X3;
-    if (f32 && sp) launch_fx<float, float>(st, d, t, u, v, w, p, prof, inter, momp);
-    else if (f32) launch_fx<float, double>(st, d, t, u, v, w, p, prof, inter, momp);
-    else if (sp) launch_fx<double, float>(st, d, t, u, v, w, p, prof, inter, momp);
-    else launch_fx<double, double>(st, d, t, u, v, w, p, prof, inter, momp);
+    if (gy && !sp) return hipErrorInvalidValue;   // the FP64 path takes it from the spectra
+    if (f32 && sp) {
+        if (gy) launch_fx<float, float, true>(st, d, t, u, v, w, p, prof, inter, momp);
+        else launch_fx<float, float, false>(st, d, t, u, v, w, p, prof, inter, momp);
+    } else if (f32) {
+        launch_fx<float, double, false>(st, d, t, u, v, w, p, prof, inter, momp);
+    } else if (sp) {
+        if (gy) launch_fx<double, float, true>(st, d, t, u, v, w, p, prof, inter, momp);
+        else launch_fx<double, float, false>(st, d, t, u, v, w, p, prof, inter, momp);
+    } else {
+        launch_fx<double, double, false>(st, d, t, u, v, w, p, prof, inter, momp);
+    }
     return hipGetLastError();
 }
 

@@ -63,10 +63,151 @@ __global__ __launch_bounds__(256) void k_plane_sums(const TI *__restrict__ u,
     }
 }
 
-hipError_t launch_plane_sums(hipStream_t st, const Dims &d, int f32, const void *u,
-                             const void *v, const void *w, const void *p, double *sums)
+// The split path's first scan: the plane sums of k_plane_sums and, per
+// plane, the sum of (D u~)^2 + (D v~)^2 + (D w~)^2 of the raw fields (D: the
+// five-point wall-normal weights of the plane, nodes j0[j] .. j0[j] + 4), from
+// which the means kernel forms the gradient energy of the fluctuations
+// (Section "Step 2": the pseudo-dissipation; the split spectra cannot give its
+// wall-normal part without losing digits to cancellation, and forming it in
+// the second scan needs every plane's four neighbours there).
+// Block (part, chunk): GY_JC planes of one 1/NSPLIT column range.  A thread
+// loads the window nodes of its column point once (GY_JC + 4 planes of u v w,
+// interior chunks, where node j0[j] = j - 2) and keeps them in registers; the
+// chunks at the walls, whose windows are clamped, load each plane's five nodes.
+// Sums in FP64, one fixed-order block reduction per value.
+constexpr int GY_JC = 4;
+template <typename TI>
+__global__ __launch_bounds__(256) void k_plane_sums_gy(const TI *__restrict__ u,
+                                                       const TI *__restrict__ v,
+                                                       const TI *__restrict__ w,
+                                                       const TI *__restrict__ p, int npl, int ny,
+                                                       Tables t, double *__restrict__ sums)
+{
+    constexpr int NV = 5 * GY_JC, NV8 = (NV + 7) / 8 * 8;   // values, in groups of eight
+    __shared__ double sh[NV8][4];
+    __shared__ double sw[GY_JC][5];   // the planes' five-point weights
+    const int part = blockIdx.x, ja = blockIdx.y * GY_JC;
+    const int nj = min(GY_JC, ny - ja);
+    const int len = (npl + NSPLIT - 1) / NSPLIT;
+    const int i0 = part * len, i1 = min(npl, i0 + len);
+    // interior: every plane's window starts two below it
+    const bool interior = t.j0[ja] == ja - 2 && t.j0[ja + nj - 1] == ja + nj - 3;
+    if ((int)threadIdx.x < 5 * GY_JC) {
+        const int q = threadIdx.x / 5, k = threadIdx.x % 5;
+        sw[q][k] = t.w5[(ja + min(q, nj - 1)) * 5 + k];
+    }
+    __syncthreads();
+    double a[GY_JC][5];
+#pragma unroll
+    for (int q = 0; q < GY_JC; ++q)
+#pragma unroll
+        for (int f = 0; f < 5; ++f) a[q][f] = 0.0;
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += 256) {
+        // plane bases are block-uniform (scalar registers); the lane offset is i
+        TI pv[GY_JC];
+#pragma unroll
+        for (int q = 0; q < GY_JC; ++q) pv[q] = (p + (size_t)(ja + min(q, nj - 1)) * npl)[i];
+        if (interior) {
+            // nodes ja - 2 .. ja + nj + 1; slots past the chunk repeat its last node
+            TI x[GY_JC + 4][3];
+#pragma unroll
+            for (int n = 0; n < GY_JC + 4; ++n) {
+                const size_t o = (size_t)(ja - 2 + min(n, nj + 3)) * npl;
+                x[n][0] = (u + o)[i];
+                x[n][1] = (v + o)[i];
+                x[n][2] = (w + o)[i];
+            }
+#pragma unroll
+            for (int q = 0; q < GY_JC; ++q) {
+                const bool ok = q < nj;
+                const int j = ja + min(q, nj - 1);
+                double du = 0.0, dv = 0.0, dw = 0.0;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    const double wk = sw[q][k];
+                    du += wk * (double)x[q + k][0];
+                    dv += wk * (double)x[q + k][1];
+                    dw += wk * (double)x[q + k][2];
+                }
+                a[q][0] += ok ? (double)x[q + 2][0] : 0.0;
+                a[q][1] += ok ? (double)x[q + 2][1] : 0.0;
+                a[q][2] += ok ? (double)x[q + 2][2] : 0.0;
+                a[q][3] += ok ? (double)pv[q] : 0.0;
+                a[q][4] += ok ? du * du + dv * dv + dw * dw : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < GY_JC; ++q) {
+                const bool ok = q < nj;
+                const int j = ja + min(q, nj - 1), js = t.j0[j];
+                TI x[5][3];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    const size_t o = (size_t)(js + k) * npl;
+                    x[k][0] = (u + o)[i];
+                    x[k][1] = (v + o)[i];
+                    x[k][2] = (w + o)[i];
+                }
+                const size_t oj = (size_t)j * npl;
+                const double uj = (double)(u + oj)[i], vj = (double)(v + oj)[i];
+                const double wj = (double)(w + oj)[i];
+                double du = 0.0, dv = 0.0, dw = 0.0;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    const double wk = sw[q][k];
+                    du += wk * (double)x[k][0];
+                    dv += wk * (double)x[k][1];
+                    dw += wk * (double)x[k][2];
+                }
+                a[q][0] += ok ? uj : 0.0;
+                a[q][1] += ok ? vj : 0.0;
+                a[q][2] += ok ? wj : 0.0;
+                a[q][3] += ok ? (double)pv[q] : 0.0;
+                a[q][4] += ok ? du * du + dv * dv + dw * dw : 0.0;
+            }
+        }
+    }
+    // NV values: wave reductions eight at a time (the last group padded with
+    // zeros), then the four waves in order
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, g = lane >> 3;
+#pragma unroll
+    for (int c = 0; c < NV8 / 8; ++c) {
+        double vals[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int vi = 8 * c + e;
+            vals[e] = vi < NV ? a[vi / 5][vi % 5] : 0.0;
+        }
+        const double r = wave_sum8(vals);
+        if ((lane & 7) == 0) sh[8 * c + g][wid] = r;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < 5 * nj) {
+        const int q = threadIdx.x / 5, f = threadIdx.x % 5;
+        const double r = sh[threadIdx.x][0] + sh[threadIdx.x][1] + sh[threadIdx.x][2] +
+                         sh[threadIdx.x][3];
+        sums[((size_t)f * ny + ja + q) * NSPLIT + part] += r;
+    }
+}
+
+hipError_t launch_plane_sums(hipStream_t st, const Dims &d, const Tables &t, int f32, int gy,
+                             const void *u, const void *v, const void *w, const void *p,
+                             double *sums)
 {
     const int npl = d.nx * d.nz;
+    if (gy) {
+        if (d.ny < 5) return hipErrorInvalidValue;
+        dim3 grid(NSPLIT, (d.ny + GY_JC - 1) / GY_JC);
+        if (f32)
+            hipLaunchKernelGGL(k_plane_sums_gy<float>, grid, dim3(256), 0, st, (const float *)u,
+                               (const float *)v, (const float *)w, (const float *)p, npl, d.ny,
+                               t, sums);
+        else
+            hipLaunchKernelGGL(k_plane_sums_gy<double>, grid, dim3(256), 0, st, (const double *)u,
+                               (const double *)v, (const double *)w, (const double *)p, npl,
+                               d.ny, t, sums);
+        return hipGetLastError();
+    }
     dim3 grid(d.ny, NSPLIT);
     if (f32)
         hipLaunchKernelGGL(k_plane_sums<float>, grid, dim3(256), 0, st,
@@ -91,7 +232,7 @@ __device__ void shear_rows(int ny, const double *w5, const int *j0, double *prof
 
 __global__ void k_means(int ny, const double *__restrict__ sums, double inv_count,
                         const double *__restrict__ w5, const int *__restrict__ j0,
-                        double *__restrict__ prof)
+                        double *__restrict__ prof, double *__restrict__ gy1)
 {
     for (int i = threadIdx.x; i < 4 * ny; i += blockDim.x) {
         double a = 0.0;
@@ -100,6 +241,24 @@ __global__ void k_means(int ny, const double *__restrict__ sums, double inv_coun
     }
     __syncthreads();
     shear_rows(ny, w5, j0, prof);
+    if (gy1) {
+        // <(D u')^2> = <(D u~)^2> - (D U)^2 per component: D is linear and the
+        // five-point D of the plane means is the plane mean of D u~
+        for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+            double a = 0.0;
+            for (int part = 0; part < NSPLIT; ++part)
+                a += sums[((size_t)4 * ny + j) * NSPLIT + part];
+            double dU = 0.0, dV = 0.0, dW = 0.0;
+            for (int k = 0; k < 5; ++k) {
+                const double wk = w5[j * 5 + k];
+                const int n = j0[j] + k;
+                dU += wk * prof[P_U * ny + n];
+                dV += wk * prof[P_V * ny + n];
+                dW += wk * prof[P_W * ny + n];
+            }
+            gy1[j] = a * inv_count - (dU * dU + dV * dV + dW * dW);
+        }
+    }
 }
 
 __global__ void k_shear(int ny, const double *__restrict__ w5, const int *__restrict__ j0,
@@ -109,10 +268,11 @@ __global__ void k_shear(int ny, const double *__restrict__ w5, const int *__rest
 }
 
 hipError_t launch_means(hipStream_t st, const Dims &d, const Tables &t, const double *sums,
-                        double count, double *prof)
+                        double count, double *prof, double *gy1)
 {
     const double inv = 1.0 / (count * (double)d.nx * (double)d.nz);
-    hipLaunchKernelGGL(k_means, dim3(1), dim3(256), 0, st, d.ny, sums, inv, t.w5, t.j0, prof);
+    hipLaunchKernelGGL(k_means, dim3(1), dim3(256), 0, st, d.ny, sums, inv, t.w5, t.j0, prof,
+                       gy1);
     return hipGetLastError();
 }
 
@@ -178,8 +338,8 @@ hipError_t launch_r0(hipStream_t st, const Dims &d, const Tables &t, const cx<do
 __global__ void k_profiles(int ny, int nzb, const double *__restrict__ momp,
                            const double *__restrict__ w5, const int *__restrict__ j0,
                            const double *__restrict__ r0, const double *__restrict__ gxz,
-                           double inv_pts, double nu, int gy_direct,
-                           double *__restrict__ prof)
+                           const double *__restrict__ gy1, double inv_pts, double nu,
+                           int gy_mode, double *__restrict__ prof)
 {
     const int j = blockIdx.x;
     if (threadIdx.x != 0) return;
@@ -204,17 +364,22 @@ __global__ void k_profiles(int ny, int nzb, const double *__restrict__ momp,
     prof[P_TX * ny + j] = s[MP_QU];
     prof[P_TY * ny + j] = s[MP_QV];
     prof[P_TZ * ny + j] = s[MP_QW];
-    // the split-BF16 path sums the wall-normal part in physical space (FP64)
-    if (gy_direct) gy = s[MP_GY];
+    // the split-BF16 path sums the wall-normal part in physical space (FP64):
+    // in the first scan (gy1), or in the second (the x pass's stencil) when
+    // the caller gave the means
+    if (gy_mode == 1) gy = gy1[j];
+    else if (gy_mode == 2) gy = s[MP_GY];
     prof[P_EPS * ny + j] = nu * (gy + gxz[j]);
 }
 
 hipError_t launch_profiles(hipStream_t st, const Dims &d, const Tables &t, const double *momp,
-                           const double *r0, const double *gxz, double count, double *prof)
+                           const double *r0, const double *gxz, const double *gy1, int gy_mode,
+                           double count, double *prof)
 {
+    if (gy_mode < 0 || gy_mode > 2 || (gy_mode == 1 && !gy1)) return hipErrorInvalidValue;
     const double inv_pts = 1.0 / (count * (double)d.nx * (double)d.nz);
     hipLaunchKernelGGL(k_profiles, dim3(d.ny), dim3(64), 0, st, d.ny, d.nzb, momp, t.w5, t.j0,
-                       r0, gxz, inv_pts, d.nu, d.prec == PREC_BF16X3 ? 1 : 0, prof);
+                       r0, gxz, gy1, inv_pts, d.nu, gy_mode, prof);
     return hipGetLastError();
 }
 

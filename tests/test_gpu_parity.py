@@ -163,6 +163,32 @@ def test_set_means_and_refinalize():
     compare(second, ref6, pairs, w.nx, "re-finalize 6 snapshots")
 
 
+def test_set_means_split_path_gradient_energy():
+    """Split path with the means given by the caller: the wall-normal gradient
+    energy of the pseudo-dissipation then comes from the x pass's five-plane
+    stencil of the fluctuations (the first scan, which otherwise sums it,
+    did not run); T14 = -4 eps* and every other term against the oracle."""
+    torch = _torch()
+    from paper_1910_06409_amd import runner
+    w = synth.workload("tiny", S=6, dtype="f32", precision="bf16x3", noise=0.3)
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 17)
+    s64 = snap.astype(np.float64)
+    prof_all = oracle.step1(s64, y, w.lx, w.lz, w.nu)
+    dev = torch.from_numpy(snap).cuda()
+    say("case split path, means from the caller")
+    r = runner.GkeRun(w.nx, w.ny, w.nz, y, w.lx, w.lz, w.nu, dtype="f32", precision="bf16x3",
+                      chunk=4)
+    r.set_means(*prof_all[:4])
+    for s in range(w.S):
+        r.accumulate_snapshot(dev[s])
+    out = [t.cpu().numpy() if t is not None else None for t in r.finalize()]
+    r.close()
+    pairs = oracle.all_pairs(w.ny)
+    ref = oracle.pair_terms(s64, y, w.lx, w.lz, w.nu, pairs, prof=prof_all)
+    compare(out, ref, pairs, w.nx, "split path, set_means", tol=TOL_BF16)
+
+
 def _onepoint(snap, y, w, prof_means):
     """Oracle one-point profiles of `snap` about externally given means."""
     return oracle.step1(snap, y, w.lx, w.lz, w.nu, means=prof_means[:4])
