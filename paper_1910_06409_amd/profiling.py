@@ -37,7 +37,7 @@ CSRC = os.path.join(HERE, "csrc")
 # timing family -> device symbol per precision, and the sources that define it
 # (every kernel also depends on the shared headers and the build flags)
 KERNELS = {
-    "plane_sums": ({"fp64": "k_plane_sums", "bf16x3": "k_plane_sums"}, ["k_stats.hip"]),
+    "plane_sums": ({"fp64": "k_plane_sums", "bf16x3": "k_plane_sums_gy"}, ["k_stats.hip"]),
     "fluct_xfft": ({"fp64": "k_fluct_xfft", "bf16x3": "k_fluct_xfft"}, ["k_spectra.hip"]),
     "zfft_pack": ({"fp64": "k_zfft_pack_blk", "bf16x3": "k_zfft_rec"}, ["k_spectra.hip"]),
     "rankk": ({"fp64": "k_rankk_f64", "bf16x3": "k_rankk_bf16x3"},
