@@ -264,7 +264,10 @@ def main():
             log(f"[bench] calibration copy of {nb} bytes done")
             del src, dst
 
-        def step(graph):
+        def step(graph, marks=None):
+            """marks: two events recorded around the second scan and finalize
+            (the span of the contract's T, from the first Step-2 accumulate to
+            the return of finalize)."""
             r.reset()
             if graph:
                 r.accumulate_batch(snaps)
@@ -274,9 +277,13 @@ def main():
                 for s in range(S):
                     r.accumulate_snapshot(snaps[s])
                 r.begin_stats()
+                if marks:
+                    marks[0].record()
                 for s in range(S):
                     r.accumulate_snapshot(snaps[s])
             r.finalize(outs)
+            if marks:
+                marks[1].record()
 
         graph = args.graph == "on"
         for i in range(warmup):
@@ -287,13 +294,17 @@ def main():
         # the per-kernel device times come from extra event-timed steps
         r.set_timing(not graph)
         r.timings(reset=True)
+        marks = [] if graph else [(torch.cuda.Event(enable_timing=True),
+                                   torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(steps):
-            step(graph)
+            step(graph, marks[i] if marks else None)
             log(f"[bench] timed step {i + 1}/{steps} done")
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        # second scan + finalize (T of the contract; pass 1 apart), per step
+        t_pass2 = (sum(a.elapsed_time(b) for a, b in marks) / 1e3 / steps) if marks else None
         ksteps = steps
         if graph:
             r.set_timing(True)
@@ -390,7 +401,7 @@ def main():
         return {"w": w, "S": S, "chunk": chunk_used, "t_step": t_step, "kernels": kernels,
                 "roofline": roof, "stages": stages, "value": w.points_out * S / t_step,
                 "tuned": ({"chunk": chunk_used, **shapes} if tuned else None),
-                "graph_ms_per_step": graph_ms}
+                "graph_ms_per_step": graph_ms, "t_pass2": t_pass2}
 
     def measure_slabs(w, slab_rows, chunk, pair_batch):
         """The config-5 path: mirror average, fundamental domain, Y1 slabs (one
@@ -522,6 +533,7 @@ def main():
             "speedup_per_snapshot_vs_main": per_snap_main / per_snap,
             "roofline": er["roofline"], "stages": er["stages"], "tuned": er["tuned"],
             "graph_ms_per_step": er["graph_ms_per_step"],
+            "pass2_ms_per_step": 1e3 * er["t_pass2"] if er["t_pass2"] else None,
             "kernels_ms_per_step": {k: v["ms_per_step"] for k, v in er["kernels"].items()},
         }
         stated = profiling.stated_error(
@@ -553,6 +565,12 @@ def main():
                    "precision": w.precision, "chunk": main_res["chunk"],
                    "points_out": w.points_out, "tuned": main_res["tuned"]},
         "points_per_s": w.points_out / t_step,
+        # the contract's T (first second-scan accumulate to the return of
+        # finalize) and the throughput over it; the first scan apart
+        "pass2": ({"ms_per_step": 1e3 * main_res["t_pass2"],
+                   "value": w.points_out * S / main_res["t_pass2"],
+                   "pass1_ms_per_step": 1e3 * (t_step - main_res["t_pass2"])}
+                  if main_res["t_pass2"] else None),
         "graph": {"timed_steps_as_graphs": args.graph == "on",
                   "graph_ms_per_step": main_res["graph_ms_per_step"]},
         "roofline": main_res["roofline"],
