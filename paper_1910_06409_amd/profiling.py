@@ -228,12 +228,14 @@ def read_summary_if_current(path: str, family: str) -> dict | None:
 
 
 def stated_error(path: str) -> dict | None:
-    """Per-term norm-wise errors recorded for a workload (a committed text
-    file: `T1: 1.2e-07` lines, a `source:` line naming the test that measured
-    them and a `command:` comment)."""
+    """Per-term errors recorded for a workload (a committed text file:
+    `T1: 1.2e-07` lines for the norm-wise error, `pw_T1: ...` lines for the
+    pointwise relative error over the points where |T| > 1e-3 max|T|, a
+    `source:` line naming the test that measured them and a `command:`
+    comment)."""
     if not os.path.exists(path):
         return None
-    terms, out = {}, {}
+    terms, pw, out = {}, {}, {}
     with open(path) as f:
         for line in f:
             line = line.strip()
@@ -244,12 +246,16 @@ def stated_error(path: str) -> dict | None:
             k, v = (x.strip() for x in line.split(":", 1))
             if k.startswith("T") and k[1:].isdigit():
                 terms[k] = float(v)
+            elif k.startswith("pw_T") and k[4:].isdigit():
+                pw[k[3:]] = float(v)
             else:
                 out[k] = v
     if not terms:
         return None
     out["per_term"] = terms
     out["max"] = max(terms.values())
+    if pw:
+        out["pointwise_per_term"] = pw
     return out
 
 
