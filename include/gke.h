@@ -329,6 +329,30 @@ gke_status gke_set_means(gke_plan_t plan, const double *U, const double *V, cons
  * missing), GKE_ERR_UNSUPPORTED (the residual in the slab modes), GKE_ERR_HIP. */
 gke_status gke_finalize(gke_plan_t plan, const gke_terms *out);
 
+/* Checkpoint and resume of the accumulation (the paper's program keeps its
+ * running sums on disk and divides them only at the end, Section "General
+ * structure of the program": a long scan can stop and continue).  The state
+ * is the scan counters, the one-point sums and moment partials, the
+ * cross-spectral accumulators and, in the general modes, the band
+ * accumulators, with a header naming the plan's shape and options.
+ * gke_state_size: the bytes of the state (it grows with the accumulators:
+ * 8 * Nk * pairs * 16 bytes, 18.6 GB at Re_tau=200).
+ * gke_save_state: first adds the snapshots of the current chunk into the
+ * accumulators (as gke_finalize does), then copies the state into `host`
+ * (caller-owned host memory, pageable or pinned, at least gke_state_size
+ * bytes); blocking.  The plan continues unchanged afterwards.
+ * gke_load_state: replaces the scan state of a plan with a workspace by a
+ * saved one; the plan must have the same grid, y, Lx, Lz, nu, dtype,
+ * precision, mirror, domain, slab rows and undersampling (chunk and block
+ * shapes may differ); in the general modes it selects the saved slab.
+ * Blocking.  The continued run equals the uninterrupted one with the same
+ * chunk boundaries bit for bit.
+ * Errors: GKE_ERR_ARG (NULL, buffer too small, not a saved state, another
+ * shape or options), GKE_ERR_STATE (no workspace), GKE_ERR_HIP. */
+gke_status gke_state_size(gke_plan_t plan, size_t *bytes);
+gke_status gke_save_state(gke_plan_t plan, void *host, size_t bytes);
+gke_status gke_load_state(gke_plan_t plan, const void *host, size_t bytes);
+
 /* Notification per slab (Section "Undersampling and parallelisation": the
  * wall-normal slices are computed one after another, each slice's results
  * written out as it completes).  fn(slab, user) is called once per

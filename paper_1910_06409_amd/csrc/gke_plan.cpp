@@ -597,6 +597,65 @@ gke_status launch_flush(gke_plan_t p)
     return GKE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Checkpoint of the accumulation state: a header, the one-point sums and
+// moment partials ([sums1, inter) of the workspace), the cross-spectral
+// accumulators and, in the general modes, the band accumulators.
+
+constexpr char kStateMagic[8] = {'G', 'K', 'E', 'S', 'T', 'A', 'T', '1'};
+struct StateHeader {
+    char magic[8];
+    int32_t nx, ny, nz, prec, dtype, mirror, domain, slab_rows, cur_slab, second_scan,
+        means_from_host, pad;
+    uint64_t cfg;                                  // hash of y, Lx, Lz, nu and the undersampling
+    int64_t n1, n2, chunks_done;
+    uint64_t small_bytes, acc_bytes, band_bytes;   // the three sections that follow
+};
+
+uint64_t fnv1a(uint64_t h, const void *data, size_t n)
+{
+    const unsigned char *b = static_cast<const unsigned char *>(data);
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+
+StateHeader state_header(gke_plan_t p)
+{
+    StateHeader h{};
+    std::memcpy(h.magic, kStateMagic, 8);
+    const gke::Dims &d = p->d;
+    h.nx = d.nx;
+    h.ny = d.ny;
+    h.nz = d.nz;
+    h.prec = d.prec;
+    h.dtype = p->dtype;
+    h.mirror = p->mirror;
+    h.domain = p->domain;
+    h.slab_rows = p->slab_rows;
+    h.cur_slab = p->general ? p->cur_slab : 0;
+    h.second_scan = p->second_scan ? 1 : 0;
+    h.means_from_host = p->means_from_host ? 1 : 0;
+    uint64_t c = 1469598103934665603ull;
+    c = fnv1a(c, p->y.data(), sizeof(double) * p->y.size());
+    c = fnv1a(c, &d.lx, sizeof(double));
+    c = fnv1a(c, &d.lz, sizeof(double));
+    c = fnv1a(c, &d.nu, sizeof(double));
+    c = fnv1a(c, p->us, sizeof(p->us));
+    h.cfg = c;
+    h.n1 = p->n1;
+    h.n2 = p->n2;
+    h.chunks_done = p->chunks_done;
+    h.small_bytes = (uint64_t)((char *)p->inter - (char *)p->sums1);
+    h.acc_bytes = (uint64_t)sizeof(cx<double>) * gke::NSPEC * d.nk * d.pstr;
+    h.band_bytes = p->general ? (uint64_t)sizeof(double) * d.nk * 5 * d.ny : 0;
+    return h;
+}
+
+size_t state_bytes(const StateHeader &h)
+{
+    return sizeof(StateHeader) + h.small_bytes + h.acc_bytes + h.band_bytes;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1452,6 +1511,86 @@ gke_status gke_begin_slab(gke_plan_t p, int slab)
     p->chunks_done = 0;
     if (p->general) return select_slab(p, slab);
     GKE_HIP(p, hipStreamSynchronize(p->stream));
+    return GKE_OK;
+}
+
+gke_status gke_state_size(gke_plan_t p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(p, GKE_ERR_ARG, "NULL argument");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    *bytes = state_bytes(state_header(p));
+    return GKE_OK;
+}
+
+gke_status gke_save_state(gke_plan_t p, void *host, size_t bytes)
+{
+    if (!p || !host) return fail(p, GKE_ERR_ARG, "NULL argument");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    {   // the snapshots of the current chunk go into the accumulators first
+        gke_status s = launch_flush(p);
+        if (s != GKE_OK) return s;
+    }
+    const StateHeader h = state_header(p);
+    if (bytes < state_bytes(h))
+        return fail(p, GKE_ERR_ARG, "state buffer too small: need " +
+                                        std::to_string(state_bytes(h)) + " bytes");
+    char *o = static_cast<char *>(host);
+    std::memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    hipStream_t st = p->stream;
+    GKE_HIP(p, hipMemcpyAsync(o, p->sums1, h.small_bytes, hipMemcpyDeviceToHost, st));
+    o += h.small_bytes;
+    if (h.acc_bytes)
+        GKE_HIP(p, hipMemcpyAsync(o, p->acc, h.acc_bytes, hipMemcpyDeviceToHost, st));
+    o += h.acc_bytes;
+    if (h.band_bytes)
+        GKE_HIP(p, hipMemcpyAsync(o, p->band, h.band_bytes, hipMemcpyDeviceToHost, st));
+    GKE_HIP(p, hipStreamSynchronize(st));
+    return GKE_OK;
+}
+
+gke_status gke_load_state(gke_plan_t p, const void *host, size_t bytes)
+{
+    if (!p || !host) return fail(p, GKE_ERR_ARG, "NULL argument");
+    if (!p->ws) return fail(p, GKE_ERR_STATE, "no workspace");
+    if (bytes < sizeof(StateHeader)) return fail(p, GKE_ERR_ARG, "state buffer too small");
+    StateHeader h;
+    std::memcpy(&h, host, sizeof(h));
+    if (std::memcmp(h.magic, kStateMagic, 8) != 0)
+        return fail(p, GKE_ERR_ARG, "not a saved state of this library");
+    if (p->general && (h.cur_slab < 0 || h.cur_slab >= (int)p->slabs.size()))
+        return fail(p, GKE_ERR_ARG, "saved slab out of range for this plan");
+    // the slab decides the pair extents of the accumulators
+    if (p->general && p->cur_slab != h.cur_slab) {
+        gke_status s = select_slab(p, h.cur_slab);
+        if (s != GKE_OK) return s;
+    }
+    StateHeader mine = state_header(p);
+    mine.cur_slab = h.cur_slab;
+    if (h.nx != mine.nx || h.ny != mine.ny || h.nz != mine.nz || h.prec != mine.prec ||
+        h.dtype != mine.dtype || h.mirror != mine.mirror || h.domain != mine.domain ||
+        h.slab_rows != mine.slab_rows || h.cfg != mine.cfg ||
+        h.small_bytes != mine.small_bytes || h.acc_bytes != mine.acc_bytes ||
+        h.band_bytes != mine.band_bytes)
+        return fail(p, GKE_ERR_ARG, "the saved state belongs to a plan of another shape or "
+                                    "options");
+    if (bytes < state_bytes(h)) return fail(p, GKE_ERR_ARG, "state buffer truncated");
+    const char *o = static_cast<const char *>(host) + sizeof(h);
+    hipStream_t st = p->stream;
+    GKE_HIP(p, hipMemcpyAsync(p->sums1, o, h.small_bytes, hipMemcpyHostToDevice, st));
+    o += h.small_bytes;
+    if (h.acc_bytes)
+        GKE_HIP(p, hipMemcpyAsync(p->acc, o, h.acc_bytes, hipMemcpyHostToDevice, st));
+    o += h.acc_bytes;
+    if (h.band_bytes)
+        GKE_HIP(p, hipMemcpyAsync(p->band, o, h.band_bytes, hipMemcpyHostToDevice, st));
+    GKE_HIP(p, hipStreamSynchronize(st));
+    p->n1 = h.n1;
+    p->n2 = h.n2;
+    p->chunks_done = h.chunks_done;
+    p->pending = 0;
+    p->second_scan = h.second_scan != 0;
+    p->means_from_host = h.means_from_host != 0;
     return GKE_OK;
 }
 

@@ -86,6 +86,9 @@ def lib() -> ctypes.CDLL:
         "gke_finalize": ([vp, ctypes.POINTER(gke_terms)], i32),
         "gke_wait_outputs": ([vp], i32),
         "gke_set_slab_callback": ([vp, SLAB_FN, vp], i32),
+        "gke_state_size": ([vp, ctypes.POINTER(sz)], i32),
+        "gke_save_state": ([vp, vp, sz], i32),
+        "gke_load_state": ([vp, vp, sz], i32),
         "gke_reconstruct": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
         "gke_get_profiles": ([vp, dp], i32),
         "gke_slab_count": ([vp, ctypes.POINTER(i32)], i32),
@@ -219,6 +222,21 @@ def gke_finalize(plan, ptrs, residual: int = 0, on_device: int = 1,
 
 def gke_wait_outputs(plan) -> None:
     _check(lib().gke_wait_outputs(plan), plan)
+
+
+def gke_state_size(plan) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().gke_state_size(plan, ctypes.byref(n)), plan)
+    return n.value
+
+
+def gke_save_state(plan, host_ptr: int, nbytes: int) -> None:
+    """Flush the current chunk and copy the scan state into host memory."""
+    _check(lib().gke_save_state(plan, host_ptr, nbytes), plan)
+
+
+def gke_load_state(plan, host_ptr: int, nbytes: int) -> None:
+    _check(lib().gke_load_state(plan, host_ptr, nbytes), plan)
 
 
 def gke_set_slab_callback(plan, fn):

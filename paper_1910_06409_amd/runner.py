@@ -146,6 +146,18 @@ class GkeRun:
     def wait_outputs(self):
         gke.gke_wait_outputs(self.plan)
 
+    def save_state(self) -> torch.Tensor:
+        """The scan state (flushing the current chunk) as a host uint8 tensor."""
+        n = gke.gke_state_size(self.plan)
+        buf = torch.empty(n, dtype=torch.uint8)
+        gke.gke_save_state(self.plan, buf.data_ptr(), n)
+        return buf
+
+    def load_state(self, buf: torch.Tensor):
+        if buf.device.type != "cpu" or buf.dtype != torch.uint8 or not buf.is_contiguous():
+            raise ValueError("state must be a contiguous host uint8 tensor")
+        gke.gke_load_state(self.plan, buf.data_ptr(), buf.numel())
+
     def on_slab(self, fn):
         """fn(slab) once per finalize when its maps are complete (None: off)."""
         self._slab_cb = gke.gke_set_slab_callback(self.plan, fn)

@@ -79,6 +79,18 @@ def test_options_and_state_errors():
         with pytest.raises(gke.GkeError) as e:
             gke.gke_finalize(p, [0] * 14)
         assert e.value.status == gke.GKE_ERR_STATE
+        # checkpoints need the workspace too; NULL buffers are argument errors
+        for call in (lambda: gke.gke_state_size(p),
+                     lambda: gke.gke_save_state(p, 4096, 1 << 20),
+                     lambda: gke.gke_load_state(p, 4096, 1 << 20)):
+            with pytest.raises(gke.GkeError) as e:
+                call()
+            assert e.value.status == gke.GKE_ERR_STATE
+        for call in (lambda: gke.gke_save_state(p, 0, 1 << 20),
+                     lambda: gke.gke_load_state(p, 0, 1 << 20)):
+            with pytest.raises(gke.GkeError) as e:
+                call()
+            assert e.value.status == gke.GKE_ERR_ARG
         with pytest.raises(gke.GkeError) as e:
             gke.gke_set_workspace(p, 0, 1 << 20)
         assert e.value.status == gke.GKE_ERR_ARG
