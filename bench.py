@@ -563,7 +563,7 @@ def main():
                                f"{w.dtype} snapshots, all (Y1,Y2) pairs, rx>=0 half plane, "
                                f"14 term maps", "grid": [w.nx, w.ny, w.nz], "snapshots": S,
                    "precision": w.precision, "chunk": main_res["chunk"],
-                   "points_out": w.points_out, "tuned": main_res["tuned"]},
+                   "points_out": w.points_out, "tuned": main_res["tuned"], "seed": args.seed},
         "points_per_s": w.points_out / t_step,
         # the contract's T (first second-scan accumulate to the return of
         # finalize) and the throughput over it; the first scan apart
