@@ -40,8 +40,6 @@ __device__ __forceinline__ u4 swapneg4(u4 x)
 {
     return u4{swapneg(x.x), swapneg(x.y), swapneg(x.z), swapneg(x.w)};
 }
-constexpr unsigned int NEG2 = 0x80008000u;   // negate both halves
-__device__ __forceinline__ u4 neg4(u4 x) { return x ^ u4{NEG2, NEG2, NEG2, NEG2}; }
 __device__ __forceinline__ bf8 as_bf8(u4 x) { return __builtin_bit_cast(bf8, x); }
 
 __device__ __forceinline__ f4 mfma(u4 a, u4 b, f4 c)
@@ -69,8 +67,9 @@ __device__ __forceinline__ void prod(f4 *ar, f4 *ai, int c, u4 ah, u4 al, const 
 }
 
 // The products of right field B over one group of 16 snapshots (31 in all
-// over the ten right fields); the products with a minus sign take the negated
-// left field.
+// over the ten right fields); the products that enter c1 and c2 with a minus
+// sign go to accumulators 9 and 10 of their own, subtracted in the FP64
+// epilogue (no negated copies of the left records).
 template <int B>
 __device__ __forceinline__ void group_products(f4 *ar, f4 *ai, const u4 *LH, const u4 *LL, u4 rh,
                                                u4 rl)
@@ -100,22 +99,22 @@ __device__ __forceinline__ void group_products(f4 *ar, f4 *ai, const u4 *LH, con
     } else if constexpr (B == F_P) {
         prod(ar, ai, 6, LH[F_V], LL[F_V], r);
     } else if constexpr (B == F_QXX) {
-        prod(ar, ai, 1, neg4(LH[F_U]), neg4(LL[F_U]), r);
+        prod(ar, ai, 9, LH[F_U], LL[F_U], r);
         prod(ar, ai, 5, LH[F_V], LL[F_V], r);
     } else if constexpr (B == F_QYY) {
         prod(ar, ai, 4, LH[F_V], LL[F_V], r);
         prod(ar, ai, 5, LH[F_V], LL[F_V], r);
     } else if constexpr (B == F_QZZ) {
-        prod(ar, ai, 2, neg4(LH[F_W]), neg4(LL[F_W]), r);
+        prod(ar, ai, 10, LH[F_W], LL[F_W], r);
         prod(ar, ai, 5, LH[F_V], LL[F_V], r);
     } else if constexpr (B == F_QXY) {
-        prod(ar, ai, 1, neg4(LH[F_V]), neg4(LL[F_V]), r);
+        prod(ar, ai, 9, LH[F_V], LL[F_V], r);
         prod(ar, ai, 4, LH[F_U], LL[F_U], r);
     } else if constexpr (B == F_QXZ) {
-        prod(ar, ai, 1, neg4(LH[F_W]), neg4(LL[F_W]), r);
-        prod(ar, ai, 2, neg4(LH[F_U]), neg4(LL[F_U]), r);
+        prod(ar, ai, 9, LH[F_W], LL[F_W], r);
+        prod(ar, ai, 10, LH[F_U], LL[F_U], r);
     } else {   // F_QYZ
-        prod(ar, ai, 2, neg4(LH[F_V]), neg4(LL[F_V]), r);
+        prod(ar, ai, 10, LH[F_V], LL[F_V], r);
         prod(ar, ai, 4, LH[F_W], LL[F_W], r);
     }
 }
@@ -152,9 +151,10 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
     const unsigned loff = (unsigned)t_rowplane[ta * 16 + row] * sizeof(SplitRec);
     const unsigned roff = (unsigned)(tb * 16 + row) * sizeof(SplitRec);
 
-    f4 ar[9], ai[9];
+    // c0 .. c8, then the minus-sign parts of c1 and c2
+    f4 ar[11], ai[11];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
+    for (int c = 0; c < 11; ++c) {
         ar[c] = f4{0.f, 0.f, 0.f, 0.f};
         ai[c] = f4{0.f, 0.f, 0.f, 0.f};
     }
@@ -166,8 +166,11 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
         // the right fields go through three register pairs, each loaded two
         // groups before its products, so that the left records (all ten
         // fields) and three right fields are live at once
+        // the 32-bit lane offset is formed before it meets the wave-uniform
+        // base, so that the loads take the base from scalar registers
+        const unsigned ro = roff + so, lo = loff + so;
         auto ldr = [&](int f, u4 &h, u4 &l) {
-            const u4 *rr = reinterpret_cast<const u4 *>(base + f * fbytes + roff + so);
+            const u4 *rr = reinterpret_cast<const u4 *>(base + f * fbytes + ro);
             h = rr[0];
             l = rr[1];
         };
@@ -177,7 +180,7 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
         u4 LH[NFIELD], LL[NFIELD];
 #pragma unroll
         for (int f = 0; f < NFIELD; ++f) {
-            const u4 *lr = reinterpret_cast<const u4 *>(base + f * fbytes + loff + so);
+            const u4 *lr = reinterpret_cast<const u4 *>(base + f * fbytes + lo);
             LH[f] = lr[0];
             LL[f] = lr[1];
         }
@@ -216,6 +219,10 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
             cr[c] = (double)ar[c][v];
             ci[c] = (double)ai[c][v];
         }
+        cr[1] -= (double)ar[9][v];
+        ci[1] -= (double)ai[9][v];
+        cr[2] -= (double)ar[10][v];
+        ci[2] -= (double)ai[10][v];
         cr[5] *= 0.2;   // (v, q) + (q, v) from the 0.2 (Q_xx + Q_yy + Q_zz) products
         ci[5] *= 0.2;
         store_spectra(acc, sp_stride, o, cr, ci, accumulate);
