@@ -117,7 +117,6 @@ struct Dims {
     int npair_tiles;  // 256 ntp pairs handled on the matrix cores
     int npair;        // all unordered pairs (tile pairs + remainder pairs)
     int pstr;         // pair stride of the accumulators: npair rounded up to 8 (128-byte rows)
-    int xblk;         // threads of an x-pass block (SMALL_BLOCK or FFT_BLOCK)
     int kxblk;        // threads of a kx-finalize block (SMALL_BLOCK or FFT_BLOCK)
     int zpblk;        // threads of a z-pass block (SMALL_BLOCK or FFT_BLOCK)
     int zb, nzb;      // z rows per block in the x pass, number of blocks

@@ -703,16 +703,15 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
         delete p;
         return fail(nullptr, GKE_ERR_UNSUPPORTED, "transform length too large for one block");
     }
-    // the smaller block shape of the x pass and the kx finalize when its cap
-    // still holds two z rows (x pass) or eight transforms (kx finalize)
+    // the smaller block shape of the kx finalize when its cap still holds
+    // eight transforms; the x pass always takes the larger one (four z rows
+    // per block at re200, measured faster than two in 256-thread blocks)
     const size_t cap_small = std::min<size_t>(cap, gke::SMALL_CAP);
-    d.xblk = (size_t)10 * sx <= cap_small && Nz % 2 == 0 ? gke::SMALL_BLOCK : gke::FFT_BLOCK;
     d.kxblk = cap_small / sx >= 8 ? gke::SMALL_BLOCK : gke::FFT_BLOCK;
-    const size_t capx = d.xblk == gke::SMALL_BLOCK ? cap_small : cap;
     const size_t capkx = d.kxblk == gke::SMALL_BLOCK ? cap_small : cap;
     // x pass: 5 complex rows per z row (ten real fields), zb | Nz
     d.zb = 16;
-    while (d.zb > 1 && (Nz % d.zb || (size_t)5 * d.zb * sx > capx)) d.zb >>= 1;
+    while (d.zb > 1 && (Nz % d.zb || (size_t)5 * d.zb * sx > cap)) d.zb >>= 1;
     d.nzb = Nz / d.zb;
     set_zpass_shape(d);
     // finalize: pairs per kz block, complex transforms (2 pairs each) per kx block

@@ -197,30 +197,19 @@ __global__ __launch_bounds__(BLOCK, GKE_FFT_WAVES) void k_fluct_xfft(const TI *_
     }
 }
 
-template <typename TI, typename T, int BLOCK, bool GY>
-static void launch_fx_shape(hipStream_t st, const Dims &d, const Tables &t, const void *u,
-                            const void *v, const void *w, const void *p, const double *prof,
-                            void *inter, double *momp)
-{
-    const size_t lds = sizeof(cx<T>) * (5 * (size_t)d.zb * fft_stride(d.nx) + d.nx);
-    with_fft_len(d.nx, [&](auto len) {
-        constexpr int NF = decltype(len)::value;
-        set_lds_limit(k_fluct_xfft<TI, T, BLOCK, NF, GY>);
-        hipLaunchKernelGGL((k_fluct_xfft<TI, T, BLOCK, NF, GY>), dim3(d.nzb * d.ny), dim3(BLOCK),
-                           lds, st, (const TI *)u, (const TI *)v, (const TI *)w, (const TI *)p,
-                           prof, d, t, (cx<T> *)inter, momp);
-    });
-}
-
 template <typename TI, typename T, bool GY>
 static void launch_fx(hipStream_t st, const Dims &d, const Tables &t, const void *u,
                       const void *v, const void *w, const void *p, const double *prof,
                       void *inter, double *momp)
 {
-    if (d.xblk == SMALL_BLOCK)
-        launch_fx_shape<TI, T, SMALL_BLOCK, GY>(st, d, t, u, v, w, p, prof, inter, momp);
-    else
-        launch_fx_shape<TI, T, FFT_BLOCK, GY>(st, d, t, u, v, w, p, prof, inter, momp);
+    const size_t lds = sizeof(cx<T>) * (5 * (size_t)d.zb * fft_stride(d.nx) + d.nx);
+    with_fft_len(d.nx, [&](auto len) {
+        constexpr int NF = decltype(len)::value;
+        set_lds_limit(k_fluct_xfft<TI, T, FFT_BLOCK, NF, GY>);
+        hipLaunchKernelGGL((k_fluct_xfft<TI, T, FFT_BLOCK, NF, GY>), dim3(d.nzb * d.ny),
+                           dim3(FFT_BLOCK), lds, st, (const TI *)u, (const TI *)v, (const TI *)w,
+                           (const TI *)p, prof, d, t, (cx<T> *)inter, momp);
+    });
 }
 
 hipError_t launch_fluct_xfft(hipStream_t st, const Dims &d, const Tables &t, int f32, int gy,
