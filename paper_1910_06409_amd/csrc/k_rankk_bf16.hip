@@ -21,8 +21,7 @@
 // c5 = (v, q) + (q, v) = 0.2 sum_i [(v, Q_ii) + (Q_ii, v)], 31 products per
 // snapshot, which costs four products more and saves forming q from split
 // values.  The products are grouped by their right field, whose rotated forms
-// are made once per group of 16 snapshots; the right fields are loaded two
-// groups ahead of their products.
+// are made once per group of 16 snapshots.
 #include "rankk_common.h"
 
 namespace gke {
@@ -119,28 +118,41 @@ __device__ __forceinline__ void group_products(f4 *ar, f4 *ai, const u4 *LH, con
     }
 }
 
-#ifndef GKE_RANKK16_MINW
-#define GKE_RANKK16_MINW 2
-#endif
+typedef __attribute__((address_space(3))) void lds_void;
 
-// One wave per (wavenumber, tile pair); groups of 16 snapshots (four quads,
-// one per lane group).  A quad past the end reloads the last one and its left
+// One tile of one group of 16 snapshots in LDS: [field][h, l][lane], 16 bytes
+// each, lane l holding plane l%16 of quad l/16 -- the order in which a wave
+// loads it and in which the MFMA operands are read back (lane-linear, free of
+// bank conflicts).
+constexpr int SB_TILE = NFIELD * 2 * 64;   // u4 entries (20 KB)
+
+// One workgroup of four waves per (wavenumber, 2 x 2 block of tile pairs).
+// Per group of 16 snapshots every wave copies one tile of the block into LDS
+// with direct global-to-LDS loads (row tiles a0 a1 through the row-plane
+// table, column tiles b0 b1), and wave 2i + j then takes the operands of pair
+// (a_i, b_j) from there: a tile shared by two pairs of the block is read from
+// L2 once instead of twice, and the loads hold no registers.  Block s is
+// sblk[8 s ..]: a0 a1 b0 b1 (b = -1 - i: the planes of row tile a_i, not
+// copied again), then the tile-pair index of wave 2i + j (-1: none; such a
+// wave still copies its tile and meets the barriers).  The 80 KB of LDS let
+// two workgroups share a compute unit, one computing while the other waits
+// for its copies.  A quad past the end copies the last one and its left
 // operands are zeroed (the records of a partial last quad hold zeros in the
 // missing snapshots, written by the z pass).
-__global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
-    const SplitRec *__restrict__ spec, Dims d, const int *__restrict__ tile_a,
-    const int *__restrict__ tile_b, const int *__restrict__ t_rowplane, int nsnap,
-    int accumulate, int total, cx<double> *__restrict__ acc)
+__global__ __launch_bounds__(256, 2) void k_rankk_bf16x3(
+    const SplitRec *__restrict__ spec, Dims d, const int *__restrict__ sblk,
+    const int *__restrict__ t_rowplane, int nsnap, int accumulate, int total,
+    cx<double> *__restrict__ acc)
 {
+    __shared__ u4 lds[4 * SB_TILE];
     const int G = gridDim.x;
     const int bid = blockIdx.x;
     const int Lg = (bid & 7) * (G >> 3) + (bid >> 3);   // XCD-aware order
-    if (Lg >= total) return;
-    const int k = Lg / d.ntp;
-    const int tp = Lg - k * d.ntp;
-    const int ta = tile_a[tp], tb = tile_b[tp];
-
-    const int lane = threadIdx.x;
+    if (Lg >= total) return;   // whole workgroups
+    const int k = Lg / d.nsb;
+    const int *sb = sblk + 8 * (Lg - k * d.nsb);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
     const int row = lane & 15, g = lane >> 4;
     const int nq = (nsnap + 3) >> 2;
     // records of this wavenumber: ((f nqs + q) nys + plane); the field and
@@ -148,8 +160,19 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
     const char *kb = reinterpret_cast<const char *>(spec_base(spec, d, k));
     const size_t fbytes = (size_t)d.nqs * d.nys * sizeof(SplitRec);
     const unsigned qbytes = (unsigned)d.nys * sizeof(SplitRec);
-    const unsigned loff = (unsigned)t_rowplane[ta * 16 + row] * sizeof(SplitRec);
-    const unsigned roff = (unsigned)(tb * 16 + row) * sizeof(SplitRec);
+    // the tile this wave copies (slot wv)
+    const int tsrc = sb[wv];
+    const bool copies = tsrc >= 0;
+    const unsigned poff =
+        copies ? (unsigned)(wv < 2 ? t_rowplane[tsrc * 16 + row] : tsrc * 16 + row) *
+                     (unsigned)sizeof(SplitRec)
+               : 0u;
+    u4 *dst = lds + wv * SB_TILE;
+    // the pair of this wave and the slots of its operands
+    const int tp = sb[4 + wv];
+    const int bj = sb[2 + (wv & 1)];
+    const u4 *Lt = lds + (wv >> 1) * SB_TILE + lane;
+    const u4 *Rt = lds + (bj >= 0 ? 2 + (wv & 1) : -1 - bj) * SB_TILE + lane;
 
     // c0 .. c8, then the minus-sign parts of c1 and c2
     f4 ar[11], ai[11];
@@ -160,54 +183,61 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
     }
 
     for (int q0 = 0; q0 < nq; q0 += 4) {
-        const bool ok = q0 + g < nq;
-        const unsigned so = (unsigned)(ok ? g : nq - 1 - q0) * qbytes;
-        const char *base = kb + (size_t)q0 * qbytes;
-        // the right fields go through three register pairs, each loaded two
-        // groups before its products, so that the left records (all ten
-        // fields) and three right fields are live at once
-        // the 32-bit lane offset is formed before it meets the wave-uniform
-        // base, so that the loads take the base from scalar registers
-        const unsigned ro = roff + so, lo = loff + so;
-        auto ldr = [&](int f, u4 &h, u4 &l) {
-            const u4 *rr = reinterpret_cast<const u4 *>(base + f * fbytes + ro);
-            h = rr[0];
-            l = rr[1];
-        };
-        u4 h0, l0, h1, l1, h2, l2;
-        ldr(F_U, h0, l0);
-        ldr(F_V, h1, l1);
-        u4 LH[NFIELD], LL[NFIELD];
+        if (copies) {
+            // the 32-bit lane offset is formed before it meets the
+            // wave-uniform base, so that the loads take the base from scalar
+            // registers
+            const unsigned lo = poff + (unsigned)min(q0 + g, nq - 1) * qbytes;
 #pragma unroll
-        for (int f = 0; f < NFIELD; ++f) {
-            const u4 *lr = reinterpret_cast<const u4 *>(base + f * fbytes + lo);
-            LH[f] = lr[0];
-            LL[f] = lr[1];
+            for (int f = 0; f < NFIELD; ++f)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    __builtin_amdgcn_global_load_lds(kb + f * fbytes + (lo + 16u * h),
+                                                     (lds_void *)(dst + (2 * f + h) * 64), 16,
+                                                     0, 0);
         }
-        if (!ok) {
+        __syncthreads();   // every wave's copies have landed
+        if (tp >= 0) {
+            const bool ok = q0 + g < nq;
+            u4 LH[NFIELD], LL[NFIELD];
 #pragma unroll
             for (int f = 0; f < NFIELD; ++f) {
-                LH[f] = u4{0u, 0u, 0u, 0u};
-                LL[f] = u4{0u, 0u, 0u, 0u};
+                LH[f] = Lt[(2 * f) * 64];
+                LL[f] = Lt[(2 * f + 1) * 64];
             }
-        }
-#define GKE_GROUP(NEXT, HN, LN, CUR, HC, LC)                 \
-        ldr(NEXT, HN, LN);                                   \
-        group_products<CUR>(ar, ai, LH, LL, HC, LC);         \
-        __builtin_amdgcn_sched_barrier(0)
-        GKE_GROUP(F_W, h2, l2, F_U, h0, l0);
-        GKE_GROUP(F_P, h0, l0, F_V, h1, l1);
-        GKE_GROUP(F_QXX, h1, l1, F_W, h2, l2);
-        GKE_GROUP(F_QYY, h2, l2, F_P, h0, l0);
-        GKE_GROUP(F_QZZ, h0, l0, F_QXX, h1, l1);
-        GKE_GROUP(F_QXY, h1, l1, F_QYY, h2, l2);
-        GKE_GROUP(F_QXZ, h2, l2, F_QZZ, h0, l0);
-        GKE_GROUP(F_QYZ, h0, l0, F_QXY, h1, l1);
+            if (!ok) {
+#pragma unroll
+                for (int f = 0; f < NFIELD; ++f) {
+                    LH[f] = u4{0u, 0u, 0u, 0u};
+                    LL[f] = u4{0u, 0u, 0u, 0u};
+                }
+            }
+            // each right field is read one group ahead of its products
+            u4 rh = Rt[(2 * F_U) * 64], rl = Rt[(2 * F_U + 1) * 64];
+#define GKE_GROUP(CUR, NEXT)                                  \
+            {                                                 \
+                const u4 nh = Rt[(2 * NEXT) * 64];            \
+                const u4 nl = Rt[(2 * NEXT + 1) * 64];        \
+                group_products<CUR>(ar, ai, LH, LL, rh, rl);  \
+                rh = nh;                                      \
+                rl = nl;                                      \
+                __builtin_amdgcn_sched_barrier(0);            \
+            }
+            GKE_GROUP(F_U, F_V)
+            GKE_GROUP(F_V, F_W)
+            GKE_GROUP(F_W, F_P)
+            GKE_GROUP(F_P, F_QXX)
+            GKE_GROUP(F_QXX, F_QYY)
+            GKE_GROUP(F_QYY, F_QZZ)
+            GKE_GROUP(F_QZZ, F_QXY)
+            GKE_GROUP(F_QXY, F_QXZ)
+            GKE_GROUP(F_QXZ, F_QYZ)
 #undef GKE_GROUP
-        group_products<F_QXZ>(ar, ai, LH, LL, h2, l2);
-        group_products<F_QYZ>(ar, ai, LH, LL, h0, l0);
-        __builtin_amdgcn_sched_barrier(0);
+            group_products<F_QYZ>(ar, ai, LH, LL, rh, rl);
+        }
+        __syncthreads();   // every wave has read its operands: the tiles may be refilled
     }
+    if (tp < 0) return;
 
     const size_t sp_stride = (size_t)d.nk * d.pstr;
 #pragma unroll
@@ -232,11 +262,11 @@ __global__ __launch_bounds__(64, GKE_RANKK16_MINW) void k_rankk_bf16x3(
 hipError_t launch_rankk_bf16x3(hipStream_t st, const Dims &d, const Tables &t,
                                const SplitRec *spec, int nsnap, int accumulate, cx<double> *acc)
 {
-    if (d.ntp > 0) {
-        const long long total = (long long)d.nk * d.ntp;
+    if (d.ntp > 0 && d.nsb > 0) {
+        const long long total = (long long)d.nk * d.nsb;
         if (total >= (1LL << 31) - 8) return hipErrorInvalidValue;
         const int G = (int)((total + 7) / 8 * 8);
-        hipLaunchKernelGGL(k_rankk_bf16x3, dim3(G), dim3(64), 0, st, spec, d, t.tile_a, t.tile_b,
+        hipLaunchKernelGGL(k_rankk_bf16x3, dim3(G), dim3(256), 0, st, spec, d, t.sblk,
                            t.rowplane, nsnap, accumulate, (int)total, acc);
     }
     return hipGetLastError();
