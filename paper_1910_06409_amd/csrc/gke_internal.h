@@ -115,7 +115,7 @@ struct Dims {
     int ntile;        // full 16-plane tiles: ny / 16
     int ntp;          // ntile (ntile + 1) / 2 unordered tile pairs
     int npair_tiles;  // 256 ntp pairs handled on the matrix cores
-    int nsb;          // 2 x 2 blocks of tile pairs (split-BF16 rank-k workgroups)
+    int nsb;          // groups of four tile pairs (split-BF16 rank-k workgroups)
     int npair;        // all unordered pairs (tile pairs + remainder pairs)
     int pstr;         // pair stride of the accumulators: npair rounded up to 8 (128-byte rows)
     int kxblk;        // threads of a kx-finalize block (SMALL_BLOCK or FFT_BLOCK)
@@ -187,8 +187,8 @@ struct Tables {
     const int *j0;           // [ny] first stencil node
     const int *tile_a;       // [ntp] tile-pair row tiles (index into rowplane / 16)
     const int *tile_b;       // [ntp] tile-pair column tiles (planes 16 b .. 16 b + 15)
-    const int *sblk;         // [8 nsb] 2 x 2 blocks of tile pairs: a0 a1 b0 b1 (b = -1 - i:
-                             // the planes of row tile a_i), then the pair of (a_i, b_j) at 4 + 2i + j
+    const int *sblk;         // [12 nsb] groups of four tile pairs (split rank-k): four tile
+                             // slots, the pair of each wave, each wave's operand slots
     const int *rowplane;     // [16 * row tiles] plane of each row of the row tiles
     const int *rowidx;       // [ny] row of plane Y1 in the full-plane map buffer, or -1
     const int *pairs;        // [npair] pair table

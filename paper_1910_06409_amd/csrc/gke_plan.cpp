@@ -16,6 +16,7 @@
 
 #include "../../include/gke.h"
 #include "gke_internal.h"
+#include "tile_groups.h"
 
 using gke::cx;
 
@@ -27,7 +28,7 @@ struct SlabTables {
     std::vector<int> rowplane;     // rows padded to a multiple of 16 (row tiles)
     std::vector<int> rowidx;       // [ny] index in rows, -1 if absent
     std::vector<int> ta, tb;       // tile pairs (row tile, column tile)
-    std::vector<int> sb;           // their 2 x 2 blocks (split rank-k), eight ints each
+    std::vector<int> sb;           // their groups of four (split rank-k), twelve ints each
     std::vector<int> pairs;        // pair codes in compact order
     std::vector<int> opairs;       // output pairs Y1 | Y2 << 16 in layout order
     int ntp = 0, npair_tiles = 0, npair = 0;
@@ -301,46 +302,6 @@ void domain_cols(gke_plan_t p, int j1, int &c0, int &c1)
     c1 = p->domain == GKE_DOMAIN_FUNDAMENTAL_FULLR ? ny - j1 : ny;
 }
 
-// The tile pairs grouped in 2 x 2 blocks for the split-BF16 rank-k: pairs
-// (a, b) with the same (a / 2, b / 2) share a block; per block eight ints,
-// row tiles a0 a1, column tiles b0 b1, then the pair index of (a_i, b_j) at
-// 4 + 2i + j (-1: none).  A position with no tile of its own repeats the
-// other one (copied, never used).  same_planes: row tile t holds planes
-// 16 t .. 16 t + 15 (the all-pairs mode), and a column tile equal to row tile
-// a_i is written b = -1 - i, so that it is not copied twice.
-std::vector<int> super_blocks(const std::vector<int> &ta, const std::vector<int> &tb, int ntp,
-                              bool same_planes)
-{
-    std::map<std::pair<int, int>, std::array<int, 4>> grp;
-    for (int i = 0; i < ntp; ++i) {
-        auto it = grp.try_emplace({ta[i] >> 1, tb[i] >> 1}, std::array<int, 4>{-1, -1, -1, -1});
-        it.first->second[2 * (ta[i] & 1) + (tb[i] & 1)] = i;
-    }
-    std::vector<int> out;
-    for (const auto &kv : grp) {
-        const std::array<int, 4> &w = kv.second;
-        int a[2], b[2];
-        for (int i = 0; i < 2; ++i) {
-            const bool has_a = w[2 * i] >= 0 || w[2 * i + 1] >= 0;
-            const bool has_b = w[i] >= 0 || w[2 + i] >= 0;
-            a[i] = 2 * kv.first.first + (has_a ? i : 1 - i);
-            b[i] = 2 * kv.first.second + (has_b ? i : 1 - i);
-        }
-        for (int i = 0; i < 2; ++i) out.push_back(a[i]);
-        for (int j = 0; j < 2; ++j) {
-            int code = b[j];
-            for (int i = 0; i < 2 && same_planes; ++i)
-                if (b[j] == a[i]) {
-                    code = -1 - i;
-                    break;
-                }
-            out.push_back(code);
-        }
-        for (int v : w) out.push_back(v);
-    }
-    return out;
-}
-
 // Tables of every slab (general modes): rows with accumulators = the slab's
 // output rows, their five-point stencil rows and, with the mirror average,
 // the reflections of both; tile pairs = every row tile against every column
@@ -383,7 +344,7 @@ void build_slabs(gke_plan_t p)
             }
         t.ntp = (int)t.ta.size();
         t.npair_tiles = 256 * t.ntp;
-        t.sb = super_blocks(t.ta, t.tb, t.ntp, false);
+        t.sb = gke::group_tile_pairs(t.ta, t.tb, t.ntp, false);
         for (int r : t.rows)
             for (int c = 16 * d.ntile; c < ny; ++c) t.pairs.push_back(r | c << 12);
         t.npair = (int)t.pairs.size();
@@ -484,12 +445,12 @@ size_t layout(gke_plan_t p, char *base)
     };
     // table and accumulator extents: all pairs, or the largest slab
     size_t ntp = std::max(d.ntp, 1), npair = d.npair, nrowp = p->h_rowplane.size();
-    size_t nrows = 0, nopairs = 1, nsb = std::max<size_t>(p->h_sb.size() / 8, 1);
+    size_t nrows = 0, nopairs = 1, nsb = std::max<size_t>(p->h_sb.size() / 12, 1);
     if (p->general) {
         ntp = npair = nrowp = nsb = 1;
         for (const auto &t : p->slabs) {
             ntp = std::max(ntp, t.ta.size());
-            nsb = std::max(nsb, t.sb.size() / 8);
+            nsb = std::max(nsb, t.sb.size() / 12);
             npair = std::max(npair, (size_t)t.npair);
             nrowp = std::max(nrowp, t.rowplane.size());
             nrows = std::max(nrows, t.rows.size());
@@ -506,7 +467,7 @@ size_t layout(gke_plan_t p, char *base)
     p->j0 = (int *)take(sizeof(int) * d.ny);
     p->ta = (int *)take(sizeof(int) * ntp);
     p->tb = (int *)take(sizeof(int) * ntp);
-    p->sblk = (int *)take(sizeof(int) * 8 * nsb);
+    p->sblk = (int *)take(sizeof(int) * 12 * nsb);
     p->pairs = (int *)take(sizeof(int) * npair);
     p->pidx = (int *)take(sizeof(int) * d.ny * d.ny);
     p->rowplane = (int *)take(sizeof(int) * nrowp);
@@ -567,7 +528,7 @@ gke_status select_slab(gke_plan_t p, int s)
         GKE_HIP(p, hipMemcpyAsync(p->opairs, t.opairs.data(), sizeof(int) * t.opairs.size(), hipMemcpyHostToDevice, st));
     GKE_HIP(p, hipStreamSynchronize(st));
     p->d.ntp = t.ntp;
-    p->d.nsb = (int)t.sb.size() / 8;
+    p->d.nsb = (int)t.sb.size() / 12;
     p->d.npair_tiles = t.npair_tiles;
     p->d.npair = t.npair;
     p->d.pstr = round8(t.npair);
@@ -808,8 +769,8 @@ gke_status gke_plan(int Nx, int Ny, int Nz, const double *y, double Lx, double L
                 for (int k = 0; k < 16; ++k)
                     p->h_pairs.push_back((16 * a + i) | (16 * b + k) << 12 | (a < b ? 1 : 0) << 24);
         }
-    p->h_sb = super_blocks(p->h_ta, p->h_tb, d.ntp, true);
-    d.nsb = (int)p->h_sb.size() / 8;
+    p->h_sb = gke::group_tile_pairs(p->h_ta, p->h_tb, d.ntp, true);
+    d.nsb = (int)p->h_sb.size() / 12;
     if (p->h_ta.empty()) {
         p->h_ta.push_back(0);
         p->h_tb.push_back(0);

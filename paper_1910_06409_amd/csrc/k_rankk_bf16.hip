@@ -126,19 +126,19 @@ typedef __attribute__((address_space(3))) void lds_void;
 // bank conflicts).
 constexpr int SB_TILE = NFIELD * 2 * 64;   // u4 entries (20 KB)
 
-// One workgroup of four waves per (wavenumber, 2 x 2 block of tile pairs).
-// Per group of 16 snapshots every wave copies one tile of the block into LDS
-// with direct global-to-LDS loads (row tiles a0 a1 through the row-plane
-// table, column tiles b0 b1), and wave 2i + j then takes the operands of pair
-// (a_i, b_j) from there: a tile shared by two pairs of the block is read from
-// L2 once instead of twice, and the loads hold no registers.  Block s is
-// sblk[8 s ..]: a0 a1 b0 b1 (b = -1 - i: the planes of row tile a_i, not
-// copied again), then the tile-pair index of wave 2i + j (-1: none; such a
-// wave still copies its tile and meets the barriers).  The 80 KB of LDS let
-// two workgroups share a compute unit, one computing while the other waits
-// for its copies.  A quad past the end copies the last one and its left
-// operands are zeroed (the records of a partial last quad hold zeros in the
-// missing snapshots, written by the z pass).
+// One workgroup of four waves per (wavenumber, group of four tile pairs that
+// use at most four tiles).  Per group of 16 snapshots every wave copies one
+// tile slot into LDS with direct global-to-LDS loads, and each wave then takes
+// the operands of its own pair from the slots: a tile shared by two pairs of
+// the group is read from L2 once, and the loads hold no registers.  Group s is
+// sblk[12 s ..]: four slots (t: row tile t, planes through the row-plane
+// table; t | 1 << 16: column tile t; -1: empty), the tile-pair index of each
+// wave (-1: none; such a wave still copies its slot and meets the barriers)
+// and each wave's left and right slot (l | r << 4).  The 80 KB of LDS let two
+// workgroups share a compute unit, one computing while the other waits for
+// its copies.  A quad past the end copies the last one and its left operands
+// are zeroed (the records of a partial last quad hold zeros in the missing
+// snapshots, written by the z pass).
 __global__ __launch_bounds__(256, 2) void k_rankk_bf16x3(
     const SplitRec *__restrict__ spec, Dims d, const int *__restrict__ sblk,
     const int *__restrict__ t_rowplane, int nsnap, int accumulate, int total,
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256, 2) void k_rankk_bf16x3(
     const int Lg = (bid & 7) * (G >> 3) + (bid >> 3);   // XCD-aware order
     if (Lg >= total) return;   // whole workgroups
     const int k = Lg / d.nsb;
-    const int *sb = sblk + 8 * (Lg - k * d.nsb);
+    const int *sb = sblk + 12 * (Lg - k * d.nsb);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, g = lane >> 4;
@@ -161,18 +161,19 @@ __global__ __launch_bounds__(256, 2) void k_rankk_bf16x3(
     const size_t fbytes = (size_t)d.nqs * d.nys * sizeof(SplitRec);
     const unsigned qbytes = (unsigned)d.nys * sizeof(SplitRec);
     // the tile this wave copies (slot wv)
-    const int tsrc = sb[wv];
-    const bool copies = tsrc >= 0;
+    const int code = sb[wv];
+    const bool copies = code >= 0;
+    const int tile = code & 0xffff;
     const unsigned poff =
-        copies ? (unsigned)(wv < 2 ? t_rowplane[tsrc * 16 + row] : tsrc * 16 + row) *
+        copies ? (unsigned)(code >> 16 ? tile * 16 + row : t_rowplane[tile * 16 + row]) *
                      (unsigned)sizeof(SplitRec)
                : 0u;
     u4 *dst = lds + wv * SB_TILE;
     // the pair of this wave and the slots of its operands
     const int tp = sb[4 + wv];
-    const int bj = sb[2 + (wv & 1)];
-    const u4 *Lt = lds + (wv >> 1) * SB_TILE + lane;
-    const u4 *Rt = lds + (bj >= 0 ? 2 + (wv & 1) : -1 - bj) * SB_TILE + lane;
+    const int ops = sb[8 + wv];
+    const u4 *Lt = lds + (ops & 15) * SB_TILE + lane;
+    const u4 *Rt = lds + (ops >> 4) * SB_TILE + lane;
 
     // c0 .. c8, then the minus-sign parts of c1 and c2
     f4 ar[11], ai[11];
