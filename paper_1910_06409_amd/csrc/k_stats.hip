@@ -103,6 +103,11 @@ __global__ __launch_bounds__(256) void k_plane_sums_gy(const TI *__restrict__ u,
 #pragma unroll
         for (int f = 0; f < 5; ++f) a[q][f] = 0.0;
     for (int i = i0 + (int)threadIdx.x; i < i1; i += 256) {
+        // an opaque zero added to the weight index keeps the weights in LDS,
+        // read at each use: hoisted out of the loop they held 40 VGPRs (144 in
+        // all, three waves per SIMD)
+        int wz = 0;
+        asm volatile("" : "+v"(wz));
         // plane bases are block-uniform (scalar registers); the lane offset is i
         TI pv[GY_JC];
 #pragma unroll
@@ -124,7 +129,7 @@ __global__ __launch_bounds__(256) void k_plane_sums_gy(const TI *__restrict__ u,
                 double du = 0.0, dv = 0.0, dw = 0.0;
 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
-                    const double wk = sw[q][k];
+                    const double wk = sw[q][k + wz];
                     du += wk * (double)x[q + k][0];
                     dv += wk * (double)x[q + k][1];
                     dw += wk * (double)x[q + k][2];
@@ -154,7 +159,7 @@ __global__ __launch_bounds__(256) void k_plane_sums_gy(const TI *__restrict__ u,
                 double du = 0.0, dv = 0.0, dw = 0.0;
 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
-                    const double wk = sw[q][k];
+                    const double wk = sw[q][k + wz];
                     du += wk * (double)x[k][0];
                     dv += wk * (double)x[k][1];
                     dw += wk * (double)x[k][2];
