@@ -260,15 +260,132 @@ __global__ __launch_bounds__(256, 2) void k_rankk_bf16x3(
     }
 }
 
+// One wave per (wavenumber, tile pair), every wave loading its own operands:
+// the form for tile-pair sets whose groups of four would leave waves idle
+// (a slab with a single row tile, where no column tile is shared and the
+// grouped kernel would copy four tiles for three pairs).  Groups of 16
+// snapshots (four quads, one per lane group).  A quad past the end reloads
+// the last one and its left operands are zeroed (the records of a partial
+// last quad hold zeros in the missing snapshots, written by the z pass).
+__global__ __launch_bounds__(64, 2) void k_rankk_bf16x3_pair(
+    const SplitRec *__restrict__ spec, Dims d, const int *__restrict__ tile_a,
+    const int *__restrict__ tile_b, const int *__restrict__ t_rowplane, int nsnap,
+    int accumulate, int total, cx<double> *__restrict__ acc)
+{
+    const int G = gridDim.x;
+    const int bid = blockIdx.x;
+    const int Lg = (bid & 7) * (G >> 3) + (bid >> 3);   // XCD-aware order
+    if (Lg >= total) return;
+    const int k = Lg / d.ntp;
+    const int tp = Lg - k * d.ntp;
+    const int ta = tile_a[tp], tb = tile_b[tp];
+
+    const int lane = threadIdx.x;
+    const int row = lane & 15, g = lane >> 4;
+    const int nq = (nsnap + 3) >> 2;
+    // records of this wavenumber: ((f nqs + q) nys + plane); the field and
+    // quad parts are wave-uniform, the plane and lane-group parts a lane offset
+    const char *kb = reinterpret_cast<const char *>(spec_base(spec, d, k));
+    const size_t fbytes = (size_t)d.nqs * d.nys * sizeof(SplitRec);
+    const unsigned qbytes = (unsigned)d.nys * sizeof(SplitRec);
+    const unsigned loff = (unsigned)t_rowplane[ta * 16 + row] * sizeof(SplitRec);
+    const unsigned roff = (unsigned)(tb * 16 + row) * sizeof(SplitRec);
+
+    // c0 .. c8, then the minus-sign parts of c1 and c2
+    f4 ar[11], ai[11];
+#pragma unroll
+    for (int c = 0; c < 11; ++c) {
+        ar[c] = f4{0.f, 0.f, 0.f, 0.f};
+        ai[c] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+    for (int q0 = 0; q0 < nq; q0 += 4) {
+        const bool ok = q0 + g < nq;
+        const unsigned so = (unsigned)(ok ? g : nq - 1 - q0) * qbytes;
+        const char *base = kb + (size_t)q0 * qbytes;
+        // the right fields go through three register pairs, each loaded two
+        // groups before its products, so that the left records (all ten
+        // fields) and three right fields are live at once
+        // the 32-bit lane offset is formed before it meets the wave-uniform
+        // base, so that the loads take the base from scalar registers
+        const unsigned ro = roff + so, lo = loff + so;
+        auto ldr = [&](int f, u4 &h, u4 &l) {
+            const u4 *rr = reinterpret_cast<const u4 *>(base + f * fbytes + ro);
+            h = rr[0];
+            l = rr[1];
+        };
+        u4 h0, l0, h1, l1, h2, l2;
+        ldr(F_U, h0, l0);
+        ldr(F_V, h1, l1);
+        u4 LH[NFIELD], LL[NFIELD];
+#pragma unroll
+        for (int f = 0; f < NFIELD; ++f) {
+            const u4 *lr = reinterpret_cast<const u4 *>(base + f * fbytes + lo);
+            LH[f] = lr[0];
+            LL[f] = lr[1];
+        }
+        if (!ok) {
+#pragma unroll
+            for (int f = 0; f < NFIELD; ++f) {
+                LH[f] = u4{0u, 0u, 0u, 0u};
+                LL[f] = u4{0u, 0u, 0u, 0u};
+            }
+        }
+#define GKE_GROUP(NEXT, HN, LN, CUR, HC, LC)                 \
+        ldr(NEXT, HN, LN);                                   \
+        group_products<CUR>(ar, ai, LH, LL, HC, LC);         \
+        __builtin_amdgcn_sched_barrier(0)
+        GKE_GROUP(F_W, h2, l2, F_U, h0, l0);
+        GKE_GROUP(F_P, h0, l0, F_V, h1, l1);
+        GKE_GROUP(F_QXX, h1, l1, F_W, h2, l2);
+        GKE_GROUP(F_QYY, h2, l2, F_P, h0, l0);
+        GKE_GROUP(F_QZZ, h0, l0, F_QXX, h1, l1);
+        GKE_GROUP(F_QXY, h1, l1, F_QYY, h2, l2);
+        GKE_GROUP(F_QXZ, h2, l2, F_QZZ, h0, l0);
+        GKE_GROUP(F_QYZ, h0, l0, F_QXY, h1, l1);
+#undef GKE_GROUP
+        group_products<F_QXZ>(ar, ai, LH, LL, h2, l2);
+        group_products<F_QYZ>(ar, ai, LH, LL, h0, l0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+
+    const size_t sp_stride = (size_t)d.nk * d.pstr;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const size_t o = (size_t)k * d.pstr + (size_t)tp * 256 + (4 * g + v) * 16 + row;
+        double cr[9], ci[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            cr[c] = (double)ar[c][v];
+            ci[c] = (double)ai[c][v];
+        }
+        cr[1] -= (double)ar[9][v];
+        ci[1] -= (double)ai[9][v];
+        cr[2] -= (double)ar[10][v];
+        ci[2] -= (double)ai[10][v];
+        cr[5] *= 0.2;   // (v, q) + (q, v) from the 0.2 (Q_xx + Q_yy + Q_zz) products
+        ci[5] *= 0.2;
+        store_spectra(acc, sp_stride, o, cr, ci, accumulate);
+    }
+}
+
 hipError_t launch_rankk_bf16x3(hipStream_t st, const Dims &d, const Tables &t,
                                const SplitRec *spec, int nsnap, int accumulate, cx<double> *acc)
 {
-    if (d.ntp > 0 && d.nsb > 0) {
+    if (d.ntp <= 0) return hipSuccess;
+    // the grouped kernel unless more than an eighth of its waves would idle
+    if (d.nsb > 0 && 8 * (4 * d.nsb - d.ntp) <= d.ntp) {
         const long long total = (long long)d.nk * d.nsb;
         if (total >= (1LL << 31) - 8) return hipErrorInvalidValue;
         const int G = (int)((total + 7) / 8 * 8);
         hipLaunchKernelGGL(k_rankk_bf16x3, dim3(G), dim3(256), 0, st, spec, d, t.sblk,
                            t.rowplane, nsnap, accumulate, (int)total, acc);
+    } else {
+        const long long total = (long long)d.nk * d.ntp;
+        if (total >= (1LL << 31) - 8) return hipErrorInvalidValue;
+        const int G = (int)((total + 7) / 8 * 8);
+        hipLaunchKernelGGL(k_rankk_bf16x3_pair, dim3(G), dim3(64), 0, st, spec, d, t.tile_a,
+                           t.tile_b, t.rowplane, nsnap, accumulate, (int)total, acc);
     }
     return hipGetLastError();
 }

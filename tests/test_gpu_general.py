@@ -111,6 +111,24 @@ def test_mirror_fundamental_bf16x3():
            w.nx, "mirror fundamental bf16x3", TOL_BF16)
 
 
+def test_split_slabs_two_row_tiles():
+    """Slabs of 20 rows at Ny = 65 (four column tiles): the inner slabs hold two
+    row tiles, so the split rank-k works in whole 2 x 2 blocks of tile pairs with
+    the operands staged in LDS; the last slab holds one row tile and takes the
+    one-wave-per-pair form.  Both against the oracle."""
+    w = synth.workload("tiny", ny=65, S=6, dtype="f32")
+    y = synth.y_grid(w)
+    snap = synth.snapshots(w, 36)
+    ny = w.ny
+    print("case Y1<=Y2 full r slab=20 ny=65 bf16x3", flush=True)
+    res, _ = _run(snap, w, y, domain=gke.GKE_DOMAIN_Y1LEY2_FULLR, slab=20, precision="bf16x3",
+                  chunk=4)
+    assert len(res) == 4
+    expect = [(a, b) for a in range(ny) for b in range(a, ny)]
+    _check(res, lambda p: oracle.pair_terms(snap.astype(np.float64), y, w.lx, w.lz, w.nu, p),
+           w.nx, "Y1<=Y2 full r slab=20 bf16x3", TOL_BF16, expect)
+
+
 @pytest.mark.timeout(900)
 def test_re200_grid_mirror_fundamental_first_slab():
     """The Re_tau=200 grid, mirror average, fundamental domain, slabs of 8 rows:
